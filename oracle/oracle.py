@@ -1,0 +1,401 @@
+"""CPU oracle for symmetrized exact diagonalization (TEST INFRASTRUCTURE ONLY).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark
+may import this module.  It shares no code with the HIP library: the C part
+(``oracle.c``, built into ``liboracle.so``) does brute-force orbit scans and
+binary search; this module adds the dense and Lanczos layers in numpy/scipy.
+
+What each function follows (thesis sections / equations):
+  * ``enumerate_basis``  - representatives = orbit minima ("representative
+    condition"), kept iff chi is trivial on the stabilizer, norm
+    sqrt(|G| |Stab|) (1-D symmetry-adapted states).
+  * ``coo_matrix``       - symmetrized matrix element of every non-branching
+    piece ("Computations in the symmetrized basis"), push form.
+  * ``row_entries``      - the same elements, row by row (gather form).
+  * ``character_formula_dim`` - the character formula n_rho = |G|^-1 sum_g
+    conj(chi(g)) Tr Gamma(g) (tower-of-states appendix), with Tr Gamma(g)
+    counted from the cycle structure of g in the Sz sector.
+  * ``kron_hamiltonian`` - H built from explicit spin matrices and Kronecker
+    products (site 0 = leftmost factor = most significant bit).
+  * ``projector_basis``  - symmetry-adapted vectors sum_g conj(chi(g)) g|s>
+    written out in the unsymmetrized basis.
+  * ``lanczos``          - the real-symmetric two-vector step and the
+    complex-Hermitian three-vector step ("The Lanczos algorithm"), no
+    reorthogonalization; T-matrix eigenvalues by a library tridiagonal solver.
+  * ``mlp_*``            - float64 reference of the learned-index network
+    (forward, loss, analytic backward) used to check the GPU training
+    kernels; parity of its gradients is pinned by central differences.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from math import comb
+
+import numpy as np
+import scipy.linalg
+import scipy.sparse
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("n_elem", ctypes.c_int32),
+        ("perm", ctypes.c_void_p), ("flip", ctypes.c_void_p),
+        ("chi_re", ctypes.c_void_p), ("chi_im", ctypes.c_void_p), ("chi_one", ctypes.c_void_p),
+        ("n_bonds", ctypes.c_int32), ("bonds", ctypes.c_void_p), ("bond_J", ctypes.c_void_p),
+        ("n_tri", ctypes.c_int32), ("tris", ctypes.c_void_p), ("tri_J", ctypes.c_void_p),
+    ]
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from oracle.build import build
+            build()
+        L = ctypes.CDLL(path)
+        P = ctypes.POINTER(_Problem)
+        vp = ctypes.c_void_p
+        L.orc_enumerate.restype = ctypes.c_int64
+        L.orc_enumerate.argtypes = [P, ctypes.c_int, vp, vp, ctypes.c_int64]
+        L.orc_coo.restype = ctypes.c_int64
+        L.orc_coo.argtypes = [P, vp, vp, ctypes.c_int64, vp, vp, vp, vp, ctypes.c_int64]
+        L.orc_rows.restype = ctypes.c_int64
+        L.orc_rows.argtypes = [P, vp, ctypes.c_int64, vp, vp, vp, vp, ctypes.c_int64, vp, vp]
+        L.orc_rep_many.restype = None
+        L.orc_rep_many.argtypes = [P, vp, ctypes.c_int64, vp, vp, vp, vp]
+        L.orc_act.restype = ctypes.c_uint64
+        L.orc_act.argtypes = [ctypes.c_int, vp, ctypes.c_int, ctypes.c_uint64]
+        L.orc_find.restype = ctypes.c_int64
+        L.orc_find.argtypes = [vp, ctypes.c_int64, ctypes.c_uint64]
+        L.orc_max_terms.restype = ctypes.c_int
+        L.orc_max_terms.argtypes = [P]
+        _LIB = L
+    return _LIB
+
+
+def _ptr(a):
+    return a.ctypes.data if a is not None and a.size else None
+
+
+class Problem:
+    """Keeps the instance arrays alive and exposes the C struct."""
+
+    def __init__(self, inst):
+        self.inst = inst
+        self.perm = np.ascontiguousarray(inst.perms, dtype=np.int32)
+        self.flip = np.ascontiguousarray(inst.flips, dtype=np.uint8)
+        self.chi_re = np.ascontiguousarray(inst.chi.real, dtype=np.float64)
+        self.chi_im = np.ascontiguousarray(inst.chi.imag, dtype=np.float64)
+        # chi(g) == 1 decided in float64 with a tolerance far below the gap
+        # between distinct roots of unity of order <= |G|
+        self.chi_one = (np.abs(inst.chi - 1.0) < 1e-6).astype(np.uint8)
+        self.bonds = np.ascontiguousarray(inst.bonds, dtype=np.int32).reshape(-1)
+        self.bond_J = np.ascontiguousarray(inst.bond_J, dtype=np.float64)
+        self.tris = np.ascontiguousarray(inst.tris, dtype=np.int32).reshape(-1)
+        self.tri_J = np.ascontiguousarray(inst.tri_Jchi, dtype=np.float64)
+        self.s = _Problem(inst.n_sites, inst.n_elem, _ptr(self.perm), _ptr(self.flip), _ptr(self.chi_re),
+                          _ptr(self.chi_im), _ptr(self.chi_one), len(inst.bonds), _ptr(self.bonds),
+                          _ptr(self.bond_J), len(inst.tris), _ptr(self.tris), _ptr(self.tri_J))
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+
+def enumerate_basis(inst):
+    """Ascending list of sector representatives and their stabilizer sizes."""
+    p = Problem(inst)
+    L = lib()
+    dim = L.orc_enumerate(p.ref, inst.n_up, None, None, 0)
+    reps = np.zeros(dim, np.uint64)
+    stabs = np.zeros(dim, np.int32)
+    d2 = L.orc_enumerate(p.ref, inst.n_up, _ptr(reps), _ptr(stabs), dim)
+    assert d2 == dim
+    return reps, stabs
+
+
+def coo_matrix(inst, reps, stabs):
+    """Symmetrized Hamiltonian in the sector basis (push form), scipy CSR."""
+    p = Problem(inst)
+    L = lib()
+    dim = len(reps)
+    reps = np.ascontiguousarray(reps, np.uint64)
+    stabs = np.ascontiguousarray(stabs, np.int32)
+    nnz = L.orc_coo(p.ref, _ptr(reps), _ptr(stabs), dim, None, None, None, None, 0)
+    ri = np.zeros(nnz, np.int64)
+    ci = np.zeros(nnz, np.int64)
+    vr = np.zeros(nnz)
+    vi = np.zeros(nnz)
+    n2 = L.orc_coo(p.ref, _ptr(reps), _ptr(stabs), dim, _ptr(ri), _ptr(ci), _ptr(vr), _ptr(vi), nnz)
+    assert n2 == nnz
+    vals = vr + 1j * vi if inst.is_complex else vr
+    return scipy.sparse.csr_matrix((vals, (ri, ci)), shape=(dim, dim))
+
+
+def row_entries(inst, rows):
+    """Gather form for the given sector representatives.
+
+    Returns (row_ptr, target_states, coefficients, row_ok, n_elements) so that
+    y(rows[r]) = sum_{e in row r} coefficients[e] * x(target_states[e]).
+    """
+    p = Problem(inst)
+    L = lib()
+    rows = np.ascontiguousarray(rows, np.uint64)
+    n = len(rows)
+    rp = np.zeros(n + 1, np.int64)
+    ok = np.zeros(n, np.int8)
+    ne = np.zeros(n, np.int32)
+    tot = L.orc_rows(p.ref, _ptr(rows), n, _ptr(rp), None, None, None, 0, _ptr(ok), _ptr(ne))
+    tgt = np.zeros(tot, np.uint64)
+    cr = np.zeros(tot)
+    cim = np.zeros(tot)
+    t2 = L.orc_rows(p.ref, _ptr(rows), n, _ptr(rp), _ptr(tgt), _ptr(cr), _ptr(cim), tot, _ptr(ok), _ptr(ne))
+    assert t2 == tot
+    return rp, tgt, cr + 1j * cim, ok.astype(bool), ne
+
+
+def rows_apply(inst, rows, xfun):
+    """y at the given rows for an input vector given as a function of the
+    representative's integer value."""
+    rp, tgt, coef, ok, ne = row_entries(inst, rows)
+    vals = coef * xfun(tgt)
+    y = np.zeros(len(rows), complex)
+    np.add.at(y, np.repeat(np.arange(len(rows)), np.diff(rp)), vals)
+    return y, ok, ne
+
+
+def rep_many(inst, states):
+    p = Problem(inst)
+    L = lib()
+    s = np.ascontiguousarray(states, np.uint64)
+    n = len(s)
+    rep = np.zeros(n, np.uint64)
+    g = np.zeros(n, np.int32)
+    st = np.zeros(n, np.int32)
+    tv = np.zeros(n, np.int8)
+    L.orc_rep_many(p.ref, _ptr(s), n, _ptr(rep), _ptr(g), _ptr(st), _ptr(tv))
+    return rep, g, st, tv.astype(bool)
+
+
+def act(inst, g, state):
+    L = lib()
+    perm = np.ascontiguousarray(inst.perms[g], np.int32)
+    return int(L.orc_act(inst.n_sites, perm.ctypes.data, int(inst.flips[g]), int(state)))
+
+
+# ---------------------------------------------------------------------------
+# exact counts
+# ---------------------------------------------------------------------------
+
+def _cycles(perm):
+    n = len(perm)
+    seen = [False] * n
+    out = []
+    for i in range(n):
+        if not seen[i]:
+            L = 0
+            j = i
+            while not seen[j]:
+                seen[j] = True
+                j = int(perm[j])
+                L += 1
+            out.append(L)
+    return out
+
+
+def fixed_count(perm, flip, n_up):
+    """Number of configurations with n_up up spins left invariant by g."""
+    cyc = _cycles(perm)
+    n = len(perm)
+    if flip:
+        if any(c % 2 for c in cyc) or 2 * n_up != n:
+            return 0
+        return 2 ** len(cyc)
+    # subsets of cycles with total length n_up
+    ways = [0] * (n_up + 1)
+    ways[0] = 1
+    for c in cyc:
+        for s in range(n_up, c - 1, -1):
+            ways[s] += ways[s - c]
+    return ways[n_up]
+
+
+def character_formula_dim(inst):
+    tot = 0j
+    for g in range(inst.n_elem):
+        tot += np.conj(inst.chi[g]) * fixed_count(inst.perms[g], inst.flips[g], inst.n_up)
+    d = tot / inst.n_elem
+    assert abs(d.imag) < 1e-6 and abs(d.real - round(d.real)) < 1e-6, d
+    return int(round(d.real))
+
+
+def sz_states(n, n_up):
+    """All n-bit integers with n_up set bits, ascending (n <= 24)."""
+    x = np.arange(1 << n, dtype=np.uint64)
+    pc = np.zeros(len(x), np.int64)
+    for b in range(n):
+        pc += ((x >> np.uint64(b)) & np.uint64(1)).astype(np.int64)
+    return x[pc == n_up]
+
+
+# ---------------------------------------------------------------------------
+# dense layer (small N)
+# ---------------------------------------------------------------------------
+
+_SZ = np.diag([-0.5, 0.5])                 # local basis (down, up): index bit 1 = up
+_SP = np.array([[0.0, 0.0], [1.0, 0.0]])   # S^+ |down> = |up>
+_SM = _SP.T
+_SX = 0.5 * (_SP + _SM)
+_SY = (_SP - _SM) / 2j
+
+
+def _site_op(op, i, n):
+    return scipy.sparse.kron(scipy.sparse.kron(scipy.sparse.identity(1 << i, format="csr"),
+                                               scipy.sparse.csr_matrix(op)),
+                             scipy.sparse.identity(1 << (n - 1 - i), format="csr"), format="csr")
+
+
+def kron_hamiltonian(inst):
+    """Full 2^N Hamiltonian from spin matrices and Kronecker products (sparse,
+    N <= 14); site 0 is the leftmost factor."""
+    n = inst.n_sites
+    assert n <= 14
+    S = {a: [_site_op(m, i, n) for i in range(n)] for a, m in (("x", _SX), ("y", _SY), ("z", _SZ))}
+    H = scipy.sparse.csr_matrix((1 << n, 1 << n), dtype=complex)
+    for (i, j), J in zip(inst.bonds.tolist(), inst.bond_J):
+        for a in "xyz":
+            H = H + J * (S[a][i] @ S[a][j])
+    eps = {("x", "y", "z"): 1, ("y", "z", "x"): 1, ("z", "x", "y"): 1,
+           ("x", "z", "y"): -1, ("z", "y", "x"): -1, ("y", "x", "z"): -1}
+    for (i, j, k), J in zip(inst.tris.tolist(), inst.tri_Jchi):
+        for (a, b, c), e in eps.items():
+            H = H + (J * e) * (S[a][i] @ S[b][j] @ S[c][k])
+    return H.tocsr()
+
+
+def apply_group_numpy(inst, g, states):
+    """g|s> on an array of states, via bit arrays (independent of orc_act)."""
+    n = inst.n_sites
+    s = np.asarray(states, np.uint64)
+    bits = np.stack([(s >> np.uint64(n - 1 - i)) & np.uint64(1) for i in range(n)], axis=1)
+    out_bits = np.zeros_like(bits)
+    out_bits[:, inst.perms[g]] = bits
+    if inst.flips[g]:
+        out_bits = np.uint64(1) - out_bits
+    out = np.zeros(len(s), np.uint64)
+    for i in range(n):
+        out |= out_bits[:, i] << np.uint64(n - 1 - i)
+    return out
+
+
+def projector_basis(inst, reps, states):
+    """Columns sum_g conj(chi(g)) g|rep>, normalized, in the basis `states`."""
+    pos = {int(s): k for k, s in enumerate(states)}
+    B = np.zeros((len(states), len(reps)), complex)
+    imgs = np.stack([apply_group_numpy(inst, g, reps) for g in range(inst.n_elem)])
+    for c in range(len(reps)):
+        for g in range(inst.n_elem):
+            B[pos[int(imgs[g, c])], c] += np.conj(inst.chi[g])
+    nrm = np.linalg.norm(B, axis=0)
+    return B / nrm
+
+
+def unsym_sector_matrix(inst):
+    """Unsymmetrized Sz-sector Hamiltonian (trivial group) via the C oracle."""
+    from dataclasses import replace
+    triv = replace(inst, perms=np.arange(inst.n_sites, dtype=np.int32)[None, :],
+                   flips=np.zeros(1, np.uint8), chi=np.ones(1, complex))
+    reps, stabs = enumerate_basis(triv)
+    return reps, coo_matrix(triv, reps, stabs)
+
+
+# ---------------------------------------------------------------------------
+# Lanczos
+# ---------------------------------------------------------------------------
+
+def lanczos(matvec, v0, n_iter, hermitian_complex=False, breakdown_tol=1e-14):
+    """T-matrix coefficients from the two-vector (real) or three-vector
+    (complex) Lanczos step.  Returns alpha[n], beta[n] where beta[k] is the
+    norm produced at step k (so the T off-diagonal is beta[:-1])."""
+    v = np.array(v0, dtype=complex if hermitian_complex else float)
+    v = v / np.linalg.norm(v)
+    alphas, betas = [], []
+    if not hermitian_complex:
+        w = np.zeros_like(v)
+        beta = 0.0
+        for _ in range(n_iter):
+            w = matvec(v) - beta * w
+            alpha = float(np.dot(w, v))
+            w = w - alpha * v
+            beta = float(np.sqrt(np.dot(w, w)))
+            alphas.append(alpha)
+            betas.append(beta)
+            if beta < breakdown_tol * max(1.0, max(abs(a) for a in alphas)):
+                break
+            v, w = w, v
+            v = v / beta
+    else:
+        vprev = np.zeros_like(v)
+        beta = 0.0
+        for _ in range(n_iter):
+            w = matvec(v)
+            alpha = float(np.vdot(w, v).real)
+            w = w - alpha * v - beta * vprev
+            vprev = v
+            beta = float(np.sqrt(np.vdot(w, w).real))
+            alphas.append(alpha)
+            betas.append(beta)
+            if beta < breakdown_tol * max(1.0, max(abs(a) for a in alphas)):
+                break
+            v = w / beta
+    return np.array(alphas), np.array(betas)
+
+
+def tmatrix_eigs(alpha, beta):
+    n = len(alpha)
+    if n == 1:
+        return np.array(alpha, float)
+    return scipy.linalg.eigh_tridiagonal(np.asarray(alpha, float), np.asarray(beta[: n - 1], float),
+                                         eigvals_only=True)
+
+
+# ---------------------------------------------------------------------------
+# learned-index network reference (float64)
+# ---------------------------------------------------------------------------
+
+def mlp_forward(params, X):
+    """y = W3 relu(W2 relu(W1 x + b1) + b2) + b3 ; returns (y, cache)."""
+    W1, b1, W2, b2, W3, b3 = params
+    z1 = X @ W1.T + b1
+    a1 = np.maximum(z1, 0.0)
+    z2 = a1 @ W2.T + b2
+    a2 = np.maximum(z2, 0.0)
+    y = a2 @ W3.T + b3
+    return y[:, 0], (X, z1, a1, z2, a2)
+
+
+def mlp_loss_grad(params, X, t):
+    """Mean squared error 0.5 * mean((y - t)^2) and its analytic gradient."""
+    W1, b1, W2, b2, W3, b3 = params
+    y, (X, z1, a1, z2, a2) = mlp_forward(params, X)
+    m = len(t)
+    r = (y - t) / m
+    loss = 0.5 * float(np.dot(y - t, y - t)) / m
+    gW3 = r[None, :] @ a2
+    gb3 = np.array([r.sum()])
+    d2 = (r[:, None] @ W3) * (z2 > 0)
+    gW2 = d2.T @ a1
+    gb2 = d2.sum(0)
+    d1 = (d2 @ W2) * (z1 > 0)
+    gW1 = d1.T @ X
+    gb1 = d1.sum(0)
+    return loss, [gW1, gb1, gW2, gb2, gW3, gb3]
+
+
+def binom(n, k):
+    return comb(n, k)

@@ -1,0 +1,273 @@
+"""Pins of the CPU oracle against facts the thesis and the mathematics fix.
+
+Every check here is independent of the oracle's own formulas: worked
+examples printed in the thesis, closed forms, a Kronecker-product
+construction from spin matrices, the character formula, projector-built
+symmetric vectors and finite differences.
+"""
+import numpy as np
+import pytest
+import scipy.sparse
+
+from oracle import oracle as O
+from workloads import lattices as L
+
+
+def _state(bits):
+    """'uudu' -> integer, first site = most significant bit, up = 1."""
+    v = 0
+    for c in bits:
+        v = (v << 1) | (1 if c == "u" else 0)
+    return v
+
+
+# --- encoding and the exchange example ("Representing Hilbert spaces") ------
+
+def test_integer_encoding_example():
+    # |up up down up> -> (1101)_2 = 13
+    assert _state("uudu") == 13
+
+
+def test_exchange_example_kron_and_terms():
+    # 1/2 (S+_2 S-_3 + S-_2 S+_3)|13> = 1/2 |11>  (sites 2,3 one-based)
+    inst = L.Instance("pair", 4, np.array([[1, 2]], np.int32), np.array([1.0]), np.zeros((0, 3), np.int32),
+                      np.zeros(0), 3, np.arange(4, dtype=np.int32)[None], np.zeros(1, np.uint8),
+                      np.ones(1, complex), [1])
+    H = O.kron_hamiltonian(inst).toarray()
+    # exchange part only: remove the diagonal Ising piece
+    assert H[11, 13] == pytest.approx(0.5)
+    assert H[13, 11] == pytest.approx(0.5)
+    rp, tgt, coef, ok, ne = O.row_entries(inst, np.array([13], np.uint64))
+    entries = {int(t): c for t, c in zip(tgt, coef)}
+    assert entries[11] == pytest.approx(0.5)
+    # Ising piece: sites 2,3 (one-based) are up, down -> -1/4
+    assert entries[13] == pytest.approx(-0.25)
+    assert ne[0] == 2
+
+
+def test_two_site_singlet_triplet():
+    # S.S = -3/4 (singlet), +1/4 (triplet)
+    inst = L.Instance("dimer", 2, np.array([[0, 1]], np.int32), np.array([1.0]), np.zeros((0, 3), np.int32),
+                      np.zeros(0), 1, np.arange(2, dtype=np.int32)[None], np.zeros(1, np.uint8),
+                      np.ones(1, complex), [1])
+    ev = np.linalg.eigvalsh(O.kron_hamiltonian(inst).toarray())
+    assert np.allclose(ev, [-0.75, 0.25, 0.25, 0.25])
+    _, Hs = O.unsym_sector_matrix(inst)
+    assert np.allclose(np.linalg.eigvalsh(Hs.toarray()), [-0.75, 0.25])
+
+
+def test_triangle_ising_counts():
+    # J sum sigma_i sigma_j on a triangle (sigma = +-1): 6 states at -J, 2 at 3J
+    inst = L.Instance("tri", 3, np.array([[0, 1], [1, 2], [2, 0]], np.int32), np.ones(3),
+                      np.zeros((0, 3), np.int32), np.zeros(0), 0, np.arange(3, dtype=np.int32)[None],
+                      np.zeros(1, np.uint8), np.ones(1, complex), [1])
+    diag = []
+    for s in range(8):
+        rp, tgt, coef, ok, ne = O.row_entries(inst, np.array([s], np.uint64))
+        d = [c for t, c in zip(tgt, coef) if int(t) == s]
+        diag.append(4 * d[0].real if d else 0.0)  # S^z S^z = sigma sigma / 4
+    assert sorted(np.round(diag, 12)) == [-1] * 6 + [3] * 2
+
+
+def test_four_site_ring_ground_state():
+    # E0 = -2J for the periodic 4-site Heisenberg ring (k = 0)
+    inst = L.chain(4)
+    reps, stabs = O.enumerate_basis(inst)
+    H = O.coo_matrix(inst, reps, stabs).toarray()
+    assert np.linalg.eigvalsh(H)[0] == pytest.approx(-2.0, abs=1e-13)
+    full = np.linalg.eigvalsh(O.kron_hamiltonian(inst).toarray())
+    assert full[0] == pytest.approx(-2.0, abs=1e-13)
+
+
+# --- sublattice-coding worked examples (section "Sublattice coding") --------
+
+def test_two_sublattice_example_representative():
+    # labels (0,2,4 | 1,3,5); sigma = |uud dud> -> rep T_1 sigma = |ddu uud> = 14
+    inst = L.chain(6, sublat=(2,))
+    assert inst.meta["positions"] == [0, 2, 4, 1, 3, 5]
+    s = _state("uuddud")
+    rep, g, st, tv = O.rep_many(inst, np.array([s], np.uint64))
+    assert int(rep[0]) == _state("dduuud") == 14
+    assert int(g[0]) == 1            # T_1
+    assert O.act(inst, 1, s) == 14
+
+
+def test_three_sublattice_example_representative():
+    # labels (0,3 | 1,4 | 2,5); same sigma -> rep T_2 sigma = |ddd uuu> = 7
+    inst = L.chain(6, sublat=(3,))
+    assert inst.meta["positions"] == [0, 3, 1, 4, 2, 5]
+    s = _state("uuddud")
+    rep, g, st, tv = O.rep_many(inst, np.array([s], np.uint64))
+    assert int(rep[0]) == 7
+    assert int(g[0]) == 2            # T_2
+    # the other candidate printed in the example: T_5 sigma = |ddu duu>
+    assert O.act(inst, 5, s) == _state("ddduuu".replace("ddduuu", "dduduu"))
+
+
+# --- enumeration vs the character formula -----------------------------------
+
+@pytest.mark.parametrize("inst", L.small_instances(), ids=lambda i: f"{i.name}-{i.sector}")
+def test_dimension_equals_character_formula(inst):
+    reps, stabs = O.enumerate_basis(inst)
+    assert len(reps) == O.character_formula_dim(inst)
+    assert np.all(np.diff(reps.astype(np.float64)) > 0)
+    # stabilizer sizes divide the group order
+    assert np.all(inst.n_elem % stabs == 0)
+
+
+def test_enumeration_trivial_group_is_sz_sector():
+    inst = L.chain(10, n_up=4)
+    from dataclasses import replace
+    triv = replace(inst, perms=np.arange(10, dtype=np.int32)[None], flips=np.zeros(1, np.uint8),
+                   chi=np.ones(1, complex))
+    reps, _ = O.enumerate_basis(triv)
+    assert np.array_equal(reps, O.sz_states(10, 4))
+
+
+def test_named_sector_dimensions():
+    # character formula at the benchmark sizes (exact integers)
+    assert O.character_formula_dim(L.chain16()) == 810
+    assert O.character_formula_dim(L.square32()) == 1184480
+    assert O.character_formula_dim(L.tri36_K()) == 42018826
+    assert O.character_formula_dim(L.square40()) == 430909650
+    dims = [O.character_formula_dim(s) for s in L.square32_sectors()]
+    assert len(dims) == 46 and sum(dims) == 150281582
+
+
+# --- Hamiltonian: unsymmetrized terms vs spin matrices ----------------------
+
+@pytest.mark.parametrize("inst", [i for i in L.small_instances() if i.n_sites <= 12],
+                         ids=lambda i: f"{i.name}-{i.sector}")
+def test_sector_terms_match_kronecker(inst):
+    states, Hs = O.unsym_sector_matrix(inst)
+    Hk = O.kron_hamiltonian(inst)
+    idx = states.astype(np.int64)
+    ref = Hk[idx][:, idx].toarray()
+    assert np.max(np.abs(Hs.toarray() - ref)) < 1e-13
+
+
+# --- symmetrized matrix vs projector-built symmetric vectors ----------------
+
+@pytest.mark.parametrize("inst", [i for i in L.small_instances() if i.n_sites <= 16],
+                         ids=lambda i: f"{i.name}-{i.sector}")
+def test_symmetrized_matrix_equals_projection(inst):
+    reps, stabs = O.enumerate_basis(inst)
+    Hsym = O.coo_matrix(inst, reps, stabs).toarray()
+    states, Hs = O.unsym_sector_matrix(inst)
+    B = O.projector_basis(inst, reps, states)
+    ref = B.conj().T @ (Hs @ B)
+    assert np.max(np.abs(Hsym - ref)) < 1e-12
+    # hermitian, and projected basis orthonormal
+    assert np.max(np.abs(Hsym - Hsym.conj().T)) < 1e-12
+    assert np.max(np.abs(B.conj().T @ B - np.eye(len(reps)))) < 1e-12
+
+
+@pytest.mark.parametrize("inst", [i for i in L.small_instances() if i.n_sites <= 16],
+                         ids=lambda i: f"{i.name}-{i.sector}")
+def test_push_equals_pull(inst):
+    reps, stabs = O.enumerate_basis(inst)
+    Hsym = O.coo_matrix(inst, reps, stabs)
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(len(reps)) + (1j * rng.standard_normal(len(reps)) if inst.is_complex else 0)
+    lut = {int(s): x[i] for i, s in enumerate(reps)}
+    y_pull, ok, _ = O.rows_apply(inst, reps, lambda t: np.array([lut[int(v)] for v in t]))
+    assert ok.all()
+    assert np.max(np.abs(Hsym @ x - y_pull)) < 1e-13
+
+
+def test_union_of_sector_spectra_is_full_spectrum():
+    # abelian group (translations x flip): sector spectra partition the Sz=0 spectrum
+    n = 10
+    allev = []
+    for k in range(n):
+        for fl in (1, -1):
+            inst = L.chain(n, k=k, flip=fl, sublat=(2,))
+            reps, stabs = O.enumerate_basis(inst)
+            if len(reps):
+                allev.extend(np.linalg.eigvalsh(O.coo_matrix(inst, reps, stabs).toarray()))
+    _, Hs = O.unsym_sector_matrix(L.chain(n))
+    full = np.linalg.eigvalsh(Hs.toarray())
+    assert len(allev) == len(full)
+    assert np.max(np.abs(np.sort(allev) - full)) < 1e-12
+
+
+def test_su2_multiplets_and_flip_parity():
+    # Sz=1 levels are a subset of Sz=0 levels; flip parity of |S,0> is (-1)^(S+N/2)
+    n = 12
+    i0 = L.chain(n, k=0, n_up=6, sublat=(2,))
+    i1 = L.chain(n, k=0, n_up=7, sublat=(2,))
+    e0 = np.linalg.eigvalsh(O.coo_matrix(i0, *O.enumerate_basis(i0)).toarray())
+    e1 = np.linalg.eigvalsh(O.coo_matrix(i1, *O.enumerate_basis(i1)).toarray())
+    for e in e1:
+        assert np.min(np.abs(e0 - e)) < 1e-10
+    # singlet ground state (S=0) lives in flip parity (-1)^(N/2) = +1 for N=12
+    ev = {}
+    for fl in (1, -1):
+        inst = L.chain(n, k=0, flip=fl, sublat=(2,))
+        ev[fl] = np.linalg.eigvalsh(O.coo_matrix(inst, *O.enumerate_basis(inst)).toarray())[0]
+    assert ev[1] < ev[-1]
+    assert ev[1] == pytest.approx(e0[0], abs=1e-12)
+
+
+# --- Lanczos ------------------------------------------------------------------
+
+@pytest.mark.parametrize("inst", [L.chain16(), L.small_instances()[13], L.small_instances()[15]],
+                         ids=lambda i: f"{i.name}-{i.sector}")
+def test_lanczos_lowest_eigenvalue(inst):
+    reps, stabs = O.enumerate_basis(inst)
+    H = O.coo_matrix(inst, reps, stabs)
+    rng = np.random.default_rng(11)
+    v0 = rng.standard_normal(len(reps))
+    if inst.is_complex:
+        v0 = v0 + 1j * rng.standard_normal(len(reps))
+    a, b = O.lanczos(lambda v: H @ v, v0, 120, hermitian_complex=inst.is_complex)
+    e = O.tmatrix_eigs(a, b)[0]
+    exact = np.linalg.eigvalsh(H.toarray())[0]
+    assert abs(e - exact) <= 1e-10 * abs(exact)
+
+
+def test_lanczos_breakdown_on_tiny_sector():
+    inst = L.chain(4)
+    reps, stabs = O.enumerate_basis(inst)
+    H = O.coo_matrix(inst, reps, stabs).toarray()
+    a, b = O.lanczos(lambda v: H @ v, np.array([1.0, 0.3]), 10)
+    assert len(a) == 2 and b[-1] < 1e-12
+    assert np.allclose(np.sort(O.tmatrix_eigs(a, b)), [-2.0, 1.0])
+
+
+def test_chain16_ground_state_value():
+    # k = 0 sector of the 16-site Heisenberg ring: Lanczos vs full diagonalization
+    inst = L.chain16()
+    reps, stabs = O.enumerate_basis(inst)
+    assert len(reps) == 810
+    H = O.coo_matrix(inst, reps, stabs).toarray()
+    e0 = np.linalg.eigvalsh(H)[0]
+    # the full Sz=0 spectrum contains the same level
+    _, Hs = O.unsym_sector_matrix(inst)
+    full0 = scipy.sparse.linalg.eigsh(Hs, k=1, which="SA")[0][0]
+    assert e0 == pytest.approx(full0, abs=1e-10)
+
+
+# --- learned-index network reference -----------------------------------------
+
+def test_mlp_gradient_central_differences():
+    rng = np.random.default_rng(3)
+    F, H = 6, 32
+    params = [rng.standard_normal((H, F)) * 0.5, rng.standard_normal(H) * 0.1,
+              rng.standard_normal((H, H)) * 0.3, rng.standard_normal(H) * 0.1,
+              rng.standard_normal((1, H)) * 0.3, rng.standard_normal(1) * 0.1]
+    X = rng.random((50, F))
+    t = rng.random(50)
+    loss, grads = O.mlp_loss_grad(params, X, t)
+    h = 1e-6
+    for p, g in zip(params, grads):
+        flat = p.reshape(-1)
+        gflat = g.reshape(-1)
+        for k in rng.choice(flat.size, size=min(8, flat.size), replace=False):
+            old = flat[k]
+            flat[k] = old + h
+            lp, _ = O.mlp_loss_grad(params, X, t)
+            flat[k] = old - h
+            lm, _ = O.mlp_loss_grad(params, X, t)
+            flat[k] = old
+            assert (lp - lm) / (2 * h) == pytest.approx(gflat[k], rel=1e-5, abs=1e-9)

@@ -1,0 +1,541 @@
+"""Problem instances for symmetrized exact diagonalization of spin-1/2 models.
+
+This module only *describes* a problem: sites, bonds, oriented triangles, a
+finite group of site permutations (optionally times a global spin flip) and a
+one-dimensional irrep of that group given by its characters.  It holds none of
+the method's arithmetic (no representative search, no matrix elements): both
+the CPU oracle and the HIP library take the arrays it produces as input.
+
+Conventions (thesis, section "Representing Hilbert spaces and operators",
+eq. for int(sigma)):
+  * a configuration of N spins is an N-bit integer; site 0 (the thesis's site
+    1) is the most significant bit, spin up = 1;
+  * a group element g moves the spin at site i to site perm[g, i]; if
+    flip[g] is set, every spin is reversed afterwards;
+  * composition: (g h) applies h first, perm_{gh} = perm_g o perm_h.
+
+Sites are labelled so that every sublattice of the chosen decomposition is a
+contiguous block of labels, sublattice 0 on the most significant bits
+(section "Generic sublattice coding algorithm": site numbering).  A nested
+chain of decompositions (coarse to fine) is kept contiguous in one labelling,
+so the representative - which depends only on the labelling - is the same
+for every N_sub in ``Instance.sublat_options``.
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass, field
+from fractions import Fraction
+
+import numpy as np
+
+
+@dataclass
+class Instance:
+    name: str
+    n_sites: int
+    bonds: np.ndarray          # int32 [nb, 2]
+    bond_J: np.ndarray         # f64 [nb]
+    tris: np.ndarray           # int32 [nt, 3], counter-clockwise (i, j, k)
+    tri_Jchi: np.ndarray       # f64 [nt]
+    n_up: int
+    perms: np.ndarray          # int32 [n_elem, n_sites]
+    flips: np.ndarray          # uint8 [n_elem]
+    chi: np.ndarray            # complex128 [n_elem]
+    sublat_options: list       # N_sub values contiguous in this labelling
+    sector: str = ""
+    meta: dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        n = self.n_sites
+        assert self.bonds.reshape(-1, 2).shape[0] == len(self.bond_J)
+        assert self.tris.reshape(-1, 3).shape[0] == len(self.tri_Jchi)
+        assert self.perms.ndim == 2 and self.perms.shape[1] == n
+        assert len(self.flips) == len(self.chi) == self.perms.shape[0]
+        assert self.bonds.size == 0 or (self.bonds.min() >= 0 and self.bonds.max() < n)
+
+    @property
+    def n_elem(self) -> int:
+        return int(self.perms.shape[0])
+
+    @property
+    def is_complex(self) -> bool:
+        return bool(np.any(np.abs(self.chi.imag) > 1e-12) or np.any(self.tri_Jchi != 0))
+
+    @property
+    def n_sublat(self) -> int:
+        return int(max(self.sublat_options))
+
+
+# ---------------------------------------------------------------------------
+# integer lattice helpers (2D tori given in lattice coordinates)
+# ---------------------------------------------------------------------------
+
+def _cross(a, b):
+    return a[0] * b[1] - a[1] * b[0]
+
+
+def _reduce(r, L1, L2):
+    """Canonical representative of r modulo the lattice spanned by L1, L2."""
+    det = _cross(L1, L2)
+    # coefficients a, b with r = a L1 + b L2 (rational)
+    a = Fraction(_cross(r, L2), det)
+    b = Fraction(_cross(L1, r), det)
+    fa = a.numerator // a.denominator
+    fb = b.numerator // b.denominator
+    return (r[0] - fa * L1[0] - fb * L2[0], r[1] - fa * L1[1] - fb * L2[1])
+
+
+def _in_lattice(r, L1, L2):
+    return _reduce(r, L1, L2) == (0, 0)
+
+
+def _matvec(P, r):
+    return (P[0][0] * r[0] + P[0][1] * r[1], P[1][0] * r[0] + P[1][1] * r[1])
+
+
+def _matmul(A, B):
+    return tuple(tuple(sum(A[i][k] * B[k][j] for k in range(2)) for j in range(2)) for i in range(2))
+
+
+def _group_closure(gens):
+    I = ((1, 0), (0, 1))
+    elems = [I]
+    frontier = [I]
+    while frontier:
+        nxt = []
+        for e in frontier:
+            for g in gens:
+                h = _matmul(g, e)
+                if h not in elems:
+                    elems.append(h)
+                    nxt.append(h)
+        frontier = nxt
+    return elems
+
+
+def one_dim_irreps(elems):
+    """All one-dimensional irreps (homomorphisms to U(1)) of a small finite
+    group of 2x2 integer matrices, as dicts element -> complex character."""
+    order = len(elems)
+    idx = {e: i for i, e in enumerate(elems)}
+    mul = [[idx[_matmul(a, b)] for b in elems] for a in elems]
+    # candidate values: order-th roots of unity; brute force on generators
+    gens = []
+    span = {idx[((1, 0), (0, 1))]}
+    for e in elems:
+        if idx[e] in span:
+            continue
+        gens.append(idx[e])
+        # closure of gens
+        cur = set(span) | {idx[e]}
+        changed = True
+        while changed:
+            changed = False
+            for a in list(cur):
+                for g in gens:
+                    c = mul[g][a]
+                    if c not in cur:
+                        cur.add(c)
+                        changed = True
+        span = cur
+    roots = [np.exp(2j * np.pi * m / order) for m in range(order)]
+    found = []
+    for vals in itertools.product(range(order), repeat=len(gens)):
+        chi = {idx[((1, 0), (0, 1))]: 1.0 + 0j}
+        for g, v in zip(gens, vals):
+            chi[g] = roots[v]
+        ok = True
+        changed = True
+        while changed and ok:
+            changed = False
+            for a in list(chi):
+                for g in gens:
+                    c = mul[g][a]
+                    val = chi[g] * chi[a]
+                    if c in chi:
+                        if abs(chi[c] - val) > 1e-9:
+                            ok = False
+                            break
+                    else:
+                        chi[c] = val
+                        changed = True
+                if not ok:
+                    break
+        if not ok or len(chi) != order:
+            continue
+        # full homomorphism check
+        for a in range(order):
+            for b in range(order):
+                if abs(chi[mul[a][b]] - chi[a] * chi[b]) > 1e-9:
+                    ok = False
+                    break
+            if not ok:
+                break
+        if ok:
+            vec = tuple(np.round(chi[i].real, 12) + 1j * np.round(chi[i].imag, 12) for i in range(order))
+            if vec not in [f[0] for f in found]:
+                found.append((vec, {elems[i]: chi[i] for i in range(order)}))
+    # trivial irrep first, then real ones, then complex
+    found.sort(key=lambda f: (any(abs(v - 1) > 1e-9 for v in f[0]),
+                              any(abs(v.imag) > 1e-9 for v in f[0])))
+    return [f[1] for f in found]
+
+
+class Torus2D:
+    """A Bravais lattice on a torus, in integer lattice coordinates.
+
+    ``L1``, ``L2``: the torus periods; ``pg_gens``: generators of the point
+    group (integer matrices acting on lattice coordinates); only elements
+    that map the torus onto itself are kept.  ``sublat_chain``: sublattice
+    subgroups (pairs of basis vectors) from coarse to fine; the finest one
+    fixes the labelling.
+    """
+
+    def __init__(self, L1, L2, pg_gens, sublat_chain, cart=((1.0, 0.0), (0.0, 1.0))):
+        self.L1, self.L2 = tuple(L1), tuple(L2)
+        self.N = abs(_cross(self.L1, self.L2))
+        self.cart = np.array(cart, dtype=float)  # rows: a1, a2 cartesian
+        pts = set()
+        R = max(abs(c) for c in self.L1 + self.L2) + 1
+        for x in range(-2 * R, 2 * R + 1):
+            for y in range(-2 * R, 2 * R + 1):
+                pts.add(_reduce((x, y), self.L1, self.L2))
+        assert len(pts) == self.N, (len(pts), self.N)
+        pg = [P for P in _group_closure(pg_gens)
+              if _in_lattice(_matvec(P, self.L1), self.L1, self.L2)
+              and _in_lattice(_matvec(P, self.L2), self.L1, self.L2)]
+        self.pg = pg
+        self.sublat_chain = [tuple(map(tuple, s)) for s in sublat_chain]
+        for B1, B2 in self.sublat_chain:
+            assert _in_lattice(self.L1, B1, B2) and _in_lattice(self.L2, B1, B2)
+        # label sites: sort by coset ids along the chain, then coordinates
+        coset_ids = []
+        for B1, B2 in self.sublat_chain:
+            reps = sorted({_reduce(p, B1, B2) for p in pts})
+            coset_ids.append({p: reps.index(_reduce(p, B1, B2)) for p in pts})
+        order = sorted(pts, key=lambda p: tuple(c[p] for c in coset_ids) + (p[1], p[0]))
+        self.coords = order
+        self.index = {p: i for i, p in enumerate(order)}
+        self.sublat_options = [abs(_cross(B1, B2)) for (B1, B2) in self.sublat_chain]
+
+    def site(self, r):
+        return self.index[_reduce(r, self.L1, self.L2)]
+
+    def translations(self):
+        return list(self.coords)
+
+    def perm(self, P, t):
+        return np.array([self.site(_add(_matvec(P, r), t)) for r in self.coords], dtype=np.int32)
+
+    def bonds(self, vectors):
+        out = []
+        for r in self.coords:
+            for d in vectors:
+                out.append((self.site(r), self.site(_add(r, d))))
+        return out
+
+    def little_group(self, q):
+        """Point-group elements P with P^T q = q modulo integers."""
+        out = []
+        for P in self.pg:
+            qp = (P[0][0] * q[0] + P[1][0] * q[1], P[0][1] * q[0] + P[1][1] * q[1])
+            d = (qp[0] - q[0], qp[1] - q[1])
+            if d[0].denominator == 1 and d[1].denominator == 1:
+                out.append(P)
+        return out
+
+    def momenta(self):
+        """All allowed q (chi(t) = exp(2 pi i q.t)) as Fractions in [0,1)^2."""
+        det = _cross(self.L1, self.L2)
+        # dual basis: g_i . L_j = delta_ij  ->  G = (L^T)^-1
+        L = [[self.L1[0], self.L2[0]], [self.L1[1], self.L2[1]]]  # columns L1, L2
+        # (L^T)^-1 = adj(L^T)/det
+        g1 = (Fraction(L[1][1], det), Fraction(-L[0][1], det))
+        g2 = (Fraction(-L[1][0], det), Fraction(L[0][0], det))
+        qs = set()
+        for m1 in range(self.N):
+            for m2 in range(self.N):
+                q = (m1 * g1[0] + m2 * g2[0], m1 * g1[1] + m2 * g2[1])
+                q = (q[0] - (q[0].numerator // q[0].denominator), q[1] - (q[1].numerator // q[1].denominator))
+                qs.add(q)
+        assert len(qs) == self.N
+        return sorted(qs)
+
+    def q_cart(self, q):
+        """Cartesian k with k . (n1 a1 + n2 a2) = 2 pi (q1 n1 + q2 n2)."""
+        A = self.cart  # rows a1, a2
+        return np.linalg.solve(A, 2 * np.pi * np.array([float(q[0]), float(q[1])]))
+
+
+def _add(a, b):
+    return (a[0] + b[0], a[1] + b[1])
+
+
+def _pg_orbit(lat, q):
+    orb = set()
+    for P in lat.pg:
+        qp = (P[0][0] * q[0] + P[1][0] * q[1], P[0][1] * q[0] + P[1][1] * q[1])
+        qp = tuple(x - (x.numerator // x.denominator) for x in qp)
+        orb.add(qp)
+    return orb
+
+
+def build_group(lat: Torus2D, q, pg_irrep, flip_parity, little=None):
+    """Group T x| L_q (x Z2 flip) with characters exp(2 pi i q.t) chi_rho(P) (+-1)^f.
+
+    Characters of the space group follow the little-group construction
+    (appendix "Representation theory for space groups"); the spin flip is a
+    direct factor (section "Discrete symmetries", product of characters).
+    """
+    if little is None:
+        little = lat.little_group(q)
+    perms, flips, chis = [], [], []
+    fl = [0] if flip_parity is None else [0, 1]
+    for P in little:
+        for t in lat.translations():
+            perm = lat.perm(P, t)
+            ph = np.exp(2j * np.pi * float(q[0] * t[0] + q[1] * t[1]))
+            for f in fl:
+                c = ph * pg_irrep[P] * (flip_parity if f else 1)
+                perms.append(perm)
+                flips.append(f)
+                chis.append(c)
+    chis = np.array(chis, dtype=np.complex128)
+    chis.real[np.abs(chis.real) < 1e-15] = 0.0
+    chis.imag[np.abs(chis.imag) < 1e-15] = 0.0
+    return np.array(perms, dtype=np.int32), np.array(flips, dtype=np.uint8), chis
+
+
+# ---------------------------------------------------------------------------
+# concrete lattices
+# ---------------------------------------------------------------------------
+
+SQ_R90 = ((0, -1), (1, 0))
+SQ_MX = ((-1, 0), (0, 1))
+TRI_R60 = ((0, -1), (1, 1))        # a1 -> a2, a2 -> a2 - a1
+TRI_MY = ((1, 1), (0, -1))         # a1 -> a1, a2 -> a1 - a2
+TRI_CART = ((1.0, 0.0), (0.5, np.sqrt(3.0) / 2.0))
+
+
+def square_lattice(L1, L2, sublat_chain, mirrors=True):
+    gens = [SQ_R90] + ([SQ_MX] if mirrors else [])
+    return Torus2D(L1, L2, gens, sublat_chain)
+
+
+def triangular_lattice(L1, L2, sublat_chain, mirrors=False):
+    gens = [TRI_R60] + ([TRI_MY] if mirrors else [])
+    return Torus2D(L1, L2, gens, sublat_chain, cart=TRI_CART)
+
+
+def _irrep_by_name(little, name):
+    irreps = one_dim_irreps(little)
+    if name in ("A", "A1"):
+        return irreps[0]
+    if isinstance(name, int):
+        return irreps[name]
+    raise ValueError(name)
+
+
+def square_j1j2(L1, L2, J1, J2, q, irrep="A1", flip=1, sublat_chain=None, mirrors=True,
+                n_up=None, name="square"):
+    lat = square_lattice(L1, L2, sublat_chain, mirrors=mirrors)
+    vec1 = [(1, 0), (0, 1)]
+    vec2 = [(1, 1), (1, -1)]
+    b1 = lat.bonds(vec1)
+    b2 = lat.bonds(vec2) if J2 != 0 else []
+    bonds = b1 + b2
+    bJ = [J1] * len(b1) + [J2] * len(b2)
+    little = lat.little_group(q)
+    rho = _irrep_by_name(little, irrep)
+    perms, flips, chis = build_group(lat, q, rho, flip, little)
+    n = lat.N
+    return Instance(name=name, n_sites=n, bonds=np.array(bonds, np.int32), bond_J=np.array(bJ, float),
+                    tris=np.zeros((0, 3), np.int32), tri_Jchi=np.zeros(0), n_up=n // 2 if n_up is None else n_up,
+                    perms=perms, flips=flips, chi=chis, sublat_options=lat.sublat_options,
+                    sector=f"q={tuple(map(str, q))}.{irrep}.{_flipname(flip)}",
+                    meta=dict(lattice=lat, little=little, q=q))
+
+
+def triangular_j1j2chi(L1, L2, J1, J2, Jchi, q, irrep="A", flip=1, sublat_chain=None, mirrors=None,
+                       n_up=None, name="triangular"):
+    if mirrors is None:
+        mirrors = (Jchi == 0)
+    lat = triangular_lattice(L1, L2, sublat_chain, mirrors=mirrors)
+    vec1 = [(1, 0), (0, 1), (-1, 1)]
+    vec2 = [(1, 1), (-1, 2), (-2, 1)]
+    b1 = lat.bonds(vec1)
+    b2 = lat.bonds(vec2) if J2 != 0 else []
+    bonds = b1 + b2
+    bJ = [J1] * len(b1) + [J2] * len(b2)
+    tris = []
+    if Jchi != 0:
+        for r in lat.coords:
+            tris.append((lat.site(r), lat.site(_add(r, (1, 0))), lat.site(_add(r, (0, 1)))))
+            tris.append((lat.site(_add(r, (1, 0))), lat.site(_add(r, (1, 1))), lat.site(_add(r, (0, 1)))))
+    little = lat.little_group(q)
+    rho = _irrep_by_name(little, irrep)
+    perms, flips, chis = build_group(lat, q, rho, flip, little)
+    n = lat.N
+    return Instance(name=name, n_sites=n, bonds=np.array(bonds, np.int32), bond_J=np.array(bJ, float),
+                    tris=np.array(tris, np.int32).reshape(-1, 3), tri_Jchi=np.full(len(tris), float(Jchi)),
+                    n_up=n // 2 if n_up is None else n_up, perms=perms, flips=flips, chi=chis,
+                    sublat_options=lat.sublat_options,
+                    sector=f"q={tuple(map(str, q))}.{irrep}.{_flipname(flip)}",
+                    meta=dict(lattice=lat, little=little, q=q))
+
+
+def _flipname(flip):
+    return {None: "noflip", 1: "even", -1: "odd"}[flip]
+
+
+def chain(N, J=1.0, k=0, flip=None, n_up=None, sublat=(2, 4), reflection=False, J2=0.0):
+    """Periodic chain; translations T_n (site p -> p+n), chi(T_n) = exp(2 pi i k n / N).
+
+    Labels: sublattices are residues mod m (nested chain ``sublat``), sites of
+    one residue class contiguous, ordered by position.
+    """
+    pos = list(range(N))
+    chain_m = list(sublat)
+    order = sorted(pos, key=lambda p: tuple(p % m for m in chain_m) + (p,))
+    lab = {p: i for i, p in enumerate(order)}
+    bonds = [(lab[p], lab[(p + 1) % N]) for p in pos]
+    bJ = [J] * N
+    if J2 != 0:
+        bonds += [(lab[p], lab[(p + 2) % N]) for p in pos]
+        bJ += [J2] * N
+    perms, flips, chis = [], [], []
+    fl = [0] if flip is None else [0, 1]
+    refl = [False, True] if reflection else [False]
+    for r in refl:
+        for t in range(N):
+            perm = np.empty(N, np.int32)
+            for p in pos:
+                img = ((-p if r else p) + t) % N
+                perm[lab[p]] = lab[img]
+            ph = np.exp(2j * np.pi * k * t / N)
+            for f in fl:
+                perms.append(perm.copy())
+                flips.append(f)
+                chis.append(ph * (flip if f else 1))
+    chis = np.array(chis, np.complex128)
+    chis.real[np.abs(chis.real) < 1e-15] = 0.0
+    chis.imag[np.abs(chis.imag) < 1e-15] = 0.0
+    opts = [m for m in chain_m if N % m == 0]
+    return Instance(name=f"chain{N}", n_sites=N, bonds=np.array(bonds, np.int32), bond_J=np.array(bJ, float),
+                    tris=np.zeros((0, 3), np.int32), tri_Jchi=np.zeros(0),
+                    n_up=N // 2 if n_up is None else n_up, perms=np.array(perms, np.int32),
+                    flips=np.array(flips, np.uint8), chi=chis, sublat_options=opts,
+                    sector=f"k={k}.{_flipname(flip)}", meta=dict(positions=order))
+
+
+# ---------------------------------------------------------------------------
+# the named workloads
+# ---------------------------------------------------------------------------
+
+SQ32_L = ((4, 4), (-4, 4))
+SQ32_CHAIN = [((1, 1), (1, -1)), ((2, 0), (0, 2)), ((2, 2), (-2, 2)), ((4, 0), (0, 4))]
+SQ40_L = ((6, 2), (-2, 6))
+SQ40_CHAIN = [((1, 1), (1, -1)), ((2, 0), (0, 2)), ((2, 2), (-2, 2))]
+TRI36_L = ((6, 0), (0, 6))
+TRI36_CHAIN = [((2, 0), (0, 2)), ((2, 2), (6, 0))]   # index 4, then 12 (= 4 x sqrt3 x sqrt3)
+Q0 = (Fraction(0), Fraction(0))
+
+
+def chain16():
+    """Heisenberg chain N=16, periodic, J=1, Sz=0, translations only, k=0."""
+    inst = chain(16, J=1.0, k=0, flip=None, sublat=(2, 4))
+    inst.name = "chain16_k0"
+    return inst
+
+
+def square32(J2=0.5, q=Q0, irrep="A1", flip=1, sublat_chain=SQ32_CHAIN):
+    """32-site square J1-J2 (torus (4,4),(-4,4)), full T x| C4v x Z2 at Gamma."""
+    inst = square_j1j2(SQ32_L[0], SQ32_L[1], 1.0, J2, q, irrep=irrep, flip=flip, sublat_chain=sublat_chain)
+    inst.name = "square32"
+    return inst
+
+
+def square40(J2=0.5, q=Q0, irrep="A", flip=1, sublat_chain=SQ40_CHAIN):
+    """40-site square J1-J2 on the torus (6,2),(-2,6); point group C4 (no mirror
+    maps this torus onto itself)."""
+    inst = square_j1j2(SQ40_L[0], SQ40_L[1], 1.0, J2, q, irrep=irrep, flip=flip, sublat_chain=sublat_chain,
+                       mirrors=False)
+    inst.name = "square40"
+    return inst
+
+
+def tri36_K(J2=0.1, Jchi=0.2, flip=1, sublat_chain=TRI36_CHAIN):
+    """36-site triangular J1-J2-Jchi at the K point, chi_K(t) = exp(2 pi i (t1 - t2)/3)."""
+    q = (Fraction(1, 3), Fraction(-1, 3) + 1)
+    inst = triangular_j1j2chi(TRI36_L[0], TRI36_L[1], 1.0, J2, Jchi, q, irrep="A", flip=flip,
+                              sublat_chain=sublat_chain)
+    inst.name = "triangular36_K"
+    return inst
+
+
+def square32_sectors(J2=0.5):
+    """Every one-dimensional sector (k orbit x 1-D irrep of L_k x flip parity)
+    of the 32-site square J1-J2 model at Sz=0.  Two-dimensional irreps of the
+    little group are outside the one-dimensional method and not listed."""
+    lat = square_lattice(SQ32_L[0], SQ32_L[1], SQ32_CHAIN)
+    seen = set()
+    out = []
+    for q in lat.momenta():
+        if q in seen:
+            continue
+        seen |= _pg_orbit(lat, q)
+        little = lat.little_group(q)
+        for ir_i, _ in enumerate(one_dim_irreps(little)):
+            for fl in (1, -1):
+                inst = square_j1j2(SQ32_L[0], SQ32_L[1], 1.0, J2, q, irrep=ir_i, flip=fl,
+                                   sublat_chain=SQ32_CHAIN)
+                inst.name = f"square32_q{float(q[0]):.3f}_{float(q[1]):.3f}_ir{ir_i}_{_flipname(fl)}"
+                out.append(inst)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# small instances: every feature of the method on sizes a dense check handles
+# ---------------------------------------------------------------------------
+
+SQ16_L = ((4, 0), (0, 4))
+SQ16_CHAIN = [((1, 1), (1, -1)), ((2, 0), (0, 2))]
+SQ20_L = ((4, 2), (-2, 4))
+SQ20_CHAIN = [((1, 1), (1, -1)), ((2, 0), (0, 2))]
+SQ8_L = ((2, 2), (-2, 2))
+SQ8_CHAIN = [((1, 1), (1, -1))]
+TRI12_L = ((2, 2), (-2, 4))
+TRI12_CHAIN = [((2, 0), (0, 2))]
+F = Fraction
+
+
+def small_instances():
+    """Diverse small sectors: translations only, dihedral chains, square and
+    triangular point groups, spin flip, complex momenta, chirality."""
+    out = []
+    out.append(chain(8, k=0))
+    out.append(chain(8, k=3))
+    out.append(chain(10, k=0, flip=1))
+    out.append(chain(10, k=5, flip=-1))
+    out.append(chain(12, k=2, flip=-1, sublat=(2, 4)))
+    out.append(chain(12, k=0, reflection=True, sublat=(2,), J2=0.4))
+    out.append(chain(12, k=0, n_up=4, sublat=(2, 4)))
+    s8 = square_j1j2(SQ8_L[0], SQ8_L[1], 1.0, 0.3, Q0, "A1", 1, SQ8_CHAIN, name="square8")
+    out.append(s8)
+    out.append(square_j1j2(SQ16_L[0], SQ16_L[1], 1.0, 0.5, Q0, "A1", 1, SQ16_CHAIN, name="square16"))
+    out.append(square_j1j2(SQ16_L[0], SQ16_L[1], 1.0, 0.5, Q0, 1, -1, SQ16_CHAIN, name="square16"))
+    out.append(square_j1j2(SQ16_L[0], SQ16_L[1], 1.0, 0.5, (F(1, 2), F(1, 2)), 2, 1, SQ16_CHAIN, name="square16"))
+    out.append(square_j1j2(SQ16_L[0], SQ16_L[1], 1.0, 0.5, (F(1, 4), F(0)), 0, -1, SQ16_CHAIN, name="square16"))
+    out.append(square_j1j2(SQ16_L[0], SQ16_L[1], 1.0, 0.5, (F(1, 4), F(1, 4)), 1, 1, SQ16_CHAIN, name="square16"))
+    out.append(square_j1j2(SQ20_L[0], SQ20_L[1], 1.0, 0.5, Q0, "A", 1, SQ20_CHAIN, mirrors=False, name="square20"))
+    out.append(square_j1j2(SQ20_L[0], SQ20_L[1], 1.0, 0.5, Q0, 2, -1, SQ20_CHAIN, mirrors=False, name="square20"))
+    out.append(triangular_j1j2chi(TRI12_L[0], TRI12_L[1], 1.0, 0.1, 0.2, (F(1, 3), F(2, 3)), "A", 1,
+                                  TRI12_CHAIN, name="triangular12"))
+    out.append(triangular_j1j2chi(TRI12_L[0], TRI12_L[1], 1.0, 0.1, 0.2, (F(1, 3), F(2, 3)), 1, -1,
+                                  TRI12_CHAIN, name="triangular12"))
+    out.append(triangular_j1j2chi(TRI12_L[0], TRI12_L[1], 1.0, 0.1, 0.0, Q0, "A1", 1, TRI12_CHAIN,
+                                  mirrors=True, name="triangular12"))
+    out.append(triangular_j1j2chi(TRI12_L[0], TRI12_L[1], 1.0, 0.0, 0.3, (F(1, 2), F(0)), 1, None,
+                                  TRI12_CHAIN, name="triangular12"))
+    return out
