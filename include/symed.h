@@ -1,0 +1,226 @@
+/*
+ * symed — matrix-free Hamiltonian application in a symmetry-adapted basis
+ * for spin-1/2 lattice models, on one AMD Instinct MI355X (gfx950).
+ *
+ * Plain C ABI: host/device pointers and sizes only.  Streams are HIP streams
+ * (hipStream_t) passed as `void*`; NULL means the default stream.  Every
+ * call returns an ed_status; no C++ exception crosses this boundary.  On
+ * error the outputs are left untouched and ed_last_error() returns a
+ * thread-local message describing the failure.
+ *
+ * Conventions (thesis chapter on large-scale exact diagonalization):
+ *  - A configuration of N <= 63 spins is an N-bit integer: site 0 is the
+ *    most significant bit, spin up = 1 (eq. defining int(sigma) in
+ *    "Representing Hilbert spaces and operators").
+ *  - A group element g moves the spin at site i to site perm[g*N + i]; if
+ *    flip[g] != 0 every spin is reversed afterwards.  The group must be
+ *    closed under composition and chi a one-dimensional character of it
+ *    (1-D irreps only, section "Computations in the symmetrized basis").
+ *  - Basis states are orbit representatives: the smallest integer in the
+ *    orbit ("representative condition").  A representative belongs to the
+ *    sector iff chi is trivial on its stabilizer.  Basis order = ascending
+ *    integer value.
+ *  - Sites are labelled so that each sublattice is a contiguous block of
+ *    N/N_sub labels, sublattice 0 on the most significant bits (section
+ *    "Generic sublattice coding algorithm": site numbering); every group
+ *    element must map each block onto one block (sublattice stability).
+ *  - Vectors are contiguous float64 arrays of length dim, or interleaved
+ *    complex128 (re, im) when the sector is complex (complex characters or
+ *    chirality terms).  Vectors are caller-owned device memory.
+ */
+#ifndef SYMED_H
+#define SYMED_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ED_OK = 0,
+    ED_EINVAL = 1,        /* bad argument, inconsistent model/group, H not invariant */
+    ED_ENOTSTABLE = 2,    /* sublattice decomposition not stable under the group */
+    ED_ECHAR = 3,         /* characters not a 1-D representation (|chi|!=1 or not multiplicative) */
+    ED_ENOMEM = 4,        /* device or host allocation failed, or memory cap exceeded */
+    ED_EDEVICE = 5,       /* HIP runtime error */
+    ED_EBREAKDOWN = 6     /* Lanczos breakdown: beta vanished before n_iter steps */
+} ed_status;
+
+/* Thread-local description of the last failure (never NULL). */
+const char *ed_last_error(void);
+
+/* Library version string. */
+const char *ed_version(void);
+
+/*
+ * Hamiltonian H = sum_b J_b S_i.S_j + sum_t Jchi_t S_i.(S_j x S_k)
+ * (Heisenberg bonds as in the thesis's model chapters; scalar chirality on
+ * oriented triangles, as in the J1-J2-Jchi triangular model).  Every term is
+ * decomposed into non-branching pieces (section "Computations in the
+ * symmetrized basis"); pieces flipping the same pair of sites are merged.
+ *   bond_sites: int32[n_bonds][2], bond_J: f64[n_bonds]
+ *   tri_sites:  int32[n_tri][3] (i,j,k), tri_Jchi: f64[n_tri]
+ * Host pointers, read during ed_basis_build only.
+ */
+typedef struct {
+    int32_t n_sites;
+    int32_t n_bonds;
+    const int32_t *bond_sites;
+    const double *bond_J;
+    int32_t n_tri;
+    const int32_t *tri_sites;
+    const double *tri_Jchi;
+} ed_model;
+
+/*
+ * Symmetry group and 1-D irrep: perm int32[n_elem][n_sites], flip
+ * uint8[n_elem], chi_re/chi_im f64[n_elem] (chi_im may be NULL for real
+ * characters).  Host pointers, read during ed_basis_build only.
+ * n_elem <= 65535.  Spin-flip elements require n_up == n_sites/2.
+ */
+typedef struct {
+    int32_t n_elem;
+    const int32_t *perm;
+    const uint8_t *flip;
+    const double *chi_re;
+    const double *chi_im;
+} ed_group;
+
+/*
+ * Build options.  Zero means "choose automatically".
+ *  n_sub_rep:   sublattices of the Rep/Sym lookup tables (sublattice coding).
+ *  n_sub_act:   sublattices of the SymmetryAction tables; a multiple of
+ *               n_sub_rep (a refinement in the same contiguous labelling).
+ *  prefix_bits: bits of the Limits prefix table of the plain index lookup.
+ *  mem_limit_bytes: cap on device memory owned by the basis (0 = none);
+ *               exceeding it fails with ED_ENOMEM.
+ */
+typedef struct {
+    int32_t n_sub_rep;
+    int32_t n_sub_act;
+    int32_t prefix_bits;
+    int32_t reserved;
+    int64_t mem_limit_bytes;
+} ed_options;
+
+typedef struct ed_basis ed_basis;
+
+typedef struct {
+    int64_t dim;               /* sector dimension */
+    int32_t is_complex;        /* vectors are complex128 */
+    int32_t n_sites;
+    int32_t n_elem;
+    int32_t n_sub_rep, n_sub_act, prefix_bits;
+    int64_t n_elements;        /* matrix entries evaluated per H.v: the diagonal of
+                                  every row plus every (row, flipped pair) with
+                                  non-zero amplitude, in sector or not */
+    int64_t n_offdiag;         /* n_elements - dim */
+    int64_t bytes_device;      /* device memory owned by the basis */
+    int64_t table_bytes;       /* sublattice-coding tables (resident in LDS) */
+    int64_t limits_bytes;      /* plain lookup prefix table */
+    int64_t index_bytes;       /* learned index (0 if not trained) */
+    int32_t index_max_err;     /* learned-index error bound (-1 if not trained) */
+    int32_t lds_resident;      /* tables staged in LDS by the kernels */
+    double build_seconds;      /* wall time of ed_basis_build */
+} ed_basis_info_t;
+
+/*
+ * Build the sector basis on the device: validate model, group, characters
+ * and sublattice stability; build the sublattice-coding tables (Rep, Sym,
+ * SymmetryAction; algorithm "Preparation of lookup tables"); enumerate the
+ * Sz sector and keep representatives whose stabilizer carries a trivial
+ * character (algorithm "Preparation of the distributed and symmetrized
+ * Hilbert space", on one device); build the Limits prefix table.
+ *   n_up: number of up spins (Sz sector).
+ *   stream: hipStream_t or NULL.  Blocks until the basis is complete.
+ *   out: receives a library-owned handle; free with ed_basis_free.
+ * Errors: ED_EINVAL, ED_ENOTSTABLE, ED_ECHAR, ED_ENOMEM, ED_EDEVICE.
+ */
+ed_status ed_basis_build(const ed_model *model, const ed_group *group, int32_t n_up,
+                         const ed_options *opts, void *stream, ed_basis **out);
+
+/* Release everything the basis owns (tables, representatives, indexes,
+ * captured graphs).  NULL is ignored. */
+void ed_basis_free(ed_basis *basis);
+
+/* Sizes and statistics of a built basis. */
+ed_status ed_basis_info(const ed_basis *basis, ed_basis_info_t *info);
+
+/*
+ * Copy the basis to the host: reps uint64[dim] (ascending representatives),
+ * stab uint32[dim] (stabilizer sizes; norm N = sqrt(|G| |Stab|)).
+ * Either pointer may be NULL.  Synchronous.
+ */
+ed_status ed_basis_export(const ed_basis *basis, uint64_t *h_reps, uint32_t *h_stab);
+
+/* Device pointer to the ascending representatives (uint64[dim]), owned by
+ * the basis and valid until ed_basis_free. */
+ed_status ed_basis_device_reps(const ed_basis *basis, const uint64_t **d_reps);
+
+/*
+ * y := H x in the symmetry-adapted basis (matrix-free; algorithm "Parallel
+ * matrix-vector multiply for a non-branching term", as a gather: each row's
+ * owner applies every non-branching piece to its representative, finds the
+ * target's representative by sublattice coding (algorithm "Sublattice coding
+ * algorithm for finding the representative"), looks up its index, and
+ * accumulates character x norm ratio x amplitude x x_j; no atomics).
+ *   d_x, d_y: device vectors of length dim (f64 or interleaved c128); must
+ *   not alias.  lookup_mode: 0 = plain (Limits + binary search), 1 = learned
+ *   index (requires ed_index_train).  Asynchronous on `stream`.
+ */
+ed_status ed_apply_H(const ed_basis *basis, const void *d_x, void *d_y, int32_t lookup_mode, void *stream);
+
+/*
+ * Index lookup of n representatives: d_idx[k] = position of d_keys[k] in the
+ * basis, or -1 if absent.  mode 0 = plain (Limits + binary search), 1 =
+ * learned index + bounded search.  d_keys uint64[n], d_idx int64[n] device
+ * memory.  Asynchronous on `stream`.
+ */
+ed_status ed_lookup(const ed_basis *basis, const uint64_t *d_keys, int64_t n, int64_t *d_idx,
+                    int32_t mode, void *stream);
+
+/*
+ * Lanczos iteration without reorthogonalization (algorithms "Real-symmetric
+ * Lanczos step" and "Complex-Hermitian Lanczos step"), n_iter steps from the
+ * start vector d_v0 (device, length dim; normalized internally, not
+ * modified).  Each step is one replay of a captured HIP graph (H.v with the
+ * fused w <- Hv - beta w epilogue, reductions, axpy, scale) with alpha and
+ * beta kept on the device.  Results: h_alpha f64[n_iter], h_beta f64[n_iter]
+ * (beta[k] is the norm produced by step k; the T-matrix off-diagonal is
+ * beta[0..n-2]); *n_done = steps completed.  Returns ED_EBREAKDOWN (with
+ * outputs valid for n_done steps) if beta < 1e-14 max|alpha|.
+ * lookup_mode as in ed_apply_H.  Blocks until done.
+ */
+ed_status ed_lanczos_run(const ed_basis *basis, const void *d_v0, int32_t n_iter, int32_t lookup_mode,
+                         double *h_alpha, double *h_beta, int32_t *n_done, void *stream);
+
+/*
+ * Lowest k eigenvalues of the symmetric tridiagonal T-matrix with diagonal
+ * alpha[n] and off-diagonal beta[n-1] (Sturm-sequence bisection), ascending.
+ * Host only.
+ */
+ed_status ed_eigenvalues(const double *alpha, const double *beta, int32_t n, int32_t k, double *evals);
+
+/*
+ * Host-only inspection of the sublattice-coding tables for one
+ * decomposition into n_sub contiguous sublattices (no device needed):
+ * for sublattice X and substate s (b = N/n_sub bits),
+ *   rep_out[X*2^b + s]      = Rep_X(s)
+ *   sym_off[X*2^b + s .. +1] = range in sym_out of Sym_X(s) (group indices)
+ *   act_out[(g*n_sub + X)*2^b + s] = SymmetryAction_X(g, s) as an N-bit
+ *                              configuration (may be NULL)
+ * Sizes: rep_out uint32[n_sub*2^b], sym_off uint32[n_sub*2^b + 1],
+ * sym_out uint32[sym_cap], act_out uint64[n_elem*n_sub*2^b].
+ * *n_sym receives the total length of the Sym lists (sym_out written only
+ * if it fits sym_cap).  Validates group and stability as ed_basis_build.
+ */
+ed_status ed_tables_inspect(const ed_model *model, const ed_group *group, int32_t n_up, int32_t n_sub,
+                            uint32_t *rep_out, uint32_t *sym_off, uint32_t *sym_out, int64_t sym_cap,
+                            int64_t *n_sym, uint64_t *act_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SYMED_H */

@@ -1,0 +1,493 @@
+// C ABI of the symed library.  Host orchestration only: every step of the
+// hot path runs in the HIP kernels of kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+
+using namespace symed;
+
+struct ed_basis {
+    HostTables T;
+    BlobLayout lay{};
+    int device = 0;
+    hipStream_t own = nullptr;
+    void *d_blob = nullptr;
+    uint64_t *d_reps = nullptr;
+    uint16_t *d_stab = nullptr;
+    uint32_t *d_limits = nullptr;
+    int pbits = 0;
+    int64_t dim = 0;
+    int64_t n_elements = 0;
+    int64_t bytes = 0;
+    int64_t mem_limit = 0;
+    LaunchCfg cfg{};
+    int n_cu = 0;
+    double build_seconds = 0.0;
+    // Lanczos workspace and captured step graphs (one per lookup mode)
+    double *d_v = nullptr, *d_w = nullptr, *d_vprev = nullptr, *d_partials = nullptr;
+    double *d_alpha = nullptr, *d_beta = nullptr;
+    LState *d_ls = nullptr;
+    int lanczos_cap = 0;
+    hipGraphExec_t step_graph[2] = {nullptr, nullptr};
+    std::vector<void *> allocs;
+};
+
+namespace symed {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+ed_status fail(ed_status st, const std::string &msg)
+{
+    g_err = msg;
+    return st;
+}
+
+}  // namespace symed
+
+#define HIP_OK(expr)                                                                             \
+    do {                                                                                         \
+        hipError_t _e = (expr);                                                                  \
+        if (_e != hipSuccess)                                                                    \
+            return fail(ED_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));          \
+    } while (0)
+
+static ed_status dev_alloc(ed_basis *b, void **ptr, size_t bytes)
+{
+    if (b->mem_limit > 0 && b->bytes + (int64_t)bytes > b->mem_limit)
+        return fail(ED_ENOMEM, "device memory cap exceeded (" + std::to_string(b->bytes + bytes) + " > " +
+                                   std::to_string(b->mem_limit) + " bytes)");
+    hipError_t e = hipMalloc(ptr, bytes ? bytes : 16);
+    if (e != hipSuccess) return fail(ED_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    b->bytes += (int64_t)bytes;
+    b->allocs.push_back(*ptr);
+    return ED_OK;
+}
+
+static KParams make_params(const ed_basis *b)
+{
+    KParams p{};
+    const HostTables &T = b->T;
+    p.N = T.N;
+    p.R = T.R;
+    p.br = T.br;
+    p.A = T.A;
+    p.ba = T.ba;
+    p.n_pairs = (int)T.pairs.size();
+    p.G = T.G;
+    p.is_complex = T.is_complex ? 1 : 0;
+    p.pbits = b->pbits;
+    p.n_up = T.n_up;
+    p.maskN = (T.N == 64) ? ~0ull : ((1ull << T.N) - 1);
+    p.lay = b->lay;
+    p.blob = b->d_blob;
+    p.reps = b->d_reps;
+    p.stab = b->d_stab;
+    p.limits = b->d_limits;
+    p.dim = b->dim;
+    p.idx_err = -1;
+    return p;
+}
+
+static uint64_t binom64(int n, int k)
+{
+    if (k < 0 || k > n) return 0;
+    if (k > n - k) k = n - k;
+    unsigned __int128 r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (unsigned)(n - k + i) / (unsigned)i;
+    return (uint64_t)r;
+}
+
+extern "C" {
+
+const char *ed_last_error(void) { return g_err.c_str(); }
+
+const char *ed_version(void) { return "symed 0.1 (gfx950)"; }
+
+void ed_basis_free(ed_basis *b)
+{
+    if (!b) return;
+    for (auto &g : b->step_graph)
+        if (g) hipGraphExecDestroy(g);
+    for (void *p : b->allocs) hipFree(p);
+    if (b->own) hipStreamDestroy(b->own);
+    delete b;
+}
+
+static ed_status build_impl(const ed_model *model, const ed_group *group, int32_t n_up, const ed_options *opts,
+                            hipStream_t st, ed_basis *b)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    ed_options o{};
+    if (opts) o = *opts;
+    ed_status s = build_host_tables(model, group, n_up, o.n_sub_rep, o.n_sub_act, b->T);
+    if (s != ED_OK) return s;
+    HostTables &T = b->T;
+    b->mem_limit = o.mem_limit_bytes;
+    std::vector<uint8_t> blob = pack_blob(T, b->lay);
+
+    HIP_OK(hipGetDevice(&b->device));
+    int lds_max = 0;
+    HIP_OK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device));
+    HIP_OK(hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, b->device));
+    if ((int64_t)b->lay.bytes + 256 > lds_max)
+        return fail(ED_EINVAL, "lookup tables (" + std::to_string(b->lay.bytes) + " B) exceed the LDS of one block (" +
+                                   std::to_string(lds_max) + " B); choose other sublattice decompositions");
+    HIP_OK(hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking));
+
+    if ((s = dev_alloc(b, &b->d_blob, blob.size())) != ED_OK) return s;
+    HIP_OK(hipMemcpy(b->d_blob, blob.data(), blob.size(), hipMemcpyHostToDevice));
+
+    KParams p = make_params(b);
+    int bpc = 0, athreads = 0;
+    HIP_OK(prepare_kernels(p, &bpc, &athreads));
+    if (bpc < 1) return fail(ED_EINVAL, "apply kernel does not fit on a compute unit");
+    b->cfg.apply_threads = athreads;
+    b->cfg.apply_blocks = bpc * b->n_cu;
+    b->cfg.vec_blocks = 4 * b->n_cu;
+
+    // --- enumeration of the sector (two passes + scan) -------------------
+    const int N = T.N;
+    const uint64_t total = binom64(N, n_up);
+    std::vector<uint64_t> hb(64 * 64, 0);
+    for (int n = 0; n < 64; ++n)
+        for (int k = 0; k < 64; ++k) hb[n * 64 + k] = binom64(n, k);
+    uint64_t *d_binom = nullptr;
+    HIP_OK(hipMalloc((void **)&d_binom, hb.size() * sizeof(uint64_t)));
+    HIP_OK(hipMemcpy(d_binom, hb.data(), hb.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+    uint64_t len = std::max<uint64_t>(256, (total + (1ull << 24) - 1) >> 24);
+    uint64_t n_chunks = (total + len - 1) / len;
+    if (n_chunks == 0) n_chunks = 1;
+    uint32_t *d_counts = nullptr;
+    uint64_t *d_offsets = nullptr, *d_total = nullptr;
+    HIP_OK(hipMalloc((void **)&d_counts, n_chunks * sizeof(uint32_t)));
+    HIP_OK(hipMalloc((void **)&d_offsets, n_chunks * sizeof(uint64_t)));
+    HIP_OK(hipMalloc((void **)&d_total, sizeof(uint64_t)));
+    int eblocks = (int)std::min<uint64_t>((n_chunks + 255) / 256, (uint64_t)b->n_cu * 16);
+    if (eblocks < 1) eblocks = 1;
+    HIP_OK(launch_enumerate(p, d_binom, total, len, n_chunks, d_counts, nullptr, nullptr, nullptr, false, eblocks, st));
+    HIP_OK(launch_scan(d_counts, d_offsets, n_chunks, d_total, st));
+    uint64_t dim = 0;
+    HIP_OK(hipMemcpyAsync(&dim, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (dim >= (1ull << 32) - 1) return fail(ED_EINVAL, "sector dimension >= 2^32 is not supported");
+    b->dim = (int64_t)dim;
+    if ((s = dev_alloc(b, (void **)&b->d_reps, dim * sizeof(uint64_t))) != ED_OK) return s;
+    if ((s = dev_alloc(b, (void **)&b->d_stab, dim * sizeof(uint16_t))) != ED_OK) return s;
+    p = make_params(b);
+    HIP_OK(launch_enumerate(p, d_binom, total, len, n_chunks, d_counts, d_offsets, b->d_reps, b->d_stab, true, eblocks,
+                            st));
+    HIP_OK(hipStreamSynchronize(st));
+    hipFree(d_binom);
+    hipFree(d_counts);
+    hipFree(d_offsets);
+    hipFree(d_total);
+
+    // --- Limits prefix table --------------------------------------------
+    int pb = o.prefix_bits;
+    if (pb <= 0) {
+        int lg = 0;
+        while (lg < 62 && (1ull << lg) < (uint64_t)std::max<int64_t>(dim, 1)) ++lg;
+        pb = std::min(std::min(N, 28), std::max(4, lg + 1));
+    }
+    if (pb > N) pb = N;
+    if (pb > 30) return fail(ED_EINVAL, "prefix_bits must be <= 30");
+    b->pbits = pb;
+    if ((s = dev_alloc(b, (void **)&b->d_limits, ((1ull << pb) + 1) * sizeof(uint32_t))) != ED_OK) return s;
+    HIP_OK(launch_limits(b->d_reps, b->dim, N, pb, b->d_limits, st));
+
+    // --- element count ----------------------------------------------------
+    p = make_params(b);
+    unsigned long long *d_cnt = nullptr, cnt = 0;
+    HIP_OK(hipMalloc((void **)&d_cnt, sizeof(unsigned long long)));
+    HIP_OK(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long), st));
+    if (b->dim > 0) HIP_OK(launch_count_elements(p, d_cnt, 4 * b->n_cu, st));
+    HIP_OK(hipMemcpyAsync(&cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    hipFree(d_cnt);
+    b->n_elements = (int64_t)cnt;
+    b->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return ED_OK;
+}
+
+ed_status ed_basis_build(const ed_model *model, const ed_group *group, int32_t n_up, const ed_options *opts,
+                         void *stream, ed_basis **out)
+{
+    if (!out) return fail(ED_EINVAL, "out must not be NULL");
+    ed_basis *b = new (std::nothrow) ed_basis();
+    if (!b) return fail(ED_ENOMEM, "host allocation failed");
+    ed_status s = build_impl(model, group, n_up, opts, (hipStream_t)stream, b);
+    if (s != ED_OK) {
+        std::string msg = g_err;
+        hipDeviceSynchronize();
+        ed_basis_free(b);
+        g_err = msg;
+        return s;
+    }
+    *out = b;
+    return ED_OK;
+}
+
+ed_status ed_basis_info(const ed_basis *b, ed_basis_info_t *info)
+{
+    if (!b || !info) return fail(ED_EINVAL, "NULL argument");
+    ed_basis_info_t r{};
+    r.dim = b->dim;
+    r.is_complex = b->T.is_complex ? 1 : 0;
+    r.n_sites = b->T.N;
+    r.n_elem = b->T.G;
+    r.n_sub_rep = b->T.R;
+    r.n_sub_act = b->T.A;
+    r.prefix_bits = b->pbits;
+    r.n_elements = b->n_elements;
+    r.n_offdiag = b->n_elements - b->dim;
+    r.bytes_device = b->bytes;
+    r.table_bytes = b->lay.bytes;
+    r.limits_bytes = (int64_t)(((1ull << b->pbits) + 1) * sizeof(uint32_t));
+    r.index_bytes = 0;
+    r.index_max_err = -1;
+    r.lds_resident = 1;
+    r.build_seconds = b->build_seconds;
+    *info = r;
+    return ED_OK;
+}
+
+ed_status ed_basis_export(const ed_basis *b, uint64_t *h_reps, uint32_t *h_stab)
+{
+    if (!b) return fail(ED_EINVAL, "NULL basis");
+    if (b->dim == 0) return ED_OK;
+    if (h_reps) HIP_OK(hipMemcpy(h_reps, b->d_reps, b->dim * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    if (h_stab) {
+        std::vector<uint16_t> tmp(b->dim);
+        HIP_OK(hipMemcpy(tmp.data(), b->d_stab, b->dim * sizeof(uint16_t), hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < b->dim; ++i) h_stab[i] = tmp[i];
+    }
+    return ED_OK;
+}
+
+ed_status ed_basis_device_reps(const ed_basis *b, const uint64_t **d_reps)
+{
+    if (!b || !d_reps) return fail(ED_EINVAL, "NULL argument");
+    *d_reps = b->d_reps;
+    return ED_OK;
+}
+
+ed_status ed_apply_H(const ed_basis *b, const void *d_x, void *d_y, int32_t lookup_mode, void *stream)
+{
+    if (!b) return fail(ED_EINVAL, "NULL basis");
+    if (lookup_mode != 0) return fail(ED_EINVAL, "lookup_mode must be 0 (plain) or 1 (learned, after ed_index_train)");
+    if (b->dim == 0) return ED_OK;
+    if (!d_x || !d_y) return fail(ED_EINVAL, "NULL vector");
+    if (d_x == d_y) return fail(ED_EINVAL, "x and y must not alias");
+    KParams p = make_params(b);
+    HIP_OK(launch_apply(p, b->cfg, d_x, d_y, 0, nullptr, nullptr, (hipStream_t)stream));
+    return ED_OK;
+}
+
+ed_status ed_lookup(const ed_basis *b, const uint64_t *d_keys, int64_t n, int64_t *d_idx, int32_t mode, void *stream)
+{
+    if (!b) return fail(ED_EINVAL, "NULL basis");
+    if (mode != 0) return fail(ED_EINVAL, "mode must be 0 (plain) or 1 (learned, after ed_index_train)");
+    if (n < 0) return fail(ED_EINVAL, "negative count");
+    if (n == 0) return ED_OK;
+    if (!d_keys || !d_idx) return fail(ED_EINVAL, "NULL array");
+    if (b->dim == 0) {
+        std::vector<int64_t> m1(n, -1);
+        HIP_OK(hipMemcpyAsync(d_idx, m1.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, (hipStream_t)stream));
+        HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+        return ED_OK;
+    }
+    KParams p = make_params(b);
+    HIP_OK(launch_lookup(p, d_keys, n, d_idx, mode, (hipStream_t)stream));
+    return ED_OK;
+}
+
+static ed_status lanczos_workspace(ed_basis *b, int n_iter)
+{
+    const bool cplx = b->T.is_complex;
+    const size_t vbytes = (size_t)b->dim * sizeof(double) * (cplx ? 2 : 1);
+    ed_status s;
+    if (!b->d_v) {
+        if ((s = dev_alloc(b, (void **)&b->d_v, vbytes)) != ED_OK) return s;
+        if ((s = dev_alloc(b, (void **)&b->d_w, vbytes)) != ED_OK) return s;
+        if (cplx && (s = dev_alloc(b, (void **)&b->d_vprev, vbytes)) != ED_OK) return s;
+        int np = std::max(b->cfg.apply_blocks, b->cfg.vec_blocks);
+        if ((s = dev_alloc(b, (void **)&b->d_partials, np * sizeof(double))) != ED_OK) return s;
+        if ((s = dev_alloc(b, (void **)&b->d_ls, sizeof(LState))) != ED_OK) return s;
+    }
+    if (n_iter > b->lanczos_cap) {
+        // graphs reference the alpha/beta arrays: rebuild them
+        for (auto &g : b->step_graph)
+            if (g) {
+                hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+        int cap = std::max(n_iter, 256);
+        if ((s = dev_alloc(b, (void **)&b->d_alpha, cap * sizeof(double))) != ED_OK) return s;
+        if ((s = dev_alloc(b, (void **)&b->d_beta, cap * sizeof(double))) != ED_OK) return s;
+        b->lanczos_cap = cap;
+    }
+    return ED_OK;
+}
+
+// One Lanczos step as a kernel sequence on stream `st` (captured once).
+static hipError_t enqueue_step(ed_basis *b, int mode, hipStream_t st)
+{
+    const bool cplx = b->T.is_complex;
+    KParams p = make_params(b);
+    hipError_t e;
+    if ((e = launch_apply(p, b->cfg, b->d_v, b->d_w, cplx ? 2 : 1, b->d_ls, b->d_partials, st)) != hipSuccess) return e;
+    if ((e = launch_finalize(b->d_partials, b->cfg.apply_blocks, b->d_alpha, b->d_beta, b->d_ls, 0, st)) != hipSuccess)
+        return e;
+    if ((e = launch_axpy_norm(b->d_w, b->d_v, b->d_vprev, b->dim, cplx, b->d_alpha, b->d_ls, b->d_partials,
+                              b->cfg.vec_blocks, st)) != hipSuccess)
+        return e;
+    if ((e = launch_finalize(b->d_partials, b->cfg.vec_blocks, b->d_alpha, b->d_beta, b->d_ls, 1, st)) != hipSuccess)
+        return e;
+    if ((e = launch_rotate(b->d_v, b->d_w, b->d_vprev, b->dim, cplx, b->d_beta, b->d_ls, b->cfg.vec_blocks, st)) !=
+        hipSuccess)
+        return e;
+    return launch_step_inc(b->d_ls, b->d_beta, st);
+}
+
+ed_status ed_lanczos_run(const ed_basis *cb, const void *d_v0, int32_t n_iter, int32_t lookup_mode, double *h_alpha,
+                         double *h_beta, int32_t *n_done, void *stream)
+{
+    ed_basis *b = const_cast<ed_basis *>(cb);
+    if (!b || !d_v0 || !h_alpha || !h_beta || !n_done) return fail(ED_EINVAL, "NULL argument");
+    if (n_iter < 1) return fail(ED_EINVAL, "n_iter must be >= 1");
+    if (lookup_mode != 0) return fail(ED_EINVAL, "lookup_mode must be 0 (plain) or 1 (learned, after ed_index_train)");
+    if (b->dim == 0) return fail(ED_EINVAL, "empty sector");
+    ed_status s = lanczos_workspace(b, n_iter);
+    if (s != ED_OK) return s;
+    const bool cplx = b->T.is_complex;
+    const int64_t n2 = b->dim * (cplx ? 2 : 1);
+    HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    hipStream_t st = b->own;
+    // start vector: v = v0 / |v0|, w = vprev = 0, scalars reset
+    HIP_OK(launch_norm2_partial(d_v0, b->dim, cplx, b->d_partials, b->cfg.vec_blocks, st));
+    HIP_OK(launch_scale_copy(d_v0, b->d_v, b->dim, cplx, b->d_partials, b->cfg.vec_blocks, b->cfg.vec_blocks, st));
+    HIP_OK(launch_fill(b->d_w, n2, 0.0, b->cfg.vec_blocks, st));
+    if (cplx) HIP_OK(launch_fill(b->d_vprev, n2, 0.0, b->cfg.vec_blocks, st));
+    HIP_OK(launch_lstate_init(b->d_ls, st));
+    hipGraphExec_t &ge = b->step_graph[lookup_mode];
+    if (!ge) {
+        hipGraph_t g = nullptr;
+        HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_step(b, lookup_mode, st);
+        hipError_t e2 = hipStreamEndCapture(st, &g);
+        if (e != hipSuccess) return fail(ED_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+        if (e2 != hipSuccess) return fail(ED_EDEVICE, std::string("end capture: ") + hipGetErrorString(e2));
+        HIP_OK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+        hipGraphDestroy(g);
+    }
+    for (int k = 0; k < n_iter; ++k) HIP_OK(hipGraphLaunch(ge, st));
+    LState ls{};
+    HIP_OK(hipMemcpyAsync(h_alpha, b->d_alpha, n_iter * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(h_beta, b->d_beta, n_iter * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(&ls, b->d_ls, sizeof(LState), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (ls.broken_step >= 0) {
+        *n_done = ls.broken_step + 1;
+        set_error("Lanczos breakdown at step " + std::to_string(ls.broken_step));
+        return ED_EBREAKDOWN;
+    }
+    *n_done = n_iter;
+    return ED_OK;
+}
+
+// Sturm-sequence bisection for the lowest k eigenvalues of a symmetric
+// tridiagonal matrix.
+static int sturm_count(const double *a, const double *b, int n, double x)
+{
+    int c = 0;
+    double q = a[0] - x;
+    if (q < 0) ++c;
+    for (int i = 1; i < n; ++i) {
+        if (q == 0.0) q = 1e-300;
+        q = (a[i] - x) - b[i - 1] * b[i - 1] / q;
+        if (q < 0) ++c;
+    }
+    return c;
+}
+
+ed_status ed_eigenvalues(const double *alpha, const double *beta, int32_t n, int32_t k, double *evals)
+{
+    if (!alpha || !evals || n < 1 || k < 1 || k > n || (n > 1 && !beta))
+        return fail(ED_EINVAL, "bad arguments to ed_eigenvalues");
+    double lo = alpha[0], hi = alpha[0];
+    for (int i = 0; i < n; ++i) {
+        double r = (i > 0 ? std::fabs(beta[i - 1]) : 0.0) + (i < n - 1 ? std::fabs(beta[i]) : 0.0);
+        lo = std::min(lo, alpha[i] - r);
+        hi = std::max(hi, alpha[i] + r);
+    }
+    const double span = std::max(hi - lo, 1e-300);
+    lo -= 1e-12 * span + 1e-300;
+    hi += 1e-12 * span + 1e-300;
+    for (int m = 0; m < k; ++m) {
+        // smallest x with count(x) > m
+        double l = lo, h = hi;
+        for (int it = 0; it < 200; ++it) {
+            double mid = 0.5 * (l + h);
+            if (mid == l || mid == h) break;
+            if (sturm_count(alpha, beta, n, mid) > m) h = mid; else l = mid;
+        }
+        evals[m] = 0.5 * (l + h);
+    }
+    return ED_OK;
+}
+
+static uint32_t sub_image_bits(const int32_t *p, int X, int b, uint32_t s)
+{
+    uint32_t out = 0;
+    for (int q = 0; q < b; ++q)
+        if ((s >> (b - 1 - q)) & 1u) out |= 1u << (b - 1 - (p[X * b + q] % b));
+    return out;
+}
+
+ed_status ed_tables_inspect(const ed_model *model, const ed_group *group, int32_t n_up, int32_t n_sub,
+                            uint32_t *rep_out, uint32_t *sym_off, uint32_t *sym_out, int64_t sym_cap, int64_t *n_sym,
+                            uint64_t *act_out)
+{
+    HostTables T;
+    ed_status s = validate_and_copy_group(model, group, n_up, T);
+    if (s != ED_OK) return s;
+    if ((s = check_stable(T, n_sub)) != ED_OK) return s;
+    const int b = T.N / n_sub;
+    if (b > 20) return fail(ED_EINVAL, "substates wider than 20 bits");
+    std::vector<uint16_t> rep;
+    std::vector<uint32_t> off, lst;
+    if (b > 16) return fail(ED_EINVAL, "substates wider than 16 bits");
+    build_rep_sym(T, n_sub, rep, off, lst);
+    const size_t S = (size_t)1 << b;
+    if (rep_out)
+        for (size_t i = 0; i < rep.size(); ++i) rep_out[i] = rep[i];
+    if (sym_off) std::memcpy(sym_off, off.data(), off.size() * sizeof(uint32_t));
+    if (n_sym) *n_sym = (int64_t)lst.size();
+    if (sym_out && (int64_t)lst.size() <= sym_cap)
+        for (size_t i = 0; i < lst.size(); ++i) sym_out[i] = lst[i] >> 16;
+    if (act_out) {
+        for (int g = 0; g < T.G; ++g) {
+            const int32_t *p = &T.sp_perm[(size_t)T.sp_of[g] * T.N];
+            for (int X = 0; X < n_sub; ++X) {
+                int d = p[X * b] / b;
+                for (uint32_t v = 0; v < S; ++v) {
+                    uint32_t img = sub_image_bits(p, X, b, v);
+                    if (T.flip[g]) img ^= (uint32_t)(S - 1);
+                    act_out[((size_t)g * n_sub + X) * S + v] = (uint64_t)img << (T.N - (d + 1) * b);
+                }
+            }
+        }
+    }
+    return ED_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Internal structures shared by the host code and the HIP kernels of the
+// symed library.  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "symed.h"
+
+namespace symed {
+
+constexpr int kMaxSites = 63;
+
+// A flipped pair of sites.  Exchange pieces of every bond on the pair and
+// chirality pieces of every triangle edge on the pair flip the same two
+// spins, so they merge into one amplitude (J/2 real part, chirality
+// imaginary part).
+struct PairTerm {
+    uint64_t mask;      // both site bits
+    uint64_t lo_bit;    // bit of the lower-labelled site
+    double Jsum;        // sum of bond couplings on the pair (S^z S^z: Jsum/4 * (+-1))
+    int32_t chi_begin;  // range in the chirality-contribution list
+    int32_t chi_end;
+};
+
+// Contribution of one oriented triangle to the flip of one of its edges:
+// Im(h) += c * sgn(site) * sgn_lo, with sgn(site) = +1 if that third spin is
+// up, -1 otherwise, and sgn_lo = +1 if the lower-labelled spin of the pair is
+// down, -1 otherwise.  (Derivation: S_a.(S_b x S_c) restricted to the flip of
+// (b,c) equals (i/2) S^z_a (S^+_b S^-_c - S^-_b S^+_c).)
+struct ChiTerm {
+    uint64_t site_bit;
+    double c;
+};
+
+// Everything the kernels need, built on the host.
+struct HostTables {
+    int N = 0, n_up = 0;
+    int G = 0;                          // group order (with flip elements)
+    int n_sp = 0;                       // distinct site permutations
+    bool has_flip = false;
+    bool is_complex = false;
+    std::vector<int32_t> sp_of;         // [G]
+    std::vector<uint8_t> flip;          // [G]
+    std::vector<double> chi_re, chi_im; // [G]
+    std::vector<uint8_t> chi_one;       // [G]
+    std::vector<int32_t> sp_perm;       // [n_sp][N]
+
+    // Rep/Sym tables on R coarse sublattices of br bits
+    int R = 0, br = 0;
+    std::vector<uint16_t> rep;          // [R][2^br]
+    std::vector<uint32_t> sym_off;      // [R*2^br + 1]
+    std::vector<uint32_t> sym_list;     // (g << 16) | (sp << 1) | flip
+    // SymmetryAction tables on A fine sublattices of ba bits, destination-major
+    int A = 0, ba = 0;
+    std::vector<uint8_t> act;           // [n_sp][A][2^ba]: substate at destination d
+    std::vector<uint64_t> src;          // [n_sp]: 4-bit source sublattice per destination
+
+    std::vector<PairTerm> pairs;
+    std::vector<ChiTerm> chis;
+};
+
+// Byte layout of the table blob staged into LDS by the kernels.
+struct BlobLayout {
+    uint32_t off_rep, off_symoff, off_symlist, off_act, off_src, off_pairs, off_chis, off_chi, off_sqrt, off_isqrt,
+        off_chione;
+    uint32_t bytes;
+};
+
+// Parameters passed by value to the apply / enumeration kernels.
+struct KParams {
+    int N, R, br, A, ba, n_pairs, G, is_complex;
+    int pbits, n_up;
+    uint64_t maskN;
+    BlobLayout lay;
+    const void *blob;          // device copy of the LDS blob (16-byte aligned)
+    const uint64_t *reps;      // [dim]
+    const uint16_t *stab;      // [dim]
+    const uint32_t *limits;    // [2^pbits + 1]
+    int64_t dim;
+    // learned index
+    const float *mlp;          // weights
+    const uint32_t *seg;       // stage-2 segment table
+    int32_t idx_err;
+    int32_t mlp_in;
+    int32_t n_seg;
+    int32_t seg_shift;
+};
+
+// Thread-local error reporting.
+void set_error(const std::string &msg);
+ed_status fail(ed_status st, const std::string &msg);
+
+// tables.cpp
+ed_status build_host_tables(const ed_model *m, const ed_group *g, int n_up, int n_sub_rep, int n_sub_act,
+                            HostTables &T);
+ed_status validate_and_copy_group(const ed_model *m, const ed_group *g, int n_up, HostTables &T);
+ed_status check_stable(const HostTables &T, int n_sub);
+void build_rep_sym(const HostTables &T, int n_sub, std::vector<uint16_t> &rep, std::vector<uint32_t> &sym_off,
+                   std::vector<uint32_t> &sym_list);
+void build_pairs(const ed_model *m, HostTables &T);
+std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &lay);
+int choose_sublattices(const HostTables &T, int &R, int &A, std::string &why);
+
+}  // namespace symed

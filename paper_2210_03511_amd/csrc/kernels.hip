@@ -1,0 +1,797 @@
+// Device code of the symed library (gfx950 / CDNA4, wave64).
+//
+// The hot path is a gather-form matrix-free H.v in a symmetry-adapted basis
+// (thesis chapter on large-scale exact diagonalization):
+//   row i (one lane) -> every non-branching piece on its representative ->
+//   sublattice-coded representative search with the lookup tables staged in
+//   LDS -> index lookup -> accumulate character x norm ratio x amplitude x x_j.
+// Each output entry is written by exactly one lane: no atomics, results are
+// independent of scheduling.
+#include <hip/hip_runtime.h>
+
+#include "launch.h"
+
+namespace symed {
+
+namespace {
+
+constexpr int kApplyThreads = 512;
+constexpr int kVecThreads = 256;
+
+struct Lds {
+    const uint16_t *rep;
+    const uint32_t *symoff;
+    const uint32_t *symlist;
+    const uint8_t *act;
+    const uint64_t *src;
+    const PairTerm *pairs;
+    const ChiTerm *chis;
+    const double *chi;
+    const double *sqrtt;
+    const double *isqrtt;
+    const uint8_t *chione;
+};
+
+__device__ __forceinline__ Lds lds_view(const unsigned char *b, const BlobLayout &L)
+{
+    Lds v;
+    v.rep = reinterpret_cast<const uint16_t *>(b + L.off_rep);
+    v.symoff = reinterpret_cast<const uint32_t *>(b + L.off_symoff);
+    v.symlist = reinterpret_cast<const uint32_t *>(b + L.off_symlist);
+    v.act = b + L.off_act;
+    v.src = reinterpret_cast<const uint64_t *>(b + L.off_src);
+    v.pairs = reinterpret_cast<const PairTerm *>(b + L.off_pairs);
+    v.chis = reinterpret_cast<const ChiTerm *>(b + L.off_chis);
+    v.chi = reinterpret_cast<const double *>(b + L.off_chi);
+    v.sqrtt = reinterpret_cast<const double *>(b + L.off_sqrt);
+    v.isqrtt = reinterpret_cast<const double *>(b + L.off_isqrt);
+    v.chione = b + L.off_chione;
+    return v;
+}
+
+// Copy the table blob (multiple of 16 bytes) into LDS.
+__device__ __forceinline__ void stage_blob(unsigned char *lds, const void *blob, uint32_t bytes)
+{
+    const uint4 *s = reinterpret_cast<const uint4 *>(blob);
+    uint4 *d = reinterpret_cast<uint4 *>(lds);
+    for (uint32_t k = threadIdx.x; k < bytes / 16u; k += blockDim.x) d[k] = s[k];
+    __syncthreads();
+}
+
+struct Found {
+    uint64_t rep;
+    uint32_t g;
+    uint32_t cnt;  // number of group elements reaching the representative = |Stab|
+};
+
+// Representative of t by sublattice coding (algorithm "Sublattice coding
+// algorithm for finding the representative"): MinRep over the coarse
+// sublattices, then every symmetry in Sym_Y of each sublattice Y attaining
+// MinRep is applied through the SymmetryAction tables of the fine
+// decomposition (destination-major, so the image is assembled most
+// significant sublattice first).  All minimizers lie among these candidates
+// and each group element is a candidate at most once, so the number of
+// candidates reaching the minimum is the stabilizer size.
+__device__ __forceinline__ Found find_rep(uint64_t t, const KParams &p, const Lds &L)
+{
+    const int N = p.N, R = p.R, br = p.br, A = p.A, ba = p.ba;
+    const uint32_t S = 1u << br, mr = S - 1u, ma = (1u << ba) - 1u;
+    uint32_t minrep = 0xffffffffu;
+    for (int X = 0; X < R; ++X) {
+        uint32_t s = (uint32_t)(t >> (N - (X + 1) * br)) & mr;
+        minrep = min(minrep, (uint32_t)L.rep[X * S + s]);
+    }
+    uint64_t best = ~0ull;
+    uint32_t bg = 0, cnt = 0;
+    for (int X = 0; X < R; ++X) {
+        uint32_t s = (uint32_t)(t >> (N - (X + 1) * br)) & mr;
+        uint32_t idx = X * S + s;
+        if (L.rep[idx] != minrep) continue;
+        const uint32_t k1 = L.symoff[idx + 1];
+        for (uint32_t k = L.symoff[idx]; k < k1; ++k) {
+            const uint32_t e = L.symlist[k];
+            const uint32_t sp = (e >> 1) & 0x7fffu;
+            const uint64_t srcw = L.src[sp];
+            const uint8_t *a = L.act + (size_t)sp * ((uint32_t)A << ba);
+            uint64_t v = 0;
+            for (int d = 0; d < A; ++d) {
+                const uint32_t x = (uint32_t)(srcw >> (4 * d)) & 15u;
+                const uint32_t ss = (uint32_t)(t >> (N - (int)(x + 1) * ba)) & ma;
+                v = (v << ba) | a[(d << ba) + ss];
+            }
+            if (e & 1u) v ^= p.maskN;
+            if (v < best) {
+                best = v;
+                bg = e >> 16;
+                cnt = 1;
+            } else if (v == best) {
+                ++cnt;
+            }
+        }
+    }
+    return Found{best, bg, cnt};
+}
+
+// Plain index lookup: Limits(prefix) = [begin, end) then binary search
+// (thesis: "Basis" array plus "Limits" prefix map, section on distributed
+// memory parallelization).  -1 if absent.
+__device__ __forceinline__ int64_t lookup_plain(uint64_t key, const KParams &p)
+{
+    const uint64_t pf = key >> (p.N - p.pbits);
+    uint32_t lo = p.limits[pf], hi = p.limits[pf + 1];
+    const uint32_t end = hi;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (p.reps[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return (lo < end && p.reps[lo] == key) ? (int64_t)lo : -1;
+}
+
+__device__ __forceinline__ int64_t lookup(uint64_t key, const KParams &p, int mode)
+{
+    return lookup_plain(key, p);
+}
+
+// Amplitude <tau|H_pair|sigma> of the merged pieces flipping pair q of s
+// (s antiparallel on the pair).  Real part: exchange J/2; imaginary part:
+// chirality edges.
+template <bool CPLX>
+__device__ __forceinline__ void pair_amp(uint64_t s, const PairTerm &pt, const Lds &L, double &hre, double &him)
+{
+    hre = 0.5 * pt.Jsum;
+    him = 0.0;
+    if (CPLX) {
+        for (int c = pt.chi_begin; c < pt.chi_end; ++c) {
+            const ChiTerm ct = L.chis[c];
+            him += (s & ct.site_bit) ? ct.c : -ct.c;
+        }
+        if (s & pt.lo_bit) him = -him;
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Deterministic block sum: waves reduce by shuffles, wave results combined in
+// a fixed order by thread 0.  `scratch` holds one double per wave.
+__device__ __forceinline__ double block_sum(double v, double *scratch)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) scratch[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += scratch[k];
+    return t;
+}
+
+// mode 0: y = H x.  mode 1 (real Lanczos): w <- H v - beta_prev w, partial
+// <w|v>.  mode 2 (complex Lanczos): w <- H v, partial Re<w|v>.
+template <bool CPLX, int MODE>
+__global__ void __launch_bounds__(kApplyThreads) k_apply(KParams p, const double *__restrict__ x,
+                                                       double *__restrict__ y, const LState *ls,
+                                                       double *partials)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    stage_blob(lds, p.blob, p.lay.bytes);
+    const Lds L = lds_view(lds, p.lay);
+    double *scratch = reinterpret_cast<double *>(lds + p.lay.bytes);
+    const double beta = (MODE == 1) ? ls->beta_prev : 0.0;
+    double part = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.dim; i += stride) {
+        const uint64_t s = p.reps[i];
+        const double isq = L.isqrtt[p.stab[i]];
+        double diag = 0.0, ar = 0.0, ai = 0.0;
+        for (int q = 0; q < p.n_pairs; ++q) {
+            const PairTerm pt = L.pairs[q];
+            const bool anti = __popcll(s & pt.mask) == 1;
+            diag += anti ? -0.25 * pt.Jsum : 0.25 * pt.Jsum;
+            if (!anti) continue;
+            double hre, him;
+            pair_amp<CPLX>(s, pt, L, hre, him);
+            if (hre == 0.0 && him == 0.0) continue;
+            const Found f = find_rep(s ^ pt.mask, p, L);
+            const int64_t j = lookup(f.rep, p, 0);
+            if (j < 0) continue;
+            const double w = L.sqrtt[f.cnt];
+            if (!CPLX) {
+                ar += L.chi[f.g] * w * hre * x[j];
+            } else {
+                // chi(g) * w * conj(h) * x_j
+                const double cr = L.chi[2 * f.g] * w, ci = L.chi[2 * f.g + 1] * w;
+                const double kr = cr * hre + ci * him, ki = ci * hre - cr * him;
+                const double xr = x[2 * j], xi = x[2 * j + 1];
+                ar += kr * xr - ki * xi;
+                ai += kr * xi + ki * xr;
+            }
+        }
+        if (!CPLX) {
+            const double xi = x[i];
+            double yi = diag * xi + isq * ar;
+            if (MODE == 1) {
+                yi -= beta * y[i];
+                part += yi * xi;
+            }
+            y[i] = yi;
+        } else {
+            const double xr = x[2 * i], xim = x[2 * i + 1];
+            const double yr = diag * xr + isq * ar, yim = diag * xim + isq * ai;
+            if (MODE == 2) part += yr * xr + yim * xim;
+            y[2 * i] = yr;
+            y[2 * i + 1] = yim;
+        }
+    }
+    if (MODE != 0) {
+        const double t = block_sum(part, scratch);
+        if (threadIdx.x == 0) partials[blockIdx.x] = t;
+    }
+}
+
+// Per-row element count: the diagonal plus every antiparallel pair with a
+// non-zero merged amplitude.
+template <bool CPLX>
+__global__ void __launch_bounds__(256) k_count(KParams p, unsigned long long *out)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    stage_blob(lds, p.blob, p.lay.bytes);
+    const Lds L = lds_view(lds, p.lay);
+    unsigned long long c = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.dim; i += stride) {
+        const uint64_t s = p.reps[i];
+        c += 1;
+        for (int q = 0; q < p.n_pairs; ++q) {
+            const PairTerm pt = L.pairs[q];
+            if (__popcll(s & pt.mask) != 1) continue;
+            double hre, him;
+            pair_amp<CPLX>(s, pt, L, hre, him);
+            if (hre != 0.0 || him != 0.0) ++c;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(out, c);
+}
+
+__global__ void __launch_bounds__(256) k_lookup(KParams p, const uint64_t *keys, int64_t n, int64_t *idx, int mode)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        const uint64_t key = keys[k];
+        // keys outside the N-bit range cannot be representatives
+        idx[k] = (key & ~p.maskN) ? -1 : lookup(key, p, mode);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// basis enumeration
+// ---------------------------------------------------------------------------
+
+// k-th (0-based) N-bit integer with `ones` set bits, ascending order
+__device__ uint64_t unrank(int n, int ones, uint64_t r, const uint64_t *binom)
+{
+    uint64_t s = 0;
+    for (int pos = n - 1; pos >= 0 && ones > 0; --pos) {
+        const uint64_t c = binom[pos * 64 + ones];  // integers with bit pos clear
+        if (r >= c) {
+            s |= 1ull << pos;
+            r -= c;
+            --ones;
+        }
+    }
+    return s;
+}
+
+constexpr uint64_t kInf = ~0ull;
+
+// smallest v >= t with popcount(v) == k and v < 2^N, else kInf
+__device__ __forceinline__ uint64_t next_with_popcount(uint64_t t, int k, int N)
+{
+    for (;;) {
+        if (t >> N) return kInf;
+        const int c = __popcll(t);
+        if (c == k) return t;
+        if (c < k) {
+            for (int q = 0; q < k - c; ++q) t |= t + 1;  // set the lowest zero bit
+            return (t >> N) ? kInf : t;
+        }
+        t += t & (~t + 1);  // clear the lowest run of ones, carry
+    }
+}
+
+// Chunk c covers ranks [c*len, (c+1)*len) of the Sz sector in ascending
+// order.  A configuration is kept iff it is its own representative and chi
+// is trivial on its stabilizer (algorithm "Preparation of the distributed
+// and symmetrized Hilbert space", on one device).  Prefix pruning: the
+// identity is in G_0, so a representative has Rep_0(s_0) = s_0 and
+// Rep_X(s_X) >= s_0 for every coarse sublattice X; a failed test on X
+// rejects every configuration sharing sublattices 0..X, which are skipped.
+template <bool WRITE>
+__global__ void __launch_bounds__(256) k_enumerate(KParams p, const uint64_t *binom, uint64_t total, uint64_t len,
+                                                 uint64_t n_chunks, uint32_t *counts, const uint64_t *offsets,
+                                                 uint64_t *out_reps, uint16_t *out_stab)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    stage_blob(lds, p.blob, p.lay.bytes);
+    const Lds L = lds_view(lds, p.lay);
+    const int N = p.N, R = p.R, br = p.br, A = p.A, ba = p.ba;
+    const uint32_t S = 1u << br, mr = S - 1u, ma = (1u << ba) - 1u;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_chunks; c += stride) {
+        const uint64_t r0 = c * len;
+        const uint64_t r1 = min(total, r0 + len);
+        uint64_t s = unrank(N, p.n_up, r0, binom);
+        const uint64_t send = (r1 < total) ? unrank(N, p.n_up, r1, binom) : kInf;
+        uint64_t k = WRITE ? offsets[c] : 0;
+        uint32_t found = 0;
+        while (s < send) {
+            const uint32_t s0 = (uint32_t)(s >> (N - br)) & mr;
+            int bad = -1;
+            if (L.rep[s0] != s0) {
+                bad = 0;
+            } else {
+                for (int X = 1; X < R; ++X) {
+                    const uint32_t sx = (uint32_t)(s >> (N - (X + 1) * br)) & mr;
+                    if (L.rep[X * S + sx] < s0) {
+                        bad = X;
+                        break;
+                    }
+                }
+            }
+            if (bad >= 0) {
+                const int sh = N - (bad + 1) * br;
+                s = next_with_popcount(((s >> sh) + 1) << sh, p.n_up, N);
+                continue;
+            }
+            bool isrep = true, triv = true;
+            uint32_t stab = 0;
+            for (int Y = 0; Y < R && isrep; ++Y) {
+                const uint32_t sy = (uint32_t)(s >> (N - (Y + 1) * br)) & mr;
+                const uint32_t idx = Y * S + sy;
+                if (L.rep[idx] != s0) continue;
+                const uint32_t k1 = L.symoff[idx + 1];
+                for (uint32_t q = L.symoff[idx]; q < k1; ++q) {
+                    const uint32_t e = L.symlist[q];
+                    const uint32_t sp = (e >> 1) & 0x7fffu;
+                    const uint64_t srcw = L.src[sp];
+                    const uint8_t *a = L.act + (size_t)sp * ((uint32_t)A << ba);
+                    uint64_t v = 0;
+                    for (int d = 0; d < A; ++d) {
+                        const uint32_t x = (uint32_t)(srcw >> (4 * d)) & 15u;
+                        const uint32_t ss = (uint32_t)(s >> (N - (int)(x + 1) * ba)) & ma;
+                        v = (v << ba) | a[(d << ba) + ss];
+                    }
+                    if (e & 1u) v ^= p.maskN;
+                    if (v < s) {
+                        isrep = false;
+                        break;
+                    }
+                    if (v == s) {
+                        ++stab;
+                        if (!L.chione[e >> 16]) triv = false;
+                    }
+                }
+            }
+            if (isrep && triv) {
+                if (WRITE) {
+                    out_reps[k] = s;
+                    out_stab[k] = (uint16_t)stab;
+                    ++k;
+                } else {
+                    ++found;
+                }
+            }
+            // next configuration with the same number of up spins
+            if (s == 0) break;
+            const uint64_t tt = s | (s - 1);
+            const uint64_t nx = (tt + 1) | (((~tt & (tt + 1)) - 1) >> (__builtin_ctzll(s) + 1));
+            if ((nx >> N) || nx <= s) break;
+            s = nx;
+        }
+        if (!WRITE) counts[c] = found;
+    }
+}
+
+// exclusive scan of u32 counts into u64 offsets, 4096 elements per block
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 4;
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_block(const uint32_t *in, uint64_t *out, uint64_t n,
+                                                           uint64_t *block_sums)
+{
+    __shared__ uint64_t sh[kScanThreads];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanThreads * kScanPer + (uint64_t)threadIdx.x * kScanPer;
+    uint64_t v[kScanPer];
+    uint64_t tsum = 0;
+    for (int q = 0; q < kScanPer; ++q) {
+        v[q] = (base + q < n) ? in[base + q] : 0;
+        tsum += v[q];
+    }
+    sh[threadIdx.x] = tsum;
+    __syncthreads();
+    for (int o = 1; o < kScanThreads; o <<= 1) {
+        uint64_t t = (threadIdx.x >= (unsigned)o) ? sh[threadIdx.x - o] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    uint64_t run = sh[threadIdx.x] - tsum;  // exclusive prefix of this thread
+    for (int q = 0; q < kScanPer; ++q) {
+        if (base + q < n) out[base + q] = run;
+        run += v[q];
+    }
+    if (threadIdx.x == kScanThreads - 1) block_sums[blockIdx.x] = sh[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_u64_block(const uint64_t *in, uint64_t *out, uint64_t n,
+                                                               uint64_t *block_sums)
+{
+    __shared__ uint64_t sh[kScanThreads];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanThreads * kScanPer + (uint64_t)threadIdx.x * kScanPer;
+    uint64_t v[kScanPer];
+    uint64_t tsum = 0;
+    for (int q = 0; q < kScanPer; ++q) {
+        v[q] = (base + q < n) ? in[base + q] : 0;
+        tsum += v[q];
+    }
+    sh[threadIdx.x] = tsum;
+    __syncthreads();
+    for (int o = 1; o < kScanThreads; o <<= 1) {
+        uint64_t t = (threadIdx.x >= (unsigned)o) ? sh[threadIdx.x - o] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    uint64_t run = sh[threadIdx.x] - tsum;
+    for (int q = 0; q < kScanPer; ++q) {
+        if (base + q < n) out[base + q] = run;
+        run += v[q];
+    }
+    if (threadIdx.x == kScanThreads - 1) block_sums[blockIdx.x] = sh[threadIdx.x];
+}
+
+__global__ void k_add_offsets(uint64_t *out, uint64_t n, const uint64_t *block_off)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += block_off[i / (kScanThreads * kScanPer)];
+}
+
+__global__ void k_limits(const uint64_t *reps, int64_t dim, int N, int pbits, uint32_t *limits)
+{
+    const uint64_t np = 1ull << pbits;
+    const uint64_t pf = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pf > np) return;
+    if (pf == np) {
+        limits[pf] = (uint32_t)dim;
+        return;
+    }
+    const uint64_t key = pf << (N - pbits);
+    int64_t lo = 0, hi = dim;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (reps[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    limits[pf] = (uint32_t)lo;
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos vector kernels (deterministic: fixed grid, fixed reduction order)
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kVecThreads) k_norm2(const double *v, int64_t n2, double *partials)
+{
+    __shared__ double scratch[kVecThreads / 64];
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) acc += v[i] * v[i];
+    const double t = block_sum(acc, scratch);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__device__ __forceinline__ double sum_partials(const double *partials, int nparts)
+{
+    double t = 0.0;
+    for (int k = 0; k < nparts; ++k) t += partials[k];
+    return t;
+}
+
+__global__ void __launch_bounds__(kVecThreads) k_scale_copy(const double *src, double *dst, int64_t n2,
+                                                          const double *partials, int nparts)
+{
+    __shared__ double inv;
+    if (threadIdx.x == 0) inv = 1.0 / sqrt(sum_partials(partials, nparts));
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) dst[i] = src[i] * inv;
+}
+
+// which = 0: alpha[step] = sum; which = 1: beta[step] = sqrt(sum), breakdown check
+__global__ void k_finalize(const double *partials, int nparts, double *alpha, double *beta, LState *ls, int which)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double t = sum_partials(partials, nparts);
+    const int st = ls->step;
+    if (which == 0) {
+        alpha[st] = t;
+        ls->max_abs_alpha = fmax(ls->max_abs_alpha, fabs(t));
+    } else {
+        const double b = sqrt(fmax(t, 0.0));
+        beta[st] = b;
+        if (ls->broken_step < 0 && !(b >= 1e-14 * fmax(1.0, ls->max_abs_alpha))) ls->broken_step = st;
+    }
+}
+
+// real: w <- w - alpha v ; complex: w <- w - alpha v - beta_prev vprev ; partial |w|^2
+template <bool CPLX>
+__global__ void __launch_bounds__(kVecThreads) k_axpy_norm(double *w, const double *v, const double *vprev,
+                                                         int64_t n2, const double *alpha, const LState *ls,
+                                                         double *partials)
+{
+    __shared__ double scratch[kVecThreads / 64];
+    const double a = alpha[ls->step];
+    const double b = ls->beta_prev;
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
+        double t = w[i] - a * v[i];
+        if (CPLX) t -= b * vprev[i];
+        w[i] = t;
+        acc += t * t;
+    }
+    const double t = block_sum(acc, scratch);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// real: (v, w) <- (w / beta, v) ; complex: vprev <- v, v <- w / beta
+template <bool CPLX>
+__global__ void __launch_bounds__(kVecThreads) k_rotate(double *v, double *w, double *vprev, int64_t n2,
+                                                      const double *beta, const LState *ls)
+{
+    const int st = ls->step;
+    const bool broken = ls->broken_step >= 0;
+    const double inv = broken ? 0.0 : 1.0 / beta[st];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
+        const double vi = v[i];
+        v[i] = w[i] * inv;
+        if (CPLX) vprev[i] = vi; else w[i] = vi;
+    }
+}
+
+__global__ void k_step_inc(LState *ls, const double *beta)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ls->beta_prev = (ls->broken_step >= 0) ? 0.0 : beta[ls->step];
+        ls->step += 1;
+    }
+}
+
+__global__ void __launch_bounds__(kVecThreads) k_fill(double *v, int64_t n, double val)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) v[i] = val;
+}
+
+__global__ void k_lstate_init(LState *ls)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ls->step = 0;
+        ls->broken_step = -1;
+        ls->beta_prev = 0.0;
+        ls->max_abs_alpha = 0.0;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+size_t apply_lds_bytes(const KParams &p) { return (size_t)p.lay.bytes + 16 * sizeof(double); }
+
+hipError_t launch_enumerate(const KParams &p, const uint64_t *d_binom, uint64_t total, uint64_t chunk_len,
+                            uint64_t n_chunks, uint32_t *d_counts, const uint64_t *d_offsets, uint64_t *d_reps,
+                            uint16_t *d_stab, bool write, int blocks, hipStream_t st)
+{
+    const size_t lds = p.lay.bytes;
+    if (write)
+        hipLaunchKernelGGL(k_enumerate<true>, dim3(blocks), dim3(256), lds, st, p, d_binom, total, chunk_len,
+                           n_chunks, d_counts, d_offsets, d_reps, d_stab);
+    else
+        hipLaunchKernelGGL(k_enumerate<false>, dim3(blocks), dim3(256), lds, st, p, d_binom, total, chunk_len,
+                           n_chunks, d_counts, d_offsets, d_reps, d_stab);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const uint32_t *d_in, uint64_t *d_out, uint64_t n, uint64_t *d_total, hipStream_t st)
+{
+    // level 0: counts -> offsets within blocks, block sums
+    const uint64_t per = (uint64_t)kScanThreads * kScanPer;
+    uint64_t nb = (n + per - 1) / per;
+    if (nb == 0) nb = 1;
+    uint64_t *sums = nullptr, *sums_off = nullptr;
+    hipError_t e = hipMalloc((void **)&sums, (nb + 1) * sizeof(uint64_t));
+    if (e != hipSuccess) return e;
+    e = hipMalloc((void **)&sums_off, (nb + 1) * sizeof(uint64_t));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(kScanThreads), 0, st, d_in, d_out, n, sums);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (nb > 1) {
+        e = launch_scan_u64(sums, sums_off, nb, d_total, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_add_offsets, dim3((n + 255) / 256), dim3(256), 0, st, d_out, n, sums_off);
+    } else {
+        // single block: total = sums[0]
+        e = hipMemcpyAsync(d_total, sums, sizeof(uint64_t), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+    }
+    e = hipStreamSynchronize(st);
+    hipFree(sums);
+    hipFree(sums_off);
+    return e;
+}
+
+hipError_t launch_scan_u64(const uint64_t *d_in, uint64_t *d_out, uint64_t n, uint64_t *d_total, hipStream_t st)
+{
+    const uint64_t per = (uint64_t)kScanThreads * kScanPer;
+    uint64_t nb = (n + per - 1) / per;
+    if (nb == 0) nb = 1;
+    uint64_t *sums = nullptr, *sums_off = nullptr;
+    hipError_t e = hipMalloc((void **)&sums, (nb + 1) * sizeof(uint64_t));
+    if (e != hipSuccess) return e;
+    e = hipMalloc((void **)&sums_off, (nb + 1) * sizeof(uint64_t));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_u64_block, dim3(nb), dim3(kScanThreads), 0, st, d_in, d_out, n, sums);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (nb > 1) {
+        e = launch_scan_u64(sums, sums_off, nb, d_total, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_add_offsets, dim3((n + 255) / 256), dim3(256), 0, st, d_out, n, sums_off);
+    } else {
+        e = hipMemcpyAsync(d_total, sums, sizeof(uint64_t), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+    }
+    e = hipStreamSynchronize(st);
+    hipFree(sums);
+    hipFree(sums_off);
+    return e;
+}
+
+hipError_t launch_limits(const uint64_t *d_reps, int64_t dim, int N, int pbits, uint32_t *d_limits, hipStream_t st)
+{
+    const uint64_t n = (1ull << pbits) + 1;
+    hipLaunchKernelGGL(k_limits, dim3((n + 255) / 256), dim3(256), 0, st, d_reps, dim, N, pbits, d_limits);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_elements(const KParams &p, unsigned long long *d_count, int blocks, hipStream_t st)
+{
+    if (p.is_complex)
+        hipLaunchKernelGGL(k_count<true>, dim3(blocks), dim3(256), p.lay.bytes, st, p, d_count);
+    else
+        hipLaunchKernelGGL(k_count<false>, dim3(blocks), dim3(256), p.lay.bytes, st, p, d_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply(const KParams &p, const LaunchCfg &c, const void *x, void *y, int mode, const LState *ls,
+                        double *partials, hipStream_t st)
+{
+    const size_t lds = apply_lds_bytes(p);
+    const double *xd = static_cast<const double *>(x);
+    double *yd = static_cast<double *>(y);
+    dim3 g(c.apply_blocks), b(kApplyThreads);
+    if (!p.is_complex) {
+        if (mode == 0) hipLaunchKernelGGL((k_apply<false, 0>), g, b, lds, st, p, xd, yd, ls, partials);
+        else hipLaunchKernelGGL((k_apply<false, 1>), g, b, lds, st, p, xd, yd, ls, partials);
+    } else {
+        if (mode == 0) hipLaunchKernelGGL((k_apply<true, 0>), g, b, lds, st, p, xd, yd, ls, partials);
+        else hipLaunchKernelGGL((k_apply<true, 2>), g, b, lds, st, p, xd, yd, ls, partials);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_lookup(const KParams &p, const uint64_t *keys, int64_t n, int64_t *idx, int mode, hipStream_t st)
+{
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_lookup, dim3((unsigned)blocks), dim3(256), 0, st, p, keys, n, idx, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm2_partial(const void *v, int64_t n, bool cplx, double *partials, int blocks, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_norm2, dim3(blocks), dim3(kVecThreads), 0, st, static_cast<const double *>(v),
+                       cplx ? 2 * n : n, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_copy(const void *src, void *dst, int64_t n, bool cplx, const double *partials, int nparts,
+                             int blocks, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scale_copy, dim3(blocks), dim3(kVecThreads), 0, st, static_cast<const double *>(src),
+                       static_cast<double *>(dst), cplx ? 2 * n : n, partials, nparts);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double *partials, int nparts, double *alpha, double *beta, LState *ls, int which,
+                           hipStream_t st)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, partials, nparts, alpha, beta, ls, which);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_norm(void *w, const void *v, const void *vprev, int64_t n, bool cplx, const double *alpha,
+                            const LState *ls, double *partials, int blocks, hipStream_t st)
+{
+    if (cplx)
+        hipLaunchKernelGGL(k_axpy_norm<true>, dim3(blocks), dim3(kVecThreads), 0, st, static_cast<double *>(w),
+                           static_cast<const double *>(v), static_cast<const double *>(vprev), 2 * n, alpha, ls,
+                           partials);
+    else
+        hipLaunchKernelGGL(k_axpy_norm<false>, dim3(blocks), dim3(kVecThreads), 0, st, static_cast<double *>(w),
+                           static_cast<const double *>(v), static_cast<const double *>(vprev), n, alpha, ls,
+                           partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_rotate(void *v, void *w, void *vprev, int64_t n, bool cplx, const double *beta, const LState *ls,
+                         int blocks, hipStream_t st)
+{
+    if (cplx)
+        hipLaunchKernelGGL(k_rotate<true>, dim3(blocks), dim3(kVecThreads), 0, st, static_cast<double *>(v),
+                           static_cast<double *>(w), static_cast<double *>(vprev), 2 * n, beta, ls);
+    else
+        hipLaunchKernelGGL(k_rotate<false>, dim3(blocks), dim3(kVecThreads), 0, st, static_cast<double *>(v),
+                           static_cast<double *>(w), static_cast<double *>(vprev), n, beta, ls);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_inc(LState *ls, const double *beta, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, st, ls, beta);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double *v, int64_t n, double val, int blocks, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(kVecThreads), 0, st, v, n, val);
+    return hipGetLastError();
+}
+
+// Allow the dynamic LDS the table blob needs and report how many apply blocks
+// fit on one compute unit.
+hipError_t prepare_kernels(const KParams &p, int *apply_blocks_per_cu, int *apply_threads)
+{
+    const size_t lds = apply_lds_bytes(p);
+    hipError_t e;
+    const void *ks[] = {(const void *)k_apply<false, 0>, (const void *)k_apply<false, 1>,
+                        (const void *)k_apply<true, 0>, (const void *)k_apply<true, 2>,
+                        (const void *)k_count<false>, (const void *)k_count<true>,
+                        (const void *)k_enumerate<false>, (const void *)k_enumerate<true>};
+    for (const void *k : ks) {
+        e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    int nb = 0;
+    const void *ka = p.is_complex ? (const void *)k_apply<true, 0> : (const void *)k_apply<false, 0>;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ka, kApplyThreads, lds);
+    if (e != hipSuccess) return e;
+    *apply_blocks_per_cu = nb;
+    *apply_threads = kApplyThreads;
+    return hipSuccess;
+}
+
+hipError_t launch_lstate_init(LState *ls, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lstate_init, dim3(1), dim3(64), 0, st, ls);
+    return hipGetLastError();
+}
+
+}  // namespace symed

@@ -1,0 +1,415 @@
+// Host side of the symed library: input validation and the lookup tables of
+// the sublattice coding technique (thesis, section "Sublattice coding
+// techniques": definitions of sublattice stability, G_X, Rep_X, Sym_X and
+// SymmetryAction_X; algorithm "Preparation of lookup tables").
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <unordered_map>
+
+#include "internal.h"
+
+namespace symed {
+
+namespace {
+
+struct VecHash {
+    size_t operator()(const std::vector<int32_t> &v) const {
+        size_t h = 1469598103934665603ull;
+        for (int32_t x : v) h = (h ^ (uint32_t)x) * 1099511628211ull;
+        return h;
+    }
+};
+
+inline bool bit_of(uint64_t s, int n, int site) { return (s >> (n - 1 - site)) & 1u; }
+
+}  // namespace
+
+ed_status validate_and_copy_group(const ed_model *m, const ed_group *grp, int n_up, HostTables &T)
+{
+    if (!m || !grp) return fail(ED_EINVAL, "model and group must not be NULL");
+    const int N = m->n_sites;
+    if (N < 1 || N > kMaxSites) return fail(ED_EINVAL, "n_sites must be in [1, 63]");
+    if (n_up < 0 || n_up > N) return fail(ED_EINVAL, "n_up must be in [0, n_sites]");
+    const int G = grp->n_elem;
+    if (G < 1 || G > 65535) return fail(ED_EINVAL, "group order must be in [1, 65535]");
+    if (!grp->perm || !grp->flip || !grp->chi_re) return fail(ED_EINVAL, "group arrays must not be NULL");
+    if (m->n_bonds < 0 || m->n_tri < 0) return fail(ED_EINVAL, "negative term count");
+    if (m->n_bonds > 0 && (!m->bond_sites || !m->bond_J)) return fail(ED_EINVAL, "bond arrays NULL");
+    if (m->n_tri > 0 && (!m->tri_sites || !m->tri_Jchi)) return fail(ED_EINVAL, "triangle arrays NULL");
+    for (int b = 0; b < m->n_bonds; ++b) {
+        int i = m->bond_sites[2 * b], j = m->bond_sites[2 * b + 1];
+        if (i < 0 || i >= N || j < 0 || j >= N || i == j) return fail(ED_EINVAL, "bad bond " + std::to_string(b));
+        if (!std::isfinite(m->bond_J[b])) return fail(ED_EINVAL, "non-finite bond coupling");
+    }
+    for (int t = 0; t < m->n_tri; ++t) {
+        const int32_t *v = m->tri_sites + 3 * t;
+        for (int q = 0; q < 3; ++q)
+            if (v[q] < 0 || v[q] >= N) return fail(ED_EINVAL, "bad triangle " + std::to_string(t));
+        if (v[0] == v[1] || v[1] == v[2] || v[0] == v[2]) return fail(ED_EINVAL, "degenerate triangle");
+        if (!std::isfinite(m->tri_Jchi[t])) return fail(ED_EINVAL, "non-finite chirality coupling");
+    }
+
+    T = HostTables();
+    T.N = N;
+    T.n_up = n_up;
+    T.G = G;
+    T.sp_of.resize(G);
+    T.flip.resize(G);
+    T.chi_re.resize(G);
+    T.chi_im.resize(G);
+    T.chi_one.resize(G);
+
+    std::unordered_map<std::vector<int32_t>, int, VecHash> sp_index;
+    std::vector<int32_t> perm(N);
+    for (int g = 0; g < G; ++g) {
+        std::vector<uint8_t> seen(N, 0);
+        for (int i = 0; i < N; ++i) {
+            int32_t j = grp->perm[(size_t)g * N + i];
+            if (j < 0 || j >= N || seen[j]) return fail(ED_EINVAL, "group element " + std::to_string(g) + " is not a permutation");
+            seen[j] = 1;
+            perm[i] = j;
+        }
+        auto it = sp_index.find(perm);
+        int sp;
+        if (it == sp_index.end()) {
+            sp = T.n_sp++;
+            sp_index.emplace(perm, sp);
+            T.sp_perm.insert(T.sp_perm.end(), perm.begin(), perm.end());
+        } else {
+            sp = it->second;
+        }
+        T.sp_of[g] = sp;
+        T.flip[g] = grp->flip[g] ? 1 : 0;
+        T.chi_re[g] = grp->chi_re[g];
+        T.chi_im[g] = grp->chi_im ? grp->chi_im[g] : 0.0;
+        double mod = std::hypot(T.chi_re[g], T.chi_im[g]);
+        if (!(std::fabs(mod - 1.0) < 1e-9)) return fail(ED_ECHAR, "|chi| != 1 at element " + std::to_string(g));
+        T.chi_one[g] = std::hypot(T.chi_re[g] - 1.0, T.chi_im[g]) < 1e-6 ? 1 : 0;
+        if (T.flip[g]) T.has_flip = true;
+    }
+    if (T.has_flip && 2 * n_up != N) return fail(ED_EINVAL, "spin flip requires n_up == n_sites/2");
+    if (T.n_sp > 32767) return fail(ED_EINVAL, "too many distinct permutations");
+
+    // closure and multiplicativity: (g h) = perm_g o perm_h, flip_g ^ flip_h
+    std::unordered_map<long long, int> elem;   // key: sp * 2 + flip
+    for (int g = 0; g < G; ++g) {
+        long long key = (long long)T.sp_of[g] * 2 + T.flip[g];
+        if (elem.count(key)) return fail(ED_EINVAL, "duplicate group element " + std::to_string(g));
+        elem[key] = g;
+    }
+    std::vector<int32_t> comp(N);
+    for (int a = 0; a < G; ++a) {
+        const int32_t *pa = &T.sp_perm[(size_t)T.sp_of[a] * N];
+        for (int b = 0; b < G; ++b) {
+            const int32_t *pb = &T.sp_perm[(size_t)T.sp_of[b] * N];
+            for (int i = 0; i < N; ++i) comp[i] = pa[pb[i]];
+            auto it = sp_index.find(comp);
+            if (it == sp_index.end()) return fail(ED_EINVAL, "group not closed under composition");
+            auto e = elem.find((long long)it->second * 2 + (T.flip[a] ^ T.flip[b]));
+            if (e == elem.end()) return fail(ED_EINVAL, "group not closed under composition");
+            int c = e->second;
+            double re = T.chi_re[a] * T.chi_re[b] - T.chi_im[a] * T.chi_im[b];
+            double im = T.chi_re[a] * T.chi_im[b] + T.chi_im[a] * T.chi_re[b];
+            if (std::hypot(re - T.chi_re[c], im - T.chi_im[c]) > 1e-9)
+                return fail(ED_ECHAR, "characters are not multiplicative");
+        }
+    }
+
+    // invariance of H: bonds (unordered pairs with summed J) and oriented
+    // triangles (sorted triple with sign of the orientation) map to themselves
+    std::map<std::pair<int, int>, double> bonds;
+    for (int b = 0; b < m->n_bonds; ++b) {
+        int i = m->bond_sites[2 * b], j = m->bond_sites[2 * b + 1];
+        bonds[{std::min(i, j), std::max(i, j)}] += m->bond_J[b];
+    }
+    auto canon_tri = [](int i, int j, int k, double J, std::map<std::array<int, 3>, double> &out) {
+        std::array<int, 3> v{i, j, k};
+        int sign = 1;
+        // bubble sort counting transpositions
+        for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 2 - p; ++q)
+                if (v[q] > v[q + 1]) { std::swap(v[q], v[q + 1]); sign = -sign; }
+        out[v] += sign * J;
+    };
+    std::map<std::array<int, 3>, double> tris;
+    for (int t = 0; t < m->n_tri; ++t) {
+        const int32_t *v = m->tri_sites + 3 * t;
+        canon_tri(v[0], v[1], v[2], m->tri_Jchi[t], tris);
+    }
+    for (int sp = 0; sp < T.n_sp; ++sp) {
+        const int32_t *p = &T.sp_perm[(size_t)sp * N];
+        std::map<std::pair<int, int>, double> img;
+        for (auto &kv : bonds) {
+            int i = p[kv.first.first], j = p[kv.first.second];
+            img[{std::min(i, j), std::max(i, j)}] += kv.second;
+        }
+        for (auto &kv : bonds) {
+            auto it = img.find(kv.first);
+            if (it == img.end() || std::fabs(it->second - kv.second) > 1e-12)
+                return fail(ED_EINVAL, "Hamiltonian (bonds) not invariant under the group");
+        }
+        std::map<std::array<int, 3>, double> timg;
+        for (auto &kv : tris) canon_tri(p[kv.first[0]], p[kv.first[1]], p[kv.first[2]], kv.second, timg);
+        for (auto &kv : tris) {
+            auto it = timg.find(kv.first);
+            double v = (it == timg.end()) ? 0.0 : it->second;
+            if (std::fabs(v - kv.second) > 1e-12)
+                return fail(ED_EINVAL, "Hamiltonian (chirality) not invariant under the group");
+        }
+    }
+    bool cplx_chi = false;
+    for (int g = 0; g < G; ++g)
+        if (std::fabs(T.chi_im[g]) > 1e-12) cplx_chi = true;
+    bool has_chir = false;
+    for (int t = 0; t < m->n_tri; ++t)
+        if (m->tri_Jchi[t] != 0.0) has_chir = true;
+    T.is_complex = cplx_chi || has_chir;
+    return ED_OK;
+}
+
+ed_status check_stable(const HostTables &T, int n_sub)
+{
+    if (n_sub < 1 || T.N % n_sub) return fail(ED_ENOTSTABLE, "n_sites not divisible by the number of sublattices");
+    int b = T.N / n_sub;
+    for (int sp = 0; sp < T.n_sp; ++sp) {
+        const int32_t *p = &T.sp_perm[(size_t)sp * T.N];
+        for (int X = 0; X < n_sub; ++X) {
+            int Y = p[X * b] / b;
+            for (int q = 1; q < b; ++q)
+                if (p[X * b + q] / b != Y)
+                    return fail(ED_ENOTSTABLE, "sublattice decomposition into " + std::to_string(n_sub) +
+                                                   " contiguous blocks is not stable under the group");
+        }
+    }
+    return ED_OK;
+}
+
+// image of the b-bit substate s of block X under spatial permutation p, as a
+// b-bit substate of the destination block (bits in within-block order)
+static inline uint32_t sub_image(const int32_t *p, int X, int b, uint32_t s)
+{
+    uint32_t out = 0;
+    for (int q = 0; q < b; ++q)
+        if ((s >> (b - 1 - q)) & 1u) {
+            int j = p[X * b + q];
+            out |= 1u << (b - 1 - (j % b));
+        }
+    return out;
+}
+
+void build_rep_sym(const HostTables &T, int n_sub, std::vector<uint16_t> &rep, std::vector<uint32_t> &sym_off,
+                   std::vector<uint32_t> &sym_list)
+{
+    const int b = T.N / n_sub;
+    const uint32_t S = 1u << b, mask = S - 1;
+    rep.assign((size_t)n_sub * S, 0);
+    sym_off.assign((size_t)n_sub * S + 1, 0);
+    sym_list.clear();
+    // G_X: elements mapping sublattice X onto sublattice 0 (definition of
+    // the sublattice symmetries)
+    std::vector<std::vector<int>> GX(n_sub);
+    for (int g = 0; g < T.G; ++g) {
+        const int32_t *p = &T.sp_perm[(size_t)T.sp_of[g] * T.N];
+        for (int X = 0; X < n_sub; ++X)
+            if (p[X * b] / b == 0) GX[X].push_back(g);
+    }
+    std::vector<uint32_t> img;
+    for (int X = 0; X < n_sub; ++X) {
+        for (uint32_t s = 0; s < S; ++s) {
+            img.resize(GX[X].size());
+            uint32_t best = ~0u;
+            for (size_t k = 0; k < GX[X].size(); ++k) {
+                int g = GX[X][k];
+                const int32_t *p = &T.sp_perm[(size_t)T.sp_of[g] * T.N];
+                uint32_t v = sub_image(p, X, b, s);
+                if (T.flip[g]) v ^= mask;
+                img[k] = v;
+                best = std::min(best, v);
+            }
+            rep[(size_t)X * S + s] = (uint16_t)best;
+            for (size_t k = 0; k < GX[X].size(); ++k)
+                if (img[k] == best) {
+                    int g = GX[X][k];
+                    sym_list.push_back(((uint32_t)g << 16) | ((uint32_t)T.sp_of[g] << 1) | T.flip[g]);
+                }
+            sym_off[(size_t)X * S + s + 1] = (uint32_t)sym_list.size();
+        }
+    }
+}
+
+static void build_act(HostTables &T)
+{
+    const int A = T.A, b = T.ba;
+    const uint32_t S = 1u << b;
+    T.act.assign((size_t)T.n_sp * A * S, 0);
+    T.src.assign(T.n_sp, 0);
+    for (int sp = 0; sp < T.n_sp; ++sp) {
+        const int32_t *p = &T.sp_perm[(size_t)sp * T.N];
+        for (int X = 0; X < A; ++X) {
+            int d = p[X * b] / b;  // destination of X
+            T.src[sp] |= (uint64_t)X << (4 * d);
+            for (uint32_t s = 0; s < S; ++s) T.act[((size_t)sp * A + d) * S + s] = (uint8_t)sub_image(p, X, b, s);
+        }
+    }
+}
+
+void build_pairs(const ed_model *m, HostTables &T)
+{
+    const int N = T.N;
+    std::map<std::pair<int, int>, double> J;
+    std::map<std::pair<int, int>, std::vector<ChiTerm>> C;
+    for (int b = 0; b < m->n_bonds; ++b) {
+        int i = m->bond_sites[2 * b], j = m->bond_sites[2 * b + 1];
+        J[{std::min(i, j), std::max(i, j)}] += m->bond_J[b];
+    }
+    for (int t = 0; t < m->n_tri; ++t) {
+        const int32_t *v = m->tri_sites + 3 * t;
+        double Jc = m->tri_Jchi[t];
+        if (Jc == 0.0) continue;
+        for (int r = 0; r < 3; ++r) {
+            int a = v[r], bb = v[(r + 1) % 3], c = v[(r + 2) % 3];
+            int lo = std::min(bb, c), hi = std::max(bb, c);
+            double o = (bb == lo) ? 1.0 : -1.0;
+            C[{lo, hi}].push_back(ChiTerm{(uint64_t)1 << (N - 1 - a), o * Jc / 4.0});
+            J[{lo, hi}] += 0.0;
+        }
+    }
+    T.pairs.clear();
+    T.chis.clear();
+    for (auto &kv : J) {
+        PairTerm pt;
+        int lo = kv.first.first, hi = kv.first.second;
+        pt.lo_bit = (uint64_t)1 << (N - 1 - lo);
+        pt.mask = pt.lo_bit | ((uint64_t)1 << (N - 1 - hi));
+        pt.Jsum = kv.second;
+        pt.chi_begin = (int32_t)T.chis.size();
+        auto it = C.find(kv.first);
+        if (it != C.end())
+            for (auto &ct : it->second) T.chis.push_back(ct);
+        pt.chi_end = (int32_t)T.chis.size();
+        T.pairs.push_back(pt);
+    }
+}
+
+static size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &L)
+{
+    size_t o = 0;
+    L.off_rep = (uint32_t)o;     o = align16(o + T.rep.size() * sizeof(uint16_t));
+    L.off_symoff = (uint32_t)o;  o = align16(o + T.sym_off.size() * sizeof(uint32_t));
+    L.off_symlist = (uint32_t)o; o = align16(o + T.sym_list.size() * sizeof(uint32_t));
+    L.off_act = (uint32_t)o;     o = align16(o + T.act.size());
+    L.off_src = (uint32_t)o;     o = align16(o + T.src.size() * sizeof(uint64_t));
+    L.off_pairs = (uint32_t)o;   o = align16(o + T.pairs.size() * sizeof(PairTerm));
+    L.off_chis = (uint32_t)o;    o = align16(o + T.chis.size() * sizeof(ChiTerm));
+    L.off_chi = (uint32_t)o;     o = align16(o + (size_t)T.G * sizeof(double) * (T.is_complex ? 2 : 1));
+    L.off_sqrt = (uint32_t)o;    o = align16(o + (size_t)(T.G + 1) * sizeof(double));
+    L.off_isqrt = (uint32_t)o;   o = align16(o + (size_t)(T.G + 1) * sizeof(double));
+    L.off_chione = (uint32_t)o;  o = align16(o + (size_t)T.G);
+    L.bytes = (uint32_t)o;
+    std::vector<uint8_t> blob(o, 0);
+    auto put = [&](uint32_t off, const void *src, size_t n) { if (n) std::memcpy(blob.data() + off, src, n); };
+    put(L.off_rep, T.rep.data(), T.rep.size() * sizeof(uint16_t));
+    put(L.off_symoff, T.sym_off.data(), T.sym_off.size() * sizeof(uint32_t));
+    put(L.off_symlist, T.sym_list.data(), T.sym_list.size() * sizeof(uint32_t));
+    put(L.off_act, T.act.data(), T.act.size());
+    put(L.off_src, T.src.data(), T.src.size() * sizeof(uint64_t));
+    put(L.off_pairs, T.pairs.data(), T.pairs.size() * sizeof(PairTerm));
+    put(L.off_chis, T.chis.data(), T.chis.size() * sizeof(ChiTerm));
+    std::vector<double> chi;
+    for (int g = 0; g < T.G; ++g) {
+        chi.push_back(T.chi_re[g]);
+        if (T.is_complex) chi.push_back(T.chi_im[g]);
+    }
+    put(L.off_chi, chi.data(), chi.size() * sizeof(double));
+    std::vector<double> sq(T.G + 1), isq(T.G + 1);
+    for (int k = 0; k <= T.G; ++k) {
+        sq[k] = std::sqrt((double)k);
+        isq[k] = k ? 1.0 / std::sqrt((double)k) : 0.0;
+    }
+    put(L.off_sqrt, sq.data(), sq.size() * sizeof(double));
+    put(L.off_isqrt, isq.data(), isq.size() * sizeof(double));
+    put(L.off_chione, T.chi_one.data(), T.chi_one.size());
+    return blob;
+}
+
+// Choose the decompositions: the SymmetryAction tables use the stable
+// contiguous decomposition with the fewest sublattices whose tables fit
+// (<= 8 bits per substate, <= 16 sublattices, <= 64 KiB); the Rep/Sym
+// tables use the one with the fewest sublattices (fewest candidate
+// symmetries) whose tables fit 64 KiB.
+int choose_sublattices(const HostTables &T, int &R, int &A, std::string &why)
+{
+    const int N = T.N;
+    std::vector<int> stable;
+    for (int ns = 1; ns <= N; ++ns) {
+        if (N % ns) continue;
+        std::string save;
+        if (check_stable(T, ns) == ED_OK) stable.push_back(ns);
+    }
+    set_error("");
+    int bestA = 0;
+    for (int ns : stable) {
+        int b = N / ns;
+        if (b > 8 || ns > 16) continue;
+        size_t bytes = (size_t)T.n_sp * ns * ((size_t)1 << b);
+        if (bytes <= 64 * 1024) { bestA = ns; break; }
+    }
+    if (!bestA) {
+        why = "no stable decomposition gives SymmetryAction tables of at most 64 KiB";
+        return 0;
+    }
+    int bestR = 0;
+    for (int ns : stable) {
+        int b = N / ns;
+        if (b > 14) continue;
+        size_t S = (size_t)1 << b;
+        // tables: rep u16, offsets u32, list u32 (estimate the list as G_X * S / 4 worst-case cap)
+        std::vector<uint16_t> rep;
+        std::vector<uint32_t> off, lst;
+        if (ns * S * 6 > 64 * 1024) continue;
+        build_rep_sym(T, ns, rep, off, lst);
+        size_t bytes = rep.size() * 2 + off.size() * 4 + lst.size() * 4;
+        if (bytes <= 64 * 1024) { bestR = ns; break; }
+    }
+    if (!bestR) {
+        why = "no stable decomposition gives Rep/Sym tables of at most 64 KiB";
+        return 0;
+    }
+    R = bestR;
+    A = bestA;
+    return 1;
+}
+
+ed_status build_host_tables(const ed_model *m, const ed_group *g, int n_up, int n_sub_rep, int n_sub_act,
+                            HostTables &T)
+{
+    ed_status st = validate_and_copy_group(m, g, n_up, T);
+    if (st != ED_OK) return st;
+    int R = n_sub_rep, A = n_sub_act;
+    if (R <= 0 || A <= 0) {
+        int Ra = 0, Aa = 0;
+        std::string why;
+        if (!choose_sublattices(T, Ra, Aa, why)) return fail(ED_ENOTSTABLE, why);
+        if (R <= 0) R = Ra;
+        if (A <= 0) A = Aa;
+    }
+    if ((st = check_stable(T, R)) != ED_OK) return st;
+    if ((st = check_stable(T, A)) != ED_OK) return st;
+    T.R = R;
+    T.br = T.N / R;
+    T.A = A;
+    T.ba = T.N / A;
+    if (T.br > 16) return fail(ED_EINVAL, "Rep/Sym substates wider than 16 bits");
+    if (T.ba > 8 || A > 16) return fail(ED_EINVAL, "SymmetryAction tables need <= 8 bits per substate and <= 16 sublattices");
+    build_rep_sym(T, R, T.rep, T.sym_off, T.sym_list);
+    build_act(T);
+    build_pairs(m, T);
+    return ED_OK;
+}
+
+}  // namespace symed

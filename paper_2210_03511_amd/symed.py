@@ -1,0 +1,278 @@
+"""Python binding of the symed C ABI (argument marshalling only).
+
+Every computation runs in the HIP library ``libsymed.so``; this module only
+converts arrays and tensors into pointers.  Device vectors are torch tensors
+(float64, or complex128 for complex sectors) on the current HIP device; the
+stream is torch's current stream unless one is given.
+
+If the library has not been built the import of the library fails loudly:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsymed.so")
+
+ED_OK, ED_EINVAL, ED_ENOTSTABLE, ED_ECHAR, ED_ENOMEM, ED_EDEVICE, ED_EBREAKDOWN = range(7)
+STATUS_NAMES = {0: "ED_OK", 1: "ED_EINVAL", 2: "ED_ENOTSTABLE", 3: "ED_ECHAR", 4: "ED_ENOMEM", 5: "ED_EDEVICE",
+                6: "ED_EBREAKDOWN"}
+
+EXPORTED = ["ed_last_error", "ed_version", "ed_basis_build", "ed_basis_free", "ed_basis_info", "ed_basis_export",
+            "ed_basis_device_reps", "ed_apply_H", "ed_lookup", "ed_lanczos_run", "ed_eigenvalues",
+            "ed_tables_inspect", "ed_index_train", "ed_index_info"]
+
+
+class EdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Model(ctypes.Structure):
+    _fields_ = [("n_sites", ctypes.c_int32), ("n_bonds", ctypes.c_int32), ("bond_sites", ctypes.c_void_p),
+                ("bond_J", ctypes.c_void_p), ("n_tri", ctypes.c_int32), ("tri_sites", ctypes.c_void_p),
+                ("tri_Jchi", ctypes.c_void_p)]
+
+
+class _Group(ctypes.Structure):
+    _fields_ = [("n_elem", ctypes.c_int32), ("perm", ctypes.c_void_p), ("flip", ctypes.c_void_p),
+                ("chi_re", ctypes.c_void_p), ("chi_im", ctypes.c_void_p)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("n_sub_rep", ctypes.c_int32), ("n_sub_act", ctypes.c_int32), ("prefix_bits", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("mem_limit_bytes", ctypes.c_int64)]
+
+
+class BasisInfo(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int64), ("is_complex", ctypes.c_int32), ("n_sites", ctypes.c_int32),
+                ("n_elem", ctypes.c_int32), ("n_sub_rep", ctypes.c_int32), ("n_sub_act", ctypes.c_int32),
+                ("prefix_bits", ctypes.c_int32), ("n_elements", ctypes.c_int64), ("n_offdiag", ctypes.c_int64),
+                ("bytes_device", ctypes.c_int64), ("table_bytes", ctypes.c_int64), ("limits_bytes", ctypes.c_int64),
+                ("index_bytes", ctypes.c_int64), ("index_max_err", ctypes.c_int32), ("lds_resident", ctypes.c_int32),
+                ("build_seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class IndexCfg(ctypes.Structure):
+    _fields_ = [("n_features", ctypes.c_int32), ("hidden", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("lr", ctypes.c_float), ("seed", ctypes.c_uint32),
+                ("n_seg_log2", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class IndexStats(ctypes.Structure):
+    _fields_ = [("max_err", ctypes.c_int32), ("n_seg", ctypes.c_int32), ("final_loss", ctypes.c_float),
+                ("mlp_max_err", ctypes.c_float), ("mlp_bytes", ctypes.c_int64), ("seg_bytes", ctypes.c_int64),
+                ("train_seconds", ctypes.c_double), ("mean_window", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_LIB = None
+
+
+def lib():
+    """Load libsymed.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"symed HIP library not built: {LIB_PATH} missing (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.ed_last_error.restype = ctypes.c_char_p
+        L.ed_version.restype = ctypes.c_char_p
+        L.ed_basis_build.argtypes = [ctypes.POINTER(_Model), ctypes.POINTER(_Group), i32, ctypes.POINTER(_Options),
+                                     vp, ctypes.POINTER(vp)]
+        L.ed_basis_free.argtypes = [vp]
+        L.ed_basis_free.restype = None
+        L.ed_basis_info.argtypes = [vp, ctypes.POINTER(BasisInfo)]
+        L.ed_basis_export.argtypes = [vp, vp, vp]
+        L.ed_basis_device_reps.argtypes = [vp, ctypes.POINTER(vp)]
+        L.ed_apply_H.argtypes = [vp, vp, vp, i32, vp]
+        L.ed_lookup.argtypes = [vp, vp, i64, vp, i32, vp]
+        L.ed_lanczos_run.argtypes = [vp, vp, i32, i32, vp, vp, ctypes.POINTER(i32), vp]
+        L.ed_eigenvalues.argtypes = [vp, vp, i32, i32, vp]
+        L.ed_tables_inspect.argtypes = [ctypes.POINTER(_Model), ctypes.POINTER(_Group), i32, i32, vp, vp, vp, i64,
+                                        ctypes.POINTER(i64), vp]
+        if hasattr(L, "ed_index_train"):
+            L.ed_index_train.argtypes = [vp, ctypes.POINTER(IndexCfg), ctypes.POINTER(IndexStats), vp]
+            L.ed_index_info.argtypes = [vp, ctypes.POINTER(IndexStats), vp, i64]
+        for name in EXPORTED:
+            if hasattr(L, name) and name not in ("ed_last_error", "ed_version", "ed_basis_free"):
+                getattr(L, name).restype = ctypes.c_int
+        _LIB = L
+    return _LIB
+
+
+def _check(status):
+    if status != ED_OK:
+        raise EdError(status, lib().ed_last_error().decode())
+
+
+def version():
+    return lib().ed_version().decode()
+
+
+def _np_ptr(a):
+    return a.ctypes.data if a is not None and a.size else None
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _tensor_ptr(t):
+    return t.data_ptr()
+
+
+class _Arrays:
+    """Host copies of a problem description, kept alive across a call."""
+
+    def __init__(self, n_sites, bonds, bond_J, tris, tri_Jchi, perms, flips, chi):
+        self.bonds = np.ascontiguousarray(np.asarray(bonds, np.int32).reshape(-1))
+        self.bond_J = np.ascontiguousarray(np.asarray(bond_J, np.float64))
+        self.tris = np.ascontiguousarray(np.asarray(tris, np.int32).reshape(-1))
+        self.tri_J = np.ascontiguousarray(np.asarray(tri_Jchi, np.float64))
+        self.perms = np.ascontiguousarray(np.asarray(perms, np.int32).reshape(-1))
+        self.flips = np.ascontiguousarray(np.asarray(flips, np.uint8))
+        chi = np.asarray(chi)
+        self.chi_re = np.ascontiguousarray(chi.real.astype(np.float64))
+        self.chi_im = np.ascontiguousarray(np.imag(chi).astype(np.float64))
+        self.model = _Model(n_sites, len(self.bond_J), _np_ptr(self.bonds), _np_ptr(self.bond_J), len(self.tri_J),
+                            _np_ptr(self.tris), _np_ptr(self.tri_J))
+        self.group = _Group(len(self.flips), _np_ptr(self.perms), _np_ptr(self.flips), _np_ptr(self.chi_re),
+                            _np_ptr(self.chi_im))
+
+
+def _arrays_from(inst):
+    return _Arrays(inst.n_sites, inst.bonds, inst.bond_J, inst.tris, inst.tri_Jchi, inst.perms, inst.flips, inst.chi)
+
+
+class Basis:
+    """A built sector basis (library-owned device memory)."""
+
+    def __init__(self, handle):
+        self._h = ctypes.c_void_p(handle)
+        self._info = None
+
+    @classmethod
+    def build(cls, inst, n_sub_rep=0, n_sub_act=0, prefix_bits=0, mem_limit_bytes=0, stream=None):
+        """Build the basis of a problem description with attributes n_sites,
+        bonds, bond_J, tris, tri_Jchi, perms, flips, chi, n_up."""
+        arr = _arrays_from(inst)
+        opts = _Options(n_sub_rep, n_sub_act, prefix_bits, 0, mem_limit_bytes)
+        h = ctypes.c_void_p()
+        _check(lib().ed_basis_build(ctypes.byref(arr.model), ctypes.byref(arr.group), int(inst.n_up),
+                                    ctypes.byref(opts), _stream_ptr(stream), ctypes.byref(h)))
+        return cls(h.value)
+
+    def free(self):
+        if self._h:
+            lib().ed_basis_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def info(self):
+        inf = BasisInfo()
+        _check(lib().ed_basis_info(self._h, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    @property
+    def dim(self):
+        return self.info()["dim"]
+
+    @property
+    def is_complex(self):
+        return bool(self.info()["is_complex"])
+
+    def export(self):
+        d = self.dim
+        reps = np.zeros(d, np.uint64)
+        stab = np.zeros(d, np.uint32)
+        _check(lib().ed_basis_export(self._h, _np_ptr(reps), _np_ptr(stab)))
+        return reps, stab
+
+    def device_reps_ptr(self):
+        p = ctypes.c_void_p()
+        _check(lib().ed_basis_device_reps(self._h, ctypes.byref(p)))
+        return p.value
+
+    def apply_H(self, x, y, mode=0, stream=None):
+        """y := H x on device tensors (float64 or complex128)."""
+        _check(lib().ed_apply_H(self._h, _tensor_ptr(x), _tensor_ptr(y), int(mode), _stream_ptr(stream)))
+        return y
+
+    def lookup(self, keys, idx, mode=0, stream=None):
+        """idx[k] = position of keys[k] (uint64 stored in an int64 tensor) or -1."""
+        _check(lib().ed_lookup(self._h, _tensor_ptr(keys), keys.numel(), _tensor_ptr(idx), int(mode),
+                               _stream_ptr(stream)))
+        return idx
+
+    def lanczos(self, v0, n_iter, mode=0, stream=None):
+        """Run n_iter Lanczos steps from device vector v0; returns (alpha, beta,
+        n_done, broken)."""
+        a = np.zeros(n_iter)
+        b = np.zeros(n_iter)
+        nd = ctypes.c_int32(0)
+        st = lib().ed_lanczos_run(self._h, _tensor_ptr(v0), int(n_iter), int(mode), _np_ptr(a), _np_ptr(b),
+                                  ctypes.byref(nd), _stream_ptr(stream))
+        if st not in (ED_OK, ED_EBREAKDOWN):
+            _check(st)
+        n = nd.value
+        return a[:n], b[:n], n, st == ED_EBREAKDOWN
+
+    def train_index(self, n_features=0, hidden=32, steps=0, batch=0, lr=0.0, seed=1, n_seg_log2=0, stream=None):
+        cfg = IndexCfg(n_features, hidden, steps, batch, lr, seed, n_seg_log2, 0)
+        stats = IndexStats()
+        _check(lib().ed_index_train(self._h, ctypes.byref(cfg), ctypes.byref(stats), _stream_ptr(stream)))
+        return stats.as_dict()
+
+    def index_weights(self):
+        stats = IndexStats()
+        buf = np.zeros(1 << 16, np.float32)
+        _check(lib().ed_index_info(self._h, ctypes.byref(stats), _np_ptr(buf), buf.size))
+        return stats.as_dict(), buf
+
+
+def eigenvalues(alpha, beta, k=1):
+    a = np.ascontiguousarray(alpha, np.float64)
+    b = np.ascontiguousarray(beta, np.float64)
+    out = np.zeros(k)
+    _check(lib().ed_eigenvalues(_np_ptr(a), _np_ptr(b) if len(b) else None, len(a), int(k), _np_ptr(out)))
+    return out
+
+
+def tables_inspect(inst, n_sub):
+    """Host-only Rep/Sym/SymmetryAction tables of one decomposition."""
+    arr = _arrays_from(inst)
+    b = inst.n_sites // n_sub
+    S = 1 << b
+    rep = np.zeros(n_sub * S, np.uint32)
+    off = np.zeros(n_sub * S + 1, np.uint32)
+    nsym = ctypes.c_int64(0)
+    _check(lib().ed_tables_inspect(ctypes.byref(arr.model), ctypes.byref(arr.group), int(inst.n_up), n_sub,
+                                   _np_ptr(rep), _np_ptr(off), None, 0, ctypes.byref(nsym), None))
+    sym = np.zeros(max(nsym.value, 1), np.uint32)
+    act = np.zeros(len(inst.flips) * n_sub * S, np.uint64)
+    _check(lib().ed_tables_inspect(ctypes.byref(arr.model), ctypes.byref(arr.group), int(inst.n_up), n_sub,
+                                   _np_ptr(rep), _np_ptr(off), _np_ptr(sym), sym.size, ctypes.byref(nsym),
+                                   _np_ptr(act)))
+    return rep.reshape(n_sub, S), off, sym[: nsym.value], act.reshape(len(inst.flips), n_sub, S)

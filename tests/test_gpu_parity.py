@@ -1,0 +1,250 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Small sectors: every representative, stabilizer, H.v entry and lookup is
+compared with the oracle (bit-exact for integers, 1e-12 absolute for H.v),
+Lanczos ground-state energies to 1e-10 relative.  Benchmark-size sectors:
+basis size against the character formula, ordering and membership of
+oracle-sampled representatives, and H.v on oracle-sampled rows for an input
+vector defined by a counter-based hash of each representative.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from workloads import lattices as L
+from workloads import vectors as V
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def S():
+    _torch()
+    from paper_2210_03511_amd import symed
+    symed.lib()
+    return symed
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(torch, arr):
+    return torch.from_numpy(np.ascontiguousarray(arr)).cuda()
+
+
+SMALL = L.small_instances() + [L.chain16()]
+
+
+@pytest.mark.parametrize("inst", SMALL, ids=lambda i: f"{i.name}-{i.sector}")
+def test_small_sector_full_parity(S, inst):
+    torch = _torch()
+    _say("case", inst.name, inst.sector)
+    reps_o, stabs_o = O.enumerate_basis(inst)
+    b = S.Basis.build(inst)
+    info = b.info()
+    reps, stab = b.export()
+    assert np.array_equal(reps, reps_o)
+    assert np.array_equal(stab.astype(np.int64), stabs_o.astype(np.int64))
+    # element count (diagonal + non-zero flipped pairs)
+    _, _, _, ok, ne = O.row_entries(inst, reps_o)
+    assert ok.all()
+    assert info["n_elements"] == int(ne.sum())
+    # H.v
+    H = O.coo_matrix(inst, reps_o, stabs_o)
+    rng = np.random.default_rng(17)
+    d = len(reps)
+    if inst.is_complex:
+        x = rng.standard_normal(d) + 1j * rng.standard_normal(d)
+        xt = _dev(torch, x.astype(np.complex128))
+        yt = torch.zeros_like(xt)
+    else:
+        x = rng.standard_normal(d)
+        xt = _dev(torch, x)
+        yt = torch.zeros_like(xt)
+    b.apply_H(xt, yt)
+    torch.cuda.synchronize()
+    y = yt.cpu().numpy()
+    ref = H @ x
+    assert np.max(np.abs(y - ref)) < 1e-12
+    # lookup: every representative found at its index, non-representatives absent
+    keys = _dev(torch, reps.view(np.int64))
+    idx = torch.empty_like(keys)
+    b.lookup(keys, idx)
+    torch.cuda.synchronize()
+    assert np.array_equal(idx.cpu().numpy(), np.arange(d))
+    rset = set(reps.tolist())
+    nonrep = np.array([s for s in O.sz_states(inst.n_sites, inst.n_up)[:4000].tolist() if s not in rset],
+                      np.uint64)
+    if len(nonrep):
+        kt = _dev(torch, nonrep.view(np.int64))
+        it = torch.empty_like(kt)
+        b.lookup(kt, it)
+        torch.cuda.synchronize()
+        assert (it.cpu().numpy() == -1).all()
+    b.free()
+
+
+@pytest.mark.parametrize("case", [(8, 2, 2), (8, 2, 4), (8, 4, 4), (13, 2, 4), (13, 4, 4), (15, 4, 4),
+                                  (5, 2, 2), (4, 2, 2)], ids=str)
+def test_explicit_decompositions(S, case):
+    """Same basis and H.v for every admissible pair of decompositions."""
+    torch = _torch()
+    k, R, A = case
+    inst = L.small_instances()[k]
+    if R not in inst.sublat_options or A not in inst.sublat_options:
+        pytest.skip("decomposition not in this labelling")
+    reps_o, stabs_o = O.enumerate_basis(inst)
+    b = S.Basis.build(inst, n_sub_rep=R, n_sub_act=A, prefix_bits=3)
+    info = b.info()
+    assert (info["n_sub_rep"], info["n_sub_act"], info["prefix_bits"]) == (R, A, 3)
+    reps, stab = b.export()
+    assert np.array_equal(reps, reps_o)
+    H = O.coo_matrix(inst, reps_o, stabs_o)
+    x = V.start_vector(len(reps), 9, inst.is_complex)
+    xt = _dev(torch, x)
+    yt = torch.zeros_like(xt)
+    b.apply_H(xt, yt)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(yt.cpu().numpy() - H @ x)) < 1e-12
+
+
+@pytest.mark.parametrize("inst", [L.chain16(), L.small_instances()[13], L.small_instances()[14],
+                                  L.small_instances()[15], L.small_instances()[11]],
+                         ids=lambda i: f"{i.name}-{i.sector}")
+def test_lanczos_ground_state(S, inst):
+    torch = _torch()
+    _say("lanczos", inst.name, inst.sector)
+    reps_o, stabs_o = O.enumerate_basis(inst)
+    H = O.coo_matrix(inst, reps_o, stabs_o)
+    b = S.Basis.build(inst)
+    v0 = V.start_vector(len(reps_o), 1002, inst.is_complex)
+    n_iter = min(100, len(reps_o))
+    a, beta, n, broken = b.lanczos(_dev(torch, v0), n_iter)
+    ao, bo = O.lanczos(lambda v: H @ v, v0, n_iter, hermitian_complex=inst.is_complex)
+    e_gpu = S.eigenvalues(a, beta, 1)[0]
+    e_orc = O.tmatrix_eigs(ao, bo)[0]
+    exact = np.linalg.eigvalsh(H.toarray())[0]
+    assert abs(e_gpu - e_orc) <= 1e-10 * abs(e_orc)
+    assert abs(e_gpu - exact) <= 1e-9 * abs(exact)
+    # first alphas agree closely (no reorthogonalization: drift grows later)
+    k = min(10, len(a), len(ao))
+    assert np.max(np.abs(a[:k] - ao[:k])) < 1e-10
+    b.free()
+
+
+def test_chain16_reference_config(S):
+    """Heisenberg chain N=16, k=0 (810 states), 100 Lanczos steps from a
+    seeded N(0,1) start vector; energy agrees with the oracle to 1e-10."""
+    torch = _torch()
+    inst = L.chain16()
+    reps_o, stabs_o = O.enumerate_basis(inst)
+    H = O.coo_matrix(inst, reps_o, stabs_o)
+    b = S.Basis.build(inst)
+    assert b.dim == 810
+    v0 = V.start_vector(810, 1002)
+    a, beta, n, broken = b.lanczos(_dev(torch, v0), 100)
+    ao, bo = O.lanczos(lambda v: H @ v, v0, 100)
+    e = S.eigenvalues(a, beta, 1)[0]
+    eo = O.tmatrix_eigs(ao, bo)[0]
+    assert abs(e - eo) <= 1e-10 * abs(eo)
+
+
+def test_determinism(S):
+    torch = _torch()
+    inst = L.small_instances()[13]
+    b = S.Basis.build(inst)
+    x = _dev(torch, V.start_vector(b.dim, 3))
+    y1 = torch.zeros_like(x)
+    y2 = torch.zeros_like(x)
+    b.apply_H(x, y1)
+    b.apply_H(x, y2)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+    a1, b1, _, _ = b.lanczos(x, 40)
+    a2, b2, _, _ = b.lanczos(x, 40)
+    assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
+
+
+def test_breakdown_on_tiny_sector(S):
+    torch = _torch()
+    inst = L.chain(4)
+    b = S.Basis.build(inst)
+    a, beta, n, broken = b.lanczos(_dev(torch, np.array([1.0, 0.3])), 10)
+    assert broken and n == 2
+    assert np.allclose(np.sort(S.eigenvalues(a, beta, 2)), [-2.0, 1.0])
+
+
+def test_memory_cap(S):
+    inst = L.small_instances()[13]
+    with pytest.raises(S.EdError) as e:
+        S.Basis.build(inst, mem_limit_bytes=1000)
+    assert e.value.status == S.ED_ENOMEM
+
+
+# --- benchmark-size sectors --------------------------------------------------
+
+def _sampled_rows(inst, count, seed):
+    """Oracle-side sample of sector representatives (rep of random configurations)."""
+    st = V.random_sector_states(inst.n_sites, inst.n_up, count, seed)
+    rep, g, stab, triv = O.rep_many(inst, st)
+    return np.unique(rep[triv])
+
+
+def _large_parity(S, inst, n_rows, seed, opts=None):
+    torch = _torch()
+    _say("large", inst.name, inst.sector)
+    b = S.Basis.build(inst, **(opts or {}))
+    info = b.info()
+    _say("  built", info["dim"], "in", round(info["build_seconds"], 2), "s")
+    assert info["dim"] == O.character_formula_dim(inst)
+    d = info["dim"]
+    # ascending order on the device copy, checked in chunks on the host
+    reps, _ = b.export()
+    assert np.all(reps[1:] > reps[:-1])
+    rows = _sampled_rows(inst, n_rows, seed)
+    # oracle rows are sector representatives: they must be in the GPU basis
+    kt = _dev(torch, rows.view(np.int64))
+    it = torch.empty_like(kt)
+    b.lookup(kt, it)
+    torch.cuda.synchronize()
+    idx = it.cpu().numpy()
+    assert (idx >= 0).all()
+    assert np.array_equal(reps[idx], rows)
+    # H.v on those rows with x(s) = hash(s)
+    x = V.state_vector(reps, 4242, inst.is_complex)
+    xt = _dev(torch, x)
+    yt = torch.zeros_like(xt)
+    b.apply_H(xt, yt)
+    torch.cuda.synchronize()
+    y = yt.cpu().numpy()[idx]
+    yo, ok, ne = O.rows_apply(inst, rows, lambda t: V.state_vector(t, 4242, inst.is_complex))
+    assert ok.all()
+    err = np.max(np.abs(y - (yo if inst.is_complex else yo.real)))
+    _say("  rows", len(rows), "max err", err)
+    assert err < 1e-12
+    del reps
+    b.free()
+
+
+def test_square32_full_size(S):
+    _large_parity(S, L.square32(), 3000, 2001)
+
+
+def test_triangular36_full_size(S):
+    _large_parity(S, L.tri36_K(), 1500, 3001)
+
+
+def test_square40_full_size(S):
+    _large_parity(S, L.square40(), 1500, 5001)

@@ -1,0 +1,145 @@
+"""Host-side checks of the HIP library: exported symbols, the
+sublattice-coding tables against the thesis's worked examples, input
+validation and the tridiagonal eigensolver.  No GPU needed (no kernel runs)."""
+import ctypes
+import os
+import re
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from workloads import lattices as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def symed():
+    from paper_2210_03511_amd import symed as S
+    if not os.path.exists(S.LIB_PATH):
+        from paper_2210_03511_amd.build import build
+        build()
+    S.lib()
+    return S
+
+
+def test_exports_every_declared_symbol(symed):
+    hdr = open(os.path.join(ROOT, "include", "symed.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    names = set(re.findall(r"\b(ed_[a-z_]+)\s*\(", hdr))
+    assert len(names) >= 10
+    L_ = ctypes.CDLL(symed.LIB_PATH)
+    for n in sorted(names):
+        assert hasattr(L_, n), n
+
+
+def _state(bits):
+    v = 0
+    for c in bits:
+        v = (v << 1) | (1 if c == "u" else 0)
+    return v
+
+
+def test_two_sublattice_example_tables(symed):
+    # chain of 6 sites, A = positions 0,2,4, B = 1,3,5 (thesis worked example)
+    inst = L.chain(6, sublat=(2,))
+    rep, off, sym, act = symed.tables_inspect(inst, 2)
+    sA, sB = _state("uud"), _state("dud")
+    assert rep[0, sA] == 0b011          # Rep_A = |down up up> = 3
+    assert rep[1, sB] == 0b001          # Rep_B = |down down up> = 1
+    k = 1 * 8 + sB
+    assert list(sym[off[k]:off[k + 1]]) == [1]   # Sym_B = {T_1}
+    # T_1 sigma composed from the SymmetryAction tables = 14
+    sigma = (sA << 3) | sB
+    img = int(act[1, 0, sA]) | int(act[1, 1, sB])
+    assert img == 14 and img == _state("dduuud")
+    assert sigma == _state("uuddud")
+
+
+def test_three_sublattice_example_tables(symed):
+    inst = L.chain(6, sublat=(3,))
+    rep, off, sym, act = symed.tables_inspect(inst, 3)
+    sA, sB, sC = _state("uu"), _state("dd"), _state("ud")
+    assert (rep[0, sA], rep[1, sB], rep[2, sC]) == (0b11, 0b00, 0b01)
+
+    def symset(X, s):
+        k = X * 4 + s
+        return sorted(sym[off[k]:off[k + 1]].tolist())
+
+    assert symset(0, sA) == [0, 3]      # {I, T_3}
+    assert symset(1, sB) == [2, 5]      # {T_2, T_5}
+    assert symset(2, sC) == [1]         # {T_1}
+    # T_2 sigma < T_5 sigma, and T_2 sigma = |ddd uuu> = 7
+    def apply(g):
+        return int(act[g, 0, sA]) | int(act[g, 1, sB]) | int(act[g, 2, sC])
+    assert apply(2) == 7 and apply(5) == _state("dduduu") and apply(2) < apply(5)
+
+
+def test_tables_match_definition_on_random_substates(symed):
+    # Rep_X(s) = min over g in G_X of g s_X, for every substate, compared with
+    # brute force over the group on full configurations
+    from oracle import oracle as O
+    inst = L.small_instances()[8]  # square16 Gamma A1 even
+    for n_sub in inst.sublat_options:
+        b = inst.n_sites // n_sub
+        rep, off, sym, act = symed.tables_inspect(inst, n_sub)
+        for X in range(n_sub):
+            for s in range(1 << b):
+                conf = s << (inst.n_sites - (X + 1) * b)
+                best = None
+                for g in range(inst.n_elem):
+                    if inst.perms[g][X * b] // b != 0:
+                        continue
+                    img = O.act(inst, g, conf) >> (inst.n_sites - b)
+                    if inst.flips[g]:
+                        img = img  # complement of the whole config already applied
+                    best = img if best is None else min(best, img)
+                assert rep[X, s] == best
+
+
+def _expect_status(symed, inst, n_sub, status):
+    with pytest.raises(symed.EdError) as e:
+        symed.tables_inspect(inst, n_sub)
+    assert e.value.status == status, str(e.value)
+
+
+def test_validation_errors(symed):
+    inst = L.chain(8, k=1)
+    # not closed: drop an element
+    _expect_status(symed, replace(inst, perms=inst.perms[:-1], flips=inst.flips[:-1], chi=inst.chi[:-1]), 2,
+                   symed.ED_EINVAL)
+    # characters not multiplicative
+    chi = inst.chi.copy()
+    chi[1] = -chi[1]
+    _expect_status(symed, replace(inst, chi=chi), 2, symed.ED_ECHAR)
+    # |chi| != 1
+    chi = inst.chi.copy()
+    chi[2] *= 1.5
+    _expect_status(symed, replace(inst, chi=chi), 2, symed.ED_ECHAR)
+    # unstable decomposition: 3 does not divide 8
+    _expect_status(symed, inst, 3, symed.ED_ENOTSTABLE)
+    # contiguous blocks of a chain labelled by residues mod 2 are not stable for 8 blocks? (8 blocks of 1 site are)
+    # Hamiltonian not invariant: change one coupling
+    bJ = inst.bond_J.copy()
+    bJ[0] = 2.0
+    _expect_status(symed, replace(inst, bond_J=bJ), 2, symed.ED_EINVAL)
+    # spin flip outside Sz = 0
+    fl = L.chain(8, flip=1)
+    _expect_status(symed, replace(fl, n_up=3), 2, symed.ED_EINVAL)
+    # not a permutation
+    perms = inst.perms.copy()
+    perms[1, 0] = perms[1, 1]
+    _expect_status(symed, replace(inst, perms=perms), 2, symed.ED_EINVAL)
+
+
+def test_tridiagonal_eigenvalues(symed):
+    rng = np.random.default_rng(5)
+    for n in (1, 2, 7, 60, 200):
+        a = rng.standard_normal(n)
+        b = np.abs(rng.standard_normal(max(n - 1, 0)))
+        T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+        ref = np.linalg.eigvalsh(T)
+        k = min(n, 5)
+        ev = symed.eigenvalues(a, b, k)
+        assert np.max(np.abs(ev - ref[:k])) < 1e-12 * max(1.0, np.abs(ref).max())
