@@ -203,6 +203,89 @@ ed_status ed_lanczos_run(const ed_basis *basis, const void *d_v0, int32_t n_iter
 ed_status ed_eigenvalues(const double *alpha, const double *beta, int32_t n, int32_t k, double *evals);
 
 /*
+ * Learned index over the ascending representative list.  A network with two
+ * hidden layers of 32 units (float32 weights; half of each layer relu(z),
+ * half min(z,0); weights kept non-negative, so the network is
+ * non-decreasing) maps the key, read as a floating-point number u = (e + 1 +
+ * mantissa) / (N + 1) with e the position of its leading one, to an estimate
+ * of its normalized position; the estimate routes the key to one of
+ * 2^log2_leaves leaves.  Each leaf stores the position range of the
+ * keys routed to it and the largest distance between a routed key's position
+ * and the leaf's linear interpolation, so the bounded binary search around
+ * the prediction finds every representative and reports absence for every
+ * other key: lookups agree exactly with the plain Limits + binary search of
+ * the thesis (section on distributed memory parallelization, "Limits" map).
+ * Training runs on the device with the library's own forward, backward and
+ * Adam kernels on minibatches of (representative, position) pairs.
+ * After training the one-input network is expanded exactly into its linear
+ * pieces (at most 1090); the index build and all lookups evaluate it through
+ * that expansion (a binary search over the breakpoints, in LDS).
+ * Zero fields mean defaults (n_features = 1 (the only value accepted),
+ * hidden = 32 (the only value accepted), steps = 3000, batch = 8192,
+ * lr = 1e-2 with cosine decay, log2_leaves ~ log2(dim / 32)).
+ */
+typedef struct {
+    int32_t n_features;
+    int32_t hidden;
+    int32_t steps;
+    int32_t batch;
+    float lr;
+    uint32_t seed;
+    int32_t log2_leaves;
+    int32_t reserved;
+} ed_index_cfg;
+
+typedef struct {
+    int32_t max_err;           /* largest leaf error bound (positions) */
+    int32_t n_leaves;
+    float final_loss;          /* last minibatch mean squared error (normalized positions) */
+    float mlp_max_err;         /* max |network estimate * dim - position| over all keys */
+    int64_t mlp_bytes;         /* network weights */
+    int64_t leaf_bytes;        /* leaf table */
+    double train_seconds;      /* training + leaf build wall time */
+    double mean_window;        /* mean search-window length over all keys */
+    int32_t n_features;        /* network inputs (1) */
+    int32_t n_pieces;          /* linear pieces of the trained network */
+    int64_t used_leaves;       /* leaves with at least one key */
+    float feature_offset;      /* network input x = (u - feature_offset) * feature_scale */
+    float feature_scale;
+} ed_index_stats;
+
+/*
+ * Train the learned index of a built basis (device kernels; blocks until
+ * done) and build its exact leaf table.  Afterwards lookup_mode / mode 1 is
+ * accepted by ed_apply_H, ed_lookup and ed_lanczos_run.  Retraining with the
+ * same leaf count replaces the index.  Errors: ED_EINVAL, ED_ENOMEM,
+ * ED_EDEVICE.
+ */
+ed_status ed_index_train(ed_basis *basis, const ed_index_cfg *cfg, ed_index_stats *out, void *stream);
+
+/* Statistics of the trained index; h_params (may be NULL) receives the
+ * float32 weights W1[32][F], b1[32], W2[32][32], b2[32], W3[32], b3 when
+ * cap is large enough.  ED_EINVAL if no index was trained. */
+ed_status ed_index_info(const ed_basis *basis, ed_index_stats *out, float *h_params, int64_t cap);
+
+/*
+ * Evaluate the trained index network (expanded form) on n keys: d_u[k] =
+ * input feature of d_keys[k], d_y[k] = network output.  Device pointers
+ * (uint64[n], float32[n], float32[n]); asynchronous on `stream`.
+ */
+ed_status ed_index_predict(const ed_basis *basis, const uint64_t *d_keys, int64_t n, float *d_u, float *d_y,
+                           void *stream);
+
+/*
+ * Loss and gradient of the index network on an explicit batch, computed by
+ * the same forward/backward kernels as training (used to verify them):
+ * loss = (1/2n) sum_s (f(X_s) - t_s)^2 (any 1 <= n_features <= 8; no weight
+ * projection).  d_params: float32 weights as in
+ * ed_index_info; d_X: float32[n][n_features] features; d_t: float32[n];
+ * d_grad: float32[#params]; d_loss: float32[1].  All device pointers.
+ * Blocks until done.
+ */
+ed_status ed_mlp_loss_grad(int32_t n_features, const float *d_params, const float *d_X, const float *d_t, int64_t n,
+                           float *d_grad, float *d_loss, void *stream);
+
+/*
  * Host-only inspection of the sublattice-coding tables for one
  * decomposition into n_sub contiguous sublattices (no device needed):
  * for sublattice X and substate s (b = N/n_sub bits),

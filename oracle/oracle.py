@@ -23,8 +23,9 @@ What each function follows (thesis sections / equations):
     complex-Hermitian three-vector step ("The Lanczos algorithm"), no
     reorthogonalization; T-matrix eigenvalues by a library tridiagonal solver.
   * ``mlp_*``            - float64 reference of the learned-index network
-    (forward, loss, analytic backward) used to check the GPU training
-    kernels; parity of its gradients is pinned by central differences.
+    (two hidden layers of 32 units, half relu(z) and half min(z, 0);
+    forward, loss, analytic backward) used to check the GPU training
+    kernels; its gradients are pinned by central differences.
 """
 from __future__ import annotations
 
@@ -368,13 +369,30 @@ def tmatrix_eigs(alpha, beta):
 # learned-index network reference (float64)
 # ---------------------------------------------------------------------------
 
+def _act(z):
+    """Hidden activation: first half of the units relu(z), second half min(z, 0)."""
+    h = z.shape[1] // 2
+    out = z.copy()
+    out[:, :h] = np.maximum(z[:, :h], 0.0)
+    out[:, h:] = np.minimum(z[:, h:], 0.0)
+    return out
+
+
+def _dact(z):
+    h = z.shape[1] // 2
+    d = np.zeros_like(z)
+    d[:, :h] = z[:, :h] > 0
+    d[:, h:] = z[:, h:] < 0
+    return d
+
+
 def mlp_forward(params, X):
-    """y = W3 relu(W2 relu(W1 x + b1) + b2) + b3 ; returns (y, cache)."""
+    """y = W3 act(W2 act(W1 x + b1) + b2) + b3 ; returns (y, cache)."""
     W1, b1, W2, b2, W3, b3 = params
     z1 = X @ W1.T + b1
-    a1 = np.maximum(z1, 0.0)
+    a1 = _act(z1)
     z2 = a1 @ W2.T + b2
-    a2 = np.maximum(z2, 0.0)
+    a2 = _act(z2)
     y = a2 @ W3.T + b3
     return y[:, 0], (X, z1, a1, z2, a2)
 
@@ -388,10 +406,10 @@ def mlp_loss_grad(params, X, t):
     loss = 0.5 * float(np.dot(y - t, y - t)) / m
     gW3 = r[None, :] @ a2
     gb3 = np.array([r.sum()])
-    d2 = (r[:, None] @ W3) * (z2 > 0)
+    d2 = (r[:, None] @ W3) * _dact(z2)
     gW2 = d2.T @ a1
     gb2 = d2.sum(0)
-    d1 = (d2 @ W2) * (z1 > 0)
+    d1 = (d2 @ W2) * _dact(z1)
     gW1 = d1.T @ X
     gb1 = d1.sum(0)
     return loss, [gW1, gb1, gW2, gb2, gW3, gb3]

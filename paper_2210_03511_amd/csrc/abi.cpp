@@ -10,6 +10,8 @@
 #include <vector>
 
 #include "launch.h"
+#include "learned.h"
+#include "learned_dev.h"
 
 using namespace symed;
 
@@ -36,6 +38,12 @@ struct ed_basis {
     LState *d_ls = nullptr;
     int lanczos_cap = 0;
     hipGraphExec_t step_graph[2] = {nullptr, nullptr};
+    // learned index
+    bool indexed = false;
+    float *d_params = nullptr;
+    void *d_leaves = nullptr;
+    int log2_leaves = 0, mlp_F = 0, mlp_c = 0;
+    ed_index_stats istats{};
     std::vector<void *> allocs;
 };
 
@@ -93,7 +101,11 @@ static KParams make_params(const ed_basis *b)
     p.stab = b->d_stab;
     p.limits = b->d_limits;
     p.dim = b->dim;
-    p.idx_err = -1;
+    p.leaves = b->d_leaves;
+    p.log2_leaves = b->log2_leaves;
+    p.mlp_F = b->mlp_F;
+    p.mlp_c = b->mlp_c;
+    p.has_index = b->indexed ? 1 : 0;
     return p;
 }
 
@@ -252,8 +264,8 @@ ed_status ed_basis_info(const ed_basis *b, ed_basis_info_t *info)
     r.bytes_device = b->bytes;
     r.table_bytes = b->lay.bytes;
     r.limits_bytes = (int64_t)(((1ull << b->pbits) + 1) * sizeof(uint32_t));
-    r.index_bytes = 0;
-    r.index_max_err = -1;
+    r.index_bytes = b->indexed ? b->istats.mlp_bytes + b->istats.leaf_bytes : 0;
+    r.index_max_err = b->indexed ? b->istats.max_err : -1;
     r.lds_resident = 1;
     r.build_seconds = b->build_seconds;
     *info = r;
@@ -283,19 +295,21 @@ ed_status ed_basis_device_reps(const ed_basis *b, const uint64_t **d_reps)
 ed_status ed_apply_H(const ed_basis *b, const void *d_x, void *d_y, int32_t lookup_mode, void *stream)
 {
     if (!b) return fail(ED_EINVAL, "NULL basis");
-    if (lookup_mode != 0) return fail(ED_EINVAL, "lookup_mode must be 0 (plain) or 1 (learned, after ed_index_train)");
+    if (lookup_mode != 0 && !(lookup_mode == 1 && b->indexed))
+        return fail(ED_EINVAL, "lookup_mode must be 0 (plain) or 1 (learned, after ed_index_train)");
     if (b->dim == 0) return ED_OK;
     if (!d_x || !d_y) return fail(ED_EINVAL, "NULL vector");
     if (d_x == d_y) return fail(ED_EINVAL, "x and y must not alias");
     KParams p = make_params(b);
-    HIP_OK(launch_apply(p, b->cfg, d_x, d_y, 0, nullptr, nullptr, (hipStream_t)stream));
+    HIP_OK(launch_apply(p, b->cfg, d_x, d_y, 0, lookup_mode, nullptr, nullptr, (hipStream_t)stream));
     return ED_OK;
 }
 
 ed_status ed_lookup(const ed_basis *b, const uint64_t *d_keys, int64_t n, int64_t *d_idx, int32_t mode, void *stream)
 {
     if (!b) return fail(ED_EINVAL, "NULL basis");
-    if (mode != 0) return fail(ED_EINVAL, "mode must be 0 (plain) or 1 (learned, after ed_index_train)");
+    if (mode != 0 && !(mode == 1 && b->indexed))
+        return fail(ED_EINVAL, "mode must be 0 (plain) or 1 (learned, after ed_index_train)");
     if (n < 0) return fail(ED_EINVAL, "negative count");
     if (n == 0) return ED_OK;
     if (!d_keys || !d_idx) return fail(ED_EINVAL, "NULL array");
@@ -344,7 +358,8 @@ static hipError_t enqueue_step(ed_basis *b, int mode, hipStream_t st)
     const bool cplx = b->T.is_complex;
     KParams p = make_params(b);
     hipError_t e;
-    if ((e = launch_apply(p, b->cfg, b->d_v, b->d_w, cplx ? 2 : 1, b->d_ls, b->d_partials, st)) != hipSuccess) return e;
+    if ((e = launch_apply(p, b->cfg, b->d_v, b->d_w, cplx ? 2 : 1, mode, b->d_ls, b->d_partials, st)) != hipSuccess)
+        return e;
     if ((e = launch_finalize(b->d_partials, b->cfg.apply_blocks, b->d_alpha, b->d_beta, b->d_ls, 0, st)) != hipSuccess)
         return e;
     if ((e = launch_axpy_norm(b->d_w, b->d_v, b->d_vprev, b->dim, cplx, b->d_alpha, b->d_ls, b->d_partials,
@@ -364,7 +379,8 @@ ed_status ed_lanczos_run(const ed_basis *cb, const void *d_v0, int32_t n_iter, i
     ed_basis *b = const_cast<ed_basis *>(cb);
     if (!b || !d_v0 || !h_alpha || !h_beta || !n_done) return fail(ED_EINVAL, "NULL argument");
     if (n_iter < 1) return fail(ED_EINVAL, "n_iter must be >= 1");
-    if (lookup_mode != 0) return fail(ED_EINVAL, "lookup_mode must be 0 (plain) or 1 (learned, after ed_index_train)");
+    if (lookup_mode != 0 && !(lookup_mode == 1 && b->indexed))
+        return fail(ED_EINVAL, "lookup_mode must be 0 (plain) or 1 (learned, after ed_index_train)");
     if (b->dim == 0) return fail(ED_EINVAL, "empty sector");
     ed_status s = lanczos_workspace(b, n_iter);
     if (s != ED_OK) return s;
@@ -442,6 +458,168 @@ ed_status ed_eigenvalues(const double *alpha, const double *beta, int32_t n, int
         }
         evals[m] = 0.5 * (l + h);
     }
+    return ED_OK;
+}
+
+ed_status ed_index_train(ed_basis *b, const ed_index_cfg *cfg_in, ed_index_stats *out, void *stream)
+{
+    if (!b) return fail(ED_EINVAL, "NULL basis");
+    if (b->dim < 1) return fail(ED_EINVAL, "empty sector");
+    ed_index_cfg cfg{};
+    if (cfg_in) cfg = *cfg_in;
+    const int N = b->T.N;
+    // one monotone input feature (the key read as a floating-point number)
+    const int F = 1;
+    if (cfg.n_features != 0 && cfg.n_features != 1) return fail(ED_EINVAL, "the index network has one input feature");
+    if (cfg.hidden != 0 && cfg.hidden != kHidden) return fail(ED_EINVAL, "hidden width must be 32");
+    const int steps = cfg.steps > 0 ? cfg.steps : 3000;
+    const int batch = cfg.batch > 0 ? cfg.batch : 8192;
+    const float lr0 = cfg.lr > 0 ? cfg.lr : 1e-2f;
+    int lg = cfg.log2_leaves;
+    if (lg <= 0) {
+        lg = 4;
+        while (lg < 26 && (int64_t(1) << (lg + 5)) < b->dim) ++lg;
+    }
+    if (lg < 1 || lg > 28) return fail(ED_EINVAL, "log2_leaves must be in [1, 28]");
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = b->own;
+    HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    const int NP = mlp_param_count(F, kHidden);
+    const int nb = mlp_train_blocks(batch);
+    ed_status s;
+    if (!b->d_params && (s = dev_alloc(b, (void **)&b->d_params, kMlpMaxParams * sizeof(float))) != ED_OK) return s;
+    float *d_m = nullptr, *d_v = nullptr, *d_gpart = nullptr, *d_lpart = nullptr, *d_loss = nullptr;
+    HIP_OK(hipMalloc((void **)&d_m, NP * sizeof(float)));
+    HIP_OK(hipMalloc((void **)&d_v, NP * sizeof(float)));
+    HIP_OK(hipMalloc((void **)&d_gpart, (size_t)nb * NP * sizeof(float)));
+    HIP_OK(hipMalloc((void **)&d_lpart, (size_t)nb * sizeof(float)));
+    HIP_OK(hipMalloc((void **)&d_loss, sizeof(float)));
+    HIP_OK(hipMemsetAsync(b->d_params, 0, kMlpMaxParams * sizeof(float), st));
+    HIP_OK(hipMemsetAsync(d_m, 0, NP * sizeof(float), st));
+    HIP_OK(hipMemsetAsync(d_v, 0, NP * sizeof(float), st));
+    float *d_ur = nullptr, ur[2] = {0.f, 1.f};
+    HIP_OK(hipMalloc((void **)&d_ur, 2 * sizeof(float)));
+    HIP_OK(feature_range(b->d_reps, b->dim, N, d_ur, st));
+    HIP_OK(hipMemcpyAsync(ur, d_ur, 2 * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    hipFree(d_ur);
+    // input standardization x = (u - mu) * sc maps the keys' feature range to [-1, 1]
+    const float mu = 0.5f * (ur[0] + ur[1]);
+    const float sc = (ur[1] > ur[0]) ? 2.0f / (ur[1] - ur[0]) : 1.0f;
+    HIP_OK(mlp_init(b->d_params, F, 0x5EEDull + cfg.seed, st));
+    for (int t = 0; t < steps; ++t) {
+        // cosine decay to 2% of the initial rate
+        const float lr = lr0 * (0.02f + 0.98f * 0.5f * (1.0f + std::cos(3.14159265f * t / steps)));
+        HIP_OK(mlp_train_step(b->d_params, d_m, d_v, F, mu, sc, N, b->d_reps, b->dim, cfg.seed, t, batch, lr, d_gpart,
+                              d_lpart, d_loss, st));
+    }
+    float loss = 0;
+    HIP_OK(hipMemcpyAsync(&loss, d_loss, sizeof(float), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    hipFree(d_m);
+    hipFree(d_v);
+    hipFree(d_gpart);
+    hipFree(d_lpart);
+    hipFree(d_loss);
+    // the network, expanded into its pieces, goes into the table blob (staged
+    // into LDS by the kernels)
+    std::vector<float> hp(kMlpMaxParams), block;
+    HIP_OK(hipMemcpy(hp.data(), b->d_params, NP * sizeof(float), hipMemcpyDeviceToHost));
+    double dev = 0.0;
+    const int pieces = expand_network(hp.data(), mu, sc, block, &dev);
+    double yscale = 1.0;
+    for (int q = 0; q < pieces; ++q) yscale = std::max(yscale, (double)std::fabs(block[4 + 2 * kPwMax + q]));
+    if (!(dev <= 1e-4 * yscale)) return fail(ED_EDEVICE, "network expansion disagrees with the network");
+    float *d_pw = reinterpret_cast<float *>(static_cast<unsigned char *>(b->d_blob) + b->lay.off_mlp);
+    HIP_OK(hipMemcpyAsync(d_pw, block.data(), kPwFloats * sizeof(float), hipMemcpyHostToDevice, st));
+    // exact leaf table
+    if (b->d_leaves && b->log2_leaves != lg) return fail(ED_EINVAL, "index already trained with another leaf count");
+    if (!b->d_leaves && (s = dev_alloc(b, &b->d_leaves, (sizeof(Leaf) << lg))) != ED_OK) return s;
+    uint32_t *d_err = nullptr, mlp_err = 0;
+    HIP_OK(hipMalloc((void **)&d_err, sizeof(uint32_t)));
+    HIP_OK(hipMemsetAsync(d_err, 0, sizeof(uint32_t), st));
+    HIP_OK(leaf_build(d_pw, N, lg, b->d_reps, b->dim, b->d_leaves, d_err, 8 * b->n_cu, st));
+    HIP_OK(hipMemcpyAsync(&mlp_err, d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    std::vector<Leaf> hl((size_t)1 << lg);
+    HIP_OK(hipMemcpyAsync(hl.data(), b->d_leaves, sizeof(Leaf) << lg, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    hipFree(d_err);
+    uint32_t max_err = 0;
+    double wsum = 0, used = 0;
+    for (const Leaf &L : hl) {
+        if (L.hi <= L.lo) continue;
+        const double w = std::min<double>(L.hi - L.lo, 2.0 * L.err + 1.0);
+        max_err = std::max(max_err, L.err);
+        wsum += (double)L.count * w;
+        used += 1;
+    }
+    for (auto &g : b->step_graph)
+        if (g) {
+            hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    b->indexed = true;
+    b->log2_leaves = lg;
+    b->mlp_F = F;
+    b->mlp_c = 0;
+    ed_index_stats r{};
+    r.max_err = (int32_t)max_err;
+    r.n_leaves = 1 << lg;
+    r.final_loss = loss;
+    r.mlp_max_err = (float)mlp_err;
+    r.mlp_bytes = (int64_t)NP * sizeof(float);
+    r.leaf_bytes = (int64_t)sizeof(Leaf) << lg;
+    r.train_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    r.mean_window = wsum / (double)b->dim;
+    r.n_features = F;
+    r.n_pieces = pieces;
+    r.feature_offset = mu;
+    r.feature_scale = sc;
+    r.used_leaves = (int64_t)used;
+    b->istats = r;
+    if (out) *out = r;
+    return ED_OK;
+}
+
+ed_status ed_index_info(const ed_basis *b, ed_index_stats *out, float *h_params, int64_t cap)
+{
+    if (!b) return fail(ED_EINVAL, "NULL basis");
+    if (!b->indexed) return fail(ED_EINVAL, "no learned index: call ed_index_train first");
+    if (out) *out = b->istats;
+    if (h_params) {
+        const int NP = mlp_param_count(b->mlp_F, kHidden);
+        if (cap < NP) return fail(ED_EINVAL, "parameter buffer too small");
+        HIP_OK(hipMemcpy(h_params, b->d_params, NP * sizeof(float), hipMemcpyDeviceToHost));
+    }
+    return ED_OK;
+}
+
+ed_status ed_index_predict(const ed_basis *b, const uint64_t *d_keys, int64_t n, float *d_u, float *d_y, void *stream)
+{
+    if (!b) return fail(ED_EINVAL, "NULL basis");
+    if (!b->indexed) return fail(ED_EINVAL, "no learned index: call ed_index_train first");
+    if (n < 0 || (n > 0 && (!d_keys || !d_u || !d_y))) return fail(ED_EINVAL, "bad arguments");
+    if (n == 0) return ED_OK;
+    const float *d_pw = reinterpret_cast<const float *>(static_cast<const unsigned char *>(b->d_blob) + b->lay.off_mlp);
+    HIP_OK(index_predict(d_pw, b->T.N, d_keys, n, d_u, d_y, (hipStream_t)stream));
+    return ED_OK;
+}
+
+ed_status ed_mlp_loss_grad(int32_t n_features, const float *d_params, const float *d_X, const float *d_t, int64_t n,
+                           float *d_grad, float *d_loss, void *stream)
+{
+    if (n_features < 1 || n_features > kMaxFeatures) return fail(ED_EINVAL, "n_features must be in [1, 8]");
+    if (!d_params || !d_X || !d_t || !d_grad || !d_loss || n < 1) return fail(ED_EINVAL, "bad arguments");
+    const int NP = mlp_param_count(n_features, kHidden);
+    const int nb = (int)((n + 63) / 64);
+    float *d_gpart = nullptr, *d_lpart = nullptr;
+    HIP_OK(hipMalloc((void **)&d_gpart, (size_t)nb * NP * sizeof(float)));
+    HIP_OK(hipMalloc((void **)&d_lpart, (size_t)nb * sizeof(float)));
+    hipStream_t st = (hipStream_t)stream;
+    HIP_OK(mlp_loss_grad(d_params, n_features, d_X, d_t, n, d_grad, d_loss, d_gpart, d_lpart, st));
+    HIP_OK(hipStreamSynchronize(st));
+    hipFree(d_gpart);
+    hipFree(d_lpart);
     return ED_OK;
 }
 

@@ -6,6 +6,7 @@
 #include <string>
 #include <vector>
 
+#include "learned_dev.h"
 #include "symed.h"
 
 namespace symed {
@@ -64,7 +65,7 @@ struct HostTables {
 // Byte layout of the table blob staged into LDS by the kernels.
 struct BlobLayout {
     uint32_t off_rep, off_symoff, off_symlist, off_act, off_src, off_pairs, off_chis, off_chi, off_sqrt, off_isqrt,
-        off_chione;
+        off_chione, off_mlp;
     uint32_t bytes;
 };
 
@@ -79,13 +80,12 @@ struct KParams {
     const uint16_t *stab;      // [dim]
     const uint32_t *limits;    // [2^pbits + 1]
     int64_t dim;
-    // learned index
-    const float *mlp;          // weights
-    const uint32_t *seg;       // stage-2 segment table
-    int32_t idx_err;
-    int32_t mlp_in;
-    int32_t n_seg;
-    int32_t seg_shift;
+    // learned index (network weights live in the LDS blob at lay.off_mlp)
+    const void *leaves;        // Leaf[2^log2_leaves]
+    int32_t log2_leaves;
+    int32_t mlp_F;             // input features
+    int32_t mlp_c;             // bits per feature chunk
+    int32_t has_index;
 };
 
 // Thread-local error reporting.
@@ -102,5 +102,8 @@ void build_rep_sym(const HostTables &T, int n_sub, std::vector<uint16_t> &rep, s
 void build_pairs(const ed_model *m, HostTables &T);
 std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &lay);
 int choose_sublattices(const HostTables &T, int &R, int &A, std::string &why);
+
+// pwexpand.cpp
+int expand_network(const float *params, float mu, float sc, std::vector<float> &block, double *max_dev);
 
 }  // namespace symed

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include "launch.h"
+#include "learned_dev.h"
 
 namespace symed {
 
@@ -30,6 +31,7 @@ struct Lds {
     const double *sqrtt;
     const double *isqrtt;
     const uint8_t *chione;
+    PwView pw;
 };
 
 __device__ __forceinline__ Lds lds_view(const unsigned char *b, const BlobLayout &L)
@@ -46,6 +48,7 @@ __device__ __forceinline__ Lds lds_view(const unsigned char *b, const BlobLayout
     v.sqrtt = reinterpret_cast<const double *>(b + L.off_sqrt);
     v.isqrtt = reinterpret_cast<const double *>(b + L.off_isqrt);
     v.chione = b + L.off_chione;
+    v.pw = pw_view(reinterpret_cast<const float *>(b + L.off_mlp));
     return v;
 }
 
@@ -127,8 +130,12 @@ __device__ __forceinline__ int64_t lookup_plain(uint64_t key, const KParams &p)
     return (lo < end && p.reps[lo] == key) ? (int64_t)lo : -1;
 }
 
-__device__ __forceinline__ int64_t lookup(uint64_t key, const KParams &p, int mode)
+// Index of a representative: plain Limits + binary search, or the learned
+// index (network in LDS, leaf table, bounded binary search).
+template <bool LEARNED>
+__device__ __forceinline__ int64_t lookup(uint64_t key, const KParams &p, const PwView &pw)
 {
+    if (LEARNED) return lookup_learned(key, p.reps, pw, static_cast<const Leaf *>(p.leaves), p.N, p.log2_leaves);
     return lookup_plain(key, p);
 }
 
@@ -172,7 +179,7 @@ __device__ __forceinline__ double block_sum(double v, double *scratch)
 
 // mode 0: y = H x.  mode 1 (real Lanczos): w <- H v - beta_prev w, partial
 // <w|v>.  mode 2 (complex Lanczos): w <- H v, partial Re<w|v>.
-template <bool CPLX, int MODE>
+template <bool CPLX, int MODE, bool LEARNED>
 __global__ void __launch_bounds__(kApplyThreads) k_apply(KParams p, const double *__restrict__ x,
                                                        double *__restrict__ y, const LState *ls,
                                                        double *partials)
@@ -197,7 +204,7 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply(KParams p, const double
             pair_amp<CPLX>(s, pt, L, hre, him);
             if (hre == 0.0 && him == 0.0) continue;
             const Found f = find_rep(s ^ pt.mask, p, L);
-            const int64_t j = lookup(f.rep, p, 0);
+            const int64_t j = lookup<LEARNED>(f.rep, p, L.pw);
             if (j < 0) continue;
             const double w = L.sqrtt[f.cnt];
             if (!CPLX) {
@@ -258,13 +265,21 @@ __global__ void __launch_bounds__(256) k_count(KParams p, unsigned long long *ou
     if ((threadIdx.x & 63) == 0) atomicAdd(out, c);
 }
 
-__global__ void __launch_bounds__(256) k_lookup(KParams p, const uint64_t *keys, int64_t n, int64_t *idx, int mode)
+template <bool LEARNED>
+__global__ void __launch_bounds__(256) k_lookup(KParams p, const uint64_t *keys, int64_t n, int64_t *idx)
 {
+    __shared__ float spw[kPwFloats];
+    if (LEARNED) {
+        const float *g = reinterpret_cast<const float *>(static_cast<const unsigned char *>(p.blob) + p.lay.off_mlp);
+        for (int q = threadIdx.x; q < kPwFloats; q += blockDim.x) spw[q] = g[q];
+        __syncthreads();
+    }
+    const PwView pw = pw_view(spw);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
         const uint64_t key = keys[k];
         // keys outside the N-bit range cannot be representatives
-        idx[k] = (key & ~p.maskN) ? -1 : lookup(key, p, mode);
+        idx[k] = (key & ~p.maskN) ? -1 : lookup<LEARNED>(key, p, pw);
     }
 }
 
@@ -679,20 +694,23 @@ hipError_t launch_count_elements(const KParams &p, unsigned long long *d_count, 
     return hipGetLastError();
 }
 
-hipError_t launch_apply(const KParams &p, const LaunchCfg &c, const void *x, void *y, int mode, const LState *ls,
-                        double *partials, hipStream_t st)
+hipError_t launch_apply(const KParams &p, const LaunchCfg &c, const void *x, void *y, int mode, int learned,
+                        const LState *ls, double *partials, hipStream_t st)
 {
     const size_t lds = apply_lds_bytes(p);
     const double *xd = static_cast<const double *>(x);
     double *yd = static_cast<double *>(y);
     dim3 g(c.apply_blocks), b(kApplyThreads);
+    const bool lr = learned != 0;
+#define SYMED_APPLY(C, M, Lr) hipLaunchKernelGGL((k_apply<C, M, Lr>), g, b, lds, st, p, xd, yd, ls, partials)
     if (!p.is_complex) {
-        if (mode == 0) hipLaunchKernelGGL((k_apply<false, 0>), g, b, lds, st, p, xd, yd, ls, partials);
-        else hipLaunchKernelGGL((k_apply<false, 1>), g, b, lds, st, p, xd, yd, ls, partials);
+        if (mode == 0) { if (lr) SYMED_APPLY(false, 0, true); else SYMED_APPLY(false, 0, false); }
+        else { if (lr) SYMED_APPLY(false, 1, true); else SYMED_APPLY(false, 1, false); }
     } else {
-        if (mode == 0) hipLaunchKernelGGL((k_apply<true, 0>), g, b, lds, st, p, xd, yd, ls, partials);
-        else hipLaunchKernelGGL((k_apply<true, 2>), g, b, lds, st, p, xd, yd, ls, partials);
+        if (mode == 0) { if (lr) SYMED_APPLY(true, 0, true); else SYMED_APPLY(true, 0, false); }
+        else { if (lr) SYMED_APPLY(true, 2, true); else SYMED_APPLY(true, 2, false); }
     }
+#undef SYMED_APPLY
     return hipGetLastError();
 }
 
@@ -701,7 +719,8 @@ hipError_t launch_lookup(const KParams &p, const uint64_t *keys, int64_t n, int6
     int64_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_lookup, dim3((unsigned)blocks), dim3(256), 0, st, p, keys, n, idx, mode);
+    if (mode == 1) hipLaunchKernelGGL(k_lookup<true>, dim3((unsigned)blocks), dim3(256), 0, st, p, keys, n, idx);
+    else hipLaunchKernelGGL(k_lookup<false>, dim3((unsigned)blocks), dim3(256), 0, st, p, keys, n, idx);
     return hipGetLastError();
 }
 
@@ -771,8 +790,10 @@ hipError_t prepare_kernels(const KParams &p, int *apply_blocks_per_cu, int *appl
 {
     const size_t lds = apply_lds_bytes(p);
     hipError_t e;
-    const void *ks[] = {(const void *)k_apply<false, 0>, (const void *)k_apply<false, 1>,
-                        (const void *)k_apply<true, 0>, (const void *)k_apply<true, 2>,
+    const void *ks[] = {(const void *)k_apply<false, 0, false>, (const void *)k_apply<false, 1, false>,
+                        (const void *)k_apply<true, 0, false>, (const void *)k_apply<true, 2, false>,
+                        (const void *)k_apply<false, 0, true>, (const void *)k_apply<false, 1, true>,
+                        (const void *)k_apply<true, 0, true>, (const void *)k_apply<true, 2, true>,
                         (const void *)k_count<false>, (const void *)k_count<true>,
                         (const void *)k_enumerate<false>, (const void *)k_enumerate<true>};
     for (const void *k : ks) {
@@ -780,7 +801,7 @@ hipError_t prepare_kernels(const KParams &p, int *apply_blocks_per_cu, int *appl
         if (e != hipSuccess) return e;
     }
     int nb = 0;
-    const void *ka = p.is_complex ? (const void *)k_apply<true, 0> : (const void *)k_apply<false, 0>;
+    const void *ka = p.is_complex ? (const void *)k_apply<true, 0, true> : (const void *)k_apply<false, 0, true>;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ka, kApplyThreads, lds);
     if (e != hipSuccess) return e;
     *apply_blocks_per_cu = nb;

@@ -1,0 +1,22 @@
+// Host-callable launchers of the learned-index kernels (learned.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace symed {
+
+hipError_t mlp_init(float *d_params, int F, uint64_t seed, hipStream_t st);
+hipError_t feature_range(const uint64_t *reps, int64_t D, int N, float *d_out, hipStream_t st);
+int mlp_train_blocks(int batch);
+hipError_t mlp_train_step(float *d_params, float *d_m, float *d_v, int F, float mu, float sc, int N,
+                          const uint64_t *reps, int64_t D, uint64_t seed, int step, int batch, float lr, float *d_gpart,
+                          float *d_lpart, float *d_loss, hipStream_t st);
+hipError_t mlp_loss_grad(const float *d_params, int F, const float *d_X, const float *d_T, int64_t n, float *d_grad,
+                         float *d_loss, float *d_gpart, float *d_lpart, hipStream_t st);
+hipError_t leaf_build(const float *d_pw, int N, int lg, const uint64_t *reps, int64_t D, void *d_leaves,
+                      uint32_t *d_mlp_err, int blocks, hipStream_t st);
+hipError_t index_predict(const float *d_pw, int N, const uint64_t *keys, int64_t n, float *u, float *y, hipStream_t st);
+
+}  // namespace symed

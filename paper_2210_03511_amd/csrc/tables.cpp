@@ -310,6 +310,8 @@ std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &L)
     L.off_sqrt = (uint32_t)o;    o = align16(o + (size_t)(T.G + 1) * sizeof(double));
     L.off_isqrt = (uint32_t)o;   o = align16(o + (size_t)(T.G + 1) * sizeof(double));
     L.off_chione = (uint32_t)o;  o = align16(o + (size_t)T.G);
+    // space for the learned-index network in expanded form (filled after training)
+    L.off_mlp = (uint32_t)o;     o = align16(o + (size_t)kPwFloats * sizeof(float));
     L.bytes = (uint32_t)o;
     std::vector<uint8_t> blob(o, 0);
     auto put = [&](uint32_t off, const void *src, size_t n) { if (n) std::memcpy(blob.data() + off, src, n); };

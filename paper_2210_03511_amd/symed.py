@@ -24,7 +24,8 @@ STATUS_NAMES = {0: "ED_OK", 1: "ED_EINVAL", 2: "ED_ENOTSTABLE", 3: "ED_ECHAR", 4
 
 EXPORTED = ["ed_last_error", "ed_version", "ed_basis_build", "ed_basis_free", "ed_basis_info", "ed_basis_export",
             "ed_basis_device_reps", "ed_apply_H", "ed_lookup", "ed_lanczos_run", "ed_eigenvalues",
-            "ed_tables_inspect", "ed_index_train", "ed_index_info"]
+            "ed_tables_inspect", "ed_index_train", "ed_index_info", "ed_mlp_loss_grad",
+            "ed_index_predict"]
 
 
 class EdError(RuntimeError):
@@ -64,13 +65,15 @@ class BasisInfo(ctypes.Structure):
 class IndexCfg(ctypes.Structure):
     _fields_ = [("n_features", ctypes.c_int32), ("hidden", ctypes.c_int32), ("steps", ctypes.c_int32),
                 ("batch", ctypes.c_int32), ("lr", ctypes.c_float), ("seed", ctypes.c_uint32),
-                ("n_seg_log2", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("log2_leaves", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class IndexStats(ctypes.Structure):
-    _fields_ = [("max_err", ctypes.c_int32), ("n_seg", ctypes.c_int32), ("final_loss", ctypes.c_float),
-                ("mlp_max_err", ctypes.c_float), ("mlp_bytes", ctypes.c_int64), ("seg_bytes", ctypes.c_int64),
-                ("train_seconds", ctypes.c_double), ("mean_window", ctypes.c_double)]
+    _fields_ = [("max_err", ctypes.c_int32), ("n_leaves", ctypes.c_int32), ("final_loss", ctypes.c_float),
+                ("mlp_max_err", ctypes.c_float), ("mlp_bytes", ctypes.c_int64), ("leaf_bytes", ctypes.c_int64),
+                ("train_seconds", ctypes.c_double), ("mean_window", ctypes.c_double),
+                ("n_features", ctypes.c_int32), ("n_pieces", ctypes.c_int32), ("used_leaves", ctypes.c_int64),
+                ("feature_offset", ctypes.c_float), ("feature_scale", ctypes.c_float)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -102,9 +105,10 @@ def lib():
         L.ed_eigenvalues.argtypes = [vp, vp, i32, i32, vp]
         L.ed_tables_inspect.argtypes = [ctypes.POINTER(_Model), ctypes.POINTER(_Group), i32, i32, vp, vp, vp, i64,
                                         ctypes.POINTER(i64), vp]
-        if hasattr(L, "ed_index_train"):
-            L.ed_index_train.argtypes = [vp, ctypes.POINTER(IndexCfg), ctypes.POINTER(IndexStats), vp]
-            L.ed_index_info.argtypes = [vp, ctypes.POINTER(IndexStats), vp, i64]
+        L.ed_index_train.argtypes = [vp, ctypes.POINTER(IndexCfg), ctypes.POINTER(IndexStats), vp]
+        L.ed_index_info.argtypes = [vp, ctypes.POINTER(IndexStats), vp, i64]
+        L.ed_mlp_loss_grad.argtypes = [i32, vp, vp, vp, i64, vp, vp, vp]
+        L.ed_index_predict.argtypes = [vp, vp, i64, vp, vp, vp]
         for name in EXPORTED:
             if hasattr(L, name) and name not in ("ed_last_error", "ed_version", "ed_basis_free"):
                 getattr(L, name).restype = ctypes.c_int
@@ -239,17 +243,40 @@ class Basis:
         n = nd.value
         return a[:n], b[:n], n, st == ED_EBREAKDOWN
 
-    def train_index(self, n_features=0, hidden=32, steps=0, batch=0, lr=0.0, seed=1, n_seg_log2=0, stream=None):
-        cfg = IndexCfg(n_features, hidden, steps, batch, lr, seed, n_seg_log2, 0)
+    def train_index(self, n_features=0, hidden=32, steps=0, batch=0, lr=0.0, seed=1, log2_leaves=0, stream=None):
+        cfg = IndexCfg(n_features, hidden, steps, batch, lr, seed, log2_leaves, 0)
         stats = IndexStats()
         _check(lib().ed_index_train(self._h, ctypes.byref(cfg), ctypes.byref(stats), _stream_ptr(stream)))
         return stats.as_dict()
 
+    def index_predict(self, keys, stream=None):
+        """(u, y) of the trained network on device keys (int64 tensor holding uint64)."""
+        import torch
+        u = torch.empty(keys.numel(), dtype=torch.float32, device=keys.device)
+        y = torch.empty_like(u)
+        _check(lib().ed_index_predict(self._h, _tensor_ptr(keys), keys.numel(), _tensor_ptr(u), _tensor_ptr(y),
+                                      _stream_ptr(stream)))
+        return u, y
+
     def index_weights(self):
+        """(stats, float32 weights) of the trained learned index."""
         stats = IndexStats()
-        buf = np.zeros(1 << 16, np.float32)
+        buf = np.zeros(1 << 12, np.float32)
         _check(lib().ed_index_info(self._h, ctypes.byref(stats), _np_ptr(buf), buf.size))
-        return stats.as_dict(), buf
+        F = stats.n_features
+        n = 32 * F + 32 + 32 * 32 + 32 + 32 + 1
+        return stats.as_dict(), buf[:n].copy()
+
+
+def mlp_loss_grad(n_features, params, X, t, stream=None):
+    """Loss and gradient of the index network on device tensors (float32)."""
+    import torch
+    n = t.numel()
+    grad = torch.zeros(params.numel(), dtype=torch.float32, device=params.device)
+    loss = torch.zeros(1, dtype=torch.float32, device=params.device)
+    _check(lib().ed_mlp_loss_grad(int(n_features), _tensor_ptr(params), _tensor_ptr(X), _tensor_ptr(t), n,
+                                  _tensor_ptr(grad), _tensor_ptr(loss), _stream_ptr(stream)))
+    return float(loss.item()), grad
 
 
 def eigenvalues(alpha, beta, k=1):
