@@ -11,46 +11,22 @@
 
 #include "launch.h"
 #include "learned_dev.h"
+#include "represent.h"
 
 namespace symed {
 
 namespace {
 
-constexpr int kApplyThreads = 512;
+// Compile-time tuning knobs (block size of the H.v kernel, lookups kept in
+// flight per lane).
+#ifndef SYMED_APPLY_THREADS
+#define SYMED_APPLY_THREADS 1024
+#endif
+#ifndef SYMED_KBATCH
+#define SYMED_KBATCH 4
+#endif
+constexpr int kApplyThreads = SYMED_APPLY_THREADS;
 constexpr int kVecThreads = 256;
-
-struct Lds {
-    const uint16_t *rep;
-    const uint32_t *symoff;
-    const uint32_t *symlist;
-    const uint8_t *act;
-    const uint64_t *src;
-    const PairTerm *pairs;
-    const ChiTerm *chis;
-    const double *chi;
-    const double *sqrtt;
-    const double *isqrtt;
-    const uint8_t *chione;
-    PwView pw;
-};
-
-__device__ __forceinline__ Lds lds_view(const unsigned char *b, const BlobLayout &L)
-{
-    Lds v;
-    v.rep = reinterpret_cast<const uint16_t *>(b + L.off_rep);
-    v.symoff = reinterpret_cast<const uint32_t *>(b + L.off_symoff);
-    v.symlist = reinterpret_cast<const uint32_t *>(b + L.off_symlist);
-    v.act = b + L.off_act;
-    v.src = reinterpret_cast<const uint64_t *>(b + L.off_src);
-    v.pairs = reinterpret_cast<const PairTerm *>(b + L.off_pairs);
-    v.chis = reinterpret_cast<const ChiTerm *>(b + L.off_chis);
-    v.chi = reinterpret_cast<const double *>(b + L.off_chi);
-    v.sqrtt = reinterpret_cast<const double *>(b + L.off_sqrt);
-    v.isqrtt = reinterpret_cast<const double *>(b + L.off_isqrt);
-    v.chione = b + L.off_chione;
-    v.pw = pw_view(reinterpret_cast<const float *>(b + L.off_mlp));
-    return v;
-}
 
 // Copy the table blob (multiple of 16 bytes) into LDS.
 __device__ __forceinline__ void stage_blob(unsigned char *lds, const void *blob, uint32_t bytes)
@@ -59,60 +35,6 @@ __device__ __forceinline__ void stage_blob(unsigned char *lds, const void *blob,
     uint4 *d = reinterpret_cast<uint4 *>(lds);
     for (uint32_t k = threadIdx.x; k < bytes / 16u; k += blockDim.x) d[k] = s[k];
     __syncthreads();
-}
-
-struct Found {
-    uint64_t rep;
-    uint32_t g;
-    uint32_t cnt;  // number of group elements reaching the representative = |Stab|
-};
-
-// Representative of t by sublattice coding (algorithm "Sublattice coding
-// algorithm for finding the representative"): MinRep over the coarse
-// sublattices, then every symmetry in Sym_Y of each sublattice Y attaining
-// MinRep is applied through the SymmetryAction tables of the fine
-// decomposition (destination-major, so the image is assembled most
-// significant sublattice first).  All minimizers lie among these candidates
-// and each group element is a candidate at most once, so the number of
-// candidates reaching the minimum is the stabilizer size.
-__device__ __forceinline__ Found find_rep(uint64_t t, const KParams &p, const Lds &L)
-{
-    const int N = p.N, R = p.R, br = p.br, A = p.A, ba = p.ba;
-    const uint32_t S = 1u << br, mr = S - 1u, ma = (1u << ba) - 1u;
-    uint32_t minrep = 0xffffffffu;
-    for (int X = 0; X < R; ++X) {
-        uint32_t s = (uint32_t)(t >> (N - (X + 1) * br)) & mr;
-        minrep = min(minrep, (uint32_t)L.rep[X * S + s]);
-    }
-    uint64_t best = ~0ull;
-    uint32_t bg = 0, cnt = 0;
-    for (int X = 0; X < R; ++X) {
-        uint32_t s = (uint32_t)(t >> (N - (X + 1) * br)) & mr;
-        uint32_t idx = X * S + s;
-        if (L.rep[idx] != minrep) continue;
-        const uint32_t k1 = L.symoff[idx + 1];
-        for (uint32_t k = L.symoff[idx]; k < k1; ++k) {
-            const uint32_t e = L.symlist[k];
-            const uint32_t sp = (e >> 1) & 0x7fffu;
-            const uint64_t srcw = L.src[sp];
-            const uint8_t *a = L.act + (size_t)sp * ((uint32_t)A << ba);
-            uint64_t v = 0;
-            for (int d = 0; d < A; ++d) {
-                const uint32_t x = (uint32_t)(srcw >> (4 * d)) & 15u;
-                const uint32_t ss = (uint32_t)(t >> (N - (int)(x + 1) * ba)) & ma;
-                v = (v << ba) | a[(d << ba) + ss];
-            }
-            if (e & 1u) v ^= p.maskN;
-            if (v < best) {
-                best = v;
-                bg = e >> 16;
-                cnt = 1;
-            } else if (v == best) {
-                ++cnt;
-            }
-        }
-    }
-    return Found{best, bg, cnt};
 }
 
 // Plain index lookup: Limits(prefix) = [begin, end) then binary search
@@ -128,6 +50,106 @@ __device__ __forceinline__ int64_t lookup_plain(uint64_t key, const KParams &p)
         if (p.reps[mid] < key) lo = mid + 1; else hi = mid;
     }
     return (lo < end && p.reps[lo] == key) ? (int64_t)lo : -1;
+}
+
+// K independent lookups advanced in lockstep: every round issues the probe
+// loads of all unfinished searches before comparing, so one lane keeps up
+// to K dependent-load chains in flight.  valid bit k set = slot k in use.
+template <int K>
+__device__ __forceinline__ void lookup_plain_batch(const uint64_t (&key)[K], uint32_t valid, const KParams &p,
+                                                   int64_t (&j)[K])
+{
+    uint32_t lo[K], hi[K], end[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (((valid >> k) & 1u) && key[k] <= p.maskN) {
+            const uint64_t pf = key[k] >> (p.N - p.pbits);
+            lo[k] = p.limits[pf];
+            hi[k] = p.limits[pf + 1];
+        } else {
+            lo[k] = hi[k] = 0;
+        }
+        end[k] = hi[k];
+    }
+    for (;;) {
+        uint64_t v[K];
+        uint32_t mid[K];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            mid[k] = (lo[k] + hi[k]) >> 1;
+            if (lo[k] < hi[k]) {
+                v[k] = p.reps[mid[k]];
+                any = true;
+            }
+        }
+        if (!any) break;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (lo[k] < hi[k]) {
+                if (v[k] < key[k]) lo[k] = mid[k] + 1; else hi[k] = mid[k];
+            }
+    }
+    uint64_t f[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) f[k] = (lo[k] < end[k]) ? p.reps[lo[k]] : ~key[k];
+#pragma unroll
+    for (int k = 0; k < K; ++k) j[k] = (lo[k] < end[k] && f[k] == key[k]) ? (int64_t)lo[k] : -1;
+}
+
+template <int K>
+__device__ __forceinline__ void lookup_learned_batch(const uint64_t (&key)[K], uint32_t valid, const KParams &p,
+                                                     const PwView &pw, int64_t (&j)[K])
+{
+    const Leaf *leaves = static_cast<const Leaf *>(p.leaves);
+    Leaf Lf[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if ((valid >> k) & 1u) {
+            uint32_t b;
+            float frac;
+            leaf_of(pw_eval(pw, key_feature(key[k], p.N)), p.log2_leaves, b, frac);
+            Lf[k] = leaves[b];
+        } else {
+            Lf[k] = Leaf{0u, 0u, 0u, 0u, 0ull, 0.0};
+        }
+    }
+    uint32_t lo[K], hi[K], end[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (Lf[k].lo < Lf[k].hi) {
+            const uint32_t pred = leaf_predict(Lf[k], key[k]);
+            lo[k] = (pred > Lf[k].lo + Lf[k].err) ? pred - Lf[k].err : Lf[k].lo;
+            hi[k] = (pred + Lf[k].err + 1 < Lf[k].hi) ? pred + Lf[k].err + 1 : Lf[k].hi;
+        } else {
+            lo[k] = hi[k] = 0;
+        }
+        end[k] = hi[k];
+    }
+    for (;;) {
+        uint64_t v[K];
+        uint32_t mid[K];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            mid[k] = (lo[k] + hi[k]) >> 1;
+            if (lo[k] < hi[k]) {
+                v[k] = p.reps[mid[k]];
+                any = true;
+            }
+        }
+        if (!any) break;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (lo[k] < hi[k]) {
+                if (v[k] < key[k]) lo[k] = mid[k] + 1; else hi[k] = mid[k];
+            }
+    }
+    uint64_t f[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) f[k] = (lo[k] < end[k]) ? p.reps[lo[k]] : ~key[k];
+#pragma unroll
+    for (int k = 0; k < K; ++k) j[k] = (lo[k] < end[k] && f[k] == key[k]) ? (int64_t)lo[k] : -1;
 }
 
 // Index of a representative: plain Limits + binary search, or the learned
@@ -177,6 +199,40 @@ __device__ __forceinline__ double block_sum(double v, double *scratch)
     return t;
 }
 
+constexpr int kBatch = SYMED_KBATCH;  // lookups in flight per lane
+
+// Flush the pending (key, coefficient) slots: lookups in lockstep, then the
+// gathers of x_j, accumulated oldest slot first (the order the pieces were
+// generated), so the sum is the same as one piece at a time.
+template <bool CPLX, bool LEARNED>
+__device__ __forceinline__ void flush_batch(const uint64_t (&key)[kBatch], const double (&cr)[kBatch],
+                                            const double (&ci)[kBatch], uint32_t valid, const KParams &p,
+                                            const PwView &pw, const double *__restrict__ x, double &ar, double &ai)
+{
+    int64_t j[kBatch];
+    if (LEARNED) lookup_learned_batch<kBatch>(key, valid, p, pw, j);
+    else lookup_plain_batch<kBatch>(key, valid, p, j);
+    double xr[kBatch], xi[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+        if (j[k] >= 0) {
+            xr[k] = CPLX ? x[2 * j[k]] : x[j[k]];
+            xi[k] = CPLX ? x[2 * j[k] + 1] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+        if (j[k] >= 0) {
+            if (!CPLX) {
+                ar += cr[k] * xr[k];
+            } else {
+                ar += cr[k] * xr[k] - ci[k] * xi[k];
+                ai += cr[k] * xi[k] + ci[k] * xr[k];
+            }
+        }
+    }
+}
+
 // mode 0: y = H x.  mode 1 (real Lanczos): w <- H v - beta_prev w, partial
 // <w|v>.  mode 2 (complex Lanczos): w <- H v, partial Re<w|v>.
 template <bool CPLX, int MODE, bool LEARNED>
@@ -195,6 +251,15 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply(KParams p, const double
         const uint64_t s = p.reps[i];
         const double isq = L.isqrtt[p.stab[i]];
         double diag = 0.0, ar = 0.0, ai = 0.0;
+        // pending pieces, oldest in slot 0
+        uint64_t key[kBatch];
+        double cr[kBatch], ci[kBatch];
+        uint32_t valid = 0;
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            key[k] = 0;
+            cr[k] = ci[k] = 0.0;
+        }
         for (int q = 0; q < p.n_pairs; ++q) {
             const PairTerm pt = L.pairs[q];
             const bool anti = __popcll(s & pt.mask) == 1;
@@ -204,20 +269,32 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply(KParams p, const double
             pair_amp<CPLX>(s, pt, L, hre, him);
             if (hre == 0.0 && him == 0.0) continue;
             const Found f = find_rep(s ^ pt.mask, p, L);
-            const int64_t j = lookup<LEARNED>(f.rep, p, L.pw);
-            if (j < 0) continue;
             const double w = L.sqrtt[f.cnt];
+            double kr, ki = 0.0;
             if (!CPLX) {
-                ar += L.chi[f.g] * w * hre * x[j];
+                kr = L.chi[f.g] * w * hre;
             } else {
-                // chi(g) * w * conj(h) * x_j
-                const double cr = L.chi[2 * f.g] * w, ci = L.chi[2 * f.g + 1] * w;
-                const double kr = cr * hre + ci * him, ki = ci * hre - cr * him;
-                const double xr = x[2 * j], xi = x[2 * j + 1];
-                ar += kr * xr - ki * xi;
-                ai += kr * xi + ki * xr;
+                // chi(g) * w * conj(h)
+                const double c_r = L.chi[2 * f.g] * w, c_i = L.chi[2 * f.g + 1] * w;
+                kr = c_r * hre + c_i * him;
+                ki = c_i * hre - c_r * him;
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch - 1; ++k) {
+                key[k] = key[k + 1];
+                cr[k] = cr[k + 1];
+                ci[k] = ci[k + 1];
+            }
+            key[kBatch - 1] = f.rep;
+            cr[kBatch - 1] = kr;
+            ci[kBatch - 1] = ki;
+            valid = (valid >> 1) | (1u << (kBatch - 1));
+            if (valid & 1u) {
+                flush_batch<CPLX, LEARNED>(key, cr, ci, valid, p, L.pw, x, ar, ai);
+                valid = 0;
             }
         }
+        if (valid) flush_batch<CPLX, LEARNED>(key, cr, ci, valid, p, L.pw, x, ar, ai);
         if (!CPLX) {
             const double xi = x[i];
             double yi = diag * xi + isq * ar;
@@ -608,7 +685,7 @@ __global__ void k_lstate_init(LState *ls)
 // launchers
 // ---------------------------------------------------------------------------
 
-size_t apply_lds_bytes(const KParams &p) { return (size_t)p.lay.bytes + 16 * sizeof(double); }
+size_t apply_lds_bytes(const KParams &p) { return (size_t)p.lay.bytes + 32 * sizeof(double); }
 
 hipError_t launch_enumerate(const KParams &p, const uint64_t *d_binom, uint64_t total, uint64_t chunk_len,
                             uint64_t n_chunks, uint32_t *d_counts, const uint64_t *d_offsets, uint64_t *d_reps,

@@ -93,7 +93,7 @@ __device__ __forceinline__ float pw_eval(const PwView &w, float u)
     return fmaf(w.slope[lo], u, w.icpt[lo]);
 }
 
-__device__ __forceinline__ PwView pw_view(const float *base)
+__host__ __device__ __forceinline__ PwView pw_view(const float *base)
 {
     PwView w;
     w.n = (int)base[0];

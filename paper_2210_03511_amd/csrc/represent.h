@@ -1,0 +1,126 @@
+// Sublattice-coded representative search (host and device).
+//
+// Shared by the H.v and enumeration kernels; also compiled for the host so
+// the same code can be checked against brute force on the CPU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "learned_dev.h"
+
+namespace symed {
+
+struct Lds {
+    const uint16_t *rep;
+    const uint32_t *symoff;
+    const uint32_t *symlist;
+    const uint8_t *act;
+    const uint64_t *src;
+    const PairTerm *pairs;
+    const ChiTerm *chis;
+    const double *chi;
+    const double *sqrtt;
+    const double *isqrtt;
+    const uint8_t *chione;
+    PwView pw;
+};
+
+__host__ __device__ __forceinline__ Lds lds_view(const unsigned char *b, const BlobLayout &L)
+{
+    Lds v;
+    v.rep = reinterpret_cast<const uint16_t *>(b + L.off_rep);
+    v.symoff = reinterpret_cast<const uint32_t *>(b + L.off_symoff);
+    v.symlist = reinterpret_cast<const uint32_t *>(b + L.off_symlist);
+    v.act = b + L.off_act;
+    v.src = reinterpret_cast<const uint64_t *>(b + L.off_src);
+    v.pairs = reinterpret_cast<const PairTerm *>(b + L.off_pairs);
+    v.chis = reinterpret_cast<const ChiTerm *>(b + L.off_chis);
+    v.chi = reinterpret_cast<const double *>(b + L.off_chi);
+    v.sqrtt = reinterpret_cast<const double *>(b + L.off_sqrt);
+    v.isqrtt = reinterpret_cast<const double *>(b + L.off_isqrt);
+    v.chione = b + L.off_chione;
+    v.pw = pw_view(reinterpret_cast<const float *>(b + L.off_mlp));
+    return v;
+}
+
+struct Found {
+    uint64_t rep;
+    uint32_t g;
+    uint32_t cnt;  // number of group elements reaching the representative = |Stab|
+};
+
+// Representative of t by sublattice coding (algorithm "Sublattice coding
+// algorithm for finding the representative"): MinRep over the coarse
+// sublattices, then every symmetry in Sym_Y of each sublattice Y attaining
+// MinRep is applied through the SymmetryAction tables of the fine
+// decomposition (destination-major, so the image is assembled most
+// significant sublattice first).  All minimizers lie among these candidates
+// and each group element is a candidate at most once, so the number of
+// candidates reaching the minimum is the stabilizer size.
+__host__ __device__ __forceinline__ Found find_rep(uint64_t t, const KParams &p, const Lds &L)
+{
+    const int N = p.N, R = p.R, br = p.br, A = p.A, ba = p.ba;
+    const uint32_t S = 1u << br, mr = S - 1u, ma = (1u << ba) - 1u;
+    uint32_t minrep = 0xffffffffu;
+    for (int X = 0; X < R; ++X) {
+        uint32_t s = (uint32_t)(t >> (N - (X + 1) * br)) & mr;
+        const uint32_t r = L.rep[X * S + s];
+        minrep = r < minrep ? r : minrep;
+    }
+    // Every candidate maps its sublattice onto the most significant coarse
+    // sublattice with image MinRep, so the fine destinations 0..d0-1 agree
+    // for all candidates; images are compared from destination d0 on and a
+    // candidate is dropped at the first destination where it exceeds the
+    // best so far.
+    const int d0 = A / R;
+    uint64_t best = ~0ull;
+    uint32_t bg = 0, cnt = 0;
+    for (int X = 0; X < R; ++X) {
+        uint32_t s = (uint32_t)(t >> (N - (X + 1) * br)) & mr;
+        uint32_t idx = X * S + s;
+        if (L.rep[idx] != minrep) continue;
+        const uint32_t k1 = L.symoff[idx + 1];
+        for (uint32_t k = L.symoff[idx]; k < k1; ++k) {
+            const uint32_t e = L.symlist[k];
+            const uint32_t sp = (e >> 1) & 0x7fffu;
+            const uint32_t fm = (e & 1u) ? ma : 0u;  // spin flip complements every substate
+            const uint64_t srcw = L.src[sp];
+            const uint8_t *a = L.act + (size_t)sp * ((uint32_t)A << ba);
+            uint64_t v = minrep;
+            uint64_t bp = 0;
+            int d = d0;
+            for (; d < A; ++d) {
+                const uint32_t x = (uint32_t)(srcw >> (4 * d)) & 15u;
+                const uint32_t ss = (uint32_t)(t >> (N - (int)(x + 1) * ba)) & ma;
+                v = (v << ba) | (uint32_t)(a[(d << ba) + ss] ^ fm);
+                bp = best >> ((A - 1 - d) * ba);
+                if (v != bp) break;
+            }
+            if (d == A) {
+                // no destination differed: the same image as the best so far,
+                // or (one fine sublattice, d0 == A) the first candidate
+                if (v == best) {
+                    ++cnt;
+                } else {
+                    best = v;
+                    bg = e >> 16;
+                    cnt = 1;
+                }
+                continue;
+            }
+            if (v > bp) continue;
+            for (++d; d < A; ++d) {
+                const uint32_t x = (uint32_t)(srcw >> (4 * d)) & 15u;
+                const uint32_t ss = (uint32_t)(t >> (N - (int)(x + 1) * ba)) & ma;
+                v = (v << ba) | (uint32_t)(a[(d << ba) + ss] ^ fm);
+            }
+            best = v;
+            bg = e >> 16;
+            cnt = 1;
+        }
+    }
+    return Found{best, bg, cnt};
+}
+
+}  // namespace symed

@@ -343,7 +343,8 @@ std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &L)
 // contiguous decomposition with the fewest sublattices whose tables fit
 // (<= 8 bits per substate, <= 16 sublattices, <= 64 KiB); the Rep/Sym
 // tables use the one with the fewest sublattices (fewest candidate
-// symmetries) whose tables fit 64 KiB.
+// symmetries) that the action decomposition refines and whose tables fit
+// 64 KiB.
 int choose_sublattices(const HostTables &T, int &R, int &A, std::string &why)
 {
     const int N = T.N;
@@ -367,6 +368,7 @@ int choose_sublattices(const HostTables &T, int &R, int &A, std::string &why)
     }
     int bestR = 0;
     for (int ns : stable) {
+        if (bestA % ns) continue;  // the action decomposition must refine this one
         int b = N / ns;
         if (b > 14) continue;
         size_t S = (size_t)1 << b;
@@ -402,6 +404,7 @@ ed_status build_host_tables(const ed_model *m, const ed_group *g, int n_up, int 
     }
     if ((st = check_stable(T, R)) != ED_OK) return st;
     if ((st = check_stable(T, A)) != ED_OK) return st;
+    if (A % R) return fail(ED_EINVAL, "n_sub_act must be a multiple of n_sub_rep");
     T.R = R;
     T.br = T.N / R;
     T.A = A;

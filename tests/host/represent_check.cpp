@@ -1,0 +1,50 @@
+// CPU check of the device representative search (represent.h, compiled for
+// the host) against brute force over the whole group, for every state of a
+// small instance.  Built and run by tests/test_represent_host.py.
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+#include "represent.h"
+using namespace symed;
+template <class T> std::vector<T> rd(FILE *f, size_t n) { std::vector<T> v(n); if (n) fread(v.data(), sizeof(T), n, f); return v; }
+int main(int argc, char **argv) {
+  FILE *f = fopen(argv[1], "rb"); int R = atoi(argv[2]), A = atoi(argv[3]);
+  int32_t hdr[5]; fread(hdr, 4, 5, f);
+  int N = hdr[0], n_up = hdr[1], G = hdr[2], nb = hdr[3], nt = hdr[4];
+  auto perm = rd<int32_t>(f, (size_t)G * N); auto flip = rd<uint8_t>(f, G);
+  auto cre = rd<double>(f, G); auto cim = rd<double>(f, G);
+  auto bonds = rd<int32_t>(f, 2 * nb); auto bJ = rd<double>(f, nb);
+  auto tris = rd<int32_t>(f, 3 * nt); auto tJ = rd<double>(f, nt);
+  fclose(f);
+  ed_model m{N, nb, bonds.data(), bJ.data(), nt, tris.data(), tJ.data()};
+  ed_group g{G, perm.data(), flip.data(), cre.data(), cim.data()};
+  HostTables T;
+  ed_status st = build_host_tables(&m, &g, n_up, R, A, T);
+  if (st != ED_OK) { printf("build_host_tables failed %d\n", st); return 2; }
+  BlobLayout lay; std::vector<uint8_t> blob = pack_blob(T, lay);
+  std::vector<uint8_t> al(blob.size() + 16); std::memcpy(al.data(), blob.data(), blob.size());
+  Lds L = lds_view(al.data(), lay);
+  KParams p{}; p.N = N; p.R = T.R; p.br = T.br; p.A = T.A; p.ba = T.ba; p.maskN = (1ull << N) - 1;
+  long long checked = 0, bad = 0;
+  for (uint64_t s = 0; s < (1ull << N); ++s) {
+    if (__builtin_popcountll(s) != n_up) continue;
+    uint64_t best = ~0ull; int cnt = 0;
+    std::vector<uint64_t> img(G);
+    for (int e = 0; e < G; ++e) {
+      uint64_t o = 0;
+      for (int i = 0; i < N; ++i) if ((s >> (N - 1 - i)) & 1) o |= 1ull << (N - 1 - perm[(size_t)e * N + i]);
+      if (flip[e]) o ^= p.maskN;
+      img[e] = o;
+      if (o < best) { best = o; cnt = 1; } else if (o == best) ++cnt;
+    }
+    Found fr = find_rep(s, p, L);
+    ++checked;
+    if (fr.rep != best || (int)fr.cnt != cnt || img[fr.g] != best) {
+      if (bad < 5) printf("mismatch s=%llx rep %llx/%llx cnt %u/%d g %u\n", (unsigned long long)s, (unsigned long long)fr.rep, (unsigned long long)best, fr.cnt, cnt, fr.g);
+      ++bad;
+    }
+  }
+  printf("R=%d A=%d checked %lld bad %lld\n", T.R, T.A, checked, bad);
+  return bad ? 1 : 0;
+}
