@@ -23,7 +23,7 @@ namespace {
 #define SYMED_APPLY_THREADS 1024
 #endif
 #ifndef SYMED_KBATCH
-#define SYMED_KBATCH 4
+#define SYMED_KBATCH 1
 #endif
 constexpr int kApplyThreads = SYMED_APPLY_THREADS;
 constexpr int kVecThreads = 256;
