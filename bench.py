@@ -189,6 +189,9 @@ def main():
         "lanczos_E0_after_steps": {("learned" if m == 1 else "plain"): energies[m] for m in modes},
         "setup": {"basis_build_s": t_build, "table_bytes": info["table_bytes"],
                   "limits_bytes": info["limits_bytes"], "device_bytes": info["bytes_device"]},
+        "search_window_keys": {"plain_mean": info["limits_mean_window"], "plain_max": info["limits_max_window"],
+                               "learned_mean": train["mean_window"] if train else None,
+                               "learned_max": train["max_err"] if train else None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_apply", "alg_bytes_per_launch": alg_bytes, "avg_launch_s": t_apply},

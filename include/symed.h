@@ -123,6 +123,8 @@ typedef struct {
     int32_t index_max_err;     /* learned-index error bound (-1 if not trained) */
     int32_t lds_resident;      /* tables staged in LDS by the kernels */
     double build_seconds;      /* wall time of ed_basis_build */
+    double limits_mean_window; /* plain lookup: mean Limits bucket over all keys */
+    int64_t limits_max_window; /* plain lookup: largest Limits bucket */
 } ed_basis_info_t;
 
 /*
@@ -209,12 +211,13 @@ ed_status ed_eigenvalues(const double *alpha, const double *beta, int32_t n, int
  * non-decreasing) maps the key, read as a floating-point number u = (e + 1 +
  * mantissa) / (N + 1) with e the position of its leading one, to an estimate
  * of its normalized position; the estimate routes the key to one of
- * 2^log2_leaves leaves.  Each leaf stores the position range of the
- * keys routed to it and the largest distance between a routed key's position
- * and the leaf's linear interpolation, so the bounded binary search around
- * the prediction finds every representative and reports absence for every
- * other key: lookups agree exactly with the plain Limits + binary search of
- * the thesis (section on distributed memory parallelization, "Limits" map).
+ * 2^log2_leaves leaves.  Each leaf stores the position range of the keys
+ * routed to it and splits that range into buckets uniform in key space
+ * (about keys_per_bucket keys each) whose begin positions are tabulated; the
+ * binary search inside the key's bucket finds every representative and
+ * reports absence for every other key, so lookups agree exactly with the
+ * plain Limits + binary search of the thesis (section on distributed memory
+ * parallelization, "Limits" map).
  * Training runs on the device with the library's own forward, backward and
  * Adam kernels on minibatches of (representative, position) pairs.
  * After training the one-input network is expanded exactly into its linear
@@ -222,7 +225,8 @@ ed_status ed_eigenvalues(const double *alpha, const double *beta, int32_t n, int
  * that expansion (a binary search over the breakpoints, in LDS).
  * Zero fields mean defaults (n_features = 1 (the only value accepted),
  * hidden = 32 (the only value accepted), steps = 3000, batch = 8192,
- * lr = 1e-2 with cosine decay, log2_leaves ~ log2(dim / 32)).
+ * lr = 1e-2 with cosine decay, log2_leaves ~ log2(dim / 256) (at most 22),
+ * keys_per_bucket = 8).
  */
 typedef struct {
     int32_t n_features;
@@ -232,18 +236,18 @@ typedef struct {
     float lr;
     uint32_t seed;
     int32_t log2_leaves;
-    int32_t reserved;
+    int32_t keys_per_bucket;
 } ed_index_cfg;
 
 typedef struct {
-    int32_t max_err;           /* largest leaf error bound (positions) */
+    int32_t max_err;           /* largest search window (keys in one bucket) */
     int32_t n_leaves;
     float final_loss;          /* last minibatch mean squared error (normalized positions) */
     float mlp_max_err;         /* max |network estimate * dim - position| over all keys */
     int64_t mlp_bytes;         /* network weights */
-    int64_t leaf_bytes;        /* leaf table */
+    int64_t leaf_bytes;        /* leaf table and bucket-begin table */
     double train_seconds;      /* training + leaf build wall time */
-    double mean_window;        /* mean search-window length over all keys */
+    double mean_window;        /* mean search window over all keys */
     int32_t n_features;        /* network inputs (1) */
     int32_t n_pieces;          /* linear pieces of the trained network */
     int64_t used_leaves;       /* leaves with at least one key */

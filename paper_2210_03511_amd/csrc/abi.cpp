@@ -25,6 +25,8 @@ struct ed_basis {
     uint16_t *d_stab = nullptr;
     uint32_t *d_limits = nullptr;
     int pbits = 0;
+    double limits_mean_window = 0.0;
+    int64_t limits_max_window = 0;
     int64_t dim = 0;
     int64_t n_elements = 0;
     int64_t bytes = 0;
@@ -42,6 +44,8 @@ struct ed_basis {
     bool indexed = false;
     float *d_params = nullptr;
     void *d_leaves = nullptr;
+    uint32_t *d_sub = nullptr;
+    uint64_t sub_cap = 0;
     int log2_leaves = 0, mlp_F = 0, mlp_c = 0;
     ed_index_stats istats{};
     std::vector<void *> allocs;
@@ -102,6 +106,7 @@ static KParams make_params(const ed_basis *b)
     p.limits = b->d_limits;
     p.dim = b->dim;
     p.leaves = b->d_leaves;
+    p.sub = b->d_sub;
     p.log2_leaves = b->log2_leaves;
     p.mlp_F = b->mlp_F;
     p.mlp_c = b->mlp_c;
@@ -216,6 +221,19 @@ static ed_status build_impl(const ed_model *model, const ed_group *group, int32_
     if ((s = dev_alloc(b, (void **)&b->d_limits, ((1ull << pb) + 1) * sizeof(uint32_t))) != ED_OK) return s;
     HIP_OK(launch_limits(b->d_reps, b->dim, N, pb, b->d_limits, st));
 
+    // --- key-weighted Limits bucket statistics (search window of the plain lookup)
+    {
+        unsigned long long *d_ls = nullptr, hls[2] = {0, 0};
+        HIP_OK(hipMalloc((void **)&d_ls, 2 * sizeof(unsigned long long)));
+        HIP_OK(hipMemsetAsync(d_ls, 0, 2 * sizeof(unsigned long long), st));
+        HIP_OK(launch_limits_stats(b->d_limits, pb, d_ls, st));
+        HIP_OK(hipMemcpyAsync(hls, d_ls, sizeof(hls), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        hipFree(d_ls);
+        b->limits_mean_window = b->dim ? (double)hls[0] / (double)b->dim : 0.0;
+        b->limits_max_window = (int64_t)hls[1];
+    }
+
     // --- element count ----------------------------------------------------
     p = make_params(b);
     unsigned long long *d_cnt = nullptr, cnt = 0;
@@ -267,6 +285,8 @@ ed_status ed_basis_info(const ed_basis *b, ed_basis_info_t *info)
     r.index_bytes = b->indexed ? b->istats.mlp_bytes + b->istats.leaf_bytes : 0;
     r.index_max_err = b->indexed ? b->istats.max_err : -1;
     r.lds_resident = 1;
+    r.limits_mean_window = b->limits_mean_window;
+    r.limits_max_window = b->limits_max_window;
     r.build_seconds = b->build_seconds;
     *info = r;
     return ED_OK;
@@ -477,8 +497,9 @@ ed_status ed_index_train(ed_basis *b, const ed_index_cfg *cfg_in, ed_index_stats
     const float lr0 = cfg.lr > 0 ? cfg.lr : 1e-2f;
     int lg = cfg.log2_leaves;
     if (lg <= 0) {
+        // about 256 keys per leaf; the key-space buckets refine further
         lg = 4;
-        while (lg < 26 && (int64_t(1) << (lg + 5)) < b->dim) ++lg;
+        while (lg < 22 && (int64_t(1) << (lg + 8)) < b->dim) ++lg;
     }
     if (lg < 1 || lg > 28) return fail(ED_EINVAL, "log2_leaves must be in [1, 28]");
     auto t0 = std::chrono::steady_clock::now();
@@ -532,27 +553,43 @@ ed_status ed_index_train(ed_basis *b, const ed_index_cfg *cfg_in, ed_index_stats
     if (!(dev <= 1e-4 * yscale)) return fail(ED_EDEVICE, "network expansion disagrees with the network");
     float *d_pw = reinterpret_cast<float *>(static_cast<unsigned char *>(b->d_blob) + b->lay.off_mlp);
     HIP_OK(hipMemcpyAsync(d_pw, block.data(), kPwFloats * sizeof(float), hipMemcpyHostToDevice, st));
-    // exact leaf table
+    // exact leaf table: ranges, key-space buckets, bucket begins
     if (b->d_leaves && b->log2_leaves != lg) return fail(ED_EINVAL, "index already trained with another leaf count");
     if (!b->d_leaves && (s = dev_alloc(b, &b->d_leaves, (sizeof(Leaf) << lg))) != ED_OK) return s;
-    uint32_t *d_err = nullptr, mlp_err = 0;
+    const uint64_t M = 1ull << lg;
+    const uint32_t target = cfg.keys_per_bucket > 0 ? (uint32_t)cfg.keys_per_bucket : 8u;
+    uint32_t *d_sizes = nullptr, *d_err = nullptr, net_err = 0;
+    uint64_t *d_offsets = nullptr, *d_total = nullptr, total = 0;
+    unsigned long long *d_stats = nullptr, hstats[2] = {0, 0};
+    HIP_OK(hipMalloc((void **)&d_sizes, M * sizeof(uint32_t)));
+    HIP_OK(hipMalloc((void **)&d_offsets, M * sizeof(uint64_t)));
+    HIP_OK(hipMalloc((void **)&d_total, sizeof(uint64_t)));
     HIP_OK(hipMalloc((void **)&d_err, sizeof(uint32_t)));
+    HIP_OK(hipMalloc((void **)&d_stats, 2 * sizeof(unsigned long long)));
     HIP_OK(hipMemsetAsync(d_err, 0, sizeof(uint32_t), st));
-    HIP_OK(leaf_build(d_pw, N, lg, b->d_reps, b->dim, b->d_leaves, d_err, 8 * b->n_cu, st));
-    HIP_OK(hipMemcpyAsync(&mlp_err, d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    std::vector<Leaf> hl((size_t)1 << lg);
-    HIP_OK(hipMemcpyAsync(hl.data(), b->d_leaves, sizeof(Leaf) << lg, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemsetAsync(d_stats, 0, 2 * sizeof(unsigned long long), st));
+    HIP_OK(leaf_ranges(d_pw, N, lg, b->d_reps, b->dim, b->d_leaves, target, d_sizes, d_err, 8 * b->n_cu, st));
+    HIP_OK(launch_scan(d_sizes, d_offsets, M, d_total, st));
+    HIP_OK(hipMemcpyAsync(&total, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
-    hipFree(d_err);
-    uint32_t max_err = 0;
-    double wsum = 0, used = 0;
-    for (const Leaf &L : hl) {
-        if (L.hi <= L.lo) continue;
-        const double w = std::min<double>(L.hi - L.lo, 2.0 * L.err + 1.0);
-        max_err = std::max(max_err, L.err);
-        wsum += (double)L.count * w;
-        used += 1;
+    if (total >= (1ull << 32)) return fail(ED_EINVAL, "leaf bucket table too large");
+    if (total + 1 > b->sub_cap) {
+        if ((s = dev_alloc(b, (void **)&b->d_sub, (total + 1) * sizeof(uint32_t))) != ED_OK) return s;
+        b->sub_cap = total + 1;
     }
+    HIP_OK(leaf_buckets(b->d_leaves, lg, b->d_reps, d_offsets, b->d_sub, d_stats, st));
+    HIP_OK(hipMemcpyAsync(&net_err, d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(hstats, d_stats, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    std::vector<uint32_t> hs(M);
+    HIP_OK(hipMemcpyAsync(hs.data(), d_sizes, M * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    hipFree(d_sizes);
+    hipFree(d_offsets);
+    hipFree(d_total);
+    hipFree(d_err);
+    hipFree(d_stats);
+    int64_t used = 0;
+    for (uint32_t v : hs) used += v ? 1 : 0;
     for (auto &g : b->step_graph)
         if (g) {
             hipGraphExecDestroy(g);
@@ -563,19 +600,19 @@ ed_status ed_index_train(ed_basis *b, const ed_index_cfg *cfg_in, ed_index_stats
     b->mlp_F = F;
     b->mlp_c = 0;
     ed_index_stats r{};
-    r.max_err = (int32_t)max_err;
+    r.max_err = (int32_t)std::min<unsigned long long>(hstats[1], 0x7fffffffull);
     r.n_leaves = 1 << lg;
     r.final_loss = loss;
-    r.mlp_max_err = (float)mlp_err;
+    r.mlp_max_err = (float)net_err;
     r.mlp_bytes = (int64_t)NP * sizeof(float);
-    r.leaf_bytes = (int64_t)sizeof(Leaf) << lg;
+    r.leaf_bytes = ((int64_t)sizeof(Leaf) << lg) + (int64_t)(total + 1) * (int64_t)sizeof(uint32_t);
     r.train_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    r.mean_window = wsum / (double)b->dim;
+    r.mean_window = (double)hstats[0] / (double)b->dim;
     r.n_features = F;
     r.n_pieces = pieces;
     r.feature_offset = mu;
     r.feature_scale = sc;
-    r.used_leaves = (int64_t)used;
+    r.used_leaves = used;
     b->istats = r;
     if (out) *out = r;
     return ED_OK;

@@ -82,6 +82,7 @@ struct KParams {
     int64_t dim;
     // learned index (network weights live in the LDS blob at lay.off_mlp)
     const void *leaves;        // Leaf[2^log2_leaves]
+    const uint32_t *sub;       // key-space buckets of the leaves
     int32_t log2_leaves;
     int32_t mlp_F;             // input features
     int32_t mlp_c;             // bits per feature chunk

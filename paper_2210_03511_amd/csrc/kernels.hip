@@ -101,55 +101,11 @@ template <int K>
 __device__ __forceinline__ void lookup_learned_batch(const uint64_t (&key)[K], uint32_t valid, const KParams &p,
                                                      const PwView &pw, int64_t (&j)[K])
 {
-    const Leaf *leaves = static_cast<const Leaf *>(p.leaves);
-    Leaf Lf[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        if ((valid >> k) & 1u) {
-            uint32_t b;
-            float frac;
-            leaf_of(pw_eval(pw, key_feature(key[k], p.N)), p.log2_leaves, b, frac);
-            Lf[k] = leaves[b];
-        } else {
-            Lf[k] = Leaf{0u, 0u, 0u, 0u, 0ull, 0.0};
-        }
-    }
-    uint32_t lo[K], hi[K], end[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        if (Lf[k].lo < Lf[k].hi) {
-            const uint32_t pred = leaf_predict(Lf[k], key[k]);
-            lo[k] = (pred > Lf[k].lo + Lf[k].err) ? pred - Lf[k].err : Lf[k].lo;
-            hi[k] = (pred + Lf[k].err + 1 < Lf[k].hi) ? pred + Lf[k].err + 1 : Lf[k].hi;
-        } else {
-            lo[k] = hi[k] = 0;
-        }
-        end[k] = hi[k];
-    }
-    for (;;) {
-        uint64_t v[K];
-        uint32_t mid[K];
-        bool any = false;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            mid[k] = (lo[k] + hi[k]) >> 1;
-            if (lo[k] < hi[k]) {
-                v[k] = p.reps[mid[k]];
-                any = true;
-            }
-        }
-        if (!any) break;
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (lo[k] < hi[k]) {
-                if (v[k] < key[k]) lo[k] = mid[k] + 1; else hi[k] = mid[k];
-            }
-    }
-    uint64_t f[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) f[k] = (lo[k] < end[k]) ? p.reps[lo[k]] : ~key[k];
-#pragma unroll
-    for (int k = 0; k < K; ++k) j[k] = (lo[k] < end[k] && f[k] == key[k]) ? (int64_t)lo[k] : -1;
+    for (int k = 0; k < K; ++k)
+        j[k] = ((valid >> k) & 1u) ? lookup_learned(key[k], p.reps, pw, static_cast<const Leaf *>(p.leaves), p.sub,
+                                                    p.N, p.log2_leaves)
+                                   : -1;
 }
 
 // Index of a representative: plain Limits + binary search, or the learned
@@ -157,7 +113,8 @@ __device__ __forceinline__ void lookup_learned_batch(const uint64_t (&key)[K], u
 template <bool LEARNED>
 __device__ __forceinline__ int64_t lookup(uint64_t key, const KParams &p, const PwView &pw)
 {
-    if (LEARNED) return lookup_learned(key, p.reps, pw, static_cast<const Leaf *>(p.leaves), p.N, p.log2_leaves);
+    if (LEARNED)
+        return lookup_learned(key, p.reps, pw, static_cast<const Leaf *>(p.leaves), p.sub, p.N, p.log2_leaves);
     return lookup_plain(key, p);
 }
 
@@ -571,6 +528,27 @@ __global__ void k_limits(const uint64_t *reps, int64_t dim, int N, int pbits, ui
     limits[pf] = (uint32_t)lo;
 }
 
+// key-weighted bucket statistics of the Limits table: sum of size^2, max size
+__global__ void k_limits_stats(const uint32_t *limits, int pbits, unsigned long long *stats)
+{
+    const uint64_t np = 1ull << pbits;
+    unsigned long long sq = 0, mx = 0;
+    for (uint64_t pf = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; pf < np; pf += (uint64_t)gridDim.x * blockDim.x) {
+        const unsigned long long w = limits[pf + 1] - limits[pf];
+        sq += w * w;
+        mx = w > mx ? w : mx;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        sq += __shfl_xor(sq, o, 64);
+        const unsigned long long t = __shfl_xor(mx, o, 64);
+        mx = t > mx ? t : mx;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&stats[0], sq);
+        atomicMax(&stats[1], mx);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Lanczos vector kernels (deterministic: fixed grid, fixed reduction order)
 // ---------------------------------------------------------------------------
@@ -759,6 +737,12 @@ hipError_t launch_limits(const uint64_t *d_reps, int64_t dim, int N, int pbits, 
 {
     const uint64_t n = (1ull << pbits) + 1;
     hipLaunchKernelGGL(k_limits, dim3((n + 255) / 256), dim3(256), 0, st, d_reps, dim, N, pbits, d_limits);
+    return hipGetLastError();
+}
+
+hipError_t launch_limits_stats(const uint32_t *d_limits, int pbits, unsigned long long *d_stats, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_limits_stats, dim3(1024), dim3(256), 0, st, d_limits, pbits, d_stats);
     return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@ hipError_t launch_enumerate(const KParams &p, const uint64_t *d_binom, uint64_t 
                             uint16_t *d_stab, bool write, int blocks, hipStream_t st);
 hipError_t launch_scan(const uint32_t *d_in, uint64_t *d_out, uint64_t n, uint64_t *d_total, hipStream_t st);
 hipError_t launch_limits(const uint64_t *d_reps, int64_t dim, int N, int pbits, uint32_t *d_limits, hipStream_t st);
+hipError_t launch_limits_stats(const uint32_t *d_limits, int pbits, unsigned long long *d_stats, hipStream_t st);
 hipError_t launch_count_elements(const KParams &p, unsigned long long *d_count, int blocks, hipStream_t st);
 hipError_t launch_apply(const KParams &p, const LaunchCfg &c, const void *x, void *y, int mode, int learned,
                         const LState *ls, double *partials, hipStream_t st);

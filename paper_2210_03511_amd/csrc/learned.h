@@ -15,8 +15,10 @@ hipError_t mlp_train_step(float *d_params, float *d_m, float *d_v, int F, float 
                           float *d_lpart, float *d_loss, hipStream_t st);
 hipError_t mlp_loss_grad(const float *d_params, int F, const float *d_X, const float *d_T, int64_t n, float *d_grad,
                          float *d_loss, float *d_gpart, float *d_lpart, hipStream_t st);
-hipError_t leaf_build(const float *d_pw, int N, int lg, const uint64_t *reps, int64_t D, void *d_leaves,
-                      uint32_t *d_mlp_err, int blocks, hipStream_t st);
+hipError_t leaf_ranges(const float *d_pw, int N, int lg, const uint64_t *reps, int64_t D, void *d_leaves,
+                       uint32_t target, uint32_t *d_sizes, uint32_t *d_net_err, int blocks, hipStream_t st);
+hipError_t leaf_buckets(void *d_leaves, int lg, const uint64_t *reps, const uint64_t *d_offsets, uint32_t *d_sub,
+                        unsigned long long *d_stats, hipStream_t st);
 hipError_t index_predict(const float *d_pw, int N, const uint64_t *keys, int64_t n, float *u, float *y, hipStream_t st);
 
 }  // namespace symed

@@ -197,6 +197,7 @@ __global__ void k_leaf_init(Leaf *leaves, uint64_t M)
         leaves[b] = Leaf{0xffffffffu, 0u, 0u, 0u, 0ull, 0.0};
 }
 
+// position range and key count of every leaf (count kept in nsub for now)
 __global__ void __launch_bounds__(256) k_leaf_range(const float *pwg, int N, int lg, const uint64_t *reps, int64_t D,
                                                   Leaf *leaves)
 {
@@ -210,28 +211,76 @@ __global__ void __launch_bounds__(256) k_leaf_range(const float *pwg, int N, int
         leaf_of(pw_eval(pw, key_feature(reps[i], N)), lg, b, frac);
         atomicMin(&leaves[b].lo, (uint32_t)i);
         atomicMax(&leaves[b].hi, (uint32_t)(i + 1));
-        atomicAdd(&leaves[b].count, 1u);
+        atomicAdd(&leaves[b].nsub, 1u);
     }
 }
 
-// empty leaves -> empty range; others: first key and key-space slope
-__global__ void k_leaf_fix(Leaf *leaves, uint64_t M, const uint64_t *reps)
+// key-space bucket count of each leaf: about `target` routed keys per bucket,
+// at most one bucket per position of the range; sizes[b] = entries of the
+// leaf's bucket-begin array (nsub + 1, or 0 for an empty leaf)
+__global__ void k_leaf_shape(Leaf *leaves, uint64_t M, const uint64_t *reps, uint32_t target, uint32_t *sizes)
 {
     for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < M; b += (uint64_t)gridDim.x * blockDim.x) {
         Leaf L = leaves[b];
         if (L.lo >= L.hi) {
             leaves[b] = Leaf{0u, 0u, 0u, 0u, 0ull, 0.0};
+            sizes[b] = 0;
             continue;
         }
+        const uint32_t count = L.nsub;
+        uint32_t nsub = (count + target - 1) / target;
+        if (nsub < 1) nsub = 1;
+        if (nsub > L.hi - L.lo) nsub = L.hi - L.lo;
         const uint64_t k0 = reps[L.lo], k1 = reps[L.hi - 1];
         L.kfirst = k0;
-        L.slope = (k1 > k0) ? (double)(L.hi - 1 - L.lo) / (double)(k1 - k0) : 0.0;
+        L.nsub = nsub;
+        L.scale = (double)nsub / ((double)(k1 - k0) + 1.0);
         leaves[b] = L;
+        sizes[b] = nsub + 1;
     }
 }
 
-__global__ void __launch_bounds__(256) k_leaf_err(const float *pwg, int N, int lg, const uint64_t *reps, int64_t D,
-                                                Leaf *leaves, uint32_t *mlp_err)
+__global__ void k_leaf_setoff(Leaf *leaves, uint64_t M, const uint64_t *offsets)
+{
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < M; b += (uint64_t)gridDim.x * blockDim.x)
+        leaves[b].off = (uint32_t)offsets[b];
+}
+
+// bucket begins of one leaf per thread: sub[off + q] = first position of
+// [lo, hi) whose key lies in bucket q or later; sub[off + nsub] = hi
+__global__ void k_leaf_fill(const Leaf *leaves, uint64_t M, const uint64_t *reps, uint32_t *sub,
+                            unsigned long long *stats)
+{
+    unsigned long long sq = 0, mx = 0;
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < M; b += (uint64_t)gridDim.x * blockDim.x) {
+        const Leaf L = leaves[b];
+        if (L.lo >= L.hi) continue;
+        uint32_t next = 0, prev = L.lo;
+        for (uint32_t p = L.lo; p < L.hi; ++p) {
+            const uint32_t q = leaf_bucket(L, reps[p]);
+            while (next <= q) {
+                sub[L.off + next] = p;
+                ++next;
+            }
+        }
+        while (next <= L.nsub) {
+            sub[L.off + next] = L.hi;
+            ++next;
+        }
+        for (uint32_t q = 0; q < L.nsub; ++q) {
+            const unsigned long long w = sub[L.off + q + 1] - sub[L.off + q];
+            sq += w * w;
+            mx = w > mx ? w : mx;
+        }
+        (void)prev;
+    }
+    atomicAdd(&stats[0], sq);
+    atomicMax(&stats[1], mx);
+}
+
+// largest |network estimate * D - position| over all keys
+__global__ void __launch_bounds__(256) k_net_err(const float *pwg, int N, const uint64_t *reps, int64_t D,
+                                               uint32_t *net_err)
 {
     __shared__ float spw[kPwFloats];
     for (int q = threadIdx.x; q < kPwFloats; q += blockDim.x) spw[q] = pwg[q];
@@ -240,19 +289,12 @@ __global__ void __launch_bounds__(256) k_leaf_err(const float *pwg, int N, int l
     uint32_t worst = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D; i += (int64_t)gridDim.x * blockDim.x) {
         const float y = pw_eval(pw, key_feature(reps[i], N));
-        uint32_t b;
-        float frac;
-        leaf_of(y, lg, b, frac);
-        const Leaf L = leaves[b];
-        const uint32_t pred = leaf_predict(L, reps[i]);
-        const uint32_t e = (pred > (uint32_t)i) ? pred - (uint32_t)i : (uint32_t)i - pred;
-        atomicMax(&leaves[b].err, e);
         const double dy = fabs((double)y * (double)D - (double)i);
         const uint32_t me = dy > 4.0e9 ? 0xffffffffu : (uint32_t)dy;
         worst = max(worst, me);
     }
     for (int o = 32; o > 0; o >>= 1) worst = max(worst, (uint32_t)__shfl_xor((int)worst, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(mlp_err, worst);
+    if ((threadIdx.x & 63) == 0) atomicMax(net_err, worst);
 }
 
 // u and the expanded network output for given keys (verification)
@@ -321,15 +363,25 @@ hipError_t mlp_loss_grad(const float *d_params, int F, const float *d_X, const f
     return hipGetLastError();
 }
 
-hipError_t leaf_build(const float *d_pw, int N, int lg, const uint64_t *reps, int64_t D, void *d_leaves,
-                      uint32_t *d_mlp_err, int blocks, hipStream_t st)
+hipError_t leaf_ranges(const float *d_pw, int N, int lg, const uint64_t *reps, int64_t D, void *d_leaves,
+                       uint32_t target, uint32_t *d_sizes, uint32_t *d_net_err, int blocks, hipStream_t st)
 {
     Leaf *lv = static_cast<Leaf *>(d_leaves);
     const uint64_t M = 1ull << lg;
     hipLaunchKernelGGL(k_leaf_init, dim3(1024), dim3(256), 0, st, lv, M);
     hipLaunchKernelGGL(k_leaf_range, dim3(blocks), dim3(256), 0, st, d_pw, N, lg, reps, D, lv);
-    hipLaunchKernelGGL(k_leaf_fix, dim3(1024), dim3(256), 0, st, lv, M, reps);
-    hipLaunchKernelGGL(k_leaf_err, dim3(blocks), dim3(256), 0, st, d_pw, N, lg, reps, D, lv, d_mlp_err);
+    hipLaunchKernelGGL(k_leaf_shape, dim3(1024), dim3(256), 0, st, lv, M, reps, target, d_sizes);
+    hipLaunchKernelGGL(k_net_err, dim3(blocks), dim3(256), 0, st, d_pw, N, reps, D, d_net_err);
+    return hipGetLastError();
+}
+
+hipError_t leaf_buckets(void *d_leaves, int lg, const uint64_t *reps, const uint64_t *d_offsets, uint32_t *d_sub,
+                        unsigned long long *d_stats, hipStream_t st)
+{
+    Leaf *lv = static_cast<Leaf *>(d_leaves);
+    const uint64_t M = 1ull << lg;
+    hipLaunchKernelGGL(k_leaf_setoff, dim3(1024), dim3(256), 0, st, lv, M, d_offsets);
+    hipLaunchKernelGGL(k_leaf_fill, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, lv, M, reps, d_sub, d_stats);
     return hipGetLastError();
 }
 

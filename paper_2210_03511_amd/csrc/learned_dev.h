@@ -106,15 +106,26 @@ __host__ __device__ __forceinline__ PwView pw_view(const float *base)
 // floats of the expansion block: header (4) + breakpoints + slopes + intercepts
 constexpr int kPwFloats = 4 + 3 * kPwMax;
 
-// A leaf: the keys routed to it occupy positions [lo, hi) (a contiguous run
-// when the network is non-decreasing); inside the leaf the position is
-// interpolated linearly in key space from its first key, and err bounds the
-// distance of every routed key from that interpolation.
+// A leaf: the keys routed to it occupy positions inside [lo, hi).  The leaf
+// is split into nsub buckets uniform in key space: key k falls in bucket
+// floor((k - kfirst) * scale) (clamped), and sub[off + q] is the first
+// position in [lo, hi) whose key falls in bucket q or later (sub[off + nsub]
+// = hi).  Buckets are monotone in the key, so every key of [lo, hi) - routed
+// here or not - lies in the bucket of its own value.
 struct Leaf {
-    uint32_t lo, hi, err, count;
-    uint64_t kfirst;  // smallest key routed here
-    double slope;     // (hi - 1 - lo) / (largest key - kfirst), 0 if one key
+    uint32_t lo, hi, off, nsub;
+    uint64_t kfirst;
+    double scale;     // nsub / (last key - kfirst + 1)
 };
+
+__host__ __device__ __forceinline__ uint32_t leaf_bucket(const Leaf &L, uint64_t key)
+{
+#pragma clang fp contract(off)
+    if (key <= L.kfirst) return 0u;
+    const double t = (double)(key - L.kfirst) * L.scale;
+    const uint32_t q = t >= (double)L.nsub ? L.nsub - 1u : (uint32_t)t;
+    return q < L.nsub ? q : L.nsub - 1u;
+}
 
 // Leaf and fractional position inside the leaf from the network output y.
 // The leaf index is clamped as an integer: for 2^m >= 2^24 the float value
@@ -132,20 +143,11 @@ __device__ __forceinline__ void leaf_of(float y, int log2_leaves, uint32_t &b, f
     frac = fminf(u - (float)bi, 1.0f);
 }
 
-__device__ __forceinline__ uint32_t leaf_predict(const Leaf &L, uint64_t key)
-{
-#pragma clang fp contract(off)
-    const uint32_t n1 = L.hi - L.lo - 1;
-    if (key <= L.kfirst || n1 == 0) return L.lo;
-    const double off = (double)(key - L.kfirst) * L.slope;
-    const uint32_t o = off >= (double)n1 ? n1 : (uint32_t)(off + 0.5);
-    return L.lo + (o > n1 ? n1 : o);
-}
-
-// Learned lookup: network (expanded form) -> leaf -> bounded binary search.
-// -1 if absent.
+// Learned lookup: network (expanded form) -> leaf -> key-space bucket ->
+// binary search.  -1 if absent.
 __device__ __forceinline__ int64_t lookup_learned(uint64_t key, const uint64_t *__restrict__ reps, const PwView &pw,
-                                                 const Leaf *__restrict__ leaves, int N, int log2_leaves)
+                                                 const Leaf *__restrict__ leaves, const uint32_t *__restrict__ sub,
+                                                 int N, int log2_leaves)
 {
     const float y = pw_eval(pw, key_feature(key, N));
     uint32_t b;
@@ -153,9 +155,8 @@ __device__ __forceinline__ int64_t lookup_learned(uint64_t key, const uint64_t *
     leaf_of(y, log2_leaves, b, frac);
     const Leaf L = leaves[b];
     if (L.lo >= L.hi) return -1;
-    const uint32_t pred = leaf_predict(L, key);
-    uint32_t lo = (pred > L.lo + L.err) ? pred - L.err : L.lo;
-    uint32_t hi = (pred + L.err + 1 < L.hi) ? pred + L.err + 1 : L.hi;
+    const uint32_t q = leaf_bucket(L, key);
+    uint32_t lo = sub[L.off + q], hi = sub[L.off + q + 1];
     const uint32_t end = hi;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;

@@ -56,7 +56,8 @@ class BasisInfo(ctypes.Structure):
                 ("prefix_bits", ctypes.c_int32), ("n_elements", ctypes.c_int64), ("n_offdiag", ctypes.c_int64),
                 ("bytes_device", ctypes.c_int64), ("table_bytes", ctypes.c_int64), ("limits_bytes", ctypes.c_int64),
                 ("index_bytes", ctypes.c_int64), ("index_max_err", ctypes.c_int32), ("lds_resident", ctypes.c_int32),
-                ("build_seconds", ctypes.c_double)]
+                ("build_seconds", ctypes.c_double), ("limits_mean_window", ctypes.c_double),
+                ("limits_max_window", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -65,7 +66,7 @@ class BasisInfo(ctypes.Structure):
 class IndexCfg(ctypes.Structure):
     _fields_ = [("n_features", ctypes.c_int32), ("hidden", ctypes.c_int32), ("steps", ctypes.c_int32),
                 ("batch", ctypes.c_int32), ("lr", ctypes.c_float), ("seed", ctypes.c_uint32),
-                ("log2_leaves", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("log2_leaves", ctypes.c_int32), ("keys_per_bucket", ctypes.c_int32)]
 
 
 class IndexStats(ctypes.Structure):
@@ -243,8 +244,9 @@ class Basis:
         n = nd.value
         return a[:n], b[:n], n, st == ED_EBREAKDOWN
 
-    def train_index(self, n_features=0, hidden=32, steps=0, batch=0, lr=0.0, seed=1, log2_leaves=0, stream=None):
-        cfg = IndexCfg(n_features, hidden, steps, batch, lr, seed, log2_leaves, 0)
+    def train_index(self, n_features=0, hidden=32, steps=0, batch=0, lr=0.0, seed=1, log2_leaves=0,
+                    keys_per_bucket=0, stream=None):
+        cfg = IndexCfg(n_features, hidden, steps, batch, lr, seed, log2_leaves, keys_per_bucket)
         stats = IndexStats()
         _check(lib().ed_index_train(self._h, ctypes.byref(cfg), ctypes.byref(stats), _stream_ptr(stream)))
         return stats.as_dict()
