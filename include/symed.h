@@ -290,6 +290,59 @@ ed_status ed_mlp_loss_grad(int32_t n_features, const float *d_params, const floa
                            float *d_grad, float *d_loss, void *stream);
 
 /*
+ * Many sectors in one persistent launch.  A batch references built bases
+ * (which must outlive it) and runs H.v, or whole Lanczos steps, for all of
+ * them at once: the rows of all sectors are cut into equal tiles, every
+ * block of one persistent grid walks the tiles round-robin and stages the
+ * tables of a tile's sector into LDS when it changes sector.  One Lanczos
+ * step of all sectors is captured once as a HIP graph and replayed.  The
+ * tile length is chosen by timing one batched H.v per candidate (2048,
+ * 8192, 32768, 131072 rows) unless fixed by tile_rows with autotune = 0.
+ * Real and complex sectors may be mixed; lookup_mode 1 needs a trained
+ * learned index in every sector.
+ */
+typedef struct ed_batch ed_batch;
+
+typedef struct {
+    int32_t tile_rows;
+    int32_t autotune;
+    int32_t reserved[2];
+} ed_batch_cfg;
+
+typedef struct {
+    int32_t n_sectors;
+    int32_t tile_rows;          /* chosen tile length */
+    int64_t n_tiles;
+    int64_t total_dim;
+    int64_t total_elements;     /* matrix entries evaluated per batched H.v */
+    int32_t apply_blocks;       /* persistent grid */
+    int32_t n_candidates;       /* autotuning: candidates timed */
+    int32_t tune_rows[8];
+    double tune_seconds[8];     /* one batched H.v per candidate */
+} ed_batch_info_t;
+
+/* Create a batch of n sectors (n <= 256); stream: hipStream_t or NULL.
+ * Allocates Lanczos vectors for every sector; blocks until set up. */
+ed_status ed_batch_create(ed_basis *const *sectors, int32_t n, const ed_batch_cfg *cfg, void *stream,
+                          ed_batch **out);
+
+/* y_s := H_s x_s for every sector s in one launch; d_x, d_y: host arrays of
+ * n device vector pointers (layout as ed_apply_H).  Asynchronous on stream. */
+ed_status ed_batch_apply(ed_batch *batch, const void *const *d_x, void *const *d_y, int32_t lookup_mode,
+                         void *stream);
+
+/* n_iter Lanczos steps of every sector from start vectors d_v0[s]; h_alpha,
+ * h_beta: f64[n][n_iter] (sector-major); n_done: int32[n].  Returns
+ * ED_EBREAKDOWN if any sector broke down (its n_done < n_iter). */
+ed_status ed_batch_lanczos(ed_batch *batch, const void *const *d_v0, int32_t n_iter, int32_t lookup_mode,
+                           double *h_alpha, double *h_beta, int32_t *n_done, void *stream);
+
+ed_status ed_batch_info(const ed_batch *batch, ed_batch_info_t *info);
+
+/* Release the batch (not its sectors).  NULL is ignored. */
+void ed_batch_free(ed_batch *batch);
+
+/*
  * Host-only inspection of the sublattice-coding tables for one
  * decomposition into n_sub contiguous sublattices (no device needed):
  * for sublattice X and substate s (b = N/n_sub bits),

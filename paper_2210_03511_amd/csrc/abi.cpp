@@ -9,47 +9,12 @@
 #include <string>
 #include <vector>
 
+#include "basis.h"
 #include "launch.h"
 #include "learned.h"
 #include "learned_dev.h"
 
 using namespace symed;
-
-struct ed_basis {
-    HostTables T;
-    BlobLayout lay{};
-    int device = 0;
-    hipStream_t own = nullptr;
-    void *d_blob = nullptr;
-    uint64_t *d_reps = nullptr;
-    uint16_t *d_stab = nullptr;
-    uint32_t *d_limits = nullptr;
-    int pbits = 0;
-    double limits_mean_window = 0.0;
-    int64_t limits_max_window = 0;
-    int64_t dim = 0;
-    int64_t n_elements = 0;
-    int64_t bytes = 0;
-    int64_t mem_limit = 0;
-    LaunchCfg cfg{};
-    int n_cu = 0;
-    double build_seconds = 0.0;
-    // Lanczos workspace and captured step graphs (one per lookup mode)
-    double *d_v = nullptr, *d_w = nullptr, *d_vprev = nullptr, *d_partials = nullptr;
-    double *d_alpha = nullptr, *d_beta = nullptr;
-    LState *d_ls = nullptr;
-    int lanczos_cap = 0;
-    hipGraphExec_t step_graph[2] = {nullptr, nullptr};
-    // learned index
-    bool indexed = false;
-    float *d_params = nullptr;
-    void *d_leaves = nullptr;
-    uint32_t *d_sub = nullptr;
-    uint64_t sub_cap = 0;
-    int log2_leaves = 0, mlp_F = 0, mlp_c = 0;
-    ed_index_stats istats{};
-    std::vector<void *> allocs;
-};
 
 namespace symed {
 
@@ -65,14 +30,8 @@ ed_status fail(ed_status st, const std::string &msg)
 
 }  // namespace symed
 
-#define HIP_OK(expr)                                                                             \
-    do {                                                                                         \
-        hipError_t _e = (expr);                                                                  \
-        if (_e != hipSuccess)                                                                    \
-            return fail(ED_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));          \
-    } while (0)
 
-static ed_status dev_alloc(ed_basis *b, void **ptr, size_t bytes)
+ed_status dev_alloc(ed_basis *b, void **ptr, size_t bytes)
 {
     if (b->mem_limit > 0 && b->bytes + (int64_t)bytes > b->mem_limit)
         return fail(ED_ENOMEM, "device memory cap exceeded (" + std::to_string(b->bytes + bytes) + " > " +
@@ -84,7 +43,7 @@ static ed_status dev_alloc(ed_basis *b, void **ptr, size_t bytes)
     return ED_OK;
 }
 
-static KParams make_params(const ed_basis *b)
+KParams make_params(const ed_basis *b)
 {
     KParams p{};
     const HostTables &T = b->T;

@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "ED_OK", 1: "ED_EINVAL", 2: "ED_ENOTSTABLE", 3: "ED_ECHAR", 4
 EXPORTED = ["ed_last_error", "ed_version", "ed_basis_build", "ed_basis_free", "ed_basis_info", "ed_basis_export",
             "ed_basis_device_reps", "ed_apply_H", "ed_lookup", "ed_lanczos_run", "ed_eigenvalues",
             "ed_tables_inspect", "ed_index_train", "ed_index_info", "ed_mlp_loss_grad",
-            "ed_index_predict"]
+            "ed_index_predict", "ed_batch_create", "ed_batch_apply", "ed_batch_lanczos", "ed_batch_info",
+            "ed_batch_free"]
 
 
 class EdError(RuntimeError):
@@ -80,6 +81,24 @@ class IndexStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class BatchCfg(ctypes.Structure):
+    _fields_ = [("tile_rows", ctypes.c_int32), ("autotune", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("n_sectors", ctypes.c_int32), ("tile_rows", ctypes.c_int32), ("n_tiles", ctypes.c_int64),
+                ("total_dim", ctypes.c_int64), ("total_elements", ctypes.c_int64), ("apply_blocks", ctypes.c_int32),
+                ("n_candidates", ctypes.c_int32), ("tune_rows", ctypes.c_int32 * 8),
+                ("tune_seconds", ctypes.c_double * 8)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        n = self.n_candidates
+        d["tune_rows"] = list(self.tune_rows)[:n]
+        d["tune_seconds"] = list(self.tune_seconds)[:n]
+        return d
+
+
 _LIB = None
 
 
@@ -110,8 +129,14 @@ def lib():
         L.ed_index_info.argtypes = [vp, ctypes.POINTER(IndexStats), vp, i64]
         L.ed_mlp_loss_grad.argtypes = [i32, vp, vp, vp, i64, vp, vp, vp]
         L.ed_index_predict.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.ed_batch_create.argtypes = [vp, i32, ctypes.POINTER(BatchCfg), vp, ctypes.POINTER(vp)]
+        L.ed_batch_apply.argtypes = [vp, vp, vp, i32, vp]
+        L.ed_batch_lanczos.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp]
+        L.ed_batch_info.argtypes = [vp, ctypes.POINTER(BatchInfo)]
+        L.ed_batch_free.argtypes = [vp]
+        L.ed_batch_free.restype = None
         for name in EXPORTED:
-            if hasattr(L, name) and name not in ("ed_last_error", "ed_version", "ed_basis_free"):
+            if hasattr(L, name) and name not in ("ed_last_error", "ed_version", "ed_basis_free", "ed_batch_free"):
                 getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -268,6 +293,58 @@ class Basis:
         F = stats.n_features
         n = 32 * F + 32 + 32 * 32 + 32 + 32 + 1
         return stats.as_dict(), buf[:n].copy()
+
+
+class Batch:
+    """Several built sectors run together: one persistent launch per H.v and
+    one captured HIP graph per Lanczos step.  The sectors must outlive it."""
+
+    def __init__(self, sectors, tile_rows=0, autotune=True, stream=None):
+        self.sectors = list(sectors)
+        n = len(self.sectors)
+        hs = (ctypes.c_void_p * n)(*[s._h.value for s in self.sectors])
+        cfg = BatchCfg(int(tile_rows), 1 if autotune else 0, (ctypes.c_int32 * 2)(0, 0))
+        h = ctypes.c_void_p()
+        _check(lib().ed_batch_create(hs, n, ctypes.byref(cfg), _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+
+    def free(self):
+        if self._h:
+            lib().ed_batch_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def info(self):
+        inf = BatchInfo()
+        _check(lib().ed_batch_info(self._h, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def apply_H(self, xs, ys, mode=0, stream=None):
+        """ys[s] := H_s xs[s] for every sector, one launch."""
+        n = len(self.sectors)
+        px = (ctypes.c_void_p * n)(*[_tensor_ptr(x) for x in xs])
+        py = (ctypes.c_void_p * n)(*[_tensor_ptr(y) for y in ys])
+        _check(lib().ed_batch_apply(self._h, px, py, int(mode), _stream_ptr(stream)))
+        return ys
+
+    def lanczos(self, v0s, n_iter, mode=0, stream=None):
+        """n_iter Lanczos steps of every sector; returns a list of
+        (alpha, beta, n_done, broken) per sector."""
+        n = len(self.sectors)
+        pv = (ctypes.c_void_p * n)(*[_tensor_ptr(v) for v in v0s])
+        a = np.zeros((n, n_iter))
+        b = np.zeros((n, n_iter))
+        nd = np.zeros(n, np.int32)
+        st = lib().ed_batch_lanczos(self._h, pv, int(n_iter), int(mode), _np_ptr(a), _np_ptr(b), _np_ptr(nd),
+                                    _stream_ptr(stream))
+        if st not in (ED_OK, ED_EBREAKDOWN):
+            _check(st)
+        return [(a[s, :nd[s]].copy(), b[s, :nd[s]].copy(), int(nd[s]), int(nd[s]) < n_iter) for s in range(n)]
 
 
 def mlp_loss_grad(n_features, params, X, t, stream=None):

@@ -1,0 +1,207 @@
+"""Batched execution of many sectors (one persistent launch per H.v, one
+captured graph per Lanczos step) against the per-sector path and the oracle.
+
+The batched kernel evaluates every row with the same per-row code as the
+single-sector kernel, so H.v must agree bit for bit with ed_apply_H; the
+Lanczos reductions are summed in another order, so alpha/beta agree to
+rounding and energies to 1e-10 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from workloads import lattices as L
+from workloads import vectors as V
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def S():
+    _torch()
+    from paper_2210_03511_amd import symed
+    symed.lib()
+    return symed
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(torch, arr):
+    return torch.from_numpy(np.ascontiguousarray(arr)).cuda()
+
+
+def _mixed_sectors():
+    """Real and complex sectors of different sizes and site counts."""
+    return L.small_instances() + [L.chain16()]
+
+
+@pytest.mark.parametrize("tile_rows,autotune", [(64, False), (7, False), (0, True)], ids=str)
+def test_batch_apply_matches_single_and_oracle(S, tile_rows, autotune):
+    torch = _torch()
+    insts = _mixed_sectors()
+    _say("batch apply", len(insts), "sectors, tile_rows", tile_rows, "autotune", autotune)
+    bases = [S.Basis.build(i) for i in insts]
+    batch = S.Batch(bases, tile_rows=tile_rows, autotune=autotune)
+    info = batch.info()
+    assert info["n_sectors"] == len(insts)
+    assert info["total_dim"] == sum(b.dim for b in bases)
+    if autotune:
+        assert info["n_candidates"] >= 2 and info["tile_rows"] in info["tune_rows"]
+    else:
+        assert info["tile_rows"] == tile_rows
+    xs, ys, refs = [], [], []
+    for k, (inst, b) in enumerate(zip(insts, bases)):
+        x = V.start_vector(b.dim, 100 + k, inst.is_complex)
+        xt = _dev(torch, x)
+        xs.append(xt)
+        ys.append(torch.full_like(xt, 7.0))   # every entry must be overwritten
+        yt = torch.zeros_like(xt)
+        b.apply_H(xt, yt)
+        refs.append(yt)
+    batch.apply_H(xs, ys)
+    torch.cuda.synchronize()
+    for inst, b, x, y, r in zip(insts, bases, xs, ys, refs):
+        assert torch.equal(y, r), f"{inst.name} {inst.sector}"
+        reps, stabs = b.export()
+        H = O.coo_matrix(inst, reps, stabs)
+        assert np.max(np.abs(y.cpu().numpy() - H @ x.cpu().numpy())) < 1e-12
+    # a second call with other vectors reuses the batch
+    xs2 = [x.flip(0).contiguous() for x in xs]
+    batch.apply_H(xs2, ys)
+    for b, x, y in zip(bases, xs2, ys):
+        r = torch.zeros_like(x)
+        b.apply_H(x, r)
+        torch.cuda.synchronize()
+        assert torch.equal(y, r)
+    batch.free()
+
+
+def test_batch_lanczos(S):
+    torch = _torch()
+    insts = [L.chain16(), L.small_instances()[13], L.small_instances()[14], L.small_instances()[15],
+             L.small_instances()[11], L.small_instances()[3]]
+    bases = [S.Basis.build(i) for i in insts]
+    batch = S.Batch(bases, tile_rows=128, autotune=False)
+    n_iter = 60
+    v0s = [_dev(torch, V.start_vector(b.dim, 1002 + k, i.is_complex)) for k, (i, b) in enumerate(zip(insts, bases))]
+    res = batch.lanczos(v0s, n_iter)
+    for k, (inst, b) in enumerate(zip(insts, bases)):
+        _say("sector", inst.name, inst.sector, "dim", b.dim)
+        a, beta, n, broken = res[k]
+        a1, b1, n1, br1 = b.lanczos(v0s[k], n_iter)
+        assert n == n1 and broken == br1
+        m = min(10, n)
+        assert np.max(np.abs(a[:m] - a1[:m])) < 1e-10
+        assert np.max(np.abs(beta[:m] - b1[:m])) < 1e-10
+        e = S.eigenvalues(a, beta, 1)[0]
+        e1 = S.eigenvalues(a1, b1, 1)[0]
+        reps, stabs = b.export()
+        H = O.coo_matrix(inst, reps, stabs)
+        ao, bo = O.lanczos(lambda v: H @ v, v0s[k].cpu().numpy(), n_iter, hermitian_complex=inst.is_complex)
+        eo = O.tmatrix_eigs(ao, bo)[0]
+        assert abs(e - e1) <= 1e-10 * abs(e1)
+        assert abs(e - eo) <= 1e-10 * abs(eo)
+    # repeated runs are identical (deterministic reductions, graph replay)
+    res2 = batch.lanczos(v0s, n_iter)
+    for r1, r2 in zip(res, res2):
+        assert np.array_equal(r1[0], r2[0]) and np.array_equal(r1[1], r2[1])
+    batch.free()
+
+
+def test_batch_breakdown_in_one_sector(S):
+    """A 2-state sector breaks down after two steps; the others run on."""
+    torch = _torch()
+    insts = [L.chain(4), L.chain16()]
+    bases = [S.Basis.build(i) for i in insts]
+    batch = S.Batch(bases, tile_rows=64, autotune=False)
+    v0s = [_dev(torch, np.array([1.0, 0.3])), _dev(torch, V.start_vector(810, 5))]
+    res = batch.lanczos(v0s, 30)
+    assert res[0][2] == 2 and res[0][3]
+    assert np.allclose(np.sort(S.eigenvalues(res[0][0], res[0][1], 2)), [-2.0, 1.0])
+    assert res[1][2] == 30 and not res[1][3]
+    batch.free()
+
+
+def test_batch_learned_lookup(S):
+    torch = _torch()
+    insts = [L.chain16(), L.small_instances()[13], L.small_instances()[14], L.small_instances()[15]]
+    bases = [S.Basis.build(i) for i in insts]
+    batch = S.Batch(bases, tile_rows=256, autotune=False)
+    xs = [_dev(torch, V.start_vector(b.dim, 7 + k, i.is_complex)) for k, (i, b) in enumerate(zip(insts, bases))]
+    with pytest.raises(S.EdError) as e:
+        batch.apply_H(xs, [torch.zeros_like(x) for x in xs], mode=1)
+    assert e.value.status == S.ED_EINVAL
+    for b in bases:
+        b.train_index(steps=300, seed=3)
+    y0 = [torch.zeros_like(x) for x in xs]
+    y1 = [torch.zeros_like(x) for x in xs]
+    batch.apply_H(xs, y0, mode=0)
+    batch.apply_H(xs, y1, mode=1)
+    torch.cuda.synchronize()
+    for a, b in zip(y0, y1):
+        assert torch.equal(a, b)
+    r0 = batch.lanczos(xs, 30, mode=0)
+    r1 = batch.lanczos(xs, 30, mode=1)
+    for a, b in zip(r0, r1):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    batch.free()
+
+
+def test_batch_rejects_bad_arguments(S):
+    with pytest.raises(S.EdError) as e:
+        S.Batch([])
+    assert e.value.status == S.ED_EINVAL
+
+
+def test_square32_all_sectors(S):
+    """Every one-dimensional sector of the 32-site square J1-J2 model in one
+    batch: per-sector dimension against the character formula, batched H.v
+    equal to the per-sector kernel on the whole vector, and oracle rows."""
+    torch = _torch()
+    insts = L.square32_sectors()
+    _say("square32 sectors", len(insts))
+    bases = []
+    for inst in insts:
+        b = S.Basis.build(inst)
+        assert b.dim == O.character_formula_dim(inst), inst.name
+        bases.append(b)
+    batch = S.Batch(bases)
+    info = batch.info()
+    _say("  total dim", info["total_dim"], "tile_rows", info["tile_rows"], "tiles", info["n_tiles"])
+    xs, ys, rows_all = [], [], []
+    for k, (inst, b) in enumerate(zip(insts, bases)):
+        reps, _ = b.export()
+        xs.append(_dev(torch, V.state_vector(reps, 4242 + k, inst.is_complex)))
+        ys.append(torch.zeros_like(xs[-1]))
+    batch.apply_H(xs, ys)
+    torch.cuda.synchronize()
+    for k, (inst, b) in enumerate(zip(insts, bases)):
+        r = torch.zeros_like(xs[k])
+        b.apply_H(xs[k], r)
+        torch.cuda.synchronize()
+        assert torch.equal(ys[k], r), inst.name
+        rep, _, _, triv = O.rep_many(inst, V.random_sector_states(32, 16, 200, 77 + k))
+        rows = np.unique(rep[triv])
+        kt = _dev(torch, rows.view(np.int64))
+        it = torch.empty_like(kt)
+        b.lookup(kt, it)
+        torch.cuda.synchronize()
+        idx = it.cpu().numpy()
+        assert (idx >= 0).all()
+        yo, ok, _ = O.rows_apply(inst, rows, lambda t: V.state_vector(t, 4242 + k, inst.is_complex))
+        assert ok.all()
+        y = ys[k].cpu().numpy()[idx]
+        assert np.max(np.abs(y - (yo if inst.is_complex else yo.real))) < 1e-12, inst.name
+    batch.free()
