@@ -226,7 +226,7 @@ ed_status ed_eigenvalues(const double *alpha, const double *beta, int32_t n, int
  * Zero fields mean defaults (n_features = 1 (the only value accepted),
  * hidden = 32 (the only value accepted), steps = 3000, batch = 8192,
  * lr = 1e-2 with cosine decay, log2_leaves ~ log2(dim / 256) (at most 22),
- * keys_per_bucket = 8).
+ * keys_per_bucket = 2; 8 halves the table at some cost in speed).
  */
 typedef struct {
     int32_t n_features;

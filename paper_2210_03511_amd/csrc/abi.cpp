@@ -516,7 +516,7 @@ ed_status ed_index_train(ed_basis *b, const ed_index_cfg *cfg_in, ed_index_stats
     if (b->d_leaves && b->log2_leaves != lg) return fail(ED_EINVAL, "index already trained with another leaf count");
     if (!b->d_leaves && (s = dev_alloc(b, &b->d_leaves, (sizeof(Leaf) << lg))) != ED_OK) return s;
     const uint64_t M = 1ull << lg;
-    const uint32_t target = cfg.keys_per_bucket > 0 ? (uint32_t)cfg.keys_per_bucket : 8u;
+    const uint32_t target = cfg.keys_per_bucket > 0 ? (uint32_t)cfg.keys_per_bucket : 2u;
     uint32_t *d_sizes = nullptr, *d_err = nullptr, net_err = 0;
     uint64_t *d_offsets = nullptr, *d_total = nullptr, total = 0;
     unsigned long long *d_stats = nullptr, hstats[2] = {0, 0};

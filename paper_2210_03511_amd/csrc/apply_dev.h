@@ -203,42 +203,55 @@ __device__ __forceinline__ double apply_row(const KParams &p, const Lds &L, int6
         key[k] = 0;
         cr[k] = ci[k] = 0.0;
     }
-    for (int q = 0; q < p.n_pairs; ++q) {
-        const PairTerm pt = L.pairs[q];
-        const bool anti = __popcll(s & pt.mask) == 1;
-        diag += anti ? -0.25 * pt.Jsum : 0.25 * pt.Jsum;
-        if (!anti) continue;
-        double hre, him;
-        pair_amp<CPLX>(s, pt, L, hre, him);
-        if (hre == 0.0 && him == 0.0) continue;
-#ifdef PROBE_FAKE_REP
-        const Found f = Found{s ^ pt.mask, 0u, 1u};
-#else
-        const Found f = find_rep(s ^ pt.mask, p, L);
-#endif
-        const double w = L.sqrtt[f.cnt];
-        double kr, ki = 0.0;
-        if (!CPLX) {
-            kr = L.chi[f.g] * w * hre;
-        } else {
-            // chi(g) * w * conj(h)
-            const double c_r = L.chi[2 * f.g] * w, c_i = L.chi[2 * f.g + 1] * w;
-            kr = c_r * hre + c_i * him;
-            ki = c_i * hre - c_r * him;
+    // Pairs are taken in windows of 128: the antiparallel pairs of the window
+    // are marked in a bit mask first (and the diagonal summed), then every
+    // lane walks its own marked pairs in ascending order.  Lanes of a wave
+    // thus stay busy while any lane has pairs left, instead of idling on the
+    // parallel pairs of the others; the order of the terms is unchanged.
+    for (int q0 = 0; q0 < p.n_pairs; q0 += 128) {
+        const int qn = min(p.n_pairs - q0, 128);
+        uint64_t m[2] = {0ull, 0ull};
+        for (int q = 0; q < qn; ++q) {
+            const PairTerm &pt = L.pairs[q0 + q];
+            const bool anti = __popcll(s & pt.mask) == 1;
+            diag += anti ? -0.25 * pt.Jsum : 0.25 * pt.Jsum;
+            m[q >> 6] |= (uint64_t)anti << (q & 63);
         }
+        for (int h = 0; h < 2; ++h) {
+            uint64_t mm = m[h];
+            while (mm) {
+                const int q = q0 + 64 * h + __builtin_ctzll(mm);
+                mm &= mm - 1;
+                const PairTerm pt = L.pairs[q];
+                double hre, him;
+                pair_amp<CPLX>(s, pt, L, hre, him);
+                if (hre == 0.0 && him == 0.0) continue;
+                const Found f = find_rep(s ^ pt.mask, p, L);
+                const double w = L.sqrtt[f.cnt];
+                double kr, ki = 0.0;
+                if (!CPLX) {
+                    kr = L.chi[f.g] * w * hre;
+                } else {
+                    // chi(g) * w * conj(h)
+                    const double c_r = L.chi[2 * f.g] * w, c_i = L.chi[2 * f.g + 1] * w;
+                    kr = c_r * hre + c_i * him;
+                    ki = c_i * hre - c_r * him;
+                }
 #pragma unroll
-        for (int k = 0; k < kBatch - 1; ++k) {
-            key[k] = key[k + 1];
-            cr[k] = cr[k + 1];
-            ci[k] = ci[k + 1];
-        }
-        key[kBatch - 1] = f.rep;
-        cr[kBatch - 1] = kr;
-        ci[kBatch - 1] = ki;
-        valid = (valid >> 1) | (1u << (kBatch - 1));
-        if (valid & 1u) {
-            flush_batch<CPLX, LEARNED>(key, cr, ci, valid, p, L.pw, x, ar, ai);
-            valid = 0;
+                for (int k = 0; k < kBatch - 1; ++k) {
+                    key[k] = key[k + 1];
+                    cr[k] = cr[k + 1];
+                    ci[k] = ci[k + 1];
+                }
+                key[kBatch - 1] = f.rep;
+                cr[kBatch - 1] = kr;
+                ci[kBatch - 1] = ki;
+                valid = (valid >> 1) | (1u << (kBatch - 1));
+                if (valid & 1u) {
+                    flush_batch<CPLX, LEARNED>(key, cr, ci, valid, p, L.pw, x, ar, ai);
+                    valid = 0;
+                }
+            }
         }
     }
     if (valid) flush_batch<CPLX, LEARNED>(key, cr, ci, valid, p, L.pw, x, ar, ai);

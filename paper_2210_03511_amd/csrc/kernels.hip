@@ -467,8 +467,8 @@ hipError_t launch_scan(const uint32_t *d_in, uint64_t *d_out, uint64_t n, uint64
         if (e != hipSuccess) return e;
     }
     e = hipStreamSynchronize(st);
-    hipFree(sums);
-    hipFree(sums_off);
+    (void)hipFree(sums);
+    (void)hipFree(sums_off);
     return e;
 }
 
@@ -493,8 +493,8 @@ hipError_t launch_scan_u64(const uint64_t *d_in, uint64_t *d_out, uint64_t n, ui
         if (e != hipSuccess) return e;
     }
     e = hipStreamSynchronize(st);
-    hipFree(sums);
-    hipFree(sums_off);
+    (void)hipFree(sums);
+    (void)hipFree(sums_off);
     return e;
 }
 
