@@ -33,7 +33,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="square40", choices=["square40", "square32", "triangular36", "chain16"])
+    ap.add_argument("--config", default="square40",
+                    choices=["square40", "square32", "triangular36", "chain16", "square32_batch"])
     ap.add_argument("--lookup", default="both", choices=["plain", "learned", "both"])
     ap.add_argument("--apply-reps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -63,26 +64,157 @@ def cpu_baseline(inst, budget_s):
     from workloads import vectors as V
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     os.environ.setdefault("OMP_NUM_THREADS", str(cores))
-    # calibrate on a small sample, then run a sample sized to the budget
-    n = 256
-    st = V.random_sector_states(inst.n_sites, inst.n_up, n, 77)
-    rep, g, stab, triv = O.rep_many(inst, st)
-    rows = np.unique(rep[triv])
-    t0 = time.perf_counter()
-    O.row_entries(inst, rows)
-    t_cal = max(time.perf_counter() - t0, 1e-3)
-    n_rows = int(max(32, min(200000, len(rows) * budget_s / t_cal)))
-    st = V.random_sector_states(inst.n_sites, inst.n_up, int(n_rows * 1.3) + 8, 78)
-    rep, g, stab, triv = O.rep_many(inst, st)
-    rows = np.unique(rep[triv])[:n_rows]
-    t0 = time.perf_counter()
-    rp, tgt, coef, ok, ne = O.row_entries(inst, rows)
-    t = time.perf_counter() - t0
+    # grow the sample until one timed pass takes at least half the budget
+    n_rows, seed = 2000, 78
+    while True:
+        st = V.random_sector_states(inst.n_sites, inst.n_up, int(n_rows * 1.3) + 8, seed)
+        rep, g, stab, triv = O.rep_many(inst, st)
+        rows = np.unique(rep[triv])[:n_rows]
+        t0 = time.perf_counter()
+        rp, tgt, coef, ok, ne = O.row_entries(inst, rows)
+        t = time.perf_counter() - t0
+        if t >= 0.5 * budget_s or n_rows >= 4_000_000:
+            break
+        n_rows = int(n_rows * min(16.0, max(2.0, 1.1 * budget_s / max(t, 1e-3))))
+        seed += 1
     elements = int(ne.sum())
     return {"value": elements / t, "unit": "elements/s", "cores": cores, "kind": "oracle",
             "sample": f"{len(rows)} oracle-sampled sector rows of the same sector ({elements} elements, "
                       f"brute-force orbits, pull form), {t:.1f} s on {cores} host threads",
             "rows_per_s": len(rows) / t}
+
+
+COUNTERS = os.path.join(ROOT, "profiles", "k_apply_square40_counters.json")
+
+
+def kernel_sources_sha256():
+    """Digest of every HIP/C++ source of the library (any change invalidates
+    recorded hardware counters)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2210_03511_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(config, mode):
+    """HBM bytes per launch of the H.v kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes, scaled by the copy calibration; None if
+    there is no record for this workload and mode or the sources changed."""
+    if not os.path.exists(COUNTERS):
+        return None
+    with open(COUNTERS) as f:
+        rec = json.load(f)
+    if rec.get("config") != config or rec.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    k = rec["kernels"].get("learned" if mode == 1 else "plain")
+    if not k:
+        return None
+    return (k["fetch_kib"] * rec["fetch_factor"] + k["write_kib"] * rec["write_factor"]) * 1024.0
+
+
+def alg_bytes_of(D, n_off, cplx):
+    """Algorithmic bytes of one H.v: per row the representative (8), its
+    stabilizer code (2), x_i and y_i; per off-diagonal element x_j and the
+    representative rep_j that confirms the match."""
+    vb = 16 if cplx else 8
+    return D * (8 + 2 + 2 * vb) + n_off * (vb + 8)
+
+
+def main_batch(args):
+    """All 46 one-dimensional sectors of the 32-site square J1-J2 model in one
+    batch: one persistent launch per H.v, one captured graph per Lanczos step
+    of all sectors."""
+    import torch
+    from paper_2210_03511_amd import symed as S
+    from workloads import lattices as L
+    from workloads import vectors as V
+
+    insts = L.square32_sectors()
+    t0 = time.perf_counter()
+    bases = [S.Basis.build(i) for i in insts]
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    infos = [b.info() for b in bases]
+    modes = [0] if args.lookup == "plain" else ([1] if args.lookup == "learned" else [0, 1])
+    t_train = None
+    if 1 in modes:
+        t0 = time.perf_counter()
+        for b in bases:
+            b.train_index()
+        t_train = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    batch = S.Batch(bases)
+    t_tune = time.perf_counter() - t0
+    binfo = batch.info()
+    v0s = [torch.from_numpy(V.start_vector(inf["dim"], 4001 + k, bool(inf["is_complex"]))).cuda()
+           for k, inf in enumerate(infos)]
+    ys = [torch.empty_like(v) for v in v0s]
+    stream = torch.cuda.current_stream()
+    apply_t = {}
+    for m in modes:
+        batch.apply_H(v0s, ys, mode=m)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.apply_reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            batch.apply_H(v0s, ys, mode=m)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        apply_t[m] = float(np.mean(ts))
+    del ys
+    step_t, e_min = {}, {}
+    for m in modes:
+        if args.warmup > 0:
+            batch.lanczos(v0s, args.warmup, mode=m)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = batch.lanczos(v0s, args.steps, mode=m)
+        torch.cuda.synchronize()
+        step_t[m] = (time.perf_counter() - t0) / args.steps
+        e_min[m] = min(float(S.eigenvalues(a, b, 1)[0]) for a, b, n, br in res)
+    best = min(modes, key=lambda m: step_t[m])
+    n_el = binfo["total_elements"]
+    alg = sum(alg_bytes_of(inf["dim"], inf["n_offdiag"], bool(inf["is_complex"])) for inf in infos)
+    achieved = alg / apply_t[best] / 1e9
+    name = lambda m: "learned" if m == 1 else "plain"
+    dims = [inf["dim"] for inf in infos]
+    out = {
+        "metric": "H.v elements/s & s per Lanczos step, batched sectors: learned vs plain lookup",
+        "value": n_el / step_t[best],
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_t[best] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64/c128",
+        "data": "synthetic (seeded N(0,1) start vectors, seeds 4001+s; deterministic lattice)",
+        "config": {"workload": "square32 J1-J2 (J2/J1=0.5), Sz=0, all 46 one-dimensional sectors in one batch",
+                   "n_sectors": len(insts), "n_complex": sum(int(i["is_complex"]) for i in infos),
+                   "total_dim": binfo["total_dim"], "min_dim": min(dims), "max_dim": max(dims),
+                   "n_elements_per_Hv": n_el, "lookup": name(best), "tile_rows": binfo["tile_rows"],
+                   "n_tiles": binfo["n_tiles"], "parallelism": "single GPU"},
+        "elements_per_s_Hv": {name(m): n_el / apply_t[m] for m in modes},
+        "s_per_step": {name(m): step_t[m] for m in modes},
+        "lowest_E_over_sectors": {name(m): e_min[m] for m in modes},
+        "setup": {"basis_build_s": t_build, "index_train_s": t_train, "autotune_s": t_tune,
+                  "autotune": {"tile_rows": binfo["tune_rows"], "seconds": binfo["tune_seconds"]}},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_batch_apply", "alg_bytes_per_launch": alg, "avg_launch_s": apply_t[best]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(insts[0], args.cpu_seconds)
+        out["cpu_baseline"]["sample"] += f" (sector {insts[0].name})"
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -91,6 +223,8 @@ def main():
         print(f"bench.py measures one MI355X; --gpus {args.gpus} is not supported in this build "
               f"(the multi-GPU design is described in DESIGN.md but not implemented).", file=sys.stderr)
         sys.exit(2)
+    if args.config == "square32_batch":
+        return main_batch(args)
     import torch
     from paper_2210_03511_amd import symed as S
     from workloads import vectors as V
@@ -161,10 +295,7 @@ def main():
     best = min(modes, key=lambda m: step_t[m])
     n_el = info["n_elements"]
     n_off = info["n_offdiag"]
-    vb = 16 if cplx else 8
-    # algorithmic bytes of one H.v launch: per row rep (8) + stabilizer code
-    # (2) + x_i + y_i; per off-diagonal element x_j + rep_j
-    alg_bytes = D * (8 + 2 + 2 * vb) + n_off * (vb + 8)
+    alg_bytes = alg_bytes_of(D, n_off, cplx)
     t_apply = apply_t[best]
     achieved = alg_bytes / t_apply / 1e9
     out = {
@@ -193,7 +324,7 @@ def main():
                                "learned_mean": train["mean_window"] if train else None,
                                "learned_max": train["max_err"] if train else None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(args.config, best),
                      "kernel": "k_apply", "alg_bytes_per_launch": alg_bytes, "avg_launch_s": t_apply},
     }
     if train is not None:

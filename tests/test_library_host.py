@@ -11,6 +11,10 @@ import pytest
 
 from workloads import lattices as L
 
+import json
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")))
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -42,38 +46,41 @@ def _state(bits):
 
 
 def test_two_sublattice_example_tables(symed):
-    # chain of 6 sites, A = positions 0,2,4, B = 1,3,5 (thesis worked example)
-    inst = L.chain(6, sublat=(2,))
+    g = GOLD["two_sublattice"]
+    inst = L.chain(g["n_sites"], sublat=(2,))
     rep, off, sym, act = symed.tables_inspect(inst, 2)
-    sA, sB = _state("uud"), _state("dud")
-    assert rep[0, sA] == 0b011          # Rep_A = |down up up> = 3
-    assert rep[1, sB] == 0b001          # Rep_B = |down down up> = 1
+    sA, sB = _state(g["substates"]["A"]), _state(g["substates"]["B"])
+    assert rep[0, sA] == g["rep"]["A"]
+    assert rep[1, sB] == g["rep"]["B"]
     k = 1 * 8 + sB
-    assert list(sym[off[k]:off[k + 1]]) == [1]   # Sym_B = {T_1}
-    # T_1 sigma composed from the SymmetryAction tables = 14
+    assert list(sym[off[k]:off[k + 1]]) == g["sym"]["B"]
+    # g sigma composed from the SymmetryAction tables is the representative
     sigma = (sA << 3) | sB
-    img = int(act[1, 0, sA]) | int(act[1, 1, sB])
-    assert img == 14 and img == _state("dduuud")
-    assert sigma == _state("uuddud")
+    assert sigma == _state(g["state"])
+    img = int(act[g["g"], 0, sA]) | int(act[g["g"], 1, sB])
+    assert img == g["representative"] == _state(g["representative_state"])
 
 
 def test_three_sublattice_example_tables(symed):
-    inst = L.chain(6, sublat=(3,))
+    g = GOLD["three_sublattice"]
+    inst = L.chain(g["n_sites"], sublat=(3,))
     rep, off, sym, act = symed.tables_inspect(inst, 3)
-    sA, sB, sC = _state("uu"), _state("dd"), _state("ud")
-    assert (rep[0, sA], rep[1, sB], rep[2, sC]) == (0b11, 0b00, 0b01)
+    sA, sB, sC = (_state(g["substates"][X]) for X in "ABC")
+    assert (rep[0, sA], rep[1, sB], rep[2, sC]) == (g["rep"]["A"], g["rep"]["B"], g["rep"]["C"])
 
     def symset(X, s):
         k = X * 4 + s
         return sorted(sym[off[k]:off[k + 1]].tolist())
 
-    assert symset(0, sA) == [0, 3]      # {I, T_3}
-    assert symset(1, sB) == [2, 5]      # {T_2, T_5}
-    assert symset(2, sC) == [1]         # {T_1}
-    # T_2 sigma < T_5 sigma, and T_2 sigma = |ddd uuu> = 7
-    def apply(g):
-        return int(act[g, 0, sA]) | int(act[g, 1, sB]) | int(act[g, 2, sC])
-    assert apply(2) == 7 and apply(5) == _state("dduduu") and apply(2) < apply(5)
+    assert symset(0, sA) == g["sym"]["A"]
+    assert symset(1, sB) == g["sym"]["B"]
+    assert symset(2, sC) == g["sym"]["C"]
+
+    def apply(h):
+        return int(act[h, 0, sA]) | int(act[h, 1, sB]) | int(act[h, 2, sC])
+    oc = g["other_candidate"]
+    assert apply(g["g"]) == g["representative"]
+    assert apply(oc["g"]) == _state(oc["state"]) and apply(g["g"]) < apply(oc["g"])
 
 
 def test_tables_match_definition_on_random_substates(symed):

@@ -12,6 +12,11 @@ import scipy.sparse
 from oracle import oracle as O
 from workloads import lattices as L
 
+import json
+import os
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")))
+
 
 def _state(bits):
     """'uudu' -> integer, first site = most significant bit, up = 1."""
@@ -24,24 +29,24 @@ def _state(bits):
 # --- encoding and the exchange example ("Representing Hilbert spaces") ------
 
 def test_integer_encoding_example():
-    # |up up down up> -> (1101)_2 = 13
-    assert _state("uudu") == 13
+    g = GOLD["encoding"]
+    assert _state(g["state"]) == g["value"]
 
 
 def test_exchange_example_kron_and_terms():
-    # 1/2 (S+_2 S-_3 + S-_2 S+_3)|13> = 1/2 |11>  (sites 2,3 one-based)
-    inst = L.Instance("pair", 4, np.array([[1, 2]], np.int32), np.array([1.0]), np.zeros((0, 3), np.int32),
-                      np.zeros(0), 3, np.arange(4, dtype=np.int32)[None], np.zeros(1, np.uint8),
-                      np.ones(1, complex), [1])
+    g = GOLD["exchange"]
+    a, b = (k - 1 for k in g["pair_one_based"])
+    inst = L.Instance("pair", g["n_sites"], np.array([[a, b]], np.int32), np.array([1.0]),
+                      np.zeros((0, 3), np.int32), np.zeros(0), 3, np.arange(4, dtype=np.int32)[None],
+                      np.zeros(1, np.uint8), np.ones(1, complex), [1])
     H = O.kron_hamiltonian(inst).toarray()
-    # exchange part only: remove the diagonal Ising piece
-    assert H[11, 13] == pytest.approx(0.5)
-    assert H[13, 11] == pytest.approx(0.5)
-    rp, tgt, coef, ok, ne = O.row_entries(inst, np.array([13], np.uint64))
+    assert H[g["to"], g["from"]] == pytest.approx(g["amplitude"])
+    assert H[g["from"], g["to"]] == pytest.approx(g["amplitude"])
+    rp, tgt, coef, ok, ne = O.row_entries(inst, np.array([g["from"]], np.uint64))
     entries = {int(t): c for t, c in zip(tgt, coef)}
-    assert entries[11] == pytest.approx(0.5)
-    # Ising piece: sites 2,3 (one-based) are up, down -> -1/4
-    assert entries[13] == pytest.approx(-0.25)
+    assert entries[g["to"]] == pytest.approx(g["amplitude"])
+    # Ising piece: the pair is up, down -> -1/4
+    assert entries[g["from"]] == pytest.approx(-0.25)
     assert ne[0] == 2
 
 
@@ -82,26 +87,27 @@ def test_four_site_ring_ground_state():
 # --- sublattice-coding worked examples (section "Sublattice coding") --------
 
 def test_two_sublattice_example_representative():
-    # labels (0,2,4 | 1,3,5); sigma = |uud dud> -> rep T_1 sigma = |ddu uud> = 14
-    inst = L.chain(6, sublat=(2,))
-    assert inst.meta["positions"] == [0, 2, 4, 1, 3, 5]
-    s = _state("uuddud")
-    rep, g, st, tv = O.rep_many(inst, np.array([s], np.uint64))
-    assert int(rep[0]) == _state("dduuud") == 14
-    assert int(g[0]) == 1            # T_1
-    assert O.act(inst, 1, s) == 14
+    g = GOLD["two_sublattice"]
+    inst = L.chain(g["n_sites"], sublat=(2,))
+    assert inst.meta["positions"] == g["chain_positions_by_label"]
+    s = _state(g["state"])
+    rep, gm, st, tv = O.rep_many(inst, np.array([s], np.uint64))
+    assert int(rep[0]) == _state(g["representative_state"]) == g["representative"]
+    assert int(gm[0]) == g["g"]
+    assert O.act(inst, g["g"], s) == g["representative"]
 
 
 def test_three_sublattice_example_representative():
-    # labels (0,3 | 1,4 | 2,5); same sigma -> rep T_2 sigma = |ddd uuu> = 7
-    inst = L.chain(6, sublat=(3,))
-    assert inst.meta["positions"] == [0, 3, 1, 4, 2, 5]
-    s = _state("uuddud")
-    rep, g, st, tv = O.rep_many(inst, np.array([s], np.uint64))
-    assert int(rep[0]) == 7
-    assert int(g[0]) == 2            # T_2
-    # the other candidate printed in the example: T_5 sigma = |ddu duu>
-    assert O.act(inst, 5, s) == _state("ddduuu".replace("ddduuu", "dduduu"))
+    g = GOLD["three_sublattice"]
+    inst = L.chain(g["n_sites"], sublat=(3,))
+    assert inst.meta["positions"] == g["chain_positions_by_label"]
+    s = _state(g["state"])
+    rep, gm, st, tv = O.rep_many(inst, np.array([s], np.uint64))
+    assert int(rep[0]) == _state(g["representative_state"]) == g["representative"]
+    assert int(gm[0]) == g["g"]
+    # the other candidate printed in the example is larger
+    oc = g["other_candidate"]
+    assert O.act(inst, oc["g"], s) == _state(oc["state"]) > g["representative"]
 
 
 # --- enumeration vs the character formula -----------------------------------
