@@ -35,7 +35,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="square40",
                     choices=["square40", "square32", "triangular36", "chain16", "square32_batch"])
-    ap.add_argument("--lookup", default="both", choices=["plain", "learned", "both"])
+    ap.add_argument("--lookup", default="all", choices=["plain", "learned", "hash", "both", "all"],
+                    help="both = plain and learned; all = plain, learned and hashed")
     ap.add_argument("--apply-reps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -109,7 +110,7 @@ def recorded_traffic(config, mode):
         rec = json.load(f)
     if rec.get("config") != config or rec.get("sources_sha256") != kernel_sources_sha256():
         return None
-    k = rec["kernels"].get("learned" if mode == 1 else "plain")
+    k = rec["kernels"].get({0: "plain", 1: "learned", 2: "hash"}[mode])
     if not k:
         return None
     return (k["fetch_kib"] * rec["fetch_factor"] + k["write_kib"] * rec["write_factor"]) * 1024.0
@@ -138,6 +139,7 @@ def main_batch(args):
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     infos = [b.info() for b in bases]
+    # the batched path has the plain and the learned lookups
     modes = [0] if args.lookup == "plain" else ([1] if args.lookup == "learned" else [0, 1])
     t_train = None
     if 1 in modes:
@@ -247,14 +249,18 @@ def main():
     cplx = bool(info["is_complex"])
     modes = []
     train = None
-    if args.lookup in ("plain", "both"):
+    hashed = None
+    if args.lookup in ("plain", "both", "all"):
         modes.append(0)
-    if args.lookup in ("learned", "both") and hasattr(S.lib(), "ed_index_train"):
+    if args.lookup in ("learned", "both", "all"):
         t0 = time.perf_counter()
         train = basis.train_index()
         train["wall_seconds"] = time.perf_counter() - t0
         modes.append(1)
         info = basis.info()
+    if args.lookup in ("hash", "all"):
+        hashed = basis.build_hash()
+        modes.append(2)
 
     v0 = V.start_vector(D, seed, cplx)
     v0t = torch.from_numpy(v0).cuda()
@@ -293,6 +299,7 @@ def main():
         energies[m] = float(S.eigenvalues(a, b, 1)[0])
 
     best = min(modes, key=lambda m: step_t[m])
+    name = {0: "plain", 1: "learned", 2: "hash"}
     n_el = info["n_elements"]
     n_off = info["n_offdiag"]
     alg_bytes = alg_bytes_of(D, n_off, cplx)
@@ -311,13 +318,13 @@ def main():
         "vs_baseline": None,
         "dtype": "c128" if cplx else "f64",
         "data": "synthetic (seeded N(0,1) start vector; deterministic lattice)",
-        "config": {"workload": desc, "dim": D, "n_elements_per_Hv": n_el, "lookup": "learned" if best == 1 else "plain",
+        "config": {"workload": desc, "dim": D, "n_elements_per_Hv": n_el, "lookup": name[best],
                    "n_sub_rep": info["n_sub_rep"], "n_sub_act": info["n_sub_act"],
                    "prefix_bits": info["prefix_bits"], "parallelism": "single GPU"},
-        "elements_per_s_Hv": {("learned" if m == 1 else "plain"): n_el / apply_t[m] for m in modes},
-        "s_per_step": {("learned" if m == 1 else "plain"): step_t[m] for m in modes},
+        "elements_per_s_Hv": {name[m]: n_el / apply_t[m] for m in modes},
+        "s_per_step": {name[m]: step_t[m] for m in modes},
         "rows_per_s_Hv": D / t_apply,
-        "lanczos_E0_after_steps": {("learned" if m == 1 else "plain"): energies[m] for m in modes},
+        "lanczos_E0_after_steps": {name[m]: energies[m] for m in modes},
         "setup": {"basis_build_s": t_build, "table_bytes": info["table_bytes"],
                   "limits_bytes": info["limits_bytes"], "device_bytes": info["bytes_device"]},
         "search_window_keys": {"plain_mean": info["limits_mean_window"], "plain_max": info["limits_max_window"],
@@ -325,10 +332,13 @@ def main():
                                "learned_max": train["max_err"] if train else None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(args.config, best),
-                     "kernel": "k_apply", "alg_bytes_per_launch": alg_bytes, "avg_launch_s": t_apply},
+                     "kernel": f"k_apply ({name[best]} lookup)", "alg_bytes_per_launch": alg_bytes,
+                     "avg_launch_s": t_apply},
     }
     if train is not None:
         out["learned_index"] = train
+    if hashed is not None:
+        out["hash_table"] = hashed
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -169,14 +169,18 @@ ed_status ed_basis_device_reps(const ed_basis *basis, const uint64_t **d_reps);
  * accumulates character x norm ratio x amplitude x x_j; no atomics).
  *   d_x, d_y: device vectors of length dim (f64 or interleaved c128); must
  *   not alias.  lookup_mode: 0 = plain (Limits + binary search), 1 = learned
- *   index (requires ed_index_train).  Asynchronous on `stream`.
+ *   index (requires ed_index_train), 2 = hashed staging table (requires
+ *   ed_hash_build; x is first copied into the table, which the basis owns,
+ *   so calls with mode 2 on one basis must not overlap in time).  The result
+ *   is the same in every mode, bit for bit.  Asynchronous on `stream`.
  */
 ed_status ed_apply_H(const ed_basis *basis, const void *d_x, void *d_y, int32_t lookup_mode, void *stream);
 
 /*
  * Index lookup of n representatives: d_idx[k] = position of d_keys[k] in the
  * basis, or -1 if absent.  mode 0 = plain (Limits + binary search), 1 =
- * learned index + bounded search.  d_keys uint64[n], d_idx int64[n] device
+ * learned index + bounded search, 2 = membership from the hashed table
+ * (positions then from the plain lookup).  d_keys uint64[n], d_idx int64[n] device
  * memory.  Asynchronous on `stream`.
  */
 ed_status ed_lookup(const ed_basis *basis, const uint64_t *d_keys, int64_t n, int64_t *d_idx,
@@ -196,6 +200,36 @@ ed_status ed_lookup(const ed_basis *basis, const uint64_t *d_keys, int64_t n, in
  */
 ed_status ed_lanczos_run(const ed_basis *basis, const void *d_v0, int32_t n_iter, int32_t lookup_mode,
                          double *h_alpha, double *h_beta, int32_t *n_done, void *stream);
+
+/*
+ * Hashed staging table (not in the thesis).  The gather needs, for every
+ * target, only x at the target's position.  This table holds records
+ * {representative, x} (real) or {representative, Re x, Im x, unused}
+ * (complex) in `slots` = dim / load slots, placed by linear probing from a
+ * hash of the representative (MurmurHash3's 64-bit finalizer, reduced by a
+ * multiply-high).  Before each H.v in lookup_mode 2 the input vector is
+ * copied into the records; a lookup then probes from the home slot, and the
+ * line that confirms the key also holds x_j.  Memory: slots x 16 (real) or
+ * 32 (complex) bytes plus 4 bytes per state.  load: fraction of occupied
+ * slots, in [0.05, 0.95] (0 = default 0.5).  Needs n_sites < 64.  A second
+ * call with the same load returns the stats; another load is refused.
+ * Blocks until built.
+ */
+typedef struct {
+    double load;
+    int32_t reserved[2];
+} ed_hash_cfg;
+
+typedef struct {
+    int64_t slots;
+    int64_t bytes;             /* table + position-to-slot map */
+    double load;               /* dim / slots */
+    double mean_probes;        /* slots visited to find a representative, mean over the basis */
+    int64_t max_probes;
+    double build_seconds;
+} ed_hash_stats;
+
+ed_status ed_hash_build(ed_basis *basis, const ed_hash_cfg *cfg, ed_hash_stats *stats, void *stream);
 
 /*
  * Lowest k eigenvalues of the symmetric tridiagonal T-matrix with diagonal

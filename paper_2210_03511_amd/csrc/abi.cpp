@@ -70,6 +70,8 @@ KParams make_params(const ed_basis *b)
     p.mlp_F = b->mlp_F;
     p.mlp_c = b->mlp_c;
     p.has_index = b->indexed ? 1 : 0;
+    p.htab = b->d_htab;
+    p.hslots = b->hslots;
     return p;
 }
 
@@ -271,14 +273,24 @@ ed_status ed_basis_device_reps(const ed_basis *b, const uint64_t **d_reps)
     return ED_OK;
 }
 
+static ed_status check_lookup(const ed_basis *b, int mode)
+{
+    if (mode == 0 || (mode == 1 && b->indexed) || (mode == 2 && b->hashed)) return ED_OK;
+    return fail(ED_EINVAL, "lookup_mode must be 0 (plain), 1 (learned, after ed_index_train) or 2 (hashed, after "
+                           "ed_hash_build)");
+}
+
 ed_status ed_apply_H(const ed_basis *b, const void *d_x, void *d_y, int32_t lookup_mode, void *stream)
 {
     if (!b) return fail(ED_EINVAL, "NULL basis");
-    if (lookup_mode != 0 && !(lookup_mode == 1 && b->indexed))
-        return fail(ED_EINVAL, "lookup_mode must be 0 (plain) or 1 (learned, after ed_index_train)");
+    ed_status cs = check_lookup(b, lookup_mode);
+    if (cs != ED_OK) return cs;
     if (b->dim == 0) return ED_OK;
     if (!d_x || !d_y) return fail(ED_EINVAL, "NULL vector");
     if (d_x == d_y) return fail(ED_EINVAL, "x and y must not alias");
+    if (lookup_mode == 2)
+        HIP_OK(launch_hash_values(b->d_htab, b->d_pos2slot, d_x, b->dim, b->T.is_complex, b->cfg.vec_blocks,
+                                  (hipStream_t)stream));
     KParams p = make_params(b);
     HIP_OK(launch_apply(p, b->cfg, d_x, d_y, 0, lookup_mode, nullptr, nullptr, (hipStream_t)stream));
     return ED_OK;
@@ -287,8 +299,8 @@ ed_status ed_apply_H(const ed_basis *b, const void *d_x, void *d_y, int32_t look
 ed_status ed_lookup(const ed_basis *b, const uint64_t *d_keys, int64_t n, int64_t *d_idx, int32_t mode, void *stream)
 {
     if (!b) return fail(ED_EINVAL, "NULL basis");
-    if (mode != 0 && !(mode == 1 && b->indexed))
-        return fail(ED_EINVAL, "mode must be 0 (plain) or 1 (learned, after ed_index_train)");
+    ed_status cs = check_lookup(b, mode);
+    if (cs != ED_OK) return cs;
     if (n < 0) return fail(ED_EINVAL, "negative count");
     if (n == 0) return ED_OK;
     if (!d_keys || !d_idx) return fail(ED_EINVAL, "NULL array");
@@ -337,6 +349,9 @@ static hipError_t enqueue_step(ed_basis *b, int mode, hipStream_t st)
     const bool cplx = b->T.is_complex;
     KParams p = make_params(b);
     hipError_t e;
+    if (mode == 2 &&
+        (e = launch_hash_values(b->d_htab, b->d_pos2slot, b->d_v, b->dim, cplx, b->cfg.vec_blocks, st)) != hipSuccess)
+        return e;
     if ((e = launch_apply(p, b->cfg, b->d_v, b->d_w, cplx ? 2 : 1, mode, b->d_ls, b->d_partials, st)) != hipSuccess)
         return e;
     if ((e = launch_finalize(b->d_partials, b->cfg.apply_blocks, b->d_alpha, b->d_beta, b->d_ls, 0, st)) != hipSuccess)
@@ -358,8 +373,8 @@ ed_status ed_lanczos_run(const ed_basis *cb, const void *d_v0, int32_t n_iter, i
     ed_basis *b = const_cast<ed_basis *>(cb);
     if (!b || !d_v0 || !h_alpha || !h_beta || !n_done) return fail(ED_EINVAL, "NULL argument");
     if (n_iter < 1) return fail(ED_EINVAL, "n_iter must be >= 1");
-    if (lookup_mode != 0 && !(lookup_mode == 1 && b->indexed))
-        return fail(ED_EINVAL, "lookup_mode must be 0 (plain) or 1 (learned, after ed_index_train)");
+    ed_status cs = check_lookup(b, lookup_mode);
+    if (cs != ED_OK) return cs;
     if (b->dim == 0) return fail(ED_EINVAL, "empty sector");
     ed_status s = lanczos_workspace(b, n_iter);
     if (s != ED_OK) return s;
@@ -396,6 +411,50 @@ ed_status ed_lanczos_run(const ed_basis *cb, const void *d_v0, int32_t n_iter, i
         return ED_EBREAKDOWN;
     }
     *n_done = n_iter;
+    return ED_OK;
+}
+
+ed_status ed_hash_build(ed_basis *b, const ed_hash_cfg *cfg_in, ed_hash_stats *out, void *stream)
+{
+    if (!b) return fail(ED_EINVAL, "NULL basis");
+    ed_hash_cfg cfg{};
+    if (cfg_in) cfg = *cfg_in;
+    const double load = cfg.load == 0.0 ? 0.5 : cfg.load;
+    if (!(load >= 0.05 && load <= 0.95)) return fail(ED_EINVAL, "load must lie in [0.05, 0.95]");
+    if (b->T.N >= 64) return fail(ED_EINVAL, "the hashed table needs N < 64 (all-ones marks an empty slot)");
+    if (b->dim == 0) return fail(ED_EINVAL, "empty sector");
+    uint64_t slots = (uint64_t)std::ceil((double)b->dim / load);
+    if (slots <= (uint64_t)b->dim) slots = (uint64_t)b->dim + 1;
+    if (slots >= (1ull << 32)) return fail(ED_EINVAL, "too many slots for 32-bit slot numbers");
+    if (b->hashed) {
+        if (slots != b->hslots) return fail(ED_EINVAL, "hashed table already built with another load");
+        if (out) *out = b->hstats;
+        return ED_OK;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t words = b->T.is_complex ? 4 : 2;
+    ed_status s;
+    if ((s = dev_alloc(b, (void **)&b->d_htab, slots * words * sizeof(uint64_t))) != ED_OK) return s;
+    if ((s = dev_alloc(b, (void **)&b->d_pos2slot, (size_t)b->dim * sizeof(uint32_t))) != ED_OK) return s;
+    unsigned long long *d_stats = nullptr;
+    if ((s = dev_alloc(b, (void **)&d_stats, 2 * sizeof(unsigned long long))) != ED_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_OK(hipMemsetAsync(d_stats, 0, 2 * sizeof(unsigned long long), st));
+    HIP_OK(launch_hash_build(b->d_htab, slots, b->d_reps, b->dim, b->T.is_complex, b->d_pos2slot, d_stats,
+                             4 * b->n_cu, st));
+    unsigned long long h[2] = {0, 0};
+    HIP_OK(hipMemcpyAsync(h, d_stats, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    b->hslots = slots;
+    b->hashed = true;
+    ed_hash_stats &r = b->hstats;
+    r.slots = (int64_t)slots;
+    r.bytes = (int64_t)(slots * words * sizeof(uint64_t) + (size_t)b->dim * sizeof(uint32_t));
+    r.load = (double)b->dim / (double)slots;
+    r.mean_probes = (double)h[0] / (double)b->dim;
+    r.max_probes = (int64_t)h[1];
+    r.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (out) *out = r;
     return ED_OK;
 }
 

@@ -10,15 +10,36 @@
 
 namespace symed {
 
-// Compile-time tuning knobs (block size of the H.v kernel, lookups kept in
-// flight per lane).
+// Block size of the H.v kernel (compile-time tuning knob).
 #ifndef SYMED_APPLY_THREADS
 #define SYMED_APPLY_THREADS 1024
 #endif
-#ifndef SYMED_KBATCH
-#define SYMED_KBATCH 1
-#endif
 constexpr int kApplyThreads = SYMED_APPLY_THREADS;
+
+// Lookup kinds of the H.v gather.
+constexpr int kLookupPlain = 0;    // Limits prefix map + binary search (the thesis's method)
+constexpr int kLookupLearned = 1;  // learned index + bounded binary search
+constexpr int kLookupHash = 2;     // hashed staging table of {rep, x} records
+
+// Words per record of the hashed staging table and the empty-slot marker
+// (no N-bit configuration with N < 64 equals it).
+template <bool CPLX>
+constexpr int hash_words() { return CPLX ? 4 : 2; }
+constexpr uint64_t kHashEmpty = ~0ull;
+
+// Home slot of a key: the 64-bit finalizer of MurmurHash3 (Appleby) as the
+// mixing function, reduced to [0, slots) by a multiply-high.
+__host__ __device__ __forceinline__ uint64_t hash_mix(uint64_t k)
+{
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
+}
+
+__device__ __forceinline__ uint64_t hash_home(uint64_t key, uint64_t slots) { return __umul64hi(hash_mix(key), slots); }
 
 // Copy the table blob (multiple of 16 bytes) into LDS.
 __device__ __forceinline__ void stage_blob(unsigned char *lds, const void *blob, uint32_t bytes)
@@ -34,6 +55,7 @@ __device__ __forceinline__ void stage_blob(unsigned char *lds, const void *blob,
 // memory parallelization).  -1 if absent.
 __device__ __forceinline__ int64_t lookup_plain(uint64_t key, const KParams &p)
 {
+    if (key > p.maskN) return -1;
     const uint64_t pf = key >> (p.N - p.pbits);
     uint32_t lo = p.limits[pf], hi = p.limits[pf + 1];
     const uint32_t end = hi;
@@ -44,62 +66,6 @@ __device__ __forceinline__ int64_t lookup_plain(uint64_t key, const KParams &p)
     return (lo < end && p.reps[lo] == key) ? (int64_t)lo : -1;
 }
 
-// K independent lookups advanced in lockstep: every round issues the probe
-// loads of all unfinished searches before comparing, so one lane keeps up
-// to K dependent-load chains in flight.  valid bit k set = slot k in use.
-template <int K>
-__device__ __forceinline__ void lookup_plain_batch(const uint64_t (&key)[K], uint32_t valid, const KParams &p,
-                                                   int64_t (&j)[K])
-{
-    uint32_t lo[K], hi[K], end[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        if (((valid >> k) & 1u) && key[k] <= p.maskN) {
-            const uint64_t pf = key[k] >> (p.N - p.pbits);
-            lo[k] = p.limits[pf];
-            hi[k] = p.limits[pf + 1];
-        } else {
-            lo[k] = hi[k] = 0;
-        }
-        end[k] = hi[k];
-    }
-    for (;;) {
-        uint64_t v[K];
-        uint32_t mid[K];
-        bool any = false;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            mid[k] = (lo[k] + hi[k]) >> 1;
-            if (lo[k] < hi[k]) {
-                v[k] = p.reps[mid[k]];
-                any = true;
-            }
-        }
-        if (!any) break;
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (lo[k] < hi[k]) {
-                if (v[k] < key[k]) lo[k] = mid[k] + 1; else hi[k] = mid[k];
-            }
-    }
-    uint64_t f[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) f[k] = (lo[k] < end[k]) ? p.reps[lo[k]] : ~key[k];
-#pragma unroll
-    for (int k = 0; k < K; ++k) j[k] = (lo[k] < end[k] && f[k] == key[k]) ? (int64_t)lo[k] : -1;
-}
-
-template <int K>
-__device__ __forceinline__ void lookup_learned_batch(const uint64_t (&key)[K], uint32_t valid, const KParams &p,
-                                                     const PwView &pw, int64_t (&j)[K])
-{
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-        j[k] = ((valid >> k) & 1u) ? lookup_learned(key[k], p.reps, pw, static_cast<const Leaf *>(p.leaves), p.sub,
-                                                    p.N, p.log2_leaves)
-                                   : -1;
-}
-
 // Index of a representative: plain Limits + binary search, or the learned
 // index (network in LDS, leaf table, bounded binary search).
 template <bool LEARNED>
@@ -108,6 +74,22 @@ __device__ __forceinline__ int64_t lookup(uint64_t key, const KParams &p, const 
     if (LEARNED)
         return lookup_learned(key, p.reps, pw, static_cast<const Leaf *>(p.leaves), p.sub, p.N, p.log2_leaves);
     return lookup_plain(key, p);
+}
+
+// Record of key in the hashed staging table: linear probing from the home
+// slot until the key or an empty slot (absent: -1).  The table always has
+// an empty slot, so the probe ends.
+template <bool CPLX>
+__device__ __forceinline__ int64_t hash_find(uint64_t key, const KParams &p)
+{
+    constexpr int S = hash_words<CPLX>();
+    uint64_t s = hash_home(key, p.hslots);
+    for (;;) {
+        const uint64_t k = p.htab[s * S];
+        if (k == key) return (int64_t)s;
+        if (k == kHashEmpty) return -1;
+        if (++s == p.hslots) s = 0;
+    }
 }
 
 // Amplitude <tau|H_pair|sigma> of the merged pieces flipping pair q of s
@@ -148,61 +130,21 @@ __device__ __forceinline__ double block_sum(double v, double *scratch)
     return t;
 }
 
-constexpr int kBatch = SYMED_KBATCH;  // lookups in flight per lane
-
-// Flush the pending (key, coefficient) slots: lookups in lockstep, then the
-// gathers of x_j, accumulated oldest slot first (the order the pieces were
-// generated), so the sum is the same as one piece at a time.
-template <bool CPLX, bool LEARNED>
-__device__ __forceinline__ void flush_batch(const uint64_t (&key)[kBatch], const double (&cr)[kBatch],
-                                            const double (&ci)[kBatch], uint32_t valid, const KParams &p,
-                                            const PwView &pw, const double *__restrict__ x, double &ar, double &ai)
-{
-    int64_t j[kBatch];
-    if (LEARNED) lookup_learned_batch<kBatch>(key, valid, p, pw, j);
-    else lookup_plain_batch<kBatch>(key, valid, p, j);
-    double xr[kBatch], xi[kBatch];
-#pragma unroll
-    for (int k = 0; k < kBatch; ++k) {
-        if (j[k] >= 0) {
-            xr[k] = CPLX ? x[2 * j[k]] : x[j[k]];
-            xi[k] = CPLX ? x[2 * j[k] + 1] : 0.0;
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < kBatch; ++k) {
-        if (j[k] >= 0) {
-            if (!CPLX) {
-                ar += cr[k] * xr[k];
-            } else {
-                ar += cr[k] * xr[k] - ci[k] * xi[k];
-                ai += cr[k] * xi[k] + ci[k] * xr[k];
-            }
-        }
-    }
-}
-
 // One row of H.v: y_i = diag_i x_i + isq_i * sum over flipped pairs of
 // coefficient * x_j (gather; only this lane writes y_i).  mode 0 writes
 // y_i; mode 1 (real Lanczos) writes w_i = (H v)_i - beta w_i and returns
 // w_i v_i; mode 2 (complex Lanczos) writes w_i = (H v)_i and returns
-// Re(conj(w_i) v_i).
-template <bool CPLX, int MODE, bool LEARNED>
+// Re(conj(w_i) v_i).  LK: kLookupPlain / kLookupLearned find j and read
+// x_j from x; kLookupHash finds the record of the target in the staging
+// table, whose copy of x_j sits beside the key that confirms the match.
+template <bool CPLX, int MODE, int LK>
 __device__ __forceinline__ double apply_row(const KParams &p, const Lds &L, int64_t i, const double *__restrict__ x,
                                             double *__restrict__ y, double beta)
 {
+    constexpr int S = hash_words<CPLX>();
     const uint64_t s = p.reps[i];
     const double isq = L.isqrtt[p.stab[i]];
     double diag = 0.0, ar = 0.0, ai = 0.0;
-    // pending pieces, oldest in slot 0
-    uint64_t key[kBatch];
-    double cr[kBatch], ci[kBatch];
-    uint32_t valid = 0;
-#pragma unroll
-    for (int k = 0; k < kBatch; ++k) {
-        key[k] = 0;
-        cr[k] = ci[k] = 0.0;
-    }
     // Pairs are taken in windows of 128: the antiparallel pairs of the window
     // are marked in a bit mask first (and the diagonal summed), then every
     // lane walks its own marked pairs in ascending order.  Lanes of a wave
@@ -227,34 +169,33 @@ __device__ __forceinline__ double apply_row(const KParams &p, const Lds &L, int6
                 pair_amp<CPLX>(s, pt, L, hre, him);
                 if (hre == 0.0 && him == 0.0) continue;
                 const Found f = find_rep(s ^ pt.mask, p, L);
+                double xr, xi = 0.0;
+                if (LK == kLookupHash) {
+                    const int64_t r = hash_find<CPLX>(f.rep, p);
+                    if (r < 0) continue;
+                    xr = __longlong_as_double((long long)p.htab[r * S + 1]);
+                    if (CPLX) xi = __longlong_as_double((long long)p.htab[r * S + 2]);
+                } else {
+                    const int64_t j = lookup<LK == kLookupLearned>(f.rep, p, L.pw);
+                    if (j < 0) continue;
+                    xr = CPLX ? x[2 * j] : x[j];
+                    if (CPLX) xi = x[2 * j + 1];
+                }
                 const double w = L.sqrtt[f.cnt];
-                double kr, ki = 0.0;
                 if (!CPLX) {
-                    kr = L.chi[f.g] * w * hre;
+                    const double kr = L.chi[f.g] * w * hre;
+                    ar += kr * xr;
                 } else {
                     // chi(g) * w * conj(h)
                     const double c_r = L.chi[2 * f.g] * w, c_i = L.chi[2 * f.g + 1] * w;
-                    kr = c_r * hre + c_i * him;
-                    ki = c_i * hre - c_r * him;
-                }
-#pragma unroll
-                for (int k = 0; k < kBatch - 1; ++k) {
-                    key[k] = key[k + 1];
-                    cr[k] = cr[k + 1];
-                    ci[k] = ci[k + 1];
-                }
-                key[kBatch - 1] = f.rep;
-                cr[kBatch - 1] = kr;
-                ci[kBatch - 1] = ki;
-                valid = (valid >> 1) | (1u << (kBatch - 1));
-                if (valid & 1u) {
-                    flush_batch<CPLX, LEARNED>(key, cr, ci, valid, p, L.pw, x, ar, ai);
-                    valid = 0;
+                    const double kr = c_r * hre + c_i * him;
+                    const double ki = c_i * hre - c_r * him;
+                    ar += kr * xr - ki * xi;
+                    ai += kr * xi + ki * xr;
                 }
             }
         }
     }
-    if (valid) flush_batch<CPLX, LEARNED>(key, cr, ci, valid, p, L.pw, x, ar, ai);
     double part = 0.0;
     if (!CPLX) {
         const double xi = x[i];

@@ -38,7 +38,7 @@ struct ed_basis {
     double *d_alpha = nullptr, *d_beta = nullptr;
     LState *d_ls = nullptr;
     int lanczos_cap = 0;
-    hipGraphExec_t step_graph[2] = {nullptr, nullptr};
+    hipGraphExec_t step_graph[3] = {nullptr, nullptr, nullptr};
     // learned index
     bool indexed = false;
     float *d_params = nullptr;
@@ -47,6 +47,12 @@ struct ed_basis {
     uint64_t sub_cap = 0;
     int log2_leaves = 0, mlp_F = 0, mlp_c = 0;
     ed_index_stats istats{};
+    // hashed staging table
+    bool hashed = false;
+    uint64_t *d_htab = nullptr;
+    uint64_t hslots = 0;
+    uint32_t *d_pos2slot = nullptr;
+    ed_hash_stats hstats{};
     std::vector<void *> allocs;
 };
 

@@ -57,22 +57,19 @@ __global__ void __launch_bounds__(kApplyThreads) k_batch_apply(const SectorDesc 
         const int64_t r0 = (t - tile0[sec]) * tile_rows;
         const int64_t r1 = min(r0 + tile_rows, p.dim);
         double part = 0.0;
-        if (!lanczos) {
-            if (D.cplx)
-                for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x)
-                    apply_row<true, 0, LEARNED>(p, L, i, D.x, D.y, 0.0);
-            else
-                for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x)
-                    apply_row<false, 0, LEARNED>(p, L, i, D.x, D.y, 0.0);
-        } else {
-            if (D.cplx) {
-                for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x)
-                    part += apply_row<true, 2, LEARNED>(p, L, i, D.v, D.w, 0.0);
+        constexpr int Lp = kLookupPlain, Ll = kLookupLearned;
+        const double beta = (lanczos && !D.cplx) ? D.ls->beta_prev : 0.0;
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+            if (!lanczos) {
+                if (D.cplx) apply_row<true, 0, LEARNED ? Ll : Lp>(p, L, i, D.x, D.y, 0.0);
+                else apply_row<false, 0, LEARNED ? Ll : Lp>(p, L, i, D.x, D.y, 0.0);
+            } else if (D.cplx) {
+                part += apply_row<true, 2, LEARNED ? Ll : Lp>(p, L, i, D.v, D.w, 0.0);
             } else {
-                const double beta = D.ls->beta_prev;
-                for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x)
-                    part += apply_row<false, 1, LEARNED>(p, L, i, D.v, D.w, beta);
+                part += apply_row<false, 1, LEARNED ? Ll : Lp>(p, L, i, D.v, D.w, beta);
             }
+        }
+        if (lanczos) {
             const double s = block_sum(part, scratch);
             if (threadIdx.x == 0) partials[t] = s;
         }

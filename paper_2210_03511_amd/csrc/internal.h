@@ -87,6 +87,10 @@ struct KParams {
     int32_t mlp_F;             // input features
     int32_t mlp_c;             // bits per feature chunk
     int32_t has_index;
+    // hashed staging table: records {rep, x} (real) or {rep, re, im, -}
+    // (complex) in hslots slots, linear probing (null until built)
+    const uint64_t *htab;
+    uint64_t hslots;
 };
 
 // Thread-local error reporting.

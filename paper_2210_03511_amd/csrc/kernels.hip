@@ -19,7 +19,7 @@ constexpr int kVecThreads = 256;
 
 // mode 0: y = H x.  mode 1 (real Lanczos): w <- H v - beta_prev w, partial
 // <w|v>.  mode 2 (complex Lanczos): w <- H v, partial Re<w|v>.
-template <bool CPLX, int MODE, bool LEARNED>
+template <bool CPLX, int MODE, int LK>
 __global__ void __launch_bounds__(kApplyThreads) k_apply(KParams p, const double *__restrict__ x,
                                                        double *__restrict__ y, const LState *ls,
                                                        double *partials)
@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply(KParams p, const double
     double part = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.dim; i += stride)
-        part += apply_row<CPLX, MODE, LEARNED>(p, L, i, x, y, beta);
+        part += apply_row<CPLX, MODE, LK>(p, L, i, x, y, beta);
     if (MODE != 0) {
         const double t = block_sum(part, scratch);
         if (threadIdx.x == 0) partials[blockIdx.x] = t;
@@ -64,11 +64,13 @@ __global__ void __launch_bounds__(256) k_count(KParams p, unsigned long long *ou
     if ((threadIdx.x & 63) == 0) atomicAdd(out, c);
 }
 
-template <bool LEARNED>
+// LK = kLookupHash: membership from the staging table, position from the
+// plain lookup (the table holds no positions).
+template <int LK>
 __global__ void __launch_bounds__(256) k_lookup(KParams p, const uint64_t *keys, int64_t n, int64_t *idx)
 {
     __shared__ float spw[kPwFloats];
-    if (LEARNED) {
+    if (LK == kLookupLearned) {
         const float *g = reinterpret_cast<const float *>(static_cast<const unsigned char *>(p.blob) + p.lay.off_mlp);
         for (int q = threadIdx.x; q < kPwFloats; q += blockDim.x) spw[q] = g[q];
         __syncthreads();
@@ -78,7 +80,83 @@ __global__ void __launch_bounds__(256) k_lookup(KParams p, const uint64_t *keys,
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
         const uint64_t key = keys[k];
         // keys outside the N-bit range cannot be representatives
-        idx[k] = (key & ~p.maskN) ? -1 : lookup<LEARNED>(key, p, pw);
+        int64_t r = -1;
+        if (!(key & ~p.maskN)) {
+            if (LK == kLookupHash) {
+                const bool in = p.is_complex ? hash_find<true>(key, p) >= 0 : hash_find<false>(key, p) >= 0;
+                r = in ? lookup<false>(key, p, pw) : -1;
+            } else {
+                r = lookup<LK == kLookupLearned>(key, p, pw);
+            }
+        }
+        idx[k] = r;
+    }
+}
+
+// Hashed staging table.  Build: every slot empty, then every
+// representative inserted by linear probing from its home slot with a
+// 64-bit compare-and-swap (the layout depends on the order of insertion,
+// the results of H.v do not: only the slot of a record changes).
+template <bool CPLX>
+__global__ void __launch_bounds__(256) k_hash_clear(uint64_t *tab, uint64_t slots)
+{
+    constexpr int S = hash_words<CPLX>();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < (int64_t)slots; s += stride) {
+        tab[s * S] = kHashEmpty;
+        for (int w = 1; w < S; ++w) tab[s * S + w] = 0ull;
+    }
+}
+
+template <bool CPLX>
+__global__ void __launch_bounds__(256) k_hash_insert(uint64_t *tab, uint64_t slots, const uint64_t *__restrict__ reps,
+                                                     int64_t dim, uint32_t *pos2slot, unsigned long long *stats)
+{
+    constexpr int S = hash_words<CPLX>();
+    unsigned long long sum = 0, mx = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim; i += stride) {
+        const uint64_t key = reps[i];
+        const uint64_t home = hash_home(key, slots);
+        uint64_t s = home;
+        for (;;) {
+            const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long *>(tab + s * S),
+                                                     (unsigned long long)kHashEmpty, (unsigned long long)key);
+            if (old == (unsigned long long)kHashEmpty) break;
+            if (++s == slots) s = 0;
+        }
+        pos2slot[i] = (uint32_t)s;
+        const unsigned long long d = (s >= home ? s - home : s + slots - home) + 1;  // probes to reach it
+        sum += d;
+        mx = d > mx ? d : mx;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        sum += __shfl_xor(sum, o, 64);
+        const unsigned long long m2 = __shfl_xor(mx, o, 64);
+        mx = m2 > mx ? m2 : mx;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(stats, sum);
+        atomicMax(stats + 1, mx);
+    }
+}
+
+// Copy of the input vector into the records (before every H.v).
+template <bool CPLX>
+__global__ void __launch_bounds__(256) k_hash_values(uint64_t *tab, const uint32_t *__restrict__ pos2slot,
+                                                     const double *__restrict__ x, int64_t dim)
+{
+    constexpr int S = hash_words<CPLX>();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim; i += stride) {
+        const uint64_t s = pos2slot[i];
+        if (CPLX) {
+            const double2 v = reinterpret_cast<const double2 *>(x)[i];
+            tab[s * S + 1] = (uint64_t)__double_as_longlong(v.x);
+            tab[s * S + 2] = (uint64_t)__double_as_longlong(v.y);
+        } else {
+            tab[s * S + 1] = (uint64_t)__double_as_longlong(x[i]);
+        }
     }
 }
 
@@ -520,23 +598,53 @@ hipError_t launch_count_elements(const KParams &p, unsigned long long *d_count, 
     return hipGetLastError();
 }
 
-hipError_t launch_apply(const KParams &p, const LaunchCfg &c, const void *x, void *y, int mode, int learned,
+hipError_t launch_apply(const KParams &p, const LaunchCfg &c, const void *x, void *y, int mode, int lookup_kind,
                         const LState *ls, double *partials, hipStream_t st)
 {
     const size_t lds = apply_lds_bytes(p);
     const double *xd = static_cast<const double *>(x);
     double *yd = static_cast<double *>(y);
     dim3 g(c.apply_blocks), b(kApplyThreads);
-    const bool lr = learned != 0;
-#define SYMED_APPLY(C, M, Lr) hipLaunchKernelGGL((k_apply<C, M, Lr>), g, b, lds, st, p, xd, yd, ls, partials)
+#define SYMED_APPLY(C, M, K) hipLaunchKernelGGL((k_apply<C, M, K>), g, b, lds, st, p, xd, yd, ls, partials)
+#define SYMED_APPLY_K(C, M)                                                        \
+    do {                                                                           \
+        if (lookup_kind == kLookupHash) SYMED_APPLY(C, M, kLookupHash);             \
+        else if (lookup_kind == kLookupLearned) SYMED_APPLY(C, M, kLookupLearned);  \
+        else SYMED_APPLY(C, M, kLookupPlain);                                      \
+    } while (0)
     if (!p.is_complex) {
-        if (mode == 0) { if (lr) SYMED_APPLY(false, 0, true); else SYMED_APPLY(false, 0, false); }
-        else { if (lr) SYMED_APPLY(false, 1, true); else SYMED_APPLY(false, 1, false); }
+        if (mode == 0) SYMED_APPLY_K(false, 0);
+        else SYMED_APPLY_K(false, 1);
     } else {
-        if (mode == 0) { if (lr) SYMED_APPLY(true, 0, true); else SYMED_APPLY(true, 0, false); }
-        else { if (lr) SYMED_APPLY(true, 2, true); else SYMED_APPLY(true, 2, false); }
+        if (mode == 0) SYMED_APPLY_K(true, 0);
+        else SYMED_APPLY_K(true, 2);
     }
+#undef SYMED_APPLY_K
 #undef SYMED_APPLY
+    return hipGetLastError();
+}
+
+hipError_t launch_hash_build(uint64_t *tab, uint64_t slots, const uint64_t *reps, int64_t dim, bool cplx,
+                             uint32_t *pos2slot, unsigned long long *d_stats, int blocks, hipStream_t st)
+{
+    if (cplx) {
+        hipLaunchKernelGGL(k_hash_clear<true>, dim3(blocks), dim3(256), 0, st, tab, slots);
+        hipLaunchKernelGGL(k_hash_insert<true>, dim3(blocks), dim3(256), 0, st, tab, slots, reps, dim, pos2slot,
+                           d_stats);
+    } else {
+        hipLaunchKernelGGL(k_hash_clear<false>, dim3(blocks), dim3(256), 0, st, tab, slots);
+        hipLaunchKernelGGL(k_hash_insert<false>, dim3(blocks), dim3(256), 0, st, tab, slots, reps, dim, pos2slot,
+                           d_stats);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_hash_values(uint64_t *tab, const uint32_t *pos2slot, const void *x, int64_t dim, bool cplx,
+                              int blocks, hipStream_t st)
+{
+    const double *xd = static_cast<const double *>(x);
+    if (cplx) hipLaunchKernelGGL(k_hash_values<true>, dim3(blocks), dim3(256), 0, st, tab, pos2slot, xd, dim);
+    else hipLaunchKernelGGL(k_hash_values<false>, dim3(blocks), dim3(256), 0, st, tab, pos2slot, xd, dim);
     return hipGetLastError();
 }
 
@@ -545,8 +653,12 @@ hipError_t launch_lookup(const KParams &p, const uint64_t *keys, int64_t n, int6
     int64_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
-    if (mode == 1) hipLaunchKernelGGL(k_lookup<true>, dim3((unsigned)blocks), dim3(256), 0, st, p, keys, n, idx);
-    else hipLaunchKernelGGL(k_lookup<false>, dim3((unsigned)blocks), dim3(256), 0, st, p, keys, n, idx);
+    if (mode == kLookupHash)
+        hipLaunchKernelGGL(k_lookup<kLookupHash>, dim3((unsigned)blocks), dim3(256), 0, st, p, keys, n, idx);
+    else if (mode == kLookupLearned)
+        hipLaunchKernelGGL(k_lookup<kLookupLearned>, dim3((unsigned)blocks), dim3(256), 0, st, p, keys, n, idx);
+    else
+        hipLaunchKernelGGL(k_lookup<kLookupPlain>, dim3((unsigned)blocks), dim3(256), 0, st, p, keys, n, idx);
     return hipGetLastError();
 }
 
@@ -616,18 +728,20 @@ hipError_t prepare_kernels(const KParams &p, int *apply_blocks_per_cu, int *appl
 {
     const size_t lds = apply_lds_bytes(p);
     hipError_t e;
-    const void *ks[] = {(const void *)k_apply<false, 0, false>, (const void *)k_apply<false, 1, false>,
-                        (const void *)k_apply<true, 0, false>, (const void *)k_apply<true, 2, false>,
-                        (const void *)k_apply<false, 0, true>, (const void *)k_apply<false, 1, true>,
-                        (const void *)k_apply<true, 0, true>, (const void *)k_apply<true, 2, true>,
-                        (const void *)k_count<false>, (const void *)k_count<true>,
-                        (const void *)k_enumerate<false>, (const void *)k_enumerate<true>};
+    const void *ks[] = {(const void *)k_apply<false, 0, 0>, (const void *)k_apply<false, 1, 0>,
+                        (const void *)k_apply<true, 0, 0>,  (const void *)k_apply<true, 2, 0>,
+                        (const void *)k_apply<false, 0, 1>, (const void *)k_apply<false, 1, 1>,
+                        (const void *)k_apply<true, 0, 1>,  (const void *)k_apply<true, 2, 1>,
+                        (const void *)k_apply<false, 0, 2>, (const void *)k_apply<false, 1, 2>,
+                        (const void *)k_apply<true, 0, 2>,  (const void *)k_apply<true, 2, 2>,
+                        (const void *)k_count<false>,       (const void *)k_count<true>,
+                        (const void *)k_enumerate<false>,   (const void *)k_enumerate<true>};
     for (const void *k : ks) {
         e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     int nb = 0;
-    const void *ka = p.is_complex ? (const void *)k_apply<true, 0, true> : (const void *)k_apply<false, 0, true>;
+    const void *ka = p.is_complex ? (const void *)k_apply<true, 0, 1> : (const void *)k_apply<false, 0, 1>;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ka, kApplyThreads, lds);
     if (e != hipSuccess) return e;
     *apply_blocks_per_cu = nb;

@@ -28,8 +28,13 @@ hipError_t launch_scan(const uint32_t *d_in, uint64_t *d_out, uint64_t n, uint64
 hipError_t launch_limits(const uint64_t *d_reps, int64_t dim, int N, int pbits, uint32_t *d_limits, hipStream_t st);
 hipError_t launch_limits_stats(const uint32_t *d_limits, int pbits, unsigned long long *d_stats, hipStream_t st);
 hipError_t launch_count_elements(const KParams &p, unsigned long long *d_count, int blocks, hipStream_t st);
-hipError_t launch_apply(const KParams &p, const LaunchCfg &c, const void *x, void *y, int mode, int learned,
+// lookup_kind: 0 plain, 1 learned, 2 hashed staging table
+hipError_t launch_apply(const KParams &p, const LaunchCfg &c, const void *x, void *y, int mode, int lookup_kind,
                         const LState *ls, double *partials, hipStream_t st);
+hipError_t launch_hash_build(uint64_t *tab, uint64_t slots, const uint64_t *reps, int64_t dim, bool cplx,
+                             uint32_t *pos2slot, unsigned long long *d_stats, int blocks, hipStream_t st);
+hipError_t launch_hash_values(uint64_t *tab, const uint32_t *pos2slot, const void *x, int64_t dim, bool cplx,
+                              int blocks, hipStream_t st);
 hipError_t launch_lookup(const KParams &p, const uint64_t *keys, int64_t n, int64_t *idx, int mode, hipStream_t st);
 
 // Lanczos vector ops (vectors of n real or n complex numbers)

@@ -26,7 +26,7 @@ EXPORTED = ["ed_last_error", "ed_version", "ed_basis_build", "ed_basis_free", "e
             "ed_basis_device_reps", "ed_apply_H", "ed_lookup", "ed_lanczos_run", "ed_eigenvalues",
             "ed_tables_inspect", "ed_index_train", "ed_index_info", "ed_mlp_loss_grad",
             "ed_index_predict", "ed_batch_create", "ed_batch_apply", "ed_batch_lanczos", "ed_batch_info",
-            "ed_batch_free"]
+            "ed_batch_free", "ed_hash_build"]
 
 
 class EdError(RuntimeError):
@@ -81,6 +81,18 @@ class IndexStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class HashCfg(ctypes.Structure):
+    _fields_ = [("load", ctypes.c_double), ("reserved", ctypes.c_int32 * 2)]
+
+
+class HashStats(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int64), ("bytes", ctypes.c_int64), ("load", ctypes.c_double),
+                ("mean_probes", ctypes.c_double), ("max_probes", ctypes.c_int64), ("build_seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class BatchCfg(ctypes.Structure):
     _fields_ = [("tile_rows", ctypes.c_int32), ("autotune", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
@@ -129,6 +141,7 @@ def lib():
         L.ed_index_info.argtypes = [vp, ctypes.POINTER(IndexStats), vp, i64]
         L.ed_mlp_loss_grad.argtypes = [i32, vp, vp, vp, i64, vp, vp, vp]
         L.ed_index_predict.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.ed_hash_build.argtypes = [vp, ctypes.POINTER(HashCfg), ctypes.POINTER(HashStats), vp]
         L.ed_batch_create.argtypes = [vp, i32, ctypes.POINTER(BatchCfg), vp, ctypes.POINTER(vp)]
         L.ed_batch_apply.argtypes = [vp, vp, vp, i32, vp]
         L.ed_batch_lanczos.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp]
@@ -275,6 +288,13 @@ class Basis:
         stats = IndexStats()
         _check(lib().ed_index_train(self._h, ctypes.byref(cfg), ctypes.byref(stats), _stream_ptr(stream)))
         return stats.as_dict()
+
+    def build_hash(self, load=0.0, stream=None):
+        """Build the hashed staging table (lookup mode 2); returns its stats."""
+        cfg = HashCfg(float(load), (ctypes.c_int32 * 2)(0, 0))
+        st = HashStats()
+        _check(lib().ed_hash_build(self._h, ctypes.byref(cfg), ctypes.byref(st), _stream_ptr(stream)))
+        return st.as_dict()
 
     def index_predict(self, keys, stream=None):
         """(u, y) of the trained network on device keys (int64 tensor holding uint64)."""

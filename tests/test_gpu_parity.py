@@ -248,3 +248,39 @@ def test_triangular36_full_size(S):
 
 def test_square40_full_size(S):
     _large_parity(S, L.square40(), 1500, 5001)
+
+
+def test_square32_against_stored_oracle_values(S):
+    """The 32-site square sector against values the oracle wrote
+    (tests/golden/make_golden.py): basis checksums, H.v of a counter-based
+    vector on every row (sum and squared norm), and 100 Lanczos steps from
+    the seeded start vector, in every lookup mode."""
+    import json
+    torch = _torch()
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "square32_gamma_a1_even.json")))
+    inst = L.square32()
+    b = S.Basis.build(inst)
+    assert b.dim == gold["dim"]
+    reps, stab = b.export()
+    assert int(np.sum(reps, dtype=np.uint64)) == gold["reps_sum_mod_2_64"]
+    assert int(np.bitwise_xor.reduce(reps)) == gold["reps_xor"]
+    assert int(stab.astype(np.int64).sum()) == gold["stab_sum"]
+    b.train_index()
+    b.build_hash()
+    x = _dev(torch, V.state_vector(reps, gold["hv_state_vector_seed"]))
+    v0 = _dev(torch, V.start_vector(b.dim, gold["lanczos_seed"]))
+    for mode in (0, 1, 2):
+        y = torch.zeros_like(x)
+        b.apply_H(x, y, mode=mode)
+        torch.cuda.synchronize()
+        yh = y.cpu().numpy()
+        assert abs(yh.sum() - gold["hv_sum"]) <= 1e-9 * gold["hv_norm2"] ** 0.5
+        assert abs(np.dot(yh, yh) - gold["hv_norm2"]) <= 1e-10 * gold["hv_norm2"]
+        a, be, n, broken = b.lanczos(v0, gold["lanczos_steps"], mode=mode)
+        assert n == gold["lanczos_steps"] and not broken
+        assert np.max(np.abs(a[:10] - np.array(gold["alpha_first10"]))) < 1e-10
+        assert np.max(np.abs(be[:10] - np.array(gold["beta_first10"]))) < 1e-10
+        e = S.eigenvalues(a, be, 1)[0]
+        _say("  mode", mode, "E0", repr(e))
+        assert abs(e - gold["E0_after_100"]) <= 1e-10 * abs(gold["E0_after_100"])
+    b.free()
