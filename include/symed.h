@@ -202,6 +202,33 @@ ed_status ed_lanczos_run(const ed_basis *basis, const void *d_v0, int32_t n_iter
                          double *h_alpha, double *h_beta, int32_t *n_done, void *stream);
 
 /*
+ * Ground-state vectors and expectation values (thesis, "The Lanczos
+ * algorithm": the eigenvectors of T give the Ritz vectors, and a second
+ * Lanczos run from the same start vector rebuilds them from the Lanczos
+ * vectors without storing those).
+ *
+ * ed_ritz_vector: k-th lowest eigenvalue (*lambda, may be NULL) and the
+ *   normalized eigenvector coef[n] of T (diagonal alpha[n], off-diagonal
+ *   beta[n-1]); Sturm bisection, then inverse iteration.  Host only.
+ * ed_lanczos_vector: repeats n_iter steps from d_v0 (as ed_lanczos_run,
+ *   same lookup_mode) and writes d_psi = sum_k coef[k] v_k, normalized
+ *   (device vector like d_v0, must not alias it).  Blocks until done.
+ * ed_expectation: <psi|O|psi> for an operator O of the same form as H
+ *   (bonds J S_i.S_j and chirality triangles), which must be invariant
+ *   under the basis's group (checked; ED_EINVAL otherwise).  O's pair table
+ *   replaces H's in the H.v kernel; the result's real part goes to *re and
+ *   the imaginary part (0 up to rounding for Hermitian O; complex sectors
+ *   only) to *im (may be NULL).  Allocates a vector of dim entries
+ *   temporarily.  Blocks until done.
+ */
+ed_status ed_ritz_vector(const double *alpha, const double *beta, int32_t n, int32_t k, double *lambda,
+                         double *coef);
+ed_status ed_lanczos_vector(const ed_basis *basis, const void *d_v0, int32_t n_iter, int32_t lookup_mode,
+                            const double *h_coef, void *d_psi, void *stream);
+ed_status ed_expectation(const ed_basis *basis, const ed_model *op, const void *d_psi, int32_t lookup_mode,
+                         double *re, double *im, void *stream);
+
+/*
  * Hashed staging table (not in the thesis).  The gather needs, for every
  * target, only x at the target's position.  This table holds records
  * {representative, x} (real) or {representative, Re x, Im x, unused}

@@ -367,29 +367,20 @@ static hipError_t enqueue_step(ed_basis *b, int mode, hipStream_t st)
     return launch_step_inc(b->d_ls, b->d_beta, st);
 }
 
-ed_status ed_lanczos_run(const ed_basis *cb, const void *d_v0, int32_t n_iter, int32_t lookup_mode, double *h_alpha,
-                         double *h_beta, int32_t *n_done, void *stream)
+}  // extern "C"
+
+// Workspace for n_iter steps and the captured step graph of a lookup mode.
+ed_status lanczos_prepare(ed_basis *b, int n_iter, int lookup_mode)
 {
-    ed_basis *b = const_cast<ed_basis *>(cb);
-    if (!b || !d_v0 || !h_alpha || !h_beta || !n_done) return fail(ED_EINVAL, "NULL argument");
     if (n_iter < 1) return fail(ED_EINVAL, "n_iter must be >= 1");
     ed_status cs = check_lookup(b, lookup_mode);
     if (cs != ED_OK) return cs;
     if (b->dim == 0) return fail(ED_EINVAL, "empty sector");
     ed_status s = lanczos_workspace(b, n_iter);
     if (s != ED_OK) return s;
-    const bool cplx = b->T.is_complex;
-    const int64_t n2 = b->dim * (cplx ? 2 : 1);
-    HIP_OK(hipStreamSynchronize((hipStream_t)stream));
-    hipStream_t st = b->own;
-    // start vector: v = v0 / |v0|, w = vprev = 0, scalars reset
-    HIP_OK(launch_norm2_partial(d_v0, b->dim, cplx, b->d_partials, b->cfg.vec_blocks, st));
-    HIP_OK(launch_scale_copy(d_v0, b->d_v, b->dim, cplx, b->d_partials, b->cfg.vec_blocks, b->cfg.vec_blocks, st));
-    HIP_OK(launch_fill(b->d_w, n2, 0.0, b->cfg.vec_blocks, st));
-    if (cplx) HIP_OK(launch_fill(b->d_vprev, n2, 0.0, b->cfg.vec_blocks, st));
-    HIP_OK(launch_lstate_init(b->d_ls, st));
     hipGraphExec_t &ge = b->step_graph[lookup_mode];
     if (!ge) {
+        hipStream_t st = b->own;
         hipGraph_t g = nullptr;
         HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         hipError_t e = enqueue_step(b, lookup_mode, st);
@@ -397,9 +388,39 @@ ed_status ed_lanczos_run(const ed_basis *cb, const void *d_v0, int32_t n_iter, i
         if (e != hipSuccess) return fail(ED_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
         if (e2 != hipSuccess) return fail(ED_EDEVICE, std::string("end capture: ") + hipGetErrorString(e2));
         HIP_OK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
     }
-    for (int k = 0; k < n_iter; ++k) HIP_OK(hipGraphLaunch(ge, st));
+    return ED_OK;
+}
+
+// Start of a run on the basis's own stream (after `stream` has drained):
+// v = v0 / |v0|, w = vprev = 0, scalars reset.
+ed_status lanczos_start(ed_basis *b, const void *d_v0, void *stream)
+{
+    const bool cplx = b->T.is_complex;
+    const int64_t n2 = b->dim * (cplx ? 2 : 1);
+    HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    hipStream_t st = b->own;
+    HIP_OK(launch_norm2_partial(d_v0, b->dim, cplx, b->d_partials, b->cfg.vec_blocks, st));
+    HIP_OK(launch_scale_copy(d_v0, b->d_v, b->dim, cplx, b->d_partials, b->cfg.vec_blocks, b->cfg.vec_blocks, st));
+    HIP_OK(launch_fill(b->d_w, n2, 0.0, b->cfg.vec_blocks, st));
+    if (cplx) HIP_OK(launch_fill(b->d_vprev, n2, 0.0, b->cfg.vec_blocks, st));
+    HIP_OK(launch_lstate_init(b->d_ls, st));
+    return ED_OK;
+}
+
+extern "C" {
+
+ed_status ed_lanczos_run(const ed_basis *cb, const void *d_v0, int32_t n_iter, int32_t lookup_mode, double *h_alpha,
+                         double *h_beta, int32_t *n_done, void *stream)
+{
+    ed_basis *b = const_cast<ed_basis *>(cb);
+    if (!b || !d_v0 || !h_alpha || !h_beta || !n_done) return fail(ED_EINVAL, "NULL argument");
+    ed_status s = lanczos_prepare(b, n_iter, lookup_mode);
+    if (s != ED_OK) return s;
+    if ((s = lanczos_start(b, d_v0, stream)) != ED_OK) return s;
+    hipStream_t st = b->own;
+    for (int k = 0; k < n_iter; ++k) HIP_OK(hipGraphLaunch(b->step_graph[lookup_mode], st));
     LState ls{};
     HIP_OK(hipMemcpyAsync(h_alpha, b->d_alpha, n_iter * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_OK(hipMemcpyAsync(h_beta, b->d_beta, n_iter * sizeof(double), hipMemcpyDeviceToHost, st));

@@ -59,6 +59,8 @@ struct ed_basis {
 
 ed_status dev_alloc(ed_basis *b, void **ptr, size_t bytes);
 symed::KParams make_params(const ed_basis *b);
+ed_status lanczos_prepare(ed_basis *b, int n_iter, int lookup_mode);
+ed_status lanczos_start(ed_basis *b, const void *d_v0, void *stream);
 
 #define HIP_OK(expr)                                                                             \
     do {                                                                                         \

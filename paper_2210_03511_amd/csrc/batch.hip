@@ -12,6 +12,8 @@
 // once as a HIP graph.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "apply_dev.h"
 #include "batch.h"
 
@@ -158,11 +160,18 @@ __global__ void k_batch_step_inc(const SectorDesc *secs, int nsec)
 
 hipError_t batch_prepare(size_t lds_bytes)
 {
+    // the limit only ever grows (it is shared by every batch in the process)
+    static std::mutex mu;
+    static size_t granted = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (lds_bytes <= granted) return hipSuccess;
     hipError_t e = hipFuncSetAttribute((const void *)k_batch_apply<false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)k_batch_apply<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds_bytes);
+    e = hipFuncSetAttribute((const void *)k_batch_apply<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds_bytes);
+    if (e == hipSuccess) granted = lds_bytes;
+    return e;
 }
 
 hipError_t batch_occupancy(size_t lds_bytes, int *blocks_per_cu)

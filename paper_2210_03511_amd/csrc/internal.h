@@ -102,6 +102,7 @@ ed_status build_host_tables(const ed_model *m, const ed_group *g, int n_up, int 
                             HostTables &T);
 ed_status validate_and_copy_group(const ed_model *m, const ed_group *g, int n_up, HostTables &T);
 ed_status check_stable(const HostTables &T, int n_sub);
+ed_status check_invariant(const ed_model *m, const HostTables &T);
 void build_rep_sym(const HostTables &T, int n_sub, std::vector<uint16_t> &rep, std::vector<uint32_t> &sym_off,
                    std::vector<uint32_t> &sym_list);
 void build_pairs(const ed_model *m, HostTables &T);

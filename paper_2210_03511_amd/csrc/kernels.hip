@@ -9,6 +9,8 @@
 // independent of scheduling.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "apply_dev.h"
 
 namespace symed {
@@ -439,6 +441,41 @@ __global__ void k_finalize(const double *partials, int nparts, double *alpha, do
     }
 }
 
+// psi <- psi + coef[step] v  (n doubles; the Ritz vector of a second
+// Lanczos pass, coefficient of the current Lanczos vector)
+__global__ void __launch_bounds__(kVecThreads) k_axpy_coef(double *psi, const double *v, int64_t n,
+                                                         const double *coef, const LState *ls)
+{
+    const double c = coef[ls->step];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) psi[i] += c * v[i];
+}
+
+// per-block partials of <a|b> = sum conj(a_i) b_i: real part in partials[b],
+// imaginary part (complex vectors) in partials[gridDim + b]
+template <bool CPLX>
+__global__ void __launch_bounds__(kVecThreads) k_dot(const double *a, const double *b, int64_t n, double *partials)
+{
+    __shared__ double scratch[kVecThreads / 64];
+    double re = 0.0, im = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if (CPLX) {
+            const double ar = a[2 * i], ai = a[2 * i + 1], br = b[2 * i], bi = b[2 * i + 1];
+            re += ar * br + ai * bi;
+            im += ar * bi - ai * br;
+        } else {
+            re += a[i] * b[i];
+        }
+    }
+    const double sr = block_sum(re, scratch);
+    if (threadIdx.x == 0) partials[blockIdx.x] = sr;
+    if (CPLX) {
+        const double si = block_sum(im, scratch);
+        if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = si;
+    }
+}
+
 // real: w <- w - alpha v ; complex: w <- w - alpha v - beta_prev vprev ; partial |w|^2
 template <bool CPLX>
 __global__ void __launch_bounds__(kVecThreads) k_axpy_norm(double *w, const double *v, const double *vprev,
@@ -716,6 +753,21 @@ hipError_t launch_step_inc(LState *ls, const double *beta, hipStream_t st)
     return hipGetLastError();
 }
 
+hipError_t launch_axpy_coef(double *psi, const double *v, int64_t n2, const double *coef, const LState *ls,
+                            int blocks, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_axpy_coef, dim3(blocks), dim3(kVecThreads), 0, st, psi, v, n2, coef, ls);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot(const void *a, const void *b, int64_t n, bool cplx, double *partials, int blocks, hipStream_t st)
+{
+    const double *ad = static_cast<const double *>(a), *bd = static_cast<const double *>(b);
+    if (cplx) hipLaunchKernelGGL(k_dot<true>, dim3(blocks), dim3(kVecThreads), 0, st, ad, bd, n, partials);
+    else hipLaunchKernelGGL(k_dot<false>, dim3(blocks), dim3(kVecThreads), 0, st, ad, bd, n, partials);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(double *v, int64_t n, double val, int blocks, hipStream_t st)
 {
     hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(kVecThreads), 0, st, v, n, val);
@@ -736,9 +788,20 @@ hipError_t prepare_kernels(const KParams &p, int *apply_blocks_per_cu, int *appl
                         (const void *)k_apply<true, 0, 2>,  (const void *)k_apply<true, 2, 2>,
                         (const void *)k_count<false>,       (const void *)k_count<true>,
                         (const void *)k_enumerate<false>,   (const void *)k_enumerate<true>};
-    for (const void *k : ks) {
-        e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
+    {
+        // the limit is per kernel, shared by every basis in the process: it
+        // only ever grows, so a later basis with smaller tables cannot
+        // invalidate the launches of an earlier one
+        static std::mutex mu;
+        static size_t granted = 0;
+        std::lock_guard<std::mutex> lock(mu);
+        if (lds > granted) {
+            for (const void *k : ks) {
+                e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                if (e != hipSuccess) return e;
+            }
+            granted = lds;
+        }
     }
     int nb = 0;
     const void *ka = p.is_complex ? (const void *)k_apply<true, 0, 1> : (const void *)k_apply<false, 0, 1>;

@@ -49,6 +49,11 @@ hipError_t launch_rotate(void *v, void *w, void *vprev, int64_t n, bool cplx, co
                          int blocks, hipStream_t st);
 hipError_t launch_step_inc(LState *ls, const double *beta, hipStream_t st);
 hipError_t launch_fill(double *v, int64_t n, double val, int blocks, hipStream_t st);
+// psi[0..n2) += coef[ls->step] * v
+hipError_t launch_axpy_coef(double *psi, const double *v, int64_t n2, const double *coef, const LState *ls,
+                            int blocks, hipStream_t st);
+// partials[0..blocks) = Re <a|b> per block; complex: partials[blocks..2 blocks) = Im
+hipError_t launch_dot(const void *a, const void *b, int64_t n, bool cplx, double *partials, int blocks, hipStream_t st);
 hipError_t launch_scan_u64(const uint64_t *d_in, uint64_t *d_out, uint64_t n, uint64_t *d_total, hipStream_t st);
 hipError_t prepare_kernels(const KParams &p, int *apply_blocks_per_cu, int *apply_threads);
 hipError_t launch_lstate_init(LState *ls, hipStream_t st);

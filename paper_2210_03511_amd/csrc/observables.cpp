@@ -1,0 +1,214 @@
+// Ground-state vectors and expectation values (C ABI): the Ritz vector of
+// the tridiagonal T-matrix, a second Lanczos pass that accumulates the
+// eigenvector from the Lanczos vectors, and <psi|O|psi> for a symmetric
+// operator O evaluated with the H.v kernel on O's own pair table.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "basis.h"
+#include "launch.h"
+
+using namespace symed;
+
+namespace {
+
+// Solve (T - mu) y = r in place for the symmetric tridiagonal T (diagonal
+// a[n], off-diagonal b[n-1]): Gaussian elimination with partial pivoting
+// (row interchanges create a second super-diagonal), then back substitution.
+// A zero pivot is replaced by a tiny one, as inverse iteration wants the
+// nearly singular solve.
+void tridiag_solve(const double *a, const double *b, int n, double mu, std::vector<double> &r)
+{
+    std::vector<double> d(n), du(n, 0.0), du2(n, 0.0), dl(n, 0.0);
+    for (int i = 0; i < n; ++i) d[i] = a[i] - mu;
+    for (int i = 0; i + 1 < n; ++i) du[i] = dl[i] = b[i];
+    const double tiny = 1e-300;
+    for (int i = 0; i + 1 < n; ++i) {
+        if (std::fabs(d[i]) >= std::fabs(dl[i])) {
+            if (d[i] == 0.0) d[i] = tiny;
+            const double m = dl[i] / d[i];
+            d[i + 1] -= m * du[i];
+            r[i + 1] -= m * r[i];
+        } else {
+            // rows i and i+1 exchanged
+            const double m = d[i] / dl[i];
+            d[i] = dl[i];
+            const double t = du[i];
+            du[i] = d[i + 1];
+            d[i + 1] = t - m * d[i + 1];
+            if (i + 2 < n) {
+                du2[i] = du[i + 1];
+                du[i + 1] = -m * du[i + 1];
+            }
+            std::swap(r[i], r[i + 1]);
+            r[i + 1] -= m * r[i];
+        }
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = r[i];
+        if (i + 1 < n) s -= du[i] * r[i + 1];
+        if (i + 2 < n) s -= du2[i] * r[i + 2];
+        r[i] = s / (d[i] != 0.0 ? d[i] : tiny);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+ed_status ed_ritz_vector(const double *alpha, const double *beta, int32_t n, int32_t k, double *lambda,
+                         double *coef)
+{
+    if (!alpha || !coef || n < 1 || k < 0 || k >= n || (n > 1 && !beta))
+        return fail(ED_EINVAL, "bad arguments");
+    std::vector<double> ev(k + 1);
+    ed_status st = ed_eigenvalues(alpha, beta, n, k + 1, ev.data());
+    if (st != ED_OK) return st;
+    const double lam = ev[k];
+    if (lambda) *lambda = lam;
+    double scale = 0.0;
+    for (int i = 0; i < n; ++i) scale = std::max(scale, std::fabs(alpha[i]));
+    for (int i = 0; i + 1 < n; ++i) scale = std::max(scale, std::fabs(beta[i]));
+    const double mu = lam + 1e-13 * std::max(scale, 1.0);
+    // inverse iteration from a fixed, generic start vector
+    std::vector<double> r(n);
+    for (int i = 0; i < n; ++i) r[i] = 1.0 + 0.5 * std::sin(1.0 + i);
+    for (int it = 0; it < 4; ++it) {
+        tridiag_solve(alpha, beta, n, mu, r);
+        double nr = 0.0;
+        for (double x : r) nr += x * x;
+        nr = std::sqrt(nr);
+        if (!(nr > 0.0) || !std::isfinite(nr)) return fail(ED_EINVAL, "inverse iteration failed");
+        for (double &x : r) x /= nr;
+    }
+    // sign convention: first non-negligible coefficient positive
+    for (int i = 0; i < n; ++i)
+        if (std::fabs(r[i]) > 1e-8) {
+            if (r[i] < 0)
+                for (double &x : r) x = -x;
+            break;
+        }
+    std::copy(r.begin(), r.end(), coef);
+    return ED_OK;
+}
+
+ed_status ed_lanczos_vector(const ed_basis *cb, const void *d_v0, int32_t n_iter, int32_t lookup_mode,
+                            const double *h_coef, void *d_psi, void *stream)
+{
+    ed_basis *b = const_cast<ed_basis *>(cb);
+    if (!b || !d_v0 || !h_coef || !d_psi) return fail(ED_EINVAL, "bad arguments");
+    if (d_psi == d_v0) return fail(ED_EINVAL, "psi must not alias v0");
+    ed_status st = lanczos_prepare(b, n_iter, lookup_mode);
+    if (st != ED_OK) return st;
+    const bool cplx = b->T.is_complex;
+    const int64_t n2 = b->dim * (cplx ? 2 : 1);
+    double *d_coef = nullptr;
+    if (hipMalloc(&d_coef, n_iter * sizeof(double)) != hipSuccess) return fail(ED_ENOMEM, "coefficients");
+    hipStream_t s = b->own;
+    auto done = [&](ed_status r) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(d_coef);
+        return r;
+    };
+    if ((st = lanczos_start(b, d_v0, stream)) != ED_OK) return done(st);
+    // the same steps again; before step k, psi += coef[k] v_k
+    hipError_t e = hipMemcpyAsync(d_coef, h_coef, n_iter * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_fill(static_cast<double *>(d_psi), n2, 0.0, b->cfg.vec_blocks, s);
+    for (int k = 0; k < n_iter && e == hipSuccess; ++k) {
+        e = launch_axpy_coef(static_cast<double *>(d_psi), b->d_v, n2, d_coef, b->d_ls, b->cfg.vec_blocks, s);
+        if (e == hipSuccess) e = hipGraphLaunch(b->step_graph[lookup_mode], s);
+    }
+    // normalize psi
+    if (e == hipSuccess) e = launch_norm2_partial(d_psi, b->dim, cplx, b->d_partials, b->cfg.vec_blocks, s);
+    if (e == hipSuccess)
+        e = launch_scale_copy(d_psi, d_psi, b->dim, cplx, b->d_partials, b->cfg.vec_blocks, b->cfg.vec_blocks, s);
+    if (e != hipSuccess) return done(fail(ED_EDEVICE, std::string("second Lanczos pass: ") + hipGetErrorString(e)));
+    return done(ED_OK);
+}
+
+ed_status ed_expectation(const ed_basis *cb, const ed_model *op, const void *d_psi, int32_t lookup_mode,
+                         double *h_re, double *h_im, void *stream)
+{
+    ed_basis *b = const_cast<ed_basis *>(cb);
+    if (!b || !op || !d_psi || !h_re) return fail(ED_EINVAL, "bad arguments");
+    if (!(lookup_mode == 0 || (lookup_mode == 1 && b->indexed) || (lookup_mode == 2 && b->hashed)))
+        return fail(ED_EINVAL, "lookup_mode not available on this basis");
+    if (op->n_sites != b->T.N) return fail(ED_EINVAL, "operator on another number of sites");
+    if ((op->n_bonds > 0 && (!op->bond_sites || !op->bond_J)) || (op->n_tri > 0 && (!op->tri_sites || !op->tri_Jchi)) ||
+        op->n_bonds < 0 || op->n_tri < 0)
+        return fail(ED_EINVAL, "operator arrays");
+    for (int q = 0; q < 2 * op->n_bonds; ++q)
+        if (op->bond_sites[q] < 0 || op->bond_sites[q] >= op->n_sites) return fail(ED_EINVAL, "bond site out of range");
+    for (int q = 0; q < 2 * op->n_bonds; q += 2)
+        if (op->bond_sites[q] == op->bond_sites[q + 1]) return fail(ED_EINVAL, "bond on one site");
+    for (int q = 0; q < 3 * op->n_tri; ++q)
+        if (op->tri_sites[q] < 0 || op->tri_sites[q] >= op->n_sites) return fail(ED_EINVAL, "triangle site out of range");
+    bool chir = false;
+    for (int t = 0; t < op->n_tri; ++t) chir |= op->tri_Jchi[t] != 0.0;
+    if (chir && !b->T.is_complex) return fail(ED_EINVAL, "a chirality operator needs a complex sector");
+    if (b->dim == 0) {
+        *h_re = 0.0;
+        if (h_im) *h_im = 0.0;
+        return ED_OK;
+    }
+    HostTables T2 = b->T;
+    ed_status st = check_invariant(op, T2);
+    if (st != ED_OK) return st;
+    build_pairs(op, T2);
+    BlobLayout lay2{};
+    std::vector<uint8_t> blob = pack_blob(T2, lay2);
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device) != hipSuccess)
+        return fail(ED_EDEVICE, "device query");
+    if ((int64_t)lay2.bytes + 256 > lds_max) return fail(ED_EINVAL, "operator tables exceed the LDS of one block");
+    const bool cplx = b->T.is_complex;
+    const size_t vbytes = (size_t)b->dim * sizeof(double) * (cplx ? 2 : 1);
+    const int nb = b->cfg.vec_blocks;
+    void *d_blob = nullptr, *d_y = nullptr;
+    double *d_part = nullptr;
+    auto cleanup = [&](ed_status r) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        (void)hipFree(d_blob);
+        (void)hipFree(d_y);
+        (void)hipFree(d_part);
+        return r;
+    };
+    if (hipMalloc(&d_blob, blob.size()) != hipSuccess || hipMalloc(&d_y, vbytes) != hipSuccess ||
+        hipMalloc((void **)&d_part, 2 * nb * sizeof(double)) != hipSuccess)
+        return cleanup(fail(ED_ENOMEM, "operator workspace"));
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(d_blob, blob.data(), blob.size(), hipMemcpyHostToDevice, s);
+    // the learned index network lives in the blob: carry it over
+    if (e == hipSuccess && b->indexed)
+        e = hipMemcpyAsync(static_cast<unsigned char *>(d_blob) + lay2.off_mlp,
+                           static_cast<const unsigned char *>(b->d_blob) + b->lay.off_mlp, kPwFloats * sizeof(float),
+                           hipMemcpyDeviceToDevice, s);
+    KParams p = make_params(b);
+    p.lay = lay2;
+    p.blob = d_blob;
+    p.n_pairs = (int)T2.pairs.size();
+    int bpc = 0, thr = 0;
+    if (e == hipSuccess) e = prepare_kernels(p, &bpc, &thr);
+    if (e == hipSuccess && lookup_mode == 2)
+        e = launch_hash_values(b->d_htab, b->d_pos2slot, d_psi, b->dim, cplx, nb, s);
+    if (e == hipSuccess) e = launch_apply(p, b->cfg, d_psi, d_y, 0, lookup_mode, nullptr, nullptr, s);
+    if (e == hipSuccess) e = launch_dot(d_psi, d_y, b->dim, cplx, d_part, nb, s);
+    std::vector<double> part(2 * nb, 0.0);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(part.data(), d_part, (cplx ? 2 : 1) * nb * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return cleanup(fail(ED_EDEVICE, std::string("expectation: ") + hipGetErrorString(e)));
+    double re = 0.0, im = 0.0;
+    for (int q = 0; q < nb; ++q) re += part[q];
+    if (cplx)
+        for (int q = 0; q < nb; ++q) im += part[nb + q];
+    *h_re = re;
+    if (h_im) *h_im = im;
+    return cleanup(ED_OK);
+}
+
+}  // extern "C"

@@ -27,6 +27,56 @@ inline bool bit_of(uint64_t s, int n, int site) { return (s >> (n - 1 - site)) &
 
 }  // namespace
 
+// Invariance of an operator under the spatial symmetries: its bonds
+// (unordered pairs with summed J) and oriented triangles (sorted triple with
+// the sign of the orientation) map onto themselves.  The spin flip is a
+// rotation by pi about x, under which both S.S and S.(SxS) are invariant.
+ed_status check_invariant(const ed_model *m, const HostTables &T)
+{
+    const int N = T.N;
+    std::map<std::pair<int, int>, double> bonds;
+    for (int b = 0; b < m->n_bonds; ++b) {
+        int i = m->bond_sites[2 * b], j = m->bond_sites[2 * b + 1];
+        bonds[{std::min(i, j), std::max(i, j)}] += m->bond_J[b];
+    }
+    auto canon_tri = [](int i, int j, int k, double J, std::map<std::array<int, 3>, double> &out) {
+        std::array<int, 3> v{i, j, k};
+        int sign = 1;
+        // bubble sort counting transpositions
+        for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 2 - p; ++q)
+                if (v[q] > v[q + 1]) { std::swap(v[q], v[q + 1]); sign = -sign; }
+        out[v] += sign * J;
+    };
+    std::map<std::array<int, 3>, double> tris;
+    for (int t = 0; t < m->n_tri; ++t) {
+        const int32_t *v = m->tri_sites + 3 * t;
+        canon_tri(v[0], v[1], v[2], m->tri_Jchi[t], tris);
+    }
+    for (int sp = 0; sp < T.n_sp; ++sp) {
+        const int32_t *p = &T.sp_perm[(size_t)sp * N];
+        std::map<std::pair<int, int>, double> img;
+        for (auto &kv : bonds) {
+            int i = p[kv.first.first], j = p[kv.first.second];
+            img[{std::min(i, j), std::max(i, j)}] += kv.second;
+        }
+        for (auto &kv : bonds) {
+            auto it = img.find(kv.first);
+            if (it == img.end() || std::fabs(it->second - kv.second) > 1e-12)
+                return fail(ED_EINVAL, "operator (bonds) not invariant under the group");
+        }
+        std::map<std::array<int, 3>, double> timg;
+        for (auto &kv : tris) canon_tri(p[kv.first[0]], p[kv.first[1]], p[kv.first[2]], kv.second, timg);
+        for (auto &kv : tris) {
+            auto it = timg.find(kv.first);
+            double v = (it == timg.end()) ? 0.0 : it->second;
+            if (std::fabs(v - kv.second) > 1e-12)
+                return fail(ED_EINVAL, "operator (chirality) not invariant under the group");
+        }
+    }
+    return ED_OK;
+}
+
 ed_status validate_and_copy_group(const ed_model *m, const ed_group *grp, int n_up, HostTables &T)
 {
     if (!m || !grp) return fail(ED_EINVAL, "model and group must not be NULL");
@@ -118,48 +168,8 @@ ed_status validate_and_copy_group(const ed_model *m, const ed_group *grp, int n_
         }
     }
 
-    // invariance of H: bonds (unordered pairs with summed J) and oriented
-    // triangles (sorted triple with sign of the orientation) map to themselves
-    std::map<std::pair<int, int>, double> bonds;
-    for (int b = 0; b < m->n_bonds; ++b) {
-        int i = m->bond_sites[2 * b], j = m->bond_sites[2 * b + 1];
-        bonds[{std::min(i, j), std::max(i, j)}] += m->bond_J[b];
-    }
-    auto canon_tri = [](int i, int j, int k, double J, std::map<std::array<int, 3>, double> &out) {
-        std::array<int, 3> v{i, j, k};
-        int sign = 1;
-        // bubble sort counting transpositions
-        for (int p = 0; p < 3; ++p)
-            for (int q = 0; q < 2 - p; ++q)
-                if (v[q] > v[q + 1]) { std::swap(v[q], v[q + 1]); sign = -sign; }
-        out[v] += sign * J;
-    };
-    std::map<std::array<int, 3>, double> tris;
-    for (int t = 0; t < m->n_tri; ++t) {
-        const int32_t *v = m->tri_sites + 3 * t;
-        canon_tri(v[0], v[1], v[2], m->tri_Jchi[t], tris);
-    }
-    for (int sp = 0; sp < T.n_sp; ++sp) {
-        const int32_t *p = &T.sp_perm[(size_t)sp * N];
-        std::map<std::pair<int, int>, double> img;
-        for (auto &kv : bonds) {
-            int i = p[kv.first.first], j = p[kv.first.second];
-            img[{std::min(i, j), std::max(i, j)}] += kv.second;
-        }
-        for (auto &kv : bonds) {
-            auto it = img.find(kv.first);
-            if (it == img.end() || std::fabs(it->second - kv.second) > 1e-12)
-                return fail(ED_EINVAL, "Hamiltonian (bonds) not invariant under the group");
-        }
-        std::map<std::array<int, 3>, double> timg;
-        for (auto &kv : tris) canon_tri(p[kv.first[0]], p[kv.first[1]], p[kv.first[2]], kv.second, timg);
-        for (auto &kv : tris) {
-            auto it = timg.find(kv.first);
-            double v = (it == timg.end()) ? 0.0 : it->second;
-            if (std::fabs(v - kv.second) > 1e-12)
-                return fail(ED_EINVAL, "Hamiltonian (chirality) not invariant under the group");
-        }
-    }
+    ed_status inv = check_invariant(m, T);
+    if (inv != ED_OK) return inv;
     bool cplx_chi = false;
     for (int g = 0; g < G; ++g)
         if (std::fabs(T.chi_im[g]) > 1e-12) cplx_chi = true;

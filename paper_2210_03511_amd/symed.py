@@ -26,7 +26,7 @@ EXPORTED = ["ed_last_error", "ed_version", "ed_basis_build", "ed_basis_free", "e
             "ed_basis_device_reps", "ed_apply_H", "ed_lookup", "ed_lanczos_run", "ed_eigenvalues",
             "ed_tables_inspect", "ed_index_train", "ed_index_info", "ed_mlp_loss_grad",
             "ed_index_predict", "ed_batch_create", "ed_batch_apply", "ed_batch_lanczos", "ed_batch_info",
-            "ed_batch_free", "ed_hash_build"]
+            "ed_batch_free", "ed_hash_build", "ed_ritz_vector", "ed_lanczos_vector", "ed_expectation"]
 
 
 class EdError(RuntimeError):
@@ -141,6 +141,9 @@ def lib():
         L.ed_index_info.argtypes = [vp, ctypes.POINTER(IndexStats), vp, i64]
         L.ed_mlp_loss_grad.argtypes = [i32, vp, vp, vp, i64, vp, vp, vp]
         L.ed_index_predict.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.ed_ritz_vector.argtypes = [vp, vp, i32, i32, vp, vp]
+        L.ed_lanczos_vector.argtypes = [vp, vp, i32, i32, vp, vp, vp]
+        L.ed_expectation.argtypes = [vp, ctypes.POINTER(_Model), vp, i32, vp, vp, vp]
         L.ed_hash_build.argtypes = [vp, ctypes.POINTER(HashCfg), ctypes.POINTER(HashStats), vp]
         L.ed_batch_create.argtypes = [vp, i32, ctypes.POINTER(BatchCfg), vp, ctypes.POINTER(vp)]
         L.ed_batch_apply.argtypes = [vp, vp, vp, i32, vp]
@@ -289,6 +292,33 @@ class Basis:
         _check(lib().ed_index_train(self._h, ctypes.byref(cfg), ctypes.byref(stats), _stream_ptr(stream)))
         return stats.as_dict()
 
+    def ground_state(self, v0, n_iter, mode=0, k=0, stream=None):
+        """Lanczos (n_iter steps from v0), then the k-th Ritz vector rebuilt
+        by a second pass; returns (eigenvalue, normalized device vector)."""
+        import torch
+        a, b, n, broken = self.lanczos(v0, n_iter, mode=mode, stream=stream)
+        lam, coef = ritz_vector(a, b, k)
+        psi = torch.empty_like(v0)
+        _check(lib().ed_lanczos_vector(self._h, _tensor_ptr(v0), n, int(mode), _np_ptr(coef), _tensor_ptr(psi),
+                                       _stream_ptr(stream)))
+        return lam, psi
+
+    def expectation(self, psi, bonds=None, bond_J=None, tris=None, tri_Jchi=None, mode=0, stream=None):
+        """<psi|O|psi> for O = sum J S_i.S_j (+ sum Jchi S_i.(S_j x S_k)); O must
+        be invariant under the basis's group.  Returns a complex number."""
+        bonds = np.ascontiguousarray(np.zeros((0, 2)) if bonds is None else bonds, np.int32).reshape(-1)
+        bond_J = np.ascontiguousarray(np.zeros(0) if bond_J is None else bond_J, np.float64)
+        tris = np.ascontiguousarray(np.zeros((0, 3)) if tris is None else tris, np.int32).reshape(-1)
+        tri_Jchi = np.ascontiguousarray(np.zeros(0) if tri_Jchi is None else tri_Jchi, np.float64)
+        n_sites = self.info()["n_sites"]
+        m = _Model(n_sites, len(bond_J), _np_ptr(bonds), _np_ptr(bond_J), len(tri_Jchi), _np_ptr(tris),
+                   _np_ptr(tri_Jchi))
+        re = ctypes.c_double(0.0)
+        im = ctypes.c_double(0.0)
+        _check(lib().ed_expectation(self._h, ctypes.byref(m), _tensor_ptr(psi), int(mode), ctypes.byref(re),
+                                    ctypes.byref(im), _stream_ptr(stream)))
+        return complex(re.value, im.value)
+
     def build_hash(self, load=0.0, stream=None):
         """Build the hashed staging table (lookup mode 2); returns its stats."""
         cfg = HashCfg(float(load), (ctypes.c_int32 * 2)(0, 0))
@@ -376,6 +406,17 @@ def mlp_loss_grad(n_features, params, X, t, stream=None):
     _check(lib().ed_mlp_loss_grad(int(n_features), _tensor_ptr(params), _tensor_ptr(X), _tensor_ptr(t), n,
                                   _tensor_ptr(grad), _tensor_ptr(loss), _stream_ptr(stream)))
     return float(loss.item()), grad
+
+
+def ritz_vector(alpha, beta, k=0):
+    """(k-th lowest eigenvalue, its normalized eigenvector) of the T-matrix."""
+    a = np.ascontiguousarray(alpha, np.float64)
+    b = np.ascontiguousarray(beta, np.float64)
+    coef = np.zeros(len(a))
+    lam = ctypes.c_double(0.0)
+    _check(lib().ed_ritz_vector(_np_ptr(a), _np_ptr(b) if len(b) else None, len(a), int(k), ctypes.byref(lam),
+                                _np_ptr(coef)))
+    return lam.value, coef
 
 
 def eigenvalues(alpha, beta, k=1):

@@ -150,3 +150,17 @@ def test_tridiagonal_eigenvalues(symed):
         k = min(n, 5)
         ev = symed.eigenvalues(a, b, k)
         assert np.max(np.abs(ev - ref[:k])) < 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_ritz_vector_matches_dense(symed):
+    rng = np.random.default_rng(5)
+    for n in (1, 2, 7, 40):
+        a = rng.standard_normal(n)
+        b = np.abs(rng.standard_normal(max(n - 1, 0))) + 0.1
+        T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+        w, v = np.linalg.eigh(T)
+        for k in range(min(n, 3)):
+            lam, c = symed.ritz_vector(a, b, k)
+            assert lam == pytest.approx(w[k], abs=1e-12)
+            assert abs(abs(np.dot(c, v[:, k])) - 1.0) < 1e-10
+            assert np.linalg.norm(T @ c - lam * c) < 1e-10

@@ -277,3 +277,30 @@ def test_mlp_gradient_central_differences():
             lm, _ = O.mlp_loss_grad(params, X, t)
             flat[k] = old
             assert (lp - lm) / (2 * h) == pytest.approx(gflat[k], rel=1e-5, abs=1e-9)
+
+
+# --- ground-state correlations ------------------------------------------------
+
+def _op_instance(inst, bonds, bond_J, tris=None, tri_J=None):
+    from dataclasses import replace
+    return replace(inst, bonds=np.asarray(bonds, np.int32), bond_J=np.asarray(bond_J, float),
+                   tris=np.zeros((0, 3), np.int32) if tris is None else np.asarray(tris, np.int32),
+                   tri_Jchi=np.zeros(0) if tri_J is None else np.asarray(tri_J, float))
+
+
+def test_ring4_correlations_closed_form():
+    # singlet ground state of the 4-site ring: <S0.S1> = -1/2 (E0 = -2 over
+    # four bonds); total spin 0 gives sum_j <S0.Sj> = 0, so <S0.S2> = +1/4
+    inst = L.chain(4)
+    reps, stabs = O.enumerate_basis(inst)
+    H = O.coo_matrix(inst, reps, stabs).toarray()
+    w, v = np.linalg.eigh(H)
+    psi = v[:, 0]
+    c = {}
+    for r in (1, 2):
+        b, J = L.chain_distance_bonds(inst, r)
+        Hr = O.coo_matrix(_op_instance(inst, b, J), reps, stabs).toarray()
+        c[r] = float(psi @ Hr @ psi)
+    assert c[1] == pytest.approx(-0.5, abs=1e-13)
+    assert c[2] == pytest.approx(0.25, abs=1e-13)
+    assert 0.75 + 2 * c[1] + c[2] == pytest.approx(0.0, abs=1e-13)

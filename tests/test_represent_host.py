@@ -22,12 +22,15 @@ def checker(tmp_path_factory):
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(hipcc):
         pytest.skip("hipcc not available")
-    if not os.path.exists(os.path.join(LIBDIR, "libsymed.so")):
+    objdir = os.path.join(LIBDIR, "_build")
+    # the library exports only its C ABI: link the table code from its objects
+    if not os.path.exists(os.path.join(objdir, "tables.cpp.o")):
         from paper_2210_03511_amd.build import build
         build()
+    objs = sorted(os.path.join(objdir, f) for f in os.listdir(objdir) if f.endswith(".o"))
     out = str(tmp_path_factory.mktemp("rc") / "represent_check")
     cmd = [hipcc, "-x", "hip", "-O2", "-std=c++17", "--offload-arch=gfx950", "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(LIBDIR, "csrc"), SRC, "-o", out, "-L" + LIBDIR, "-lsymed", "-Wl,-rpath," + LIBDIR]
+           "-I", os.path.join(LIBDIR, "csrc"), SRC, "-x", "none"] + objs + ["-o", out]
     subprocess.run(cmd, check=True, capture_output=True)
     return out
 

@@ -539,3 +539,14 @@ def small_instances():
     out.append(triangular_j1j2chi(TRI12_L[0], TRI12_L[1], 1.0, 0.0, 0.3, (F(1, 2), F(0)), 1, None,
                                   TRI12_CHAIN, name="triangular12"))
     return out
+
+
+def chain_distance_bonds(inst, r):
+    """Bonds (i, i + r) for every position i of a chain instance, in its site
+    labels, each with weight 1/N: sum_i S_i.S_(i+r) / N, the correlation at
+    distance r of a translation-invariant state."""
+    pos = inst.meta["positions"]          # label -> position
+    n = inst.n_sites
+    lab = {p: i for i, p in enumerate(pos)}
+    bonds = np.array([(lab[p], lab[(p + r) % n]) for p in range(n)], np.int32)
+    return bonds, np.full(n, 1.0 / n)
