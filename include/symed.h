@@ -125,6 +125,8 @@ typedef struct {
     double build_seconds;      /* wall time of ed_basis_build */
     double limits_mean_window; /* plain lookup: mean Limits bucket over all keys */
     int64_t limits_max_window; /* plain lookup: largest Limits bucket */
+    int32_t apply_blocks;      /* persistent grid of the H.v kernel */
+    int32_t apply_threads;     /* its block size */
 } ed_basis_info_t;
 
 /*

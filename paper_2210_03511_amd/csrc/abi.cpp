@@ -248,6 +248,8 @@ ed_status ed_basis_info(const ed_basis *b, ed_basis_info_t *info)
     r.lds_resident = 1;
     r.limits_mean_window = b->limits_mean_window;
     r.limits_max_window = b->limits_max_window;
+    r.apply_blocks = b->cfg.apply_blocks;
+    r.apply_threads = b->cfg.apply_threads;
     r.build_seconds = b->build_seconds;
     *info = r;
     return ED_OK;
@@ -588,10 +590,20 @@ ed_status ed_index_train(ed_basis *b, const ed_index_cfg *cfg_in, ed_index_stats
     double dev = 0.0;
     const int pieces = expand_network(hp.data(), mu, sc, block, &dev);
     double yscale = 1.0;
-    for (int q = 0; q < pieces; ++q) yscale = std::max(yscale, (double)std::fabs(block[4 + 2 * kPwMax + q]));
+    for (int q = 0; q < pieces; ++q) yscale = std::max(yscale, (double)std::fabs(block[kPwHeader + 2 * pieces + q]));
     if (!(dev <= 1e-4 * yscale)) return fail(ED_EDEVICE, "network expansion disagrees with the network");
+    if (b->lay.off_mlp + block.size() * sizeof(float) > b->lay.reserved)
+        return fail(ED_EDEVICE, "network expansion larger than its reserved space");
     float *d_pw = reinterpret_cast<float *>(static_cast<unsigned char *>(b->d_blob) + b->lay.off_mlp);
-    HIP_OK(hipMemcpyAsync(d_pw, block.data(), kPwFloats * sizeof(float), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(d_pw, block.data(), block.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    // the kernels now stage the pieces too; the blocks per compute unit follow
+    b->lay.bytes = (uint32_t)((b->lay.off_mlp + block.size() * sizeof(float) + 15) & ~(size_t)15);
+    {
+        int bpc = 0, athreads = 0;
+        HIP_OK(prepare_kernels(make_params(b), &bpc, &athreads));
+        if (bpc < 1) return fail(ED_EINVAL, "tables and network exceed the LDS of one compute unit");
+        b->cfg.apply_blocks = bpc * b->n_cu;
+    }
     // exact leaf table: ranges, key-space buckets, bucket begins
     if (b->d_leaves && b->log2_leaves != lg) return fail(ED_EINVAL, "index already trained with another leaf count");
     if (!b->d_leaves && (s = dev_alloc(b, &b->d_leaves, (sizeof(Leaf) << lg))) != ED_OK) return s;

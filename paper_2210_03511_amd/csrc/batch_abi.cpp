@@ -74,6 +74,30 @@ static ed_status layout_tiles(ed_batch *b, int64_t tile_rows)
     return ED_OK;
 }
 
+// The tables a sector stages into LDS grow when its learned index is trained
+// after the batch was made: size the batched launch for the largest, and
+// drop the captured steps, which hold the old launch shape.
+static ed_status fit_lds(ed_batch *b)
+{
+    size_t need = 0;
+    for (auto *s : b->secs) need = std::max(need, (size_t)s->lay.bytes);
+    if (need <= b->lds) return ED_OK;
+    if (batch_prepare(need) != hipSuccess) return fail(ED_EDEVICE, "kernel attribute");
+    int bpc = 0;
+    if (batch_occupancy(need, &bpc) != hipSuccess || bpc < 1)
+        return fail(ED_EINVAL, "batched kernel does not fit on a compute unit");
+    HIP_OK(hipStreamSynchronize(b->own));
+    b->lds = need;
+    b->apply_blocks = bpc * b->n_cu;
+    b->info.apply_blocks = b->apply_blocks;
+    for (auto &g : b->graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    return ED_OK;
+}
+
 static ed_status check_mode(const ed_batch *b, int mode)
 {
     if (mode != 0 && mode != 1) return fail(ED_EINVAL, "lookup_mode must be 0 or 1");
@@ -218,6 +242,7 @@ ed_status ed_batch_apply(ed_batch *b, const void *const *d_x, void *const *d_y, 
     if (!b || !d_x || !d_y) return fail(ED_EINVAL, "NULL argument");
     ed_status st = check_mode(b, lookup_mode);
     if (st != ED_OK) return st;
+    if ((st = fit_lds(b)) != ED_OK) return st;
     const int n = (int)b->secs.size();
     bool changed = false;
     for (int s = 0; s < n; ++s) {
@@ -243,6 +268,7 @@ ed_status ed_batch_lanczos(ed_batch *b, const void *const *d_v0, int32_t n_iter,
     if (!b || !d_v0 || !h_alpha || !h_beta || !n_done || n_iter < 1) return fail(ED_EINVAL, "bad arguments");
     ed_status st = check_mode(b, lookup_mode);
     if (st != ED_OK) return st;
+    if ((st = fit_lds(b)) != ED_OK) return st;
     const int n = (int)b->secs.size();
     if (n_iter > b->lanczos_cap) {
         b->alpha.assign(n, nullptr);

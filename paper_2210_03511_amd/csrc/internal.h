@@ -53,10 +53,14 @@ struct HostTables {
     std::vector<uint16_t> rep;          // [R][2^br]
     std::vector<uint32_t> sym_off;      // [R*2^br + 1]
     std::vector<uint32_t> sym_list;     // (g << 16) | (sp << 1) | flip
-    // SymmetryAction tables on A fine sublattices of ba bits, destination-major
+    // SymmetryAction tables on A fine sublattices of ba bits, destination-major.
+    // The table of (symmetry, destination d) maps the substate of the source
+    // sublattice to the substate it becomes at d; it only depends on how the
+    // symmetry orders the sites, so many coincide and each distinct table is
+    // stored once.
     int A = 0, ba = 0;
-    std::vector<uint8_t> act;           // [n_sp][A][2^ba]: substate at destination d
-    std::vector<uint64_t> src;          // [n_sp]: 4-bit source sublattice per destination
+    std::vector<uint16_t> act_tab;      // [n_tab][2^ba]: distinct tables
+    std::vector<uint16_t> act_ent;      // [n_sp][A]: (table << 4) | source sublattice
 
     std::vector<PairTerm> pairs;
     std::vector<ChiTerm> chis;
@@ -64,9 +68,10 @@ struct HostTables {
 
 // Byte layout of the table blob staged into LDS by the kernels.
 struct BlobLayout {
-    uint32_t off_rep, off_symoff, off_symlist, off_act, off_src, off_pairs, off_chis, off_chi, off_sqrt, off_isqrt,
+    uint32_t off_rep, off_symoff, off_symlist, off_atab, off_aent, off_pairs, off_chis, off_chi, off_sqrt, off_isqrt,
         off_chione, off_mlp;
-    uint32_t bytes;
+    uint32_t bytes;      // staged into LDS: up to the network pieces in use
+    uint32_t reserved;   // allocated: room for the largest network expansion
 };
 
 // Parameters passed by value to the apply / enumeration kernels.

@@ -22,7 +22,7 @@ constexpr int kVecThreads = 256;
 // mode 0: y = H x.  mode 1 (real Lanczos): w <- H v - beta_prev w, partial
 // <w|v>.  mode 2 (complex Lanczos): w <- H v, partial Re<w|v>.
 template <bool CPLX, int MODE, int LK>
-__global__ void __launch_bounds__(kApplyThreads) k_apply(KParams p, const double *__restrict__ x,
+__global__ void __launch_bounds__(kApplyThreads, 2) k_apply(KParams p, const double *__restrict__ x,
                                                        double *__restrict__ y, const LState *ls,
                                                        double *partials)
 {
@@ -251,15 +251,10 @@ __global__ void __launch_bounds__(256) k_enumerate(KParams p, const uint64_t *bi
                 const uint32_t k1 = L.symoff[idx + 1];
                 for (uint32_t q = L.symoff[idx]; q < k1; ++q) {
                     const uint32_t e = L.symlist[q];
-                    const uint32_t sp = (e >> 1) & 0x7fffu;
-                    const uint64_t srcw = L.src[sp];
-                    const uint8_t *a = L.act + (size_t)sp * ((uint32_t)A << ba);
+                    const uint32_t sp = e >> 1;
+                    const uint16_t *en = L.aent + (size_t)sp * A;
                     uint64_t v = 0;
-                    for (int d = 0; d < A; ++d) {
-                        const uint32_t x = (uint32_t)(srcw >> (4 * d)) & 15u;
-                        const uint32_t ss = (uint32_t)(s >> (N - (int)(x + 1) * ba)) & ma;
-                        v = (v << ba) | a[(d << ba) + ss];
-                    }
+                    for (int d = 0; d < A; ++d) v = (v << ba) | act_image(en, L.atab, s, d, N, ba);
                     if (e & 1u) v ^= p.maskN;
                     if (v < s) {
                         isrep = false;
@@ -267,7 +262,7 @@ __global__ void __launch_bounds__(256) k_enumerate(KParams p, const uint64_t *bi
                     }
                     if (v == s) {
                         ++stab;
-                        if (!L.chione[e >> 16]) triv = false;
+                        if (!L.chione[e]) triv = false;
                     }
                 }
             }

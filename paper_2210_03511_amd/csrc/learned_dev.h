@@ -72,8 +72,11 @@ __device__ __forceinline__ float mlp_eval(const float *__restrict__ P, int F, co
 // float64) into breakpoints brk[0..n-2] (ascending) and per-piece values
 // y = fmaf(slope[i], u, icpt[i]) for piece i = number of breakpoints <= u.
 // The index build and every lookup evaluate the network through this
-// expansion, so their arithmetic is identical.
+// expansion, so their arithmetic is identical.  Block layout (floats):
+// header (n, 3 unused), brk[n], slope[n], icpt[n] (brk[n-1] unused), so a
+// block takes 4 + 3n floats.
 constexpr int kPwMax = kHidden + kHidden * (kHidden + 1) + 2;
+constexpr int kPwHeader = 4;
 
 struct PwView {
     int n;                  // pieces
@@ -97,14 +100,15 @@ __host__ __device__ __forceinline__ PwView pw_view(const float *base)
 {
     PwView w;
     w.n = (int)base[0];
-    w.brk = base + 4;
-    w.slope = base + 4 + kPwMax;
-    w.icpt = base + 4 + 2 * kPwMax;
+    w.brk = base + kPwHeader;
+    w.slope = base + kPwHeader + w.n;
+    w.icpt = base + kPwHeader + 2 * w.n;
     return w;
 }
 
-// floats of the expansion block: header (4) + breakpoints + slopes + intercepts
-constexpr int kPwFloats = 4 + 3 * kPwMax;
+// floats of an expansion block with n pieces, and of the largest one
+__host__ __device__ constexpr int pw_floats(int n) { return kPwHeader + 3 * n; }
+constexpr int kPwFloats = pw_floats(kPwMax);
 
 // A leaf: the keys routed to it occupy positions inside [lo, hi).  The leaf
 // is split into nsub buckets uniform in key space: key k falls in bucket

@@ -164,7 +164,8 @@ ed_status ed_expectation(const ed_basis *cb, const ed_model *op, const void *d_p
     int lds_max = 0;
     if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device) != hipSuccess)
         return fail(ED_EDEVICE, "device query");
-    if ((int64_t)lay2.bytes + 256 > lds_max) return fail(ED_EINVAL, "operator tables exceed the LDS of one block");
+    if ((int64_t)lay2.bytes + (b->lay.bytes - b->lay.off_mlp) + 256 > lds_max)
+        return fail(ED_EINVAL, "operator tables exceed the LDS of one block");
     const bool cplx = b->T.is_complex;
     const size_t vbytes = (size_t)b->dim * sizeof(double) * (cplx ? 2 : 1);
     const int nb = b->cfg.vec_blocks;
@@ -183,10 +184,12 @@ ed_status ed_expectation(const ed_basis *cb, const ed_model *op, const void *d_p
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(d_blob, blob.data(), blob.size(), hipMemcpyHostToDevice, s);
     // the learned index network lives in the blob: carry it over
-    if (e == hipSuccess && b->indexed)
+    if (e == hipSuccess && b->indexed) {
         e = hipMemcpyAsync(static_cast<unsigned char *>(d_blob) + lay2.off_mlp,
                            static_cast<const unsigned char *>(b->d_blob) + b->lay.off_mlp, kPwFloats * sizeof(float),
                            hipMemcpyDeviceToDevice, s);
+        lay2.bytes = lay2.off_mlp + (b->lay.bytes - b->lay.off_mlp);
+    }
     KParams p = make_params(b);
     p.lay = lay2;
     p.blob = d_blob;

@@ -106,9 +106,10 @@ int expand_network(const float *params, float mu, float sc, std::vector<float> &
     std::sort(brk.begin(), brk.end());
     brk.erase(std::unique(brk.begin(), brk.end()), brk.end());
     const int pieces = (int)brk.size() + 1;
-    block.assign(kPwFloats, 0.0f);
+    block.assign(pw_floats(pieces), 0.0f);
     block[0] = (float)pieces;
-    float *fb = block.data() + 4, *fs = block.data() + 4 + kPwMax, *fi = block.data() + 4 + 2 * kPwMax;
+    float *fb = block.data() + kPwHeader, *fs = block.data() + kPwHeader + pieces,
+          *fi = block.data() + kPwHeader + 2 * pieces;
     for (int p = 0; p < pieces; ++p) {
         double m;
         if (brk.empty()) m = 0.0;

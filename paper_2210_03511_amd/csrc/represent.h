@@ -13,10 +13,10 @@ namespace symed {
 
 struct Lds {
     const uint16_t *rep;
-    const uint32_t *symoff;
-    const uint32_t *symlist;
-    const uint8_t *act;
-    const uint64_t *src;
+    const uint16_t *symoff;
+    const uint16_t *symlist;    // symmetry codes (sp << 1) | flip
+    const uint16_t *atab;   // distinct SymmetryAction tables, 2^ba entries each
+    const uint16_t *aent;   // [n_sp][A]: (table << 4) | source sublattice
     const PairTerm *pairs;
     const ChiTerm *chis;
     const double *chi;
@@ -30,10 +30,10 @@ __host__ __device__ __forceinline__ Lds lds_view(const unsigned char *b, const B
 {
     Lds v;
     v.rep = reinterpret_cast<const uint16_t *>(b + L.off_rep);
-    v.symoff = reinterpret_cast<const uint32_t *>(b + L.off_symoff);
-    v.symlist = reinterpret_cast<const uint32_t *>(b + L.off_symlist);
-    v.act = b + L.off_act;
-    v.src = reinterpret_cast<const uint64_t *>(b + L.off_src);
+    v.symoff = reinterpret_cast<const uint16_t *>(b + L.off_symoff);
+    v.symlist = reinterpret_cast<const uint16_t *>(b + L.off_symlist);
+    v.atab = reinterpret_cast<const uint16_t *>(b + L.off_atab);
+    v.aent = reinterpret_cast<const uint16_t *>(b + L.off_aent);
     v.pairs = reinterpret_cast<const PairTerm *>(b + L.off_pairs);
     v.chis = reinterpret_cast<const ChiTerm *>(b + L.off_chis);
     v.chi = reinterpret_cast<const double *>(b + L.off_chi);
@@ -44,9 +44,21 @@ __host__ __device__ __forceinline__ Lds lds_view(const unsigned char *b, const B
     return v;
 }
 
+// Substate that a symmetry puts at fine destination d of the configuration
+// t (spin flip not applied); en: the symmetry's A entries (table << 4) |
+// source sublattice.
+__host__ __device__ __forceinline__ uint32_t act_image(const uint16_t *en, const uint16_t *atab, uint64_t t, int d,
+                                                      int N, int ba)
+{
+    const uint32_t ent = en[d];
+    const uint32_t x = ent & 15u;
+    const uint32_t ss = (uint32_t)(t >> (N - (int)(x + 1) * ba)) & ((1u << ba) - 1u);
+    return atab[((ent >> 4) << ba) + ss];
+}
+
 struct Found {
     uint64_t rep;
-    uint32_t g;
+    uint32_t g;    // code (sp << 1) | flip of a symmetry reaching the representative
     uint32_t cnt;  // number of group elements reaching the representative = |Stab|
 };
 
@@ -83,17 +95,14 @@ __host__ __device__ __forceinline__ Found find_rep(uint64_t t, const KParams &p,
         const uint32_t k1 = L.symoff[idx + 1];
         for (uint32_t k = L.symoff[idx]; k < k1; ++k) {
             const uint32_t e = L.symlist[k];
-            const uint32_t sp = (e >> 1) & 0x7fffu;
+            const uint32_t sp = e >> 1;
             const uint32_t fm = (e & 1u) ? ma : 0u;  // spin flip complements every substate
-            const uint64_t srcw = L.src[sp];
-            const uint8_t *a = L.act + (size_t)sp * ((uint32_t)A << ba);
+            const uint16_t *en = L.aent + (size_t)sp * A;
             uint64_t v = minrep;
             uint64_t bp = 0;
             int d = d0;
             for (; d < A; ++d) {
-                const uint32_t x = (uint32_t)(srcw >> (4 * d)) & 15u;
-                const uint32_t ss = (uint32_t)(t >> (N - (int)(x + 1) * ba)) & ma;
-                v = (v << ba) | (uint32_t)(a[(d << ba) + ss] ^ fm);
+                v = (v << ba) | (act_image(en, L.atab, t, d, N, ba) ^ fm);
                 bp = best >> ((A - 1 - d) * ba);
                 if (v != bp) break;
             }
@@ -104,19 +113,15 @@ __host__ __device__ __forceinline__ Found find_rep(uint64_t t, const KParams &p,
                     ++cnt;
                 } else {
                     best = v;
-                    bg = e >> 16;
+                    bg = e;
                     cnt = 1;
                 }
                 continue;
             }
             if (v > bp) continue;
-            for (++d; d < A; ++d) {
-                const uint32_t x = (uint32_t)(srcw >> (4 * d)) & 15u;
-                const uint32_t ss = (uint32_t)(t >> (N - (int)(x + 1) * ba)) & ma;
-                v = (v << ba) | (uint32_t)(a[(d << ba) + ss] ^ fm);
-            }
+            for (++d; d < A; ++d) v = (v << ba) | (act_image(en, L.atab, t, d, N, ba) ^ fm);
             best = v;
-            bg = e >> 16;
+            bg = e;
             cnt = 1;
         }
     }

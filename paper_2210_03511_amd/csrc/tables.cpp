@@ -250,20 +250,44 @@ void build_rep_sym(const HostTables &T, int n_sub, std::vector<uint16_t> &rep, s
     }
 }
 
-static void build_act(HostTables &T)
+// Distinct SymmetryAction tables of the decomposition into A sublattices
+// (at most `limit`; -1 if there are more).  rows / tabs receive them if given.
+static int act_tables(const HostTables &T, int A, int limit, std::vector<uint16_t> *ents, std::vector<uint16_t> *tabs)
 {
-    const int A = T.A, b = T.ba;
+    const int b = T.N / A;
     const uint32_t S = 1u << b;
-    T.act.assign((size_t)T.n_sp * A * S, 0);
-    T.src.assign(T.n_sp, 0);
+    // the map from source positions to destination positions identifies a table
+    std::map<std::vector<uint8_t>, int> ids;
+    if (ents) ents->assign((size_t)T.n_sp * A, 0);
+    if (tabs) tabs->clear();
+    std::vector<uint8_t> key(b);
     for (int sp = 0; sp < T.n_sp; ++sp) {
         const int32_t *p = &T.sp_perm[(size_t)sp * T.N];
         for (int X = 0; X < A; ++X) {
-            int d = p[X * b] / b;  // destination of X
-            T.src[sp] |= (uint64_t)X << (4 * d);
-            for (uint32_t s = 0; s < S; ++s) T.act[((size_t)sp * A + d) * S + s] = (uint8_t)sub_image(p, X, b, s);
+            const int d = p[X * b] / b;  // destination of X
+            for (int q = 0; q < b; ++q) key[q] = (uint8_t)(p[X * b + q] % b);
+            auto it = ids.find(key);
+            int id;
+            if (it == ids.end()) {
+                id = (int)ids.size();
+                if (id >= limit) return -1;
+                ids.emplace(key, id);
+                if (tabs)
+                    for (uint32_t s = 0; s < S; ++s) tabs->push_back((uint16_t)sub_image(p, X, b, s));
+            } else {
+                id = it->second;
+            }
+            if (ents) (*ents)[(size_t)sp * A + d] = (uint16_t)((id << 4) | X);
         }
     }
+    return (int)ids.size();
+}
+
+static ed_status build_act(HostTables &T)
+{
+    if (act_tables(T, T.A, 4096, &T.act_ent, &T.act_tab) < 0)
+        return fail(ED_EINVAL, "more than 4096 distinct SymmetryAction tables; choose more sublattices");
+    return ED_OK;
 }
 
 void build_pairs(const ed_model *m, HostTables &T)
@@ -310,32 +334,42 @@ std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &L)
 {
     size_t o = 0;
     L.off_rep = (uint32_t)o;     o = align16(o + T.rep.size() * sizeof(uint16_t));
-    L.off_symoff = (uint32_t)o;  o = align16(o + T.sym_off.size() * sizeof(uint32_t));
-    L.off_symlist = (uint32_t)o; o = align16(o + T.sym_list.size() * sizeof(uint32_t));
-    L.off_act = (uint32_t)o;     o = align16(o + T.act.size());
-    L.off_src = (uint32_t)o;     o = align16(o + T.src.size() * sizeof(uint64_t));
+    L.off_symoff = (uint32_t)o;  o = align16(o + T.sym_off.size() * sizeof(uint16_t));
+    L.off_symlist = (uint32_t)o; o = align16(o + T.sym_list.size() * sizeof(uint16_t));
+    L.off_atab = (uint32_t)o;    o = align16(o + T.act_tab.size() * sizeof(uint16_t));
+    L.off_aent = (uint32_t)o;    o = align16(o + T.act_ent.size() * sizeof(uint16_t));
     L.off_pairs = (uint32_t)o;   o = align16(o + T.pairs.size() * sizeof(PairTerm));
     L.off_chis = (uint32_t)o;    o = align16(o + T.chis.size() * sizeof(ChiTerm));
-    L.off_chi = (uint32_t)o;     o = align16(o + (size_t)T.G * sizeof(double) * (T.is_complex ? 2 : 1));
+    L.off_chi = (uint32_t)o;     o = align16(o + (size_t)2 * T.n_sp * sizeof(double) * (T.is_complex ? 2 : 1));
     L.off_sqrt = (uint32_t)o;    o = align16(o + (size_t)(T.G + 1) * sizeof(double));
     L.off_isqrt = (uint32_t)o;   o = align16(o + (size_t)(T.G + 1) * sizeof(double));
-    L.off_chione = (uint32_t)o;  o = align16(o + (size_t)T.G);
+    L.off_chione = (uint32_t)o;  o = align16(o + (size_t)2 * T.n_sp);
     // space for the learned-index network in expanded form (filled after training)
-    L.off_mlp = (uint32_t)o;     o = align16(o + (size_t)kPwFloats * sizeof(float));
-    L.bytes = (uint32_t)o;
+    L.off_mlp = (uint32_t)o;
+    L.bytes = (uint32_t)align16(o + kPwHeader * sizeof(float));   // no network yet: header only
+    o = align16(o + (size_t)kPwFloats * sizeof(float));
+    L.reserved = (uint32_t)o;
     std::vector<uint8_t> blob(o, 0);
     auto put = [&](uint32_t off, const void *src, size_t n) { if (n) std::memcpy(blob.data() + off, src, n); };
     put(L.off_rep, T.rep.data(), T.rep.size() * sizeof(uint16_t));
-    put(L.off_symoff, T.sym_off.data(), T.sym_off.size() * sizeof(uint32_t));
-    put(L.off_symlist, T.sym_list.data(), T.sym_list.size() * sizeof(uint32_t));
-    put(L.off_act, T.act.data(), T.act.size());
-    put(L.off_src, T.src.data(), T.src.size() * sizeof(uint64_t));
+    // device form: 16-bit offsets, and for each symmetry its code (sp << 1) | flip
+    std::vector<uint16_t> off16(T.sym_off.begin(), T.sym_off.end()), code(T.sym_list.size());
+    for (size_t k = 0; k < T.sym_list.size(); ++k) code[k] = (uint16_t)(T.sym_list[k] & 0xffffu);
+    put(L.off_symoff, off16.data(), off16.size() * sizeof(uint16_t));
+    put(L.off_symlist, code.data(), code.size() * sizeof(uint16_t));
+    put(L.off_atab, T.act_tab.data(), T.act_tab.size() * sizeof(uint16_t));
+    put(L.off_aent, T.act_ent.data(), T.act_ent.size() * sizeof(uint16_t));
     put(L.off_pairs, T.pairs.data(), T.pairs.size() * sizeof(PairTerm));
     put(L.off_chis, T.chis.data(), T.chis.size() * sizeof(ChiTerm));
-    std::vector<double> chi;
+    // characters and the "chi == 1" flags by symmetry code (sp << 1) | flip
+    const int w = T.is_complex ? 2 : 1;
+    std::vector<double> chi((size_t)2 * T.n_sp * w, 0.0);
+    std::vector<uint8_t> one((size_t)2 * T.n_sp, 0);
     for (int g = 0; g < T.G; ++g) {
-        chi.push_back(T.chi_re[g]);
-        if (T.is_complex) chi.push_back(T.chi_im[g]);
+        const size_t c = ((size_t)T.sp_of[g] << 1) | T.flip[g];
+        chi[c * w] = T.chi_re[g];
+        if (T.is_complex) chi[c * w + 1] = T.chi_im[g];
+        one[c] = T.chi_one[g];
     }
     put(L.off_chi, chi.data(), chi.size() * sizeof(double));
     std::vector<double> sq(T.G + 1), isq(T.G + 1);
@@ -345,13 +379,14 @@ std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &L)
     }
     put(L.off_sqrt, sq.data(), sq.size() * sizeof(double));
     put(L.off_isqrt, isq.data(), isq.size() * sizeof(double));
-    put(L.off_chione, T.chi_one.data(), T.chi_one.size());
+    put(L.off_chione, one.data(), one.size());
     return blob;
 }
 
 // Choose the decompositions: the SymmetryAction tables use the stable
-// contiguous decomposition with the fewest sublattices whose tables fit
-// (<= 8 bits per substate, <= 16 sublattices, <= 64 KiB); the Rep/Sym
+// contiguous decomposition with the fewest sublattices (fewest destination
+// steps per candidate) whose distinct tables fit (<= 12 bits per substate,
+// <= 16 sublattices, tables of <= 48 KiB together); the Rep/Sym
 // tables use the one with the fewest sublattices (fewest candidate
 // symmetries) that the action decomposition refines and whose tables fit
 // 64 KiB.
@@ -368,12 +403,18 @@ int choose_sublattices(const HostTables &T, int &R, int &A, std::string &why)
     int bestA = 0;
     for (int ns : stable) {
         int b = N / ns;
-        if (b > 8 || ns > 16) continue;
-        size_t bytes = (size_t)T.n_sp * ns * ((size_t)1 << b);
-        if (bytes <= 64 * 1024) { bestA = ns; break; }
+        if (b > 12 || ns > 16) continue;
+        const size_t per = ((size_t)1 << b) * sizeof(uint16_t);
+        const int limit = (int)std::min<size_t>(4096, 48 * 1024 / per);
+        if (limit < 1 || act_tables(T, ns, limit, nullptr, nullptr) < 0) continue;
+        // the Rep/Sym decomposition must divide it: some stable one with small enough tables
+        bool refinable = false;
+        for (int r : stable)
+            if (ns % r == 0 && N / r <= 14) refinable = true;
+        if (refinable) { bestA = ns; break; }
     }
     if (!bestA) {
-        why = "no stable decomposition gives SymmetryAction tables of at most 64 KiB";
+        why = "no stable decomposition gives distinct SymmetryAction tables within 48 KiB";
         return 0;
     }
     int bestR = 0;
@@ -387,7 +428,8 @@ int choose_sublattices(const HostTables &T, int &R, int &A, std::string &why)
         std::vector<uint32_t> off, lst;
         if (ns * S * 6 > 64 * 1024) continue;
         build_rep_sym(T, ns, rep, off, lst);
-        size_t bytes = rep.size() * 2 + off.size() * 4 + lst.size() * 4;
+        size_t bytes = rep.size() * 2 + off.size() * 2 + lst.size() * 2;
+        if (lst.size() > 65535) continue;
         if (bytes <= 64 * 1024) { bestR = ns; break; }
     }
     if (!bestR) {
@@ -420,9 +462,12 @@ ed_status build_host_tables(const ed_model *m, const ed_group *g, int n_up, int 
     T.A = A;
     T.ba = T.N / A;
     if (T.br > 16) return fail(ED_EINVAL, "Rep/Sym substates wider than 16 bits");
-    if (T.ba > 8 || A > 16) return fail(ED_EINVAL, "SymmetryAction tables need <= 8 bits per substate and <= 16 sublattices");
+    if (T.ba > 12 || A > 16)
+        return fail(ED_EINVAL, "SymmetryAction tables need <= 12 bits per substate and <= 16 sublattices");
     build_rep_sym(T, R, T.rep, T.sym_off, T.sym_list);
-    build_act(T);
+    if (T.sym_list.size() > 65535 || T.n_sp >= 32768)
+        return fail(ED_EINVAL, "Sym tables too large for 16-bit entries; choose more Rep sublattices");
+    if ((st = build_act(T)) != ED_OK) return st;
     build_pairs(m, T);
     return ED_OK;
 }

@@ -58,7 +58,8 @@ class BasisInfo(ctypes.Structure):
                 ("bytes_device", ctypes.c_int64), ("table_bytes", ctypes.c_int64), ("limits_bytes", ctypes.c_int64),
                 ("index_bytes", ctypes.c_int64), ("index_max_err", ctypes.c_int32), ("lds_resident", ctypes.c_int32),
                 ("build_seconds", ctypes.c_double), ("limits_mean_window", ctypes.c_double),
-                ("limits_max_window", ctypes.c_int64)]
+                ("limits_max_window", ctypes.c_int64), ("apply_blocks", ctypes.c_int32),
+                ("apply_threads", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

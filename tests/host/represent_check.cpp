@@ -25,6 +25,9 @@ int main(int argc, char **argv) {
   BlobLayout lay; std::vector<uint8_t> blob = pack_blob(T, lay);
   std::vector<uint8_t> al(blob.size() + 16); std::memcpy(al.data(), blob.data(), blob.size());
   Lds L = lds_view(al.data(), lay);
+  // find_rep reports a symmetry by its code (sp << 1) | flip
+  std::vector<int> g_of_code(2 * T.n_sp, 0);
+  for (int e = 0; e < T.G; ++e) g_of_code[(T.sp_of[e] << 1) | T.flip[e]] = e;
   KParams p{}; p.N = N; p.R = T.R; p.br = T.br; p.A = T.A; p.ba = T.ba; p.maskN = (1ull << N) - 1;
   long long checked = 0, bad = 0;
   for (uint64_t s = 0; s < (1ull << N); ++s) {
@@ -40,7 +43,7 @@ int main(int argc, char **argv) {
     }
     Found fr = find_rep(s, p, L);
     ++checked;
-    if (fr.rep != best || (int)fr.cnt != cnt || img[fr.g] != best) {
+    if (fr.rep != best || (int)fr.cnt != cnt || img[g_of_code[fr.g]] != best) {
       if (bad < 5) printf("mismatch s=%llx rep %llx/%llx cnt %u/%d g %u\n", (unsigned long long)s, (unsigned long long)fr.rep, (unsigned long long)best, fr.cnt, cnt, fr.g);
       ++bad;
     }
