@@ -94,9 +94,9 @@ void ed_basis_free(ed_basis *b)
 {
     if (!b) return;
     for (auto &g : b->step_graph)
-        if (g) hipGraphExecDestroy(g);
-    for (void *p : b->allocs) hipFree(p);
-    if (b->own) hipStreamDestroy(b->own);
+        if (g) (void)hipGraphExecDestroy(g);
+    for (void *p : b->allocs) (void)hipFree(p);
+    if (b->own) (void)hipStreamDestroy(b->own);
     delete b;
 }
 
@@ -132,6 +132,7 @@ static ed_status build_impl(const ed_model *model, const ed_group *group, int32_
     b->cfg.apply_blocks = bpc * b->n_cu;
     b->cfg.vec_blocks = 4 * b->n_cu;
 
+    TmpPool tmp;  // temporaries of the build
     // --- enumeration of the sector (two passes + scan) -------------------
     const int N = T.N;
     const uint64_t total = binom64(N, n_up);
@@ -139,16 +140,16 @@ static ed_status build_impl(const ed_model *model, const ed_group *group, int32_
     for (int n = 0; n < 64; ++n)
         for (int k = 0; k < 64; ++k) hb[n * 64 + k] = binom64(n, k);
     uint64_t *d_binom = nullptr;
-    HIP_OK(hipMalloc((void **)&d_binom, hb.size() * sizeof(uint64_t)));
+    HIP_OK(tmp.alloc((void **)&d_binom, hb.size() * sizeof(uint64_t)));
     HIP_OK(hipMemcpy(d_binom, hb.data(), hb.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
     uint64_t len = std::max<uint64_t>(256, (total + (1ull << 24) - 1) >> 24);
     uint64_t n_chunks = (total + len - 1) / len;
     if (n_chunks == 0) n_chunks = 1;
     uint32_t *d_counts = nullptr;
     uint64_t *d_offsets = nullptr, *d_total = nullptr;
-    HIP_OK(hipMalloc((void **)&d_counts, n_chunks * sizeof(uint32_t)));
-    HIP_OK(hipMalloc((void **)&d_offsets, n_chunks * sizeof(uint64_t)));
-    HIP_OK(hipMalloc((void **)&d_total, sizeof(uint64_t)));
+    HIP_OK(tmp.alloc((void **)&d_counts, n_chunks * sizeof(uint32_t)));
+    HIP_OK(tmp.alloc((void **)&d_offsets, n_chunks * sizeof(uint64_t)));
+    HIP_OK(tmp.alloc((void **)&d_total, sizeof(uint64_t)));
     int eblocks = (int)std::min<uint64_t>((n_chunks + 255) / 256, (uint64_t)b->n_cu * 16);
     if (eblocks < 1) eblocks = 1;
     HIP_OK(launch_enumerate(p, d_binom, total, len, n_chunks, d_counts, nullptr, nullptr, nullptr, false, eblocks, st));
@@ -164,10 +165,6 @@ static ed_status build_impl(const ed_model *model, const ed_group *group, int32_
     HIP_OK(launch_enumerate(p, d_binom, total, len, n_chunks, d_counts, d_offsets, b->d_reps, b->d_stab, true, eblocks,
                             st));
     HIP_OK(hipStreamSynchronize(st));
-    hipFree(d_binom);
-    hipFree(d_counts);
-    hipFree(d_offsets);
-    hipFree(d_total);
 
     // --- Limits prefix table --------------------------------------------
     int pb = o.prefix_bits;
@@ -185,12 +182,11 @@ static ed_status build_impl(const ed_model *model, const ed_group *group, int32_
     // --- key-weighted Limits bucket statistics (search window of the plain lookup)
     {
         unsigned long long *d_ls = nullptr, hls[2] = {0, 0};
-        HIP_OK(hipMalloc((void **)&d_ls, 2 * sizeof(unsigned long long)));
+        HIP_OK(tmp.alloc((void **)&d_ls, 2 * sizeof(unsigned long long)));
         HIP_OK(hipMemsetAsync(d_ls, 0, 2 * sizeof(unsigned long long), st));
         HIP_OK(launch_limits_stats(b->d_limits, pb, d_ls, st));
         HIP_OK(hipMemcpyAsync(hls, d_ls, sizeof(hls), hipMemcpyDeviceToHost, st));
         HIP_OK(hipStreamSynchronize(st));
-        hipFree(d_ls);
         b->limits_mean_window = b->dim ? (double)hls[0] / (double)b->dim : 0.0;
         b->limits_max_window = (int64_t)hls[1];
     }
@@ -198,12 +194,11 @@ static ed_status build_impl(const ed_model *model, const ed_group *group, int32_
     // --- element count ----------------------------------------------------
     p = make_params(b);
     unsigned long long *d_cnt = nullptr, cnt = 0;
-    HIP_OK(hipMalloc((void **)&d_cnt, sizeof(unsigned long long)));
+    HIP_OK(tmp.alloc((void **)&d_cnt, sizeof(unsigned long long)));
     HIP_OK(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long), st));
     if (b->dim > 0) HIP_OK(launch_count_elements(p, d_cnt, 4 * b->n_cu, st));
     HIP_OK(hipMemcpyAsync(&cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
-    hipFree(d_cnt);
     b->n_elements = (int64_t)cnt;
     b->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return ED_OK;
@@ -218,7 +213,7 @@ ed_status ed_basis_build(const ed_model *model, const ed_group *group, int32_t n
     ed_status s = build_impl(model, group, n_up, opts, (hipStream_t)stream, b);
     if (s != ED_OK) {
         std::string msg = g_err;
-        hipDeviceSynchronize();
+        (void)hipDeviceSynchronize();  // nothing of the failed build may still run when it is freed
         ed_basis_free(b);
         g_err = msg;
         return s;
@@ -334,7 +329,7 @@ static ed_status lanczos_workspace(ed_basis *b, int n_iter)
         // graphs reference the alpha/beta arrays: rebuild them
         for (auto &g : b->step_graph)
             if (g) {
-                hipGraphExecDestroy(g);
+                (void)hipGraphExecDestroy(g);
                 g = nullptr;
             }
         int cap = std::max(n_iter, 256);
@@ -548,23 +543,23 @@ ed_status ed_index_train(ed_basis *b, const ed_index_cfg *cfg_in, ed_index_stats
     HIP_OK(hipStreamSynchronize((hipStream_t)stream));
     const int NP = mlp_param_count(F, kHidden);
     const int nb = mlp_train_blocks(batch);
+    TmpPool tmp;
     ed_status s;
     if (!b->d_params && (s = dev_alloc(b, (void **)&b->d_params, kMlpMaxParams * sizeof(float))) != ED_OK) return s;
     float *d_m = nullptr, *d_v = nullptr, *d_gpart = nullptr, *d_lpart = nullptr, *d_loss = nullptr;
-    HIP_OK(hipMalloc((void **)&d_m, NP * sizeof(float)));
-    HIP_OK(hipMalloc((void **)&d_v, NP * sizeof(float)));
-    HIP_OK(hipMalloc((void **)&d_gpart, (size_t)nb * NP * sizeof(float)));
-    HIP_OK(hipMalloc((void **)&d_lpart, (size_t)nb * sizeof(float)));
-    HIP_OK(hipMalloc((void **)&d_loss, sizeof(float)));
+    HIP_OK(tmp.alloc((void **)&d_m, NP * sizeof(float)));
+    HIP_OK(tmp.alloc((void **)&d_v, NP * sizeof(float)));
+    HIP_OK(tmp.alloc((void **)&d_gpart, (size_t)nb * NP * sizeof(float)));
+    HIP_OK(tmp.alloc((void **)&d_lpart, (size_t)nb * sizeof(float)));
+    HIP_OK(tmp.alloc((void **)&d_loss, sizeof(float)));
     HIP_OK(hipMemsetAsync(b->d_params, 0, kMlpMaxParams * sizeof(float), st));
     HIP_OK(hipMemsetAsync(d_m, 0, NP * sizeof(float), st));
     HIP_OK(hipMemsetAsync(d_v, 0, NP * sizeof(float), st));
     float *d_ur = nullptr, ur[2] = {0.f, 1.f};
-    HIP_OK(hipMalloc((void **)&d_ur, 2 * sizeof(float)));
+    HIP_OK(tmp.alloc((void **)&d_ur, 2 * sizeof(float)));
     HIP_OK(feature_range(b->d_reps, b->dim, N, d_ur, st));
     HIP_OK(hipMemcpyAsync(ur, d_ur, 2 * sizeof(float), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
-    hipFree(d_ur);
     // input standardization x = (u - mu) * sc maps the keys' feature range to [-1, 1]
     const float mu = 0.5f * (ur[0] + ur[1]);
     const float sc = (ur[1] > ur[0]) ? 2.0f / (ur[1] - ur[0]) : 1.0f;
@@ -578,11 +573,6 @@ ed_status ed_index_train(ed_basis *b, const ed_index_cfg *cfg_in, ed_index_stats
     float loss = 0;
     HIP_OK(hipMemcpyAsync(&loss, d_loss, sizeof(float), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
-    hipFree(d_m);
-    hipFree(d_v);
-    hipFree(d_gpart);
-    hipFree(d_lpart);
-    hipFree(d_loss);
     // the network, expanded into its pieces, goes into the table blob (staged
     // into LDS by the kernels)
     std::vector<float> hp(kMlpMaxParams), block;
@@ -612,11 +602,11 @@ ed_status ed_index_train(ed_basis *b, const ed_index_cfg *cfg_in, ed_index_stats
     uint32_t *d_sizes = nullptr, *d_err = nullptr, net_err = 0;
     uint64_t *d_offsets = nullptr, *d_total = nullptr, total = 0;
     unsigned long long *d_stats = nullptr, hstats[2] = {0, 0};
-    HIP_OK(hipMalloc((void **)&d_sizes, M * sizeof(uint32_t)));
-    HIP_OK(hipMalloc((void **)&d_offsets, M * sizeof(uint64_t)));
-    HIP_OK(hipMalloc((void **)&d_total, sizeof(uint64_t)));
-    HIP_OK(hipMalloc((void **)&d_err, sizeof(uint32_t)));
-    HIP_OK(hipMalloc((void **)&d_stats, 2 * sizeof(unsigned long long)));
+    HIP_OK(tmp.alloc((void **)&d_sizes, M * sizeof(uint32_t)));
+    HIP_OK(tmp.alloc((void **)&d_offsets, M * sizeof(uint64_t)));
+    HIP_OK(tmp.alloc((void **)&d_total, sizeof(uint64_t)));
+    HIP_OK(tmp.alloc((void **)&d_err, sizeof(uint32_t)));
+    HIP_OK(tmp.alloc((void **)&d_stats, 2 * sizeof(unsigned long long)));
     HIP_OK(hipMemsetAsync(d_err, 0, sizeof(uint32_t), st));
     HIP_OK(hipMemsetAsync(d_stats, 0, 2 * sizeof(unsigned long long), st));
     HIP_OK(leaf_ranges(d_pw, N, lg, b->d_reps, b->dim, b->d_leaves, target, d_sizes, d_err, 8 * b->n_cu, st));
@@ -634,16 +624,11 @@ ed_status ed_index_train(ed_basis *b, const ed_index_cfg *cfg_in, ed_index_stats
     std::vector<uint32_t> hs(M);
     HIP_OK(hipMemcpyAsync(hs.data(), d_sizes, M * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
-    hipFree(d_sizes);
-    hipFree(d_offsets);
-    hipFree(d_total);
-    hipFree(d_err);
-    hipFree(d_stats);
     int64_t used = 0;
     for (uint32_t v : hs) used += v ? 1 : 0;
     for (auto &g : b->step_graph)
         if (g) {
-            hipGraphExecDestroy(g);
+            (void)hipGraphExecDestroy(g);
             g = nullptr;
         }
     b->indexed = true;
@@ -700,14 +685,13 @@ ed_status ed_mlp_loss_grad(int32_t n_features, const float *d_params, const floa
     if (!d_params || !d_X || !d_t || !d_grad || !d_loss || n < 1) return fail(ED_EINVAL, "bad arguments");
     const int NP = mlp_param_count(n_features, kHidden);
     const int nb = (int)((n + 63) / 64);
+    TmpPool tmp;
     float *d_gpart = nullptr, *d_lpart = nullptr;
-    HIP_OK(hipMalloc((void **)&d_gpart, (size_t)nb * NP * sizeof(float)));
-    HIP_OK(hipMalloc((void **)&d_lpart, (size_t)nb * sizeof(float)));
+    HIP_OK(tmp.alloc((void **)&d_gpart, (size_t)nb * NP * sizeof(float)));
+    HIP_OK(tmp.alloc((void **)&d_lpart, (size_t)nb * sizeof(float)));
     hipStream_t st = (hipStream_t)stream;
     HIP_OK(mlp_loss_grad(d_params, n_features, d_X, d_t, n, d_grad, d_loss, d_gpart, d_lpart, st));
     HIP_OK(hipStreamSynchronize(st));
-    hipFree(d_gpart);
-    hipFree(d_lpart);
     return ED_OK;
 }
 

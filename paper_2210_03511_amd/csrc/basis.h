@@ -58,6 +58,25 @@ struct ed_basis {
 
 
 ed_status dev_alloc(ed_basis *b, void **ptr, size_t bytes);
+
+// Temporary device buffers of one call, freed when the call returns (error
+// returns included).
+struct TmpPool {
+    std::vector<void *> ptrs;
+    TmpPool() = default;
+    TmpPool(const TmpPool &) = delete;
+    TmpPool &operator=(const TmpPool &) = delete;
+    ~TmpPool()
+    {
+        for (void *q : ptrs) (void)hipFree(q);
+    }
+    hipError_t alloc(void **q, size_t bytes)
+    {
+        hipError_t e = hipMalloc(q, bytes ? bytes : 16);
+        if (e == hipSuccess) ptrs.push_back(*q);
+        return e;
+    }
+};
 symed::KParams make_params(const ed_basis *b);
 ed_status lanczos_prepare(ed_basis *b, int n_iter, int lookup_mode);
 ed_status lanczos_start(ed_basis *b, const void *d_v0, void *stream);

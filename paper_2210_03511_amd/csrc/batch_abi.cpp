@@ -126,6 +126,8 @@ ed_status ed_batch_create(ed_basis *const *sectors, int32_t n, const ed_batch_cf
 {
     if (!sectors || !out || n < 1) return fail(ED_EINVAL, "bad arguments");
     if (n > kMaxSectors) return fail(ED_EINVAL, "at most 256 sectors per batch");
+    // work queued on the caller's stream (e.g. the sectors' builds) comes first
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return fail(ED_EDEVICE, "stream");
     ed_batch_cfg cfg{};
     if (cfg_in) cfg = *cfg_in;
     ed_batch *b = new (std::nothrow) ed_batch();

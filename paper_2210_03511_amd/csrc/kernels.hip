@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(256) k_enumerate(KParams p, const uint64_t *bi
     stage_blob(lds, p.blob, p.lay.bytes);
     const Lds L = lds_view(lds, p.lay);
     const int N = p.N, R = p.R, br = p.br, A = p.A, ba = p.ba;
-    const uint32_t S = 1u << br, mr = S - 1u, ma = (1u << ba) - 1u;
+    const uint32_t S = 1u << br, mr = S - 1u;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_chunks; c += stride) {
         const uint64_t r0 = c * len;

@@ -23,7 +23,6 @@ struct VecHash {
     }
 };
 
-inline bool bit_of(uint64_t s, int n, int site) { return (s >> (n - 1 - site)) & 1u; }
 
 }  // namespace
 
