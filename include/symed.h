@@ -261,6 +261,19 @@ typedef struct {
 ed_status ed_hash_build(ed_basis *basis, const ed_hash_cfg *cfg, ed_hash_stats *stats, void *stream);
 
 /*
+ * n_more further steps of the last ed_lanczos_run on this basis (any
+ * available lookup_mode: the steps are the same bit for bit), from the
+ * device state it left; h_alpha, h_beta: f64[n_more] for the new steps only;
+ * *n_done = new steps completed.  A run and its resumptions give exactly the
+ * coefficients of one run of the total length, so convergence can be
+ * checked between chunks.  ED_EINVAL if there is no run to resume (none
+ * yet, or ed_lanczos_vector ran since); ED_EBREAKDOWN if the run broke
+ * down.  Blocks until done.
+ */
+ed_status ed_lanczos_resume(const ed_basis *basis, int32_t n_more, int32_t lookup_mode, double *h_alpha,
+                            double *h_beta, int32_t *n_done, void *stream);
+
+/*
  * Lowest k eigenvalues of the symmetric tridiagonal T-matrix with diagonal
  * alpha[n] and off-diagonal beta[n-1] (Sturm-sequence bisection), ascending.
  * Host only.

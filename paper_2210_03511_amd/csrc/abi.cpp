@@ -312,7 +312,9 @@ ed_status ed_lookup(const ed_basis *b, const uint64_t *d_keys, int64_t n, int64_
     return ED_OK;
 }
 
-static ed_status lanczos_workspace(ed_basis *b, int n_iter)
+// Vectors, scalars and alpha/beta arrays for n_iter steps; when the arrays
+// grow, their first `keep` entries (steps already done) are carried over.
+static ed_status lanczos_workspace(ed_basis *b, int n_iter, int keep)
 {
     const bool cplx = b->T.is_complex;
     const size_t vbytes = (size_t)b->dim * sizeof(double) * (cplx ? 2 : 1);
@@ -332,9 +334,16 @@ static ed_status lanczos_workspace(ed_basis *b, int n_iter)
                 (void)hipGraphExecDestroy(g);
                 g = nullptr;
             }
-        int cap = std::max(n_iter, 256);
-        if ((s = dev_alloc(b, (void **)&b->d_alpha, cap * sizeof(double))) != ED_OK) return s;
-        if ((s = dev_alloc(b, (void **)&b->d_beta, cap * sizeof(double))) != ED_OK) return s;
+        int cap = std::max(n_iter, std::max(256, 2 * b->lanczos_cap));
+        double *na = nullptr, *nb = nullptr;
+        if ((s = dev_alloc(b, (void **)&na, cap * sizeof(double))) != ED_OK) return s;
+        if ((s = dev_alloc(b, (void **)&nb, cap * sizeof(double))) != ED_OK) return s;
+        if (keep > 0 && b->d_alpha) {
+            HIP_OK(hipMemcpy(na, b->d_alpha, keep * sizeof(double), hipMemcpyDeviceToDevice));
+            HIP_OK(hipMemcpy(nb, b->d_beta, keep * sizeof(double), hipMemcpyDeviceToDevice));
+        }
+        b->d_alpha = na;
+        b->d_beta = nb;
         b->lanczos_cap = cap;
     }
     return ED_OK;
@@ -367,13 +376,13 @@ static hipError_t enqueue_step(ed_basis *b, int mode, hipStream_t st)
 }  // extern "C"
 
 // Workspace for n_iter steps and the captured step graph of a lookup mode.
-ed_status lanczos_prepare(ed_basis *b, int n_iter, int lookup_mode)
+ed_status lanczos_prepare(ed_basis *b, int n_iter, int lookup_mode, int keep)
 {
     if (n_iter < 1) return fail(ED_EINVAL, "n_iter must be >= 1");
     ed_status cs = check_lookup(b, lookup_mode);
     if (cs != ED_OK) return cs;
     if (b->dim == 0) return fail(ED_EINVAL, "empty sector");
-    ed_status s = lanczos_workspace(b, n_iter);
+    ed_status s = lanczos_workspace(b, n_iter, keep);
     if (s != ED_OK) return s;
     hipGraphExec_t &ge = b->step_graph[lookup_mode];
     if (!ge) {
@@ -406,6 +415,30 @@ ed_status lanczos_start(ed_basis *b, const void *d_v0, void *stream)
     return ED_OK;
 }
 
+// Steps done + 1 .. done + n of the run on the basis's stream; alpha/beta of
+// these steps to the host.  Records how far the run got.
+ed_status lanczos_advance(ed_basis *b, int done, int n, int lookup_mode, double *h_alpha, double *h_beta,
+                          int32_t *n_done)
+{
+    hipStream_t st = b->own;
+    for (int k = 0; k < n; ++k) HIP_OK(hipGraphLaunch(b->step_graph[lookup_mode], st));
+    LState ls{};
+    HIP_OK(hipMemcpyAsync(h_alpha, b->d_alpha + done, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(h_beta, b->d_beta + done, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(&ls, b->d_ls, sizeof(LState), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    b->lanczos_steps = done + n;
+    if (ls.broken_step >= 0) {
+        b->lanczos_broken = true;
+        *n_done = ls.broken_step + 1 - done;
+        set_error("Lanczos breakdown at step " + std::to_string(ls.broken_step));
+        return ED_EBREAKDOWN;
+    }
+    b->lanczos_broken = false;
+    *n_done = n;
+    return ED_OK;
+}
+
 extern "C" {
 
 ed_status ed_lanczos_run(const ed_basis *cb, const void *d_v0, int32_t n_iter, int32_t lookup_mode, double *h_alpha,
@@ -413,23 +446,31 @@ ed_status ed_lanczos_run(const ed_basis *cb, const void *d_v0, int32_t n_iter, i
 {
     ed_basis *b = const_cast<ed_basis *>(cb);
     if (!b || !d_v0 || !h_alpha || !h_beta || !n_done) return fail(ED_EINVAL, "NULL argument");
-    ed_status s = lanczos_prepare(b, n_iter, lookup_mode);
+    b->lanczos_steps = -1;
+    ed_status s = lanczos_prepare(b, n_iter, lookup_mode, 0);
     if (s != ED_OK) return s;
     if ((s = lanczos_start(b, d_v0, stream)) != ED_OK) return s;
-    hipStream_t st = b->own;
-    for (int k = 0; k < n_iter; ++k) HIP_OK(hipGraphLaunch(b->step_graph[lookup_mode], st));
-    LState ls{};
-    HIP_OK(hipMemcpyAsync(h_alpha, b->d_alpha, n_iter * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(h_beta, b->d_beta, n_iter * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(&ls, b->d_ls, sizeof(LState), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
-    if (ls.broken_step >= 0) {
-        *n_done = ls.broken_step + 1;
-        set_error("Lanczos breakdown at step " + std::to_string(ls.broken_step));
+    return lanczos_advance(b, 0, n_iter, lookup_mode, h_alpha, h_beta, n_done);
+}
+
+ed_status ed_lanczos_resume(const ed_basis *cb, int32_t n_more, int32_t lookup_mode, double *h_alpha,
+                            double *h_beta, int32_t *n_done, void *stream)
+{
+    ed_basis *b = const_cast<ed_basis *>(cb);
+    if (!b || !h_alpha || !h_beta || !n_done) return fail(ED_EINVAL, "NULL argument");
+    if (n_more < 1) return fail(ED_EINVAL, "n_more must be >= 1");
+    if (b->lanczos_steps < 0) return fail(ED_EINVAL, "no Lanczos run to resume on this basis");
+    const int done = b->lanczos_steps;
+    if (b->lanczos_broken) {
+        *n_done = 0;
+        set_error("the run being resumed broke down");
         return ED_EBREAKDOWN;
     }
-    *n_done = n_iter;
-    return ED_OK;
+    if ((int64_t)done + n_more > (1 << 30)) return fail(ED_EINVAL, "too many steps");
+    ed_status s = lanczos_prepare(b, done + n_more, lookup_mode, done);
+    if (s != ED_OK) return s;
+    HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    return lanczos_advance(b, done, n_more, lookup_mode, h_alpha, h_beta, n_done);
 }
 
 ed_status ed_hash_build(ed_basis *b, const ed_hash_cfg *cfg_in, ed_hash_stats *out, void *stream)

@@ -38,6 +38,8 @@ struct ed_basis {
     double *d_alpha = nullptr, *d_beta = nullptr;
     LState *d_ls = nullptr;
     int lanczos_cap = 0;
+    int lanczos_steps = -1;        // steps of the current run (-1: none to resume)
+    bool lanczos_broken = false;
     hipGraphExec_t step_graph[3] = {nullptr, nullptr, nullptr};
     // learned index
     bool indexed = false;
@@ -78,7 +80,9 @@ struct TmpPool {
     }
 };
 symed::KParams make_params(const ed_basis *b);
-ed_status lanczos_prepare(ed_basis *b, int n_iter, int lookup_mode);
+ed_status lanczos_prepare(ed_basis *b, int n_iter, int lookup_mode, int keep);
+ed_status lanczos_advance(ed_basis *b, int done, int n, int lookup_mode, double *h_alpha, double *h_beta,
+                          int32_t *n_done);
 ed_status lanczos_start(ed_basis *b, const void *d_v0, void *stream);
 
 #define HIP_OK(expr)                                                                             \

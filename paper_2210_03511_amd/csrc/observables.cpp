@@ -102,7 +102,8 @@ ed_status ed_lanczos_vector(const ed_basis *cb, const void *d_v0, int32_t n_iter
     ed_basis *b = const_cast<ed_basis *>(cb);
     if (!b || !d_v0 || !h_coef || !d_psi) return fail(ED_EINVAL, "bad arguments");
     if (d_psi == d_v0) return fail(ED_EINVAL, "psi must not alias v0");
-    ed_status st = lanczos_prepare(b, n_iter, lookup_mode);
+    b->lanczos_steps = -1;  // the second pass replaces the run's state
+    ed_status st = lanczos_prepare(b, n_iter, lookup_mode, 0);
     if (st != ED_OK) return st;
     const bool cplx = b->T.is_complex;
     const int64_t n2 = b->dim * (cplx ? 2 : 1);

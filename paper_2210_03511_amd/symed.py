@@ -26,7 +26,7 @@ EXPORTED = ["ed_last_error", "ed_version", "ed_basis_build", "ed_basis_free", "e
             "ed_basis_device_reps", "ed_apply_H", "ed_lookup", "ed_lanczos_run", "ed_eigenvalues",
             "ed_tables_inspect", "ed_index_train", "ed_index_info", "ed_mlp_loss_grad",
             "ed_index_predict", "ed_batch_create", "ed_batch_apply", "ed_batch_lanczos", "ed_batch_info",
-            "ed_batch_free", "ed_hash_build", "ed_ritz_vector", "ed_lanczos_vector", "ed_expectation"]
+            "ed_batch_free", "ed_hash_build", "ed_ritz_vector", "ed_lanczos_vector", "ed_expectation", "ed_lanczos_resume"]
 
 
 class EdError(RuntimeError):
@@ -142,6 +142,7 @@ def lib():
         L.ed_index_info.argtypes = [vp, ctypes.POINTER(IndexStats), vp, i64]
         L.ed_mlp_loss_grad.argtypes = [i32, vp, vp, vp, i64, vp, vp, vp]
         L.ed_index_predict.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.ed_lanczos_resume.argtypes = [vp, i32, i32, vp, vp, ctypes.POINTER(i32), vp]
         L.ed_ritz_vector.argtypes = [vp, vp, i32, i32, vp, vp]
         L.ed_lanczos_vector.argtypes = [vp, vp, i32, i32, vp, vp, vp]
         L.ed_expectation.argtypes = [vp, ctypes.POINTER(_Model), vp, i32, vp, vp, vp]
@@ -281,6 +282,19 @@ class Basis:
         nd = ctypes.c_int32(0)
         st = lib().ed_lanczos_run(self._h, _tensor_ptr(v0), int(n_iter), int(mode), _np_ptr(a), _np_ptr(b),
                                   ctypes.byref(nd), _stream_ptr(stream))
+        if st not in (ED_OK, ED_EBREAKDOWN):
+            _check(st)
+        n = nd.value
+        return a[:n], b[:n], n, st == ED_EBREAKDOWN
+
+    def lanczos_resume(self, n_more, mode=0, stream=None):
+        """n_more further steps of the last lanczos() run; returns (alpha, beta,
+        n_done, broken) for the new steps."""
+        a = np.zeros(n_more)
+        b = np.zeros(n_more)
+        nd = ctypes.c_int32(0)
+        st = lib().ed_lanczos_resume(self._h, int(n_more), int(mode), _np_ptr(a), _np_ptr(b), ctypes.byref(nd),
+                                     _stream_ptr(stream))
         if st not in (ED_OK, ED_EBREAKDOWN):
             _check(st)
         n = nd.value

@@ -284,3 +284,38 @@ def test_square32_against_stored_oracle_values(S):
         _say("  mode", mode, "E0", repr(e))
         assert abs(e - gold["E0_after_100"]) <= 1e-10 * abs(gold["E0_after_100"])
     b.free()
+
+
+def test_lanczos_resume_equals_one_run(S):
+    """A run resumed in chunks (across the growth of the alpha/beta arrays
+    and across lookup modes) gives the coefficients of one run, bit for bit."""
+    torch = _torch()
+    inst = L.chain16()
+    b = S.Basis.build(inst)
+    b.train_index(steps=200)
+    b.build_hash()
+    v0 = _dev(torch, V.start_vector(b.dim, 1002))
+    a1, b1, n1, br1 = b.lanczos(v0, 300, mode=0)
+    assert n1 == 300 and not br1
+    a2, b2, n2, _ = b.lanczos(v0, 120, mode=0)
+    parts_a, parts_b = [a2], [b2]
+    for mode, k in ((1, 100), (2, 80)):
+        a3, b3, n3, br3 = b.lanczos_resume(k, mode=mode)
+        assert n3 == k and not br3
+        parts_a.append(a3)
+        parts_b.append(b3)
+    assert np.array_equal(np.concatenate(parts_a), a1)
+    assert np.array_equal(np.concatenate(parts_b), b1)
+    b.free()
+
+
+def test_lanczos_resume_errors(S):
+    torch = _torch()
+    b = S.Basis.build(L.chain(4))
+    with pytest.raises(S.EdError) as e:
+        b.lanczos_resume(3)
+    assert e.value.status == S.ED_EINVAL
+    a, beta, n, broken = b.lanczos(_dev(torch, np.array([1.0, 0.3])), 10)
+    assert broken and n == 2
+    a2, b2, n2, broken2 = b.lanczos_resume(5)
+    assert broken2 and n2 == 0
