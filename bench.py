@@ -139,14 +139,18 @@ def main_batch(args):
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     infos = [b.info() for b in bases]
-    # the batched path has the plain and the learned lookups
-    modes = [0] if args.lookup == "plain" else ([1] if args.lookup == "learned" else [0, 1])
-    t_train = None
+    modes = {"plain": [0], "learned": [1], "hash": [2], "both": [0, 1], "all": [0, 1, 2]}[args.lookup]
+    t_train = t_hash = None
     if 1 in modes:
         t0 = time.perf_counter()
         for b in bases:
             b.train_index()
         t_train = time.perf_counter() - t0
+    if 2 in modes:
+        t0 = time.perf_counter()
+        for b in bases:
+            b.build_hash()
+        t_hash = time.perf_counter() - t0
     t0 = time.perf_counter()
     batch = S.Batch(bases)
     t_tune = time.perf_counter() - t0
@@ -184,7 +188,7 @@ def main_batch(args):
     n_el = binfo["total_elements"]
     alg = sum(alg_bytes_of(inf["dim"], inf["n_offdiag"], bool(inf["is_complex"])) for inf in infos)
     achieved = alg / apply_t[best] / 1e9
-    name = lambda m: "learned" if m == 1 else "plain"
+    name = {0: "plain", 1: "learned", 2: "hash"}.get
     dims = [inf["dim"] for inf in infos]
     out = {
         "metric": "H.v elements/s & s per Lanczos step, batched sectors: learned vs plain lookup",
@@ -207,7 +211,7 @@ def main_batch(args):
         "elements_per_s_Hv": {name(m): n_el / apply_t[m] for m in modes},
         "s_per_step": {name(m): step_t[m] for m in modes},
         "lowest_E_over_sectors": {name(m): e_min[m] for m in modes},
-        "setup": {"basis_build_s": t_build, "index_train_s": t_train, "autotune_s": t_tune,
+        "setup": {"basis_build_s": t_build, "index_train_s": t_train, "hash_build_s": t_hash, "autotune_s": t_tune,
                   "autotune": {"tile_rows": binfo["tune_rows"], "seconds": binfo["tune_seconds"]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,

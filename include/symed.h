@@ -375,7 +375,9 @@ ed_status ed_mlp_loss_grad(int32_t n_features, const float *d_params, const floa
  * tile length is chosen by timing one batched H.v per candidate (2048,
  * 8192, 32768, 131072 rows) unless fixed by tile_rows with autotune = 0.
  * Real and complex sectors may be mixed; lookup_mode 1 needs a trained
- * learned index in every sector.
+ * learned index in every sector, lookup_mode 2 the hashed staging table in
+ * every sector (the input vectors are copied into the tables first, so
+ * mode-2 calls must not overlap with other calls on those sectors).
  */
 typedef struct ed_batch ed_batch;
 

@@ -12,6 +12,7 @@
 // once as a HIP graph.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
 
 #include "apply_dev.h"
@@ -35,7 +36,7 @@ __device__ __forceinline__ int sector_of(const int64_t *tile0, int nsec, int64_t
 
 // lanczos = 0: y_s = H_s x_s.  lanczos = 1: w_s <- H_s v_s - beta_s w_s
 // (real sectors) or w_s <- H_s v_s (complex sectors), partial <w|v> per tile.
-template <bool LEARNED>
+template <int LK>
 __global__ void __launch_bounds__(kApplyThreads) k_batch_apply(const SectorDesc *__restrict__ secs, int nsec,
                                                              const int64_t *__restrict__ tile0g, int64_t ntiles,
                                                              int64_t tile_rows, int lanczos, double *partials)
@@ -59,21 +60,45 @@ __global__ void __launch_bounds__(kApplyThreads) k_batch_apply(const SectorDesc 
         const int64_t r0 = (t - tile0[sec]) * tile_rows;
         const int64_t r1 = min(r0 + tile_rows, p.dim);
         double part = 0.0;
-        constexpr int Lp = kLookupPlain, Ll = kLookupLearned;
         const double beta = (lanczos && !D.cplx) ? D.ls->beta_prev : 0.0;
         for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
             if (!lanczos) {
-                if (D.cplx) apply_row<true, 0, LEARNED ? Ll : Lp>(p, L, i, D.x, D.y, 0.0);
-                else apply_row<false, 0, LEARNED ? Ll : Lp>(p, L, i, D.x, D.y, 0.0);
+                if (D.cplx) apply_row<true, 0, LK>(p, L, i, D.x, D.y, 0.0);
+                else apply_row<false, 0, LK>(p, L, i, D.x, D.y, 0.0);
             } else if (D.cplx) {
-                part += apply_row<true, 2, LEARNED ? Ll : Lp>(p, L, i, D.v, D.w, 0.0);
+                part += apply_row<true, 2, LK>(p, L, i, D.v, D.w, 0.0);
             } else {
-                part += apply_row<false, 1, LEARNED ? Ll : Lp>(p, L, i, D.v, D.w, beta);
+                part += apply_row<false, 1, LK>(p, L, i, D.v, D.w, beta);
             }
         }
         if (lanczos) {
             const double s = block_sum(part, scratch);
             if (threadIdx.x == 0) partials[t] = s;
+        }
+    }
+}
+
+// Copy of each sector's input (x, or v in a Lanczos step) into its hashed
+// staging table, tile by tile.
+__global__ void __launch_bounds__(kBatchVecThreads) k_batch_hash_values(const SectorDesc *__restrict__ secs, int nsec,
+                                                                      const int64_t *__restrict__ tile0g,
+                                                                      int64_t ntiles, int64_t tile_rows, int lanczos)
+{
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int sec = sector_of(tile0g, nsec, t);
+        const SectorDesc &D = secs[sec];
+        const int64_t r0 = (t - D.tile0) * tile_rows;
+        const int64_t r1 = min(r0 + tile_rows, D.p.dim);
+        const double *x = lanczos ? D.v : D.x;
+        uint64_t *tab = const_cast<uint64_t *>(D.p.htab);
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+            const uint64_t s = D.pos2slot[i];
+            if (D.cplx) {
+                tab[s * 4 + 1] = (uint64_t)__double_as_longlong(x[2 * i]);
+                tab[s * 4 + 2] = (uint64_t)__double_as_longlong(x[2 * i + 1]);
+            } else {
+                tab[s * 2 + 1] = (uint64_t)__double_as_longlong(x[i]);
+            }
         }
     }
 }
@@ -165,40 +190,57 @@ hipError_t batch_prepare(size_t lds_bytes)
     static size_t granted = 0;
     std::lock_guard<std::mutex> lock(mu);
     if (lds_bytes <= granted) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute((const void *)k_batch_apply<false>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_batch_apply<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds_bytes);
-    if (e == hipSuccess) granted = lds_bytes;
-    return e;
+    const void *ks[] = {(const void *)k_batch_apply<kLookupPlain>, (const void *)k_batch_apply<kLookupLearned>,
+                        (const void *)k_batch_apply<kLookupHash>};
+    for (const void *k : ks) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    granted = lds_bytes;
+    return hipSuccess;
 }
 
 hipError_t batch_occupancy(size_t lds_bytes, int *blocks_per_cu)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)k_batch_apply<false>,
-                                                        kApplyThreads, lds_bytes);
+    // the fewest blocks per compute unit over the lookup kinds
+    const void *ks[] = {(const void *)k_batch_apply<kLookupPlain>, (const void *)k_batch_apply<kLookupLearned>,
+                        (const void *)k_batch_apply<kLookupHash>};
+    int best = 1 << 30;
+    for (const void *k : ks) {
+        int nb = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kApplyThreads, lds_bytes);
+        if (e != hipSuccess) return e;
+        best = std::min(best, nb);
+    }
+    *blocks_per_cu = best;
+    return hipSuccess;
 }
 
 hipError_t launch_batch_apply(const SectorDesc *d_secs, int nsec, const int64_t *d_tile0, int64_t ntiles,
-                              int64_t tile_rows, int lanczos, int learned, double *partials, int blocks, size_t lds,
-                              hipStream_t st)
+                              int64_t tile_rows, int lanczos, int lookup, double *partials, int blocks, size_t lds,
+                              int vec_blocks, hipStream_t st)
 {
-    if (learned)
-        hipLaunchKernelGGL(k_batch_apply<true>, dim3(blocks), dim3(kApplyThreads), lds, st, d_secs, nsec, d_tile0,
-                           ntiles, tile_rows, lanczos, partials);
-    else
-        hipLaunchKernelGGL(k_batch_apply<false>, dim3(blocks), dim3(kApplyThreads), lds, st, d_secs, nsec, d_tile0,
-                           ntiles, tile_rows, lanczos, partials);
+    if (lookup == kLookupHash) {
+        hipLaunchKernelGGL(k_batch_hash_values, dim3(vec_blocks), dim3(kBatchVecThreads), 0, st, d_secs, nsec,
+                           d_tile0, ntiles, tile_rows, lanczos);
+        hipLaunchKernelGGL(k_batch_apply<kLookupHash>, dim3(blocks), dim3(kApplyThreads), lds, st, d_secs, nsec,
+                           d_tile0, ntiles, tile_rows, lanczos, partials);
+    } else if (lookup == kLookupLearned) {
+        hipLaunchKernelGGL(k_batch_apply<kLookupLearned>, dim3(blocks), dim3(kApplyThreads), lds, st, d_secs, nsec,
+                           d_tile0, ntiles, tile_rows, lanczos, partials);
+    } else {
+        hipLaunchKernelGGL(k_batch_apply<kLookupPlain>, dim3(blocks), dim3(kApplyThreads), lds, st, d_secs, nsec,
+                           d_tile0, ntiles, tile_rows, lanczos, partials);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_batch_step(const SectorDesc *d_secs, int nsec, const int64_t *d_tile0, int64_t ntiles,
-                             int64_t tile_rows, int learned, double *partials, int apply_blocks, int vec_blocks,
+                             int64_t tile_rows, int lookup, double *partials, int apply_blocks, int vec_blocks,
                              size_t lds, hipStream_t st)
 {
-    hipError_t e = launch_batch_apply(d_secs, nsec, d_tile0, ntiles, tile_rows, 1, learned, partials, apply_blocks,
-                                      lds, st);
+    hipError_t e = launch_batch_apply(d_secs, nsec, d_tile0, ntiles, tile_rows, 1, lookup, partials, apply_blocks,
+                                      lds, vec_blocks, st);
     if (e != hipSuccess) return e;
     const int fb = (nsec + 63) / 64;
     hipLaunchKernelGGL(k_batch_finalize, dim3(fb), dim3(64), 0, st, d_secs, nsec, partials, 0);

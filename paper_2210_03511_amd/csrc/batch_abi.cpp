@@ -28,7 +28,7 @@ struct ed_batch {
     std::vector<double *> v, w, vprev, alpha, beta;
     LState *d_ls = nullptr;
     int lanczos_cap = 0;
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
     std::vector<void *> allocs;
     ed_batch_info_t info{};
 };
@@ -100,7 +100,10 @@ static ed_status fit_lds(ed_batch *b)
 
 static ed_status check_mode(const ed_batch *b, int mode)
 {
-    if (mode != 0 && mode != 1) return fail(ED_EINVAL, "lookup_mode must be 0 or 1");
+    if (mode < 0 || mode > 2) return fail(ED_EINVAL, "lookup_mode must be 0, 1 or 2");
+    if (mode == 2)
+        for (auto *s : b->secs)
+            if (!s->hashed) return fail(ED_EINVAL, "lookup_mode 2 needs the hashed table in every sector");
     if (mode == 1)
         for (auto *s : b->secs)
             if (!s->indexed) return fail(ED_EINVAL, "lookup_mode 1 needs a trained index in every sector");
@@ -151,6 +154,7 @@ ed_status ed_batch_create(ed_basis *const *sectors, int32_t n, const ed_batch_cf
         SectorDesc &D = b->hdesc[s];
         D = SectorDesc{};
         D.p = make_params(e);
+        D.pos2slot = e->d_pos2slot;
         D.cplx = e->T.is_complex ? 1 : 0;
         b->lds = std::max(b->lds, (size_t)e->lay.bytes);
         total += e->dim;
@@ -253,13 +257,15 @@ ed_status ed_batch_apply(ed_batch *b, const void *const *d_x, void *const *d_y, 
         b->hdesc[s].x = static_cast<const double *>(d_x[s]);
         b->hdesc[s].y = static_cast<double *>(d_y[s]);
         KParams p = make_params(b->secs[s]);
-        if (memcmp(&p, &b->hdesc[s].p, sizeof(KParams))) changed = true;
+        if (memcmp(&p, &b->hdesc[s].p, sizeof(KParams)) || b->hdesc[s].pos2slot != b->secs[s]->d_pos2slot)
+            changed = true;
         b->hdesc[s].p = p;
+        b->hdesc[s].pos2slot = b->secs[s]->d_pos2slot;
     }
     hipStream_t stm = (hipStream_t)stream;
     if (changed) HIP_OK(hipMemcpyAsync(b->d_desc, b->hdesc.data(), n * sizeof(SectorDesc), hipMemcpyHostToDevice, stm));
     HIP_OK(launch_batch_apply(b->d_desc, n, b->d_tile0, b->ntiles, b->tile_rows, 0, lookup_mode, b->d_partials,
-                              b->apply_blocks, b->lds, stm));
+                              b->apply_blocks, b->lds, b->vec_blocks, stm));
     if (changed) HIP_OK(hipStreamSynchronize(stm));  // the host descriptor copy must outlive the transfer
     return ED_OK;
 }
@@ -289,7 +295,10 @@ ed_status ed_batch_lanczos(ed_batch *b, const void *const *d_v0, int32_t n_iter,
                 g = nullptr;
             }
     }
-    for (int s = 0; s < n; ++s) b->hdesc[s].p = make_params(b->secs[s]);
+    for (int s = 0; s < n; ++s) {
+        b->hdesc[s].p = make_params(b->secs[s]);
+        b->hdesc[s].pos2slot = b->secs[s]->d_pos2slot;
+    }
     HIP_OK(hipStreamSynchronize((hipStream_t)stream));
     hipStream_t stm = b->own;
     HIP_OK(hipMemcpyAsync(b->d_desc, b->hdesc.data(), n * sizeof(SectorDesc), hipMemcpyHostToDevice, stm));

@@ -205,3 +205,31 @@ def test_square32_all_sectors(S):
         y = ys[k].cpu().numpy()[idx]
         assert np.max(np.abs(y - (yo if inst.is_complex else yo.real))) < 1e-12, inst.name
     batch.free()
+
+
+def test_batch_hash_lookup(S):
+    """Mode 2 in the batch: every sector's hashed table, same results bit
+    for bit as the plain lookup, for H.v and Lanczos."""
+    torch = _torch()
+    insts = [L.chain16(), L.small_instances()[13], L.small_instances()[14], L.small_instances()[15],
+             L.small_instances()[11]]
+    bases = [S.Basis.build(i) for i in insts]
+    batch = S.Batch(bases, tile_rows=512, autotune=False)
+    xs = [_dev(torch, V.start_vector(b.dim, 9 + k, i.is_complex)) for k, (i, b) in enumerate(zip(insts, bases))]
+    with pytest.raises(S.EdError) as e:
+        batch.apply_H(xs, [torch.zeros_like(x) for x in xs], mode=2)
+    assert e.value.status == S.ED_EINVAL
+    for b in bases:
+        b.build_hash()
+    y0 = [torch.zeros_like(x) for x in xs]
+    y2 = [torch.zeros_like(x) for x in xs]
+    batch.apply_H(xs, y0, mode=0)
+    batch.apply_H(xs, y2, mode=2)
+    torch.cuda.synchronize()
+    for a, b in zip(y0, y2):
+        assert torch.equal(a, b)
+    r0 = batch.lanczos(xs, 30, mode=0)
+    r2 = batch.lanczos(xs, 30, mode=2)
+    for a, b in zip(r0, r2):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    batch.free()
