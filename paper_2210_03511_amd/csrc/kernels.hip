@@ -21,8 +21,11 @@ constexpr int kVecThreads = 256;
 
 // mode 0: y = H x.  mode 1 (real Lanczos): w <- H v - beta_prev w, partial
 // <w|v>.  mode 2 (complex Lanczos): w <- H v, partial Re<w|v>.
+// At least 8 waves per SIMD (two 1024-thread blocks per CU when the tables
+// leave room in LDS): the register budget is capped at 64 per lane, which
+// every variant meets without spilling.
 template <bool CPLX, int MODE, int LK>
-__global__ void __launch_bounds__(kApplyThreads, 2) k_apply(KParams p, const double *__restrict__ x,
+__global__ void __launch_bounds__(kApplyThreads, 8) k_apply(KParams p, const double *__restrict__ x,
                                                        double *__restrict__ y, const LState *ls,
                                                        double *partials)
 {
