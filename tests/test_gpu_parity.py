@@ -319,3 +319,44 @@ def test_lanczos_resume_errors(S):
     assert broken and n == 2
     a2, b2, n2, broken2 = b.lanczos_resume(5)
     assert broken2 and n2 == 0
+
+
+def test_single_state_and_empty_sectors(S):
+    """Degenerate sectors: one state (all spins down: four bonds give +1/4
+    each) and none (k = 1 with all spins down: the character is not trivial
+    on the stabilizer)."""
+    torch = _torch()
+    one = L.chain(4, n_up=0)
+    b = S.Basis.build(one)
+    assert b.dim == 1
+    x = _dev(torch, np.array([2.0]))
+    for mode in (0, 2):
+        if mode == 2:
+            b.build_hash()
+        y = torch.zeros_like(x)
+        b.apply_H(x, y, mode=mode)
+        torch.cuda.synchronize()
+        assert y.item() == 2.0
+    a, beta, n, broken = b.lanczos(x, 5)
+    assert n == 1 and broken and a[0] == pytest.approx(1.0, abs=1e-15)
+    keys = _dev(torch, np.array([0, 1, 5], np.int64))
+    idx = torch.empty_like(keys)
+    b.lookup(keys, idx)
+    torch.cuda.synchronize()
+    assert idx.cpu().tolist() == [0, -1, -1]
+    b.free()
+    empty = L.chain(4, k=1, n_up=0)
+    e = S.Basis.build(empty)
+    assert e.dim == 0 and e.info()["n_elements"] == 0
+    z = torch.zeros(0, dtype=torch.complex128, device="cuda")
+    e.apply_H(z, torch.zeros_like(z))           # nothing to do
+    keys = _dev(torch, np.array([0, 3], np.int64))
+    idx = torch.empty_like(keys)
+    e.lookup(keys, idx)
+    torch.cuda.synchronize()
+    assert idx.cpu().tolist() == [-1, -1]
+    for call in (lambda: e.lanczos(z, 3), lambda: e.build_hash(), lambda: e.train_index(steps=10)):
+        with pytest.raises(S.EdError) as err:
+            call()
+        assert err.value.status == S.ED_EINVAL
+    e.free()
