@@ -43,6 +43,21 @@ ed_status dev_alloc(ed_basis *b, void **ptr, size_t bytes)
     return ED_OK;
 }
 
+// Persistent grids of the apply kernel: as many blocks per compute unit as
+// fit, except for a plain lookup over long Limits windows (more than 64 keys
+// on average) in arrays larger than the 256 MiB last-level cache: its binary
+// searches touch so many lines that a second block per compute unit only
+// thrashes the caches (measured at 40 sites: 2.31 s with one block, 2.78 s
+// with two; at 32 sites, where everything is cached, two blocks are faster).
+static void set_grids(ed_basis *b, int blocks_per_cu)
+{
+    b->cfg.apply_blocks = blocks_per_cu * b->n_cu;
+    b->cfg.lookup_blocks[1] = b->cfg.lookup_blocks[2] = b->cfg.apply_blocks;
+    const double searched = (double)b->dim * sizeof(uint64_t) + (double)((1ull << b->pbits) + 1) * sizeof(uint32_t);
+    const bool thrash = b->limits_mean_window > 64.0 && searched > 256.0 * (1 << 20);
+    b->cfg.lookup_blocks[0] = (thrash ? 1 : blocks_per_cu) * b->n_cu;
+}
+
 KParams make_params(const ed_basis *b)
 {
     KParams p{};
@@ -129,7 +144,7 @@ static ed_status build_impl(const ed_model *model, const ed_group *group, int32_
     HIP_OK(prepare_kernels(p, &bpc, &athreads));
     if (bpc < 1) return fail(ED_EINVAL, "apply kernel does not fit on a compute unit");
     b->cfg.apply_threads = athreads;
-    b->cfg.apply_blocks = bpc * b->n_cu;
+    set_grids(b, bpc);
     b->cfg.vec_blocks = 4 * b->n_cu;
 
     TmpPool tmp;  // temporaries of the build
@@ -189,6 +204,7 @@ static ed_status build_impl(const ed_model *model, const ed_group *group, int32_
         HIP_OK(hipStreamSynchronize(st));
         b->limits_mean_window = b->dim ? (double)hls[0] / (double)b->dim : 0.0;
         b->limits_max_window = (int64_t)hls[1];
+        set_grids(b, b->cfg.apply_blocks / b->n_cu);
     }
 
     // --- element count ----------------------------------------------------
@@ -323,7 +339,8 @@ static ed_status lanczos_workspace(ed_basis *b, int n_iter, int keep)
         if ((s = dev_alloc(b, (void **)&b->d_v, vbytes)) != ED_OK) return s;
         if ((s = dev_alloc(b, (void **)&b->d_w, vbytes)) != ED_OK) return s;
         if (cplx && (s = dev_alloc(b, (void **)&b->d_vprev, vbytes)) != ED_OK) return s;
-        int np = std::max(b->cfg.apply_blocks, b->cfg.vec_blocks);
+        // one partial per 64 rows of the apply kernel, one per block of the vector kernels
+        const int64_t np = std::max<int64_t>((b->dim + 63) / 64, b->cfg.vec_blocks);
         if ((s = dev_alloc(b, (void **)&b->d_partials, np * sizeof(double))) != ED_OK) return s;
         if ((s = dev_alloc(b, (void **)&b->d_ls, sizeof(LState))) != ED_OK) return s;
     }
@@ -360,7 +377,7 @@ static hipError_t enqueue_step(ed_basis *b, int mode, hipStream_t st)
         return e;
     if ((e = launch_apply(p, b->cfg, b->d_v, b->d_w, cplx ? 2 : 1, mode, b->d_ls, b->d_partials, st)) != hipSuccess)
         return e;
-    if ((e = launch_finalize(b->d_partials, b->cfg.apply_blocks, b->d_alpha, b->d_beta, b->d_ls, 0, st)) != hipSuccess)
+    if ((e = launch_finalize(b->d_partials, (b->dim + 63) / 64, b->d_alpha, b->d_beta, b->d_ls, 0, st)) != hipSuccess)
         return e;
     if ((e = launch_axpy_norm(b->d_w, b->d_v, b->d_vprev, b->dim, cplx, b->d_alpha, b->d_ls, b->d_partials,
                               b->cfg.vec_blocks, st)) != hipSuccess)
@@ -633,7 +650,7 @@ ed_status ed_index_train(ed_basis *b, const ed_index_cfg *cfg_in, ed_index_stats
         int bpc = 0, athreads = 0;
         HIP_OK(prepare_kernels(make_params(b), &bpc, &athreads));
         if (bpc < 1) return fail(ED_EINVAL, "tables and network exceed the LDS of one compute unit");
-        b->cfg.apply_blocks = bpc * b->n_cu;
+        set_grids(b, bpc);
     }
     // exact leaf table: ranges, key-space buckets, bucket begins
     if (b->d_leaves && b->log2_leaves != lg) return fail(ED_EINVAL, "index already trained with another leaf count");

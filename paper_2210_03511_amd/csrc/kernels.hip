@@ -20,7 +20,10 @@ namespace {
 constexpr int kVecThreads = 256;
 
 // mode 0: y = H x.  mode 1 (real Lanczos): w <- H v - beta_prev w, partial
-// <w|v>.  mode 2 (complex Lanczos): w <- H v, partial Re<w|v>.
+// <w|v>.  mode 2 (complex Lanczos): w <- H v, partial Re<w|v>.  The partials
+// are one per 64 consecutive rows (partials[i / 64]), so their sum in
+// k_finalize does not depend on the grid: every grid and lookup gives the
+// same Lanczos coefficients.
 // At least 8 waves per SIMD (two 1024-thread blocks per CU when the tables
 // leave room in LDS): the register budget is capped at 64 per lane, which
 // every variant meets without spilling.
@@ -32,15 +35,18 @@ __global__ void __launch_bounds__(kApplyThreads, 8) k_apply(KParams p, const dou
     extern __shared__ __align__(16) unsigned char lds[];
     stage_blob(lds, p.blob, p.lay.bytes);
     const Lds L = lds_view(lds, p.lay);
-    double *scratch = reinterpret_cast<double *>(lds + p.lay.bytes);
     const double beta = (MODE == 1) ? ls->beta_prev : 0.0;
-    double part = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.dim; i += stride)
-        part += apply_row<CPLX, MODE, LK>(p, L, i, x, y, beta);
-    if (MODE != 0) {
-        const double t = block_sum(part, scratch);
-        if (threadIdx.x == 0) partials[blockIdx.x] = t;
+    const int lane = threadIdx.x & 63;
+    // rows of one wave are 64 consecutive rows; the loop is wave-uniform
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane); i0 < p.dim; i0 += stride) {
+        const int64_t i = i0 + lane;
+        double part = 0.0;
+        if (i < p.dim) part = apply_row<CPLX, MODE, LK>(p, L, i, x, y, beta);
+        if (MODE != 0) {
+            part = wave_sum(part);
+            if (lane == 0) partials[i0 >> 6] = part;
+        }
     }
 }
 
@@ -423,11 +429,19 @@ __global__ void __launch_bounds__(kVecThreads) k_scale_copy(const double *src, d
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) dst[i] = src[i] * inv;
 }
 
-// which = 0: alpha[step] = sum; which = 1: beta[step] = sqrt(sum), breakdown check
-__global__ void k_finalize(const double *partials, int nparts, double *alpha, double *beta, LState *ls, int which)
+// which = 0: alpha[step] = sum; which = 1: beta[step] = sqrt(sum), breakdown
+// check.  One block of kFinalizeThreads: thread t adds partials t, t + T,
+// t + 2T, ... in order, then the block sum in a fixed order.
+constexpr int kFinalizeThreads = 1024;
+
+__global__ void __launch_bounds__(kFinalizeThreads) k_finalize(const double *partials, int64_t nparts, double *alpha,
+                                                               double *beta, LState *ls, int which)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double t = sum_partials(partials, nparts);
+    __shared__ double scratch[kFinalizeThreads / 64];
+    double acc = 0.0;
+    for (int64_t k = threadIdx.x; k < nparts; k += blockDim.x) acc += partials[k];
+    const double t = block_sum(acc, scratch);
+    if (threadIdx.x != 0) return;
     const int st = ls->step;
     if (which == 0) {
         alpha[st] = t;
@@ -541,7 +555,7 @@ __global__ void k_lstate_init(LState *ls)
 // launchers
 // ---------------------------------------------------------------------------
 
-size_t apply_lds_bytes(const KParams &p) { return (size_t)p.lay.bytes + 32 * sizeof(double); }
+size_t apply_lds_bytes(const KParams &p) { return (size_t)p.lay.bytes; }
 
 hipError_t launch_enumerate(const KParams &p, const uint64_t *d_binom, uint64_t total, uint64_t chunk_len,
                             uint64_t n_chunks, uint32_t *d_counts, const uint64_t *d_offsets, uint64_t *d_reps,
@@ -639,7 +653,7 @@ hipError_t launch_apply(const KParams &p, const LaunchCfg &c, const void *x, voi
     const size_t lds = apply_lds_bytes(p);
     const double *xd = static_cast<const double *>(x);
     double *yd = static_cast<double *>(y);
-    dim3 g(c.apply_blocks), b(kApplyThreads);
+    dim3 g(c.lookup_blocks[lookup_kind]), b(kApplyThreads);
 #define SYMED_APPLY(C, M, K) hipLaunchKernelGGL((k_apply<C, M, K>), g, b, lds, st, p, xd, yd, ls, partials)
 #define SYMED_APPLY_K(C, M)                                                        \
     do {                                                                           \
@@ -712,10 +726,10 @@ hipError_t launch_scale_copy(const void *src, void *dst, int64_t n, bool cplx, c
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double *partials, int nparts, double *alpha, double *beta, LState *ls, int which,
+hipError_t launch_finalize(const double *partials, int64_t nparts, double *alpha, double *beta, LState *ls, int which,
                            hipStream_t st)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, partials, nparts, alpha, beta, ls, which);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinalizeThreads), 0, st, partials, nparts, alpha, beta, ls, which);
     return hipGetLastError();
 }
 

@@ -16,7 +16,8 @@ struct LState {
 };
 
 struct LaunchCfg {
-    int apply_blocks;   // grid of the apply kernel (persistent, grid-stride)
+    int apply_blocks;      // largest grid of the apply kernel (persistent, grid-stride)
+    int lookup_blocks[3];  // its grid per lookup kind (plain, learned, hashed)
     int apply_threads;  // block size of the apply kernel
     int vec_blocks;     // grid of the streaming vector kernels
 };
@@ -41,7 +42,7 @@ hipError_t launch_lookup(const KParams &p, const uint64_t *keys, int64_t n, int6
 hipError_t launch_norm2_partial(const void *v, int64_t n, bool cplx, double *partials, int blocks, hipStream_t st);
 hipError_t launch_scale_copy(const void *src, void *dst, int64_t n, bool cplx, const double *partials, int nparts,
                              int blocks, hipStream_t st);
-hipError_t launch_finalize(const double *partials, int nparts, double *alpha, double *beta, LState *ls, int which,
+hipError_t launch_finalize(const double *partials, int64_t nparts, double *alpha, double *beta, LState *ls, int which,
                            hipStream_t st);
 hipError_t launch_axpy_norm(void *w, const void *v, const void *vprev, int64_t n, bool cplx, const double *alpha,
                             const LState *ls, double *partials, int blocks, hipStream_t st);
