@@ -92,6 +92,35 @@ __device__ __forceinline__ int64_t hash_find(uint64_t key, const KParams &p)
     }
 }
 
+// x of key from the hashed staging table; false if the key is absent.  Each
+// probe reads the whole record (16 B, or both 16 B halves of a complex
+// record at once), so x arrives with the key that confirms it and is not
+// fetched again after the line may have left the caches.
+template <bool CPLX>
+__device__ __forceinline__ bool hash_get(uint64_t key, const KParams &p, double &xr, double &xi)
+{
+    const uint4 *rec = reinterpret_cast<const uint4 *>(p.htab);
+    uint64_t s = hash_home(key, p.hslots);
+    for (;;) {
+        uint4 a = rec[CPLX ? 2 * s : s];
+        uint4 b = make_uint4(0u, 0u, 0u, 0u);
+        if (CPLX) b = rec[2 * s + 1];
+        // The record's words pass through an empty statement (no code), so
+        // the compiler issues the whole record as one load instead of
+        // deferring the x words to a second load after the key compare.
+        asm("" : "+v"(a.x), "+v"(a.y), "+v"(a.z), "+v"(a.w));
+        if (CPLX) asm("" : "+v"(b.x), "+v"(b.y));
+        const uint64_t k = ((uint64_t)a.y << 32) | a.x;
+        if (k == key) {
+            xr = __hiloint2double((int)a.w, (int)a.z);
+            if (CPLX) xi = __hiloint2double((int)b.y, (int)b.x);
+            return true;
+        }
+        if (k == kHashEmpty) return false;
+        if (++s == p.hslots) s = 0;
+    }
+}
+
 // Amplitude <tau|H_pair|sigma> of the merged pieces flipping pair q of s
 // (s antiparallel on the pair).  Real part: exchange J/2; imaginary part:
 // chirality edges.
@@ -141,7 +170,6 @@ template <bool CPLX, int MODE, int LK>
 __device__ __forceinline__ double apply_row(const KParams &p, const Lds &L, int64_t i, const double *__restrict__ x,
                                             double *__restrict__ y, double beta)
 {
-    constexpr int S = hash_words<CPLX>();
     const uint64_t s = p.reps[i];
     const double isq = L.isqrtt[p.stab[i]];
     double diag = 0.0, ar = 0.0, ai = 0.0;
@@ -171,10 +199,7 @@ __device__ __forceinline__ double apply_row(const KParams &p, const Lds &L, int6
                 const Found f = find_rep(s ^ pt.mask, p, L);
                 double xr, xi = 0.0;
                 if (LK == kLookupHash) {
-                    const int64_t r = hash_find<CPLX>(f.rep, p);
-                    if (r < 0) continue;
-                    xr = __longlong_as_double((long long)p.htab[r * S + 1]);
-                    if (CPLX) xi = __longlong_as_double((long long)p.htab[r * S + 2]);
+                    if (!hash_get<CPLX>(f.rep, p, xr, xi)) continue;
                 } else {
                     const int64_t j = lookup<LK == kLookupLearned>(f.rep, p, L.pw);
                     if (j < 0) continue;
