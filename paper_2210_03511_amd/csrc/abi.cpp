@@ -495,7 +495,10 @@ ed_status ed_hash_build(ed_basis *b, const ed_hash_cfg *cfg_in, ed_hash_stats *o
     if (!b) return fail(ED_EINVAL, "NULL basis");
     ed_hash_cfg cfg{};
     if (cfg_in) cfg = *cfg_in;
-    const double load = cfg.load == 0.0 ? 0.5 : cfg.load;
+    // Default: a quarter of the slots occupied (about 1.17 probes per lookup),
+    // or the smallest load whose slot count still fits in 32 bits.
+    const double load = cfg.load != 0.0 ? cfg.load
+                                         : std::max(0.25, std::ceil((double)b->dim / 4.0e9 * 100.0) / 100.0);
     if (!(load >= 0.05 && load <= 0.95)) return fail(ED_EINVAL, "load must lie in [0.05, 0.95]");
     if (b->T.N >= 64) return fail(ED_EINVAL, "the hashed table needs N < 64 (all-ones marks an empty slot)");
     if (b->dim == 0) return fail(ED_EINVAL, "empty sector");
