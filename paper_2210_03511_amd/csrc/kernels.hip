@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(256) k_enumerate(KParams p, const uint64_t *bi
     stage_blob(lds, p.blob, p.lay.bytes);
     const Lds L = lds_view(lds, p.lay);
     const int N = p.N, R = p.R, br = p.br, A = p.A, ba = p.ba;
-    const uint32_t S = 1u << br, mr = S - 1u;
+    const uint32_t S = 1u << br, mr = S - 1u, ma = (1u << ba) - 1u;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_chunks; c += stride) {
         const uint64_t r0 = c * len;
@@ -261,9 +261,9 @@ __global__ void __launch_bounds__(256) k_enumerate(KParams p, const uint64_t *bi
                 for (uint32_t q = L.symoff[idx]; q < k1; ++q) {
                     const uint32_t e = L.symlist[q];
                     const uint32_t sp = e >> 1;
-                    const uint16_t *en = L.aent + (size_t)sp * A;
+                    const uint32_t *en = L.aent + (size_t)sp * A;
                     uint64_t v = 0;
-                    for (int d = 0; d < A; ++d) v = (v << ba) | act_image(en, L.atab, s, d, N, ba);
+                    for (int d = 0; d < A; ++d) v = (v << ba) | act_image(en, L.atab, s, d, ma);
                     if (e & 1u) v ^= p.maskN;
                     if (v < s) {
                         isrep = false;

@@ -16,7 +16,7 @@ struct Lds {
     const uint16_t *symoff;
     const uint16_t *symlist;    // symmetry codes (sp << 1) | flip
     const uint16_t *atab;   // distinct SymmetryAction tables, 2^ba entries each
-    const uint16_t *aent;   // [n_sp][A]: (table << 4) | source sublattice
+    const uint32_t *aent;   // [n_sp][A]: (offset of the table in atab << 8) | shift of the source substate
     const PairTerm *pairs;
     const ChiTerm *chis;
     const double *chi;
@@ -33,7 +33,7 @@ __host__ __device__ __forceinline__ Lds lds_view(const unsigned char *b, const B
     v.symoff = reinterpret_cast<const uint16_t *>(b + L.off_symoff);
     v.symlist = reinterpret_cast<const uint16_t *>(b + L.off_symlist);
     v.atab = reinterpret_cast<const uint16_t *>(b + L.off_atab);
-    v.aent = reinterpret_cast<const uint16_t *>(b + L.off_aent);
+    v.aent = reinterpret_cast<const uint32_t *>(b + L.off_aent);
     v.pairs = reinterpret_cast<const PairTerm *>(b + L.off_pairs);
     v.chis = reinterpret_cast<const ChiTerm *>(b + L.off_chis);
     v.chi = reinterpret_cast<const double *>(b + L.off_chi);
@@ -45,15 +45,15 @@ __host__ __device__ __forceinline__ Lds lds_view(const unsigned char *b, const B
 }
 
 // Substate that a symmetry puts at fine destination d of the configuration
-// t (spin flip not applied); en: the symmetry's A entries (table << 4) |
-// source sublattice.
-__host__ __device__ __forceinline__ uint32_t act_image(const uint16_t *en, const uint16_t *atab, uint64_t t, int d,
-                                                      int N, int ba)
+// t (spin flip not applied); en: the symmetry's A entries, each the offset
+// of its table in atab (<< 8) and the right shift that brings the source
+// substate of t to the low bits.
+__host__ __device__ __forceinline__ uint32_t act_image(const uint32_t *en, const uint16_t *atab, uint64_t t, int d,
+                                                      uint32_t ma)
 {
     const uint32_t ent = en[d];
-    const uint32_t x = ent & 15u;
-    const uint32_t ss = (uint32_t)(t >> (N - (int)(x + 1) * ba)) & ((1u << ba) - 1u);
-    return atab[((ent >> 4) << ba) + ss];
+    const uint32_t ss = (uint32_t)(t >> (ent & 63u)) & ma;
+    return atab[(ent >> 8) + ss];
 }
 
 struct Found {
@@ -97,12 +97,12 @@ __host__ __device__ __forceinline__ Found find_rep(uint64_t t, const KParams &p,
             const uint32_t e = L.symlist[k];
             const uint32_t sp = e >> 1;
             const uint32_t fm = (e & 1u) ? ma : 0u;  // spin flip complements every substate
-            const uint16_t *en = L.aent + (size_t)sp * A;
+            const uint32_t *en = L.aent + (size_t)sp * A;
             uint64_t v = minrep;
             uint64_t bp = 0;
             int d = d0;
             for (; d < A; ++d) {
-                v = (v << ba) | (act_image(en, L.atab, t, d, N, ba) ^ fm);
+                v = (v << ba) | (act_image(en, L.atab, t, d, ma) ^ fm);
                 bp = best >> ((A - 1 - d) * ba);
                 if (v != bp) break;
             }
@@ -119,7 +119,7 @@ __host__ __device__ __forceinline__ Found find_rep(uint64_t t, const KParams &p,
                 continue;
             }
             if (v > bp) continue;
-            for (++d; d < A; ++d) v = (v << ba) | (act_image(en, L.atab, t, d, N, ba) ^ fm);
+            for (++d; d < A; ++d) v = (v << ba) | (act_image(en, L.atab, t, d, ma) ^ fm);
             best = v;
             bg = e;
             cnt = 1;
