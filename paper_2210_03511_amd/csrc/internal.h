@@ -70,6 +70,7 @@ struct HostTables {
 struct BlobLayout {
     uint32_t off_rep, off_symoff, off_symlist, off_atab, off_aent, off_pairs, off_chis, off_chi, off_sqrt, off_isqrt,
         off_chione, off_mlp;
+    uint32_t aent_lg;    // log2 of the row stride (entries) of the SymmetryAction entries
     uint32_t bytes;      // staged into LDS: up to the network pieces in use
     uint32_t reserved;   // allocated: room for the largest network expansion
 };

@@ -261,7 +261,7 @@ __global__ void __launch_bounds__(256) k_enumerate(KParams p, const uint64_t *bi
                 for (uint32_t q = L.symoff[idx]; q < k1; ++q) {
                     const uint32_t e = L.symlist[q];
                     const uint32_t sp = e >> 1;
-                    const uint32_t *en = L.aent + (size_t)sp * A;
+                    const uint32_t *en = L.aent + ((size_t)sp << L.aent_lg);
                     uint64_t v = 0;
                     for (int d = 0; d < A; ++d) v = (v << ba) | act_image(en, L.atab, s, d, ma);
                     if (e & 1u) v ^= p.maskN;

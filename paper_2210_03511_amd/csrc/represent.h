@@ -16,7 +16,8 @@ struct Lds {
     const uint16_t *symoff;
     const uint16_t *symlist;    // symmetry codes (sp << 1) | flip
     const uint16_t *atab;   // distinct SymmetryAction tables, 2^ba entries each
-    const uint32_t *aent;   // [n_sp][A]: (offset of the table in atab << 8) | shift of the source substate
+    const uint32_t *aent;   // [n_sp][2^aent_lg >= A]: (offset of the table in atab << 8) | shift of the source substate
+    uint32_t aent_lg;
     const PairTerm *pairs;
     const ChiTerm *chis;
     const double *chi;
@@ -34,6 +35,7 @@ __host__ __device__ __forceinline__ Lds lds_view(const unsigned char *b, const B
     v.symlist = reinterpret_cast<const uint16_t *>(b + L.off_symlist);
     v.atab = reinterpret_cast<const uint16_t *>(b + L.off_atab);
     v.aent = reinterpret_cast<const uint32_t *>(b + L.off_aent);
+    v.aent_lg = L.aent_lg;
     v.pairs = reinterpret_cast<const PairTerm *>(b + L.off_pairs);
     v.chis = reinterpret_cast<const ChiTerm *>(b + L.off_chis);
     v.chi = reinterpret_cast<const double *>(b + L.off_chi);
@@ -74,11 +76,17 @@ __host__ __device__ __forceinline__ Found find_rep(uint64_t t, const KParams &p,
 {
     const int N = p.N, R = p.R, br = p.br, A = p.A, ba = p.ba;
     const uint32_t S = 1u << br, mr = S - 1u, ma = (1u << ba) - 1u;
-    uint32_t minrep = 0xffffffffu;
+    // MinRep, and in xm the coarse sublattices that attain it (R <= 16)
+    uint32_t minrep = 0xffffffffu, xm = 0;
     for (int X = 0; X < R; ++X) {
         uint32_t s = (uint32_t)(t >> (N - (X + 1) * br)) & mr;
         const uint32_t r = L.rep[X * S + s];
-        minrep = r < minrep ? r : minrep;
+        if (r < minrep) {
+            minrep = r;
+            xm = 1u << X;
+        } else if (r == minrep) {
+            xm |= 1u << X;
+        }
     }
     // Every candidate maps its sublattice onto the most significant coarse
     // sublattice with image MinRep, so the fine destinations 0..d0-1 agree
@@ -88,16 +96,17 @@ __host__ __device__ __forceinline__ Found find_rep(uint64_t t, const KParams &p,
     const int d0 = A / R;
     uint64_t best = ~0ull;
     uint32_t bg = 0, cnt = 0;
-    for (int X = 0; X < R; ++X) {
+    while (xm) {
+        const int X = __builtin_ctz(xm);
+        xm &= xm - 1u;
         uint32_t s = (uint32_t)(t >> (N - (X + 1) * br)) & mr;
         uint32_t idx = X * S + s;
-        if (L.rep[idx] != minrep) continue;
         const uint32_t k1 = L.symoff[idx + 1];
         for (uint32_t k = L.symoff[idx]; k < k1; ++k) {
             const uint32_t e = L.symlist[k];
             const uint32_t sp = e >> 1;
             const uint32_t fm = (e & 1u) ? ma : 0u;  // spin flip complements every substate
-            const uint32_t *en = L.aent + (size_t)sp * A;
+            const uint32_t *en = L.aent + ((size_t)sp << L.aent_lg);
             uint64_t v = minrep;
             uint64_t bp = 0;
             int d = d0;

@@ -336,7 +336,10 @@ std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &L)
     L.off_symoff = (uint32_t)o;  o = align16(o + T.sym_off.size() * sizeof(uint16_t));
     L.off_symlist = (uint32_t)o; o = align16(o + T.sym_list.size() * sizeof(uint16_t));
     L.off_atab = (uint32_t)o;    o = align16(o + T.act_tab.size() * sizeof(uint16_t));
-    L.off_aent = (uint32_t)o;    o = align16(o + T.act_ent.size() * sizeof(uint32_t));
+    // entry rows padded to a power-of-two stride (a shift instead of a multiply)
+    L.aent_lg = 0;
+    while ((1 << L.aent_lg) < T.A) ++L.aent_lg;
+    L.off_aent = (uint32_t)o;    o = align16(o + ((size_t)T.n_sp << L.aent_lg) * sizeof(uint32_t));
     L.off_pairs = (uint32_t)o;   o = align16(o + T.pairs.size() * sizeof(PairTerm));
     L.off_chis = (uint32_t)o;    o = align16(o + T.chis.size() * sizeof(ChiTerm));
     L.off_chi = (uint32_t)o;     o = align16(o + (size_t)2 * T.n_sp * sizeof(double) * (T.is_complex ? 2 : 1));
@@ -359,11 +362,12 @@ std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &L)
     put(L.off_atab, T.act_tab.data(), T.act_tab.size() * sizeof(uint16_t));
     // device form of the entries: table offset in atab << 8 | right shift of
     // the source substate (offsets < 4096 << 12 = 2^24, shifts < 64)
-    std::vector<uint32_t> ent32(T.act_ent.size());
-    for (size_t k = 0; k < T.act_ent.size(); ++k) {
-        const uint32_t e = T.act_ent[k], X = e & 15u;
-        ent32[k] = (((e >> 4) << T.ba) << 8) | (uint32_t)(T.N - (int)(X + 1) * T.ba);
-    }
+    std::vector<uint32_t> ent32((size_t)T.n_sp << L.aent_lg, 0u);
+    for (int sp = 0; sp < T.n_sp; ++sp)
+        for (int d = 0; d < T.A; ++d) {
+            const uint32_t e = T.act_ent[(size_t)sp * T.A + d], X = e & 15u;
+            ent32[((size_t)sp << L.aent_lg) + d] = (((e >> 4) << T.ba) << 8) | (uint32_t)(T.N - (int)(X + 1) * T.ba);
+        }
     put(L.off_aent, ent32.data(), ent32.size() * sizeof(uint32_t));
     put(L.off_pairs, T.pairs.data(), T.pairs.size() * sizeof(PairTerm));
     put(L.off_chis, T.chis.data(), T.chis.size() * sizeof(ChiTerm));
