@@ -121,6 +121,10 @@ def lib():
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"symed HIP library not built: {LIB_PATH} missing (run __graft_entry__.build())")
+        # torch first: its HIP runtime (same soname, libamdhip64.so.7) is then
+        # the one the library binds to, so the library and the tensors handed
+        # to it share one runtime whichever of the two a program touches first.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         L.ed_last_error.restype = ctypes.c_char_p

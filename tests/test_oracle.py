@@ -254,6 +254,41 @@ def test_chain16_ground_state_value():
     assert e0 == pytest.approx(full0, abs=1e-10)
 
 
+# --- tower of states ------------------------------------------------------------
+
+def _tos_label(inst):
+    q = tuple(inst.meta["q"])
+    name = {(0, 0): "Gamma", (0.5, 0.5): "M"}.get((float(q[0]), float(q[1])), str(q))
+    return f"{name}.A1" if inst.meta["irrep"] == 0 else f"{name}.ir{inst.meta['irrep']}"
+
+
+def test_tower_of_states_square16_neel_table():
+    """The lowest level of each total spin S of the 4 x 4 Heisenberg
+    antiferromagnet carries the irrep the thesis's Neel tower-of-states table
+    assigns to it (Gamma.A1 for even S, M.A1 for odd S).  The lowest level at
+    Sz = S is the lowest of spin S because E_min(Sz) rises with Sz; the
+    minimum over the one-dimensional sectors equals the full Sz-sector
+    minimum, so no two-dimensional irrep holds a lower level."""
+    g = GOLD["tos_neel_square"]
+    emin = []
+    for S in g["S"]:
+        rows = []
+        for inst in L.square16_sectors(J2=0.0, n_up=8 + S):
+            reps, stabs = O.enumerate_basis(inst)
+            if len(reps):
+                rows.append((np.linalg.eigvalsh(O.coo_matrix(inst, reps, stabs).toarray())[0], inst))
+        rows.sort(key=lambda r: r[0])
+        e0, inst0 = rows[0]
+        expect = [k for k, m in g["multiplicity"].items() if m[g["S"].index(S)] == 1]
+        assert [_tos_label(inst0)] == expect
+        assert rows[1][0] > e0 + 1e-6                      # the lowest level is not degenerate across sectors
+        _, Hs = O.unsym_sector_matrix(inst0)               # same model and Sz, trivial group
+        full0 = scipy.sparse.linalg.eigsh(Hs, k=1, which="SA")[0][0]
+        assert e0 == pytest.approx(full0, abs=1e-9)
+        emin.append(e0)
+    assert all(a < b for a, b in zip(emin, emin[1:]))
+
+
 # --- learned-index network reference -----------------------------------------
 
 def test_mlp_gradient_central_differences():

@@ -354,7 +354,8 @@ def square_j1j2(L1, L2, J1, J2, q, irrep="A1", flip=1, sublat_chain=None, mirror
                     tris=np.zeros((0, 3), np.int32), tri_Jchi=np.zeros(0), n_up=n // 2 if n_up is None else n_up,
                     perms=perms, flips=flips, chi=chis, sublat_options=lat.sublat_options,
                     sector=f"q={tuple(map(str, q))}.{irrep}.{_flipname(flip)}",
-                    meta=dict(lattice=lat, little=little, q=q))
+                    meta=dict(lattice=lat, little=little, q=q, irrep=0 if irrep in ("A", "A1") else irrep,
+                              flip=flip))
 
 
 def triangular_j1j2chi(L1, L2, J1, J2, Jchi, q, irrep="A", flip=1, sublat_chain=None, mirrors=None,
@@ -474,11 +475,18 @@ def tri36_K(J2=0.1, Jchi=0.2, flip=1, sublat_chain=TRI36_CHAIN):
     return inst
 
 
-def square32_sectors(J2=0.5):
-    """Every one-dimensional sector (k orbit x 1-D irrep of L_k x flip parity)
-    of the 32-site square J1-J2 model at Sz=0.  Two-dimensional irreps of the
-    little group are outside the one-dimensional method and not listed."""
-    lat = square_lattice(SQ32_L[0], SQ32_L[1], SQ32_CHAIN)
+def square_sectors(L, chain, J2=0.5, n_up=None, name="square"):
+    """Every one-dimensional sector (k orbit x 1-D irrep of L_k, x flip parity
+    at Sz = 0) of the square J1-J2 model (J1 = 1) on the torus L at the given
+    number of up spins.  Away from Sz = 0 the spin flip is not a symmetry of
+    the sector, so it is left out of the group.  Two-dimensional irreps of the
+    little group are outside the one-dimensional method and not listed.
+    ``meta`` of each instance holds q, the irrep index (0 = A1, the trivial
+    irrep) and the flip parity (None away from Sz = 0)."""
+    lat = square_lattice(L[0], L[1], chain)
+    n = lat.N
+    n_up = n // 2 if n_up is None else n_up
+    flips = (1, -1) if 2 * n_up == n else (None,)
     seen = set()
     out = []
     for q in lat.momenta():
@@ -487,12 +495,28 @@ def square32_sectors(J2=0.5):
         seen |= _pg_orbit(lat, q)
         little = lat.little_group(q)
         for ir_i, _ in enumerate(one_dim_irreps(little)):
-            for fl in (1, -1):
-                inst = square_j1j2(SQ32_L[0], SQ32_L[1], 1.0, J2, q, irrep=ir_i, flip=fl,
-                                   sublat_chain=SQ32_CHAIN)
-                inst.name = f"square32_q{float(q[0]):.3f}_{float(q[1]):.3f}_ir{ir_i}_{_flipname(fl)}"
+            for fl in flips:
+                inst = square_j1j2(L[0], L[1], 1.0, J2, q, irrep=ir_i, flip=fl, sublat_chain=chain, n_up=n_up)
+                inst.name = (f"{name}{n}_Sz{Fraction(2 * n_up - n, 2)}_q{float(q[0]):.3f}_{float(q[1]):.3f}_ir{ir_i}"
+                             + ("" if fl is None else f"_{_flipname(fl)}"))
                 out.append(inst)
     return out
+
+
+def square32_sectors(J2=0.5, n_up=None):
+    """Every one-dimensional sector of the 32-site square J1-J2 model."""
+    out = square_sectors(SQ32_L, SQ32_CHAIN, J2, n_up)
+    if n_up is None:
+        for inst in out:
+            q = inst.meta["q"]
+            inst.name = (f"square32_q{float(q[0]):.3f}_{float(q[1]):.3f}_ir{inst.meta['irrep']}_"
+                         f"{_flipname(inst.meta['flip'])}")
+    return out
+
+
+def square16_sectors(J2=0.0, n_up=None):
+    """Every one-dimensional sector of the 16-site (4 x 4) square J1-J2 model."""
+    return square_sectors(SQ16_L, SQ16_CHAIN, J2, n_up)
 
 
 # ---------------------------------------------------------------------------
