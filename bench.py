@@ -226,8 +226,9 @@ def main_batch(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one MI355X; --gpus {args.gpus} is not supported in this build "
-              f"(the multi-GPU design is described in DESIGN.md but not implemented).", file=sys.stderr)
+        print(f"bench.py measures one MI355X; --gpus {args.gpus} is not supported: the library runs on one GPU "
+              f"(rows would shard by contiguous blocks with an all-gather of the new vector per step, which is "
+              f"not implemented).", file=sys.stderr)
         sys.exit(2)
     if args.config == "square32_batch":
         return main_batch(args)
