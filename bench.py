@@ -191,7 +191,7 @@ def main_batch(args):
     name = {0: "plain", 1: "learned", 2: "hash"}.get
     dims = [inf["dim"] for inf in infos]
     out = {
-        "metric": "H.v elements/s & s per Lanczos step, batched sectors: learned vs plain lookup",
+        "metric": "H\u00b7v elements/s & s per Lanczos step, batched sectors: learned vs plain lookup",
         "value": n_el / step_t[best],
         "unit": "elements/s",
         "n_gpus": 1,
@@ -310,8 +310,9 @@ def main():
     alg_bytes = alg_bytes_of(D, n_off, cplx)
     t_apply = apply_t[best]
     achieved = alg_bytes / t_apply / 1e9
+    traffic = recorded_traffic(args.config, best)
     out = {
-        "metric": "H.v elements/s & s per Lanczos step, 40-site square: learned vs plain lookup",
+        "metric": "H\u00b7v elements/s & s per Lanczos step, 40-site square: learned vs plain lookup",
         "value": n_el / step_t[best],
         "unit": "elements/s",
         "n_gpus": 1,
@@ -336,9 +337,12 @@ def main():
                                "learned_mean": train["mean_window"] if train else None,
                                "learned_max": train["max_err"] if train else None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(args.config, best),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"k_apply ({name[best]} lookup)", "alg_bytes_per_launch": alg_bytes,
-                     "avg_launch_s": t_apply},
+                     "avg_launch_s": t_apply,
+                     # algorithmic bytes over counted HBM bytes, and the counted rate
+                     "gather_efficiency": None if traffic is None else alg_bytes / traffic,
+                     "counted_GBps": None if traffic is None else traffic / t_apply / 1e9},
     }
     if train is not None:
         out["learned_index"] = train

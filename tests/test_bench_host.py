@@ -1,0 +1,38 @@
+"""Host-side pieces of the benchmark (no GPU): refusal of several GPUs,
+the algorithmic byte count and the guard on recorded hardware counters."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one MI355X" in r.stderr and not r.stdout.strip()
+
+
+def test_algorithmic_bytes():
+    # per row: rep 8 + stabilizer 2 + x_i + y_i; per off-diagonal element: x_j + rep_j
+    assert bench.alg_bytes_of(10, 100, False) == 10 * 26 + 100 * 16
+    assert bench.alg_bytes_of(10, 100, True) == 10 * 42 + 100 * 24
+
+
+def test_recorded_traffic_only_for_matching_sources(tmp_path, monkeypatch):
+    rec = {"config": "square40", "sources_sha256": bench.kernel_sources_sha256(), "fetch_factor": 2.0,
+           "write_factor": 1.0, "kernels": {"hash": {"fetch_kib": 10.0, "write_kib": 3.0}}}
+    p = tmp_path / "c.json"
+    p.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "COUNTERS", str(p))
+    assert bench.recorded_traffic("square40", 2) == (10.0 * 2.0 + 3.0) * 1024.0
+    assert bench.recorded_traffic("square40", 0) is None          # no record for this lookup
+    assert bench.recorded_traffic("triangular36", 2) is None      # another workload
+    rec["sources_sha256"] = "0" * 64
+    p.write_text(json.dumps(rec))
+    assert bench.recorded_traffic("square40", 2) is None          # sources changed since the counters
