@@ -87,7 +87,17 @@ KParams make_params(const ed_basis *b)
     p.has_index = b->indexed ? 1 : 0;
     p.htab = b->d_htab;
     p.hslots = b->hslots;
+    p.lrec = b->d_lrec;
     return p;
+}
+
+hipError_t stage_input(const ed_basis *b, int lookup_mode, const void *d_x, hipStream_t st)
+{
+    if (lookup_mode == 2)
+        return launch_hash_values(b->d_htab, b->d_pos2slot, d_x, b->dim, b->T.is_complex, b->cfg.vec_blocks, st);
+    if (lookup_mode == 1 && b->d_lrec)
+        return launch_hash_values(b->d_lrec, nullptr, d_x, b->dim, b->T.is_complex, b->cfg.vec_blocks, st);
+    return hipSuccess;
 }
 
 static uint64_t binom64(int n, int k)
@@ -301,9 +311,7 @@ ed_status ed_apply_H(const ed_basis *b, const void *d_x, void *d_y, int32_t look
     if (b->dim == 0) return ED_OK;
     if (!d_x || !d_y) return fail(ED_EINVAL, "NULL vector");
     if (d_x == d_y) return fail(ED_EINVAL, "x and y must not alias");
-    if (lookup_mode == 2)
-        HIP_OK(launch_hash_values(b->d_htab, b->d_pos2slot, d_x, b->dim, b->T.is_complex, b->cfg.vec_blocks,
-                                  (hipStream_t)stream));
+    HIP_OK(stage_input(b, lookup_mode, d_x, (hipStream_t)stream));
     KParams p = make_params(b);
     HIP_OK(launch_apply(p, b->cfg, d_x, d_y, 0, lookup_mode, nullptr, nullptr, (hipStream_t)stream));
     return ED_OK;
@@ -372,9 +380,7 @@ static hipError_t enqueue_step(ed_basis *b, int mode, hipStream_t st)
     const bool cplx = b->T.is_complex;
     KParams p = make_params(b);
     hipError_t e;
-    if (mode == 2 &&
-        (e = launch_hash_values(b->d_htab, b->d_pos2slot, b->d_v, b->dim, cplx, b->cfg.vec_blocks, st)) != hipSuccess)
-        return e;
+    if ((e = stage_input(b, mode, b->d_v, st)) != hipSuccess) return e;
     if ((e = launch_apply(p, b->cfg, b->d_v, b->d_w, cplx ? 2 : 1, mode, b->d_ls, b->d_partials, st)) != hipSuccess)
         return e;
     if ((e = launch_finalize(b->d_partials, (b->dim + 63) / 64, b->d_alpha, b->d_beta, b->d_ls, 0, st)) != hipSuccess)
@@ -692,6 +698,14 @@ ed_status ed_index_train(ed_basis *b, const ed_index_cfg *cfg_in, ed_index_stats
             (void)hipGraphExecDestroy(g);
             g = nullptr;
         }
+    if (!b->d_lrec && !b->T.is_complex) {
+        // records {rep, x} in basis order (real sectors): the H.v gather
+        // reads x_j from the record its search ends on
+        const size_t words = 2;
+        if ((s = dev_alloc(b, (void **)&b->d_lrec, (size_t)b->dim * words * sizeof(uint64_t))) != ED_OK) return s;
+        HIP_OK(launch_lrec_keys(b->d_lrec, b->d_reps, b->dim, b->T.is_complex, b->cfg.vec_blocks, st));
+        HIP_OK(hipStreamSynchronize(st));
+    }
     b->indexed = true;
     b->log2_leaves = lg;
     b->mlp_F = F;

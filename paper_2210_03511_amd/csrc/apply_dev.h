@@ -66,7 +66,7 @@ __device__ __forceinline__ int64_t lookup_plain(uint64_t key, const KParams &p)
     return (lo < end && p.reps[lo] == key) ? (int64_t)lo : -1;
 }
 
-// Index of a representative: plain Limits + binary search, or the learned
+// Index of a representative (ed_lookup): plain Limits + binary search, or the learned
 // index (network in LDS, leaf table, bounded binary search).
 template <bool LEARNED>
 __device__ __forceinline__ int64_t lookup(uint64_t key, const KParams &p, const PwView &pw)
@@ -121,6 +121,42 @@ __device__ __forceinline__ bool hash_get(uint64_t key, const KParams &p, double 
     }
 }
 
+// x of key through the learned index (network -> leaf -> key-space bucket,
+// as in lookup_learned) over the records {rep, x} kept in basis order (real
+// sectors): the
+// binary search compares the record keys, and the record it ends on is read
+// whole, so x comes with the key that confirms the match.  false if absent.
+template <bool CPLX>
+__device__ __forceinline__ bool learned_get(uint64_t key, const KParams &p, const PwView &pw, double &xr, double &xi)
+{
+    constexpr int S = hash_words<CPLX>();
+    const float y = pw_eval(pw, key_feature(key, p.N));
+    uint32_t b;
+    float frac;
+    leaf_of(y, p.log2_leaves, b, frac);
+    const Leaf L = static_cast<const Leaf *>(p.leaves)[b];
+    if (L.lo >= L.hi) return false;
+    const uint32_t q = leaf_bucket(L, key);
+    uint32_t lo = p.sub[L.off + q], hi = p.sub[L.off + q + 1];
+    const uint32_t end = hi;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (p.lrec[(uint64_t)mid * S] < key) lo = mid + 1; else hi = mid;
+    }
+    if (lo >= end) return false;
+    const uint4 *rec = reinterpret_cast<const uint4 *>(p.lrec);
+    uint4 a = rec[CPLX ? 2 * (uint64_t)lo : lo];
+    uint4 c = make_uint4(0u, 0u, 0u, 0u);
+    if (CPLX) c = rec[2 * (uint64_t)lo + 1];
+    // whole-record load (see hash_get)
+    asm("" : "+v"(a.x), "+v"(a.y), "+v"(a.z), "+v"(a.w));
+    if (CPLX) asm("" : "+v"(c.x), "+v"(c.y));
+    if ((((uint64_t)a.y << 32) | a.x) != key) return false;
+    xr = __hiloint2double((int)a.w, (int)a.z);
+    if (CPLX) xi = __hiloint2double((int)c.y, (int)c.x);
+    return true;
+}
+
 // Amplitude <tau|H_pair|sigma> of the merged pieces flipping pair q of s
 // (s antiparallel on the pair).  Real part: exchange J/2; imaginary part:
 // chirality edges.
@@ -163,9 +199,12 @@ __device__ __forceinline__ double block_sum(double v, double *scratch)
 // coefficient * x_j (gather; only this lane writes y_i).  mode 0 writes
 // y_i; mode 1 (real Lanczos) writes w_i = (H v)_i - beta w_i and returns
 // w_i v_i; mode 2 (complex Lanczos) writes w_i = (H v)_i and returns
-// Re(conj(w_i) v_i).  LK: kLookupPlain / kLookupLearned find j and read
-// x_j from x; kLookupHash finds the record of the target in the staging
-// table, whose copy of x_j sits beside the key that confirms the match.
+// Re(conj(w_i) v_i).  LK: kLookupPlain finds j and reads x_j from x;
+// kLookupHash finds the record of the target in the hashed staging table,
+// and kLookupLearned (real sectors) in the records kept in basis order; the
+// record's copy of x_j sits beside the key that confirms the match.  Complex
+// sectors search the learned index over the representatives and read x_j
+// from x: their 32 B records would spread the search over 4x the lines.
 template <bool CPLX, int MODE, int LK>
 __device__ __forceinline__ double apply_row(const KParams &p, const Lds &L, int64_t i, const double *__restrict__ x,
                                             double *__restrict__ y, double beta)
@@ -200,6 +239,8 @@ __device__ __forceinline__ double apply_row(const KParams &p, const Lds &L, int6
                 double xr, xi = 0.0;
                 if (LK == kLookupHash) {
                     if (!hash_get<CPLX>(f.rep, p, xr, xi)) continue;
+                } else if (LK == kLookupLearned && !CPLX) {
+                    if (!learned_get<CPLX>(f.rep, p, L.pw, xr, xi)) continue;
                 } else {
                     const int64_t j = lookup<LK == kLookupLearned>(f.rep, p, L.pw);
                     if (j < 0) continue;

@@ -43,6 +43,7 @@ struct ed_basis {
     hipGraphExec_t step_graph[3] = {nullptr, nullptr, nullptr};
     // learned index
     bool indexed = false;
+    uint64_t *d_lrec = nullptr;   // {rep, x} records in basis order for the learned lookup (real sectors)
     float *d_params = nullptr;
     void *d_leaves = nullptr;
     uint32_t *d_sub = nullptr;
@@ -80,6 +81,9 @@ struct TmpPool {
     }
 };
 symed::KParams make_params(const ed_basis *b);
+// Copy of the H.v input into the records of lookup mode 1 (basis order, real
+// sectors) or 2 (hashed table); nothing otherwise.
+hipError_t stage_input(const ed_basis *b, int lookup_mode, const void *d_x, hipStream_t st);
 ed_status lanczos_prepare(ed_basis *b, int n_iter, int lookup_mode, int keep);
 ed_status lanczos_advance(ed_basis *b, int done, int n, int lookup_mode, double *h_alpha, double *h_beta,
                           int32_t *n_done);

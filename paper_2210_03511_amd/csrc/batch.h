@@ -27,8 +27,8 @@ struct SectorDesc {
 
 hipError_t batch_prepare(size_t lds_bytes);
 hipError_t batch_occupancy(size_t lds_bytes, int *blocks_per_cu);
-// lookup: 0 plain, 1 learned, 2 hashed staging table (the input vectors are
-// copied into the sectors' tables first)
+// lookup: 0 plain, 1 learned, 2 hashed staging table (for 1 and 2 the input
+// vectors are copied into the sectors' records first)
 hipError_t launch_batch_apply(const SectorDesc *d_secs, int nsec, const int64_t *d_tile0, int64_t ntiles,
                               int64_t tile_rows, int lanczos, int lookup, double *partials, int blocks, size_t lds,
                               int vec_blocks, hipStream_t st);

@@ -78,11 +78,14 @@ __global__ void __launch_bounds__(kApplyThreads) k_batch_apply(const SectorDesc 
     }
 }
 
-// Copy of each sector's input (x, or v in a Lanczos step) into its hashed
-// staging table, tile by tile.
+// Copy of each sector's input (x, or v in a Lanczos step) into its records,
+// tile by tile: the hashed staging table (lookup kind 2, slot pos2slot[i])
+// or the learned lookup's records in basis order (kind 1, slot i; real
+// sectors only).
 __global__ void __launch_bounds__(kBatchVecThreads) k_batch_hash_values(const SectorDesc *__restrict__ secs, int nsec,
                                                                       const int64_t *__restrict__ tile0g,
-                                                                      int64_t ntiles, int64_t tile_rows, int lanczos)
+                                                                      int64_t ntiles, int64_t tile_rows, int lanczos,
+                                                                      int lookup)
 {
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int sec = sector_of(tile0g, nsec, t);
@@ -90,9 +93,11 @@ __global__ void __launch_bounds__(kBatchVecThreads) k_batch_hash_values(const Se
         const int64_t r0 = (t - D.tile0) * tile_rows;
         const int64_t r1 = min(r0 + tile_rows, D.p.dim);
         const double *x = lanczos ? D.v : D.x;
-        uint64_t *tab = const_cast<uint64_t *>(D.p.htab);
+        const bool hashed = lookup == kLookupHash;
+        uint64_t *tab = const_cast<uint64_t *>(hashed ? D.p.htab : D.p.lrec);
+        if (!tab) continue;  // complex sector under the learned lookup: no records
         for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-            const uint64_t s = D.pos2slot[i];
+            const uint64_t s = hashed ? (uint64_t)D.pos2slot[i] : (uint64_t)i;
             if (D.cplx) {
                 tab[s * 4 + 1] = (uint64_t)__double_as_longlong(x[2 * i]);
                 tab[s * 4 + 2] = (uint64_t)__double_as_longlong(x[2 * i + 1]);
@@ -222,10 +227,12 @@ hipError_t launch_batch_apply(const SectorDesc *d_secs, int nsec, const int64_t 
 {
     if (lookup == kLookupHash) {
         hipLaunchKernelGGL(k_batch_hash_values, dim3(vec_blocks), dim3(kBatchVecThreads), 0, st, d_secs, nsec,
-                           d_tile0, ntiles, tile_rows, lanczos);
+                           d_tile0, ntiles, tile_rows, lanczos, lookup);
         hipLaunchKernelGGL(k_batch_apply<kLookupHash>, dim3(blocks), dim3(kApplyThreads), lds, st, d_secs, nsec,
                            d_tile0, ntiles, tile_rows, lanczos, partials);
     } else if (lookup == kLookupLearned) {
+        hipLaunchKernelGGL(k_batch_hash_values, dim3(vec_blocks), dim3(kBatchVecThreads), 0, st, d_secs, nsec,
+                           d_tile0, ntiles, tile_rows, lanczos, lookup);
         hipLaunchKernelGGL(k_batch_apply<kLookupLearned>, dim3(blocks), dim3(kApplyThreads), lds, st, d_secs, nsec,
                            d_tile0, ntiles, tile_rows, lanczos, partials);
     } else {

@@ -97,6 +97,9 @@ struct KParams {
     // (complex) in hslots slots, linear probing (null until built)
     const uint64_t *htab;
     uint64_t hslots;
+    // learned lookup: {rep, x} records in basis order, one per representative
+    // (real sectors; null until the index is trained)
+    const uint64_t *lrec;
 };
 
 // Thread-local error reporting.

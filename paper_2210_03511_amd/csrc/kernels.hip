@@ -152,7 +152,21 @@ __global__ void __launch_bounds__(256) k_hash_insert(uint64_t *tab, uint64_t slo
     }
 }
 
-// Copy of the input vector into the records (before every H.v).
+// Keys of the learned lookup's records, in basis order (x is copied in
+// before every H.v, as for the hashed table, with slot = row).
+template <bool CPLX>
+__global__ void __launch_bounds__(256) k_lrec_keys(uint64_t *rec, const uint64_t *__restrict__ reps, int64_t dim)
+{
+    constexpr int S = hash_words<CPLX>();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim; i += stride) {
+        rec[i * S] = reps[i];
+        for (int w = 1; w < S; ++w) rec[i * S + w] = 0ull;
+    }
+}
+
+// Copy of the input vector into the records (before every H.v); pos2slot
+// null: record i belongs to row i.
 template <bool CPLX>
 __global__ void __launch_bounds__(256) k_hash_values(uint64_t *tab, const uint32_t *__restrict__ pos2slot,
                                                      const double *__restrict__ x, int64_t dim)
@@ -160,7 +174,7 @@ __global__ void __launch_bounds__(256) k_hash_values(uint64_t *tab, const uint32
     constexpr int S = hash_words<CPLX>();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim; i += stride) {
-        const uint64_t s = pos2slot[i];
+        const uint64_t s = pos2slot ? pos2slot[i] : (uint64_t)i;
         if (CPLX) {
             const double2 v = reinterpret_cast<const double2 *>(x)[i];
             tab[s * S + 1] = (uint64_t)__double_as_longlong(v.x);
@@ -694,6 +708,13 @@ hipError_t launch_hash_values(uint64_t *tab, const uint32_t *pos2slot, const voi
     const double *xd = static_cast<const double *>(x);
     if (cplx) hipLaunchKernelGGL(k_hash_values<true>, dim3(blocks), dim3(256), 0, st, tab, pos2slot, xd, dim);
     else hipLaunchKernelGGL(k_hash_values<false>, dim3(blocks), dim3(256), 0, st, tab, pos2slot, xd, dim);
+    return hipGetLastError();
+}
+
+hipError_t launch_lrec_keys(uint64_t *rec, const uint64_t *reps, int64_t dim, bool cplx, int blocks, hipStream_t st)
+{
+    if (cplx) hipLaunchKernelGGL(k_lrec_keys<true>, dim3(blocks), dim3(256), 0, st, rec, reps, dim);
+    else hipLaunchKernelGGL(k_lrec_keys<false>, dim3(blocks), dim3(256), 0, st, rec, reps, dim);
     return hipGetLastError();
 }
 

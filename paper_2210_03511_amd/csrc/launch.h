@@ -34,8 +34,12 @@ hipError_t launch_apply(const KParams &p, const LaunchCfg &c, const void *x, voi
                         const LState *ls, double *partials, hipStream_t st);
 hipError_t launch_hash_build(uint64_t *tab, uint64_t slots, const uint64_t *reps, int64_t dim, bool cplx,
                              uint32_t *pos2slot, unsigned long long *d_stats, int blocks, hipStream_t st);
+// x into the records: record pos2slot[i] (hashed table) or i (pos2slot null,
+// the learned lookup's records in basis order).
 hipError_t launch_hash_values(uint64_t *tab, const uint32_t *pos2slot, const void *x, int64_t dim, bool cplx,
                               int blocks, hipStream_t st);
+// Records {rep, x} in basis order for the learned lookup: write the keys.
+hipError_t launch_lrec_keys(uint64_t *rec, const uint64_t *reps, int64_t dim, bool cplx, int blocks, hipStream_t st);
 hipError_t launch_lookup(const KParams &p, const uint64_t *keys, int64_t n, int64_t *idx, int mode, hipStream_t st);
 
 // Lanczos vector ops (vectors of n real or n complex numbers)

@@ -197,8 +197,7 @@ ed_status ed_expectation(const ed_basis *cb, const ed_model *op, const void *d_p
     p.n_pairs = (int)T2.pairs.size();
     int bpc = 0, thr = 0;
     if (e == hipSuccess) e = prepare_kernels(p, &bpc, &thr);
-    if (e == hipSuccess && lookup_mode == 2)
-        e = launch_hash_values(b->d_htab, b->d_pos2slot, d_psi, b->dim, cplx, nb, s);
+    if (e == hipSuccess) e = stage_input(b, lookup_mode, d_psi, s);
     if (e == hipSuccess) e = launch_apply(p, b->cfg, d_psi, d_y, 0, lookup_mode, nullptr, nullptr, s);
     if (e == hipSuccess) e = launch_dot(d_psi, d_y, b->dim, cplx, d_part, nb, s);
     std::vector<double> part(2 * nb, 0.0);

@@ -108,6 +108,12 @@ def test_learned_lookup_is_exact(S, inst):
     b.apply_H(x, y1, mode=1)
     torch.cuda.synchronize()
     assert torch.equal(y0, y1)
+    # another input: the records the learned gather reads must follow it
+    x2 = (0.5 * x.flip(0)).contiguous()
+    b.apply_H(x2, y0, mode=0)
+    b.apply_H(x2, y1, mode=1)
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1)
     a0, b0, _, _ = b.lanczos(x, 30, mode=0)
     a1, b1, _, _ = b.lanczos(x, 30, mode=1)
     assert np.array_equal(a0, a1) and np.array_equal(b0, b1)
@@ -176,3 +182,28 @@ def test_expanded_network_equals_network(S):
     assert np.max(np.abs(y.cpu().numpy() - yo)) <= 1e-5 * max(1.0, np.abs(yo).max())
     # the network is non-decreasing in the key
     assert np.all(np.diff(yo) >= -1e-6)
+
+
+@pytest.mark.parametrize("make", [L.square40, L.tri36_K], ids=["square40", "triangular36"])
+def test_learned_full_size_equals_plain(S, make):
+    """At benchmark sizes: the learned-index H.v equals the plain lookup's on
+    every row (real sectors read x from the index's records, complex ones
+    from x)."""
+    torch = _torch()
+    inst = make()
+    _say("learned full size", inst.name)
+    b = S.Basis.build(inst)
+    st = b.train_index()
+    _say("  max_err", st["max_err"], "mean window", round(st["mean_window"], 2))
+    g = torch.Generator(device="cuda")
+    g.manual_seed(12)
+    dt = torch.complex128 if inst.is_complex else torch.float64
+    x = torch.randn(b.dim, dtype=dt, device="cuda", generator=g)
+    y0 = torch.zeros_like(x)
+    b.apply_H(x, y0, mode=0)
+    y1 = torch.zeros_like(x)
+    b.apply_H(x, y1, mode=1)
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1)
+    del y0, y1, x
+    b.free()
