@@ -88,6 +88,7 @@ KParams make_params(const ed_basis *b)
     p.htab = b->d_htab;
     p.hslots = b->hslots;
     p.lrec = b->d_lrec;
+    p.gtab = b->d_gtab;
     return p;
 }
 
@@ -135,7 +136,8 @@ static ed_status build_impl(const ed_model *model, const ed_group *group, int32_
     if (s != ED_OK) return s;
     HostTables &T = b->T;
     b->mem_limit = o.mem_limit_bytes;
-    std::vector<uint8_t> blob = pack_blob(T, b->lay);
+    std::vector<uint8_t> gblob;
+    std::vector<uint8_t> blob = pack_blob(T, b->lay, &gblob);
 
     HIP_OK(hipGetDevice(&b->device));
     int lds_max = 0;
@@ -148,6 +150,11 @@ static ed_status build_impl(const ed_model *model, const ed_group *group, int32_
 
     if ((s = dev_alloc(b, &b->d_blob, blob.size())) != ED_OK) return s;
     HIP_OK(hipMemcpy(b->d_blob, blob.data(), blob.size(), hipMemcpyHostToDevice));
+    if (b->lay.rep_global) {
+        // Rep/Sym tables too large for LDS: read through the caches
+        if ((s = dev_alloc(b, &b->d_gtab, gblob.size())) != ED_OK) return s;
+        HIP_OK(hipMemcpy(b->d_gtab, gblob.data(), gblob.size(), hipMemcpyHostToDevice));
+    }
 
     KParams p = make_params(b);
     int bpc = 0, athreads = 0;

@@ -43,6 +43,7 @@ struct ed_basis {
     hipGraphExec_t step_graph[3] = {nullptr, nullptr, nullptr};
     // learned index
     bool indexed = false;
+    void *d_gtab = nullptr;       // Rep/Sym tables when they do not fit LDS
     uint64_t *d_lrec = nullptr;   // {rep, x} records in basis order for the learned lookup (real sectors)
     float *d_params = nullptr;
     void *d_leaves = nullptr;

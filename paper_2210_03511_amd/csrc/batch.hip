@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(kApplyThreads) k_batch_apply(const SectorDesc 
             stage_blob(lds, p.blob, p.lay.bytes);
             cur = sec;
         }
-        const Lds L = lds_view(lds, p.lay);
+        const Lds L = lds_view(lds, p.lay, static_cast<const unsigned char *>(p.gtab));
         const int64_t r0 = (t - tile0[sec]) * tile_rows;
         const int64_t r1 = min(r0 + tile_rows, p.dim);
         double part = 0.0;

@@ -48,8 +48,10 @@ struct HostTables {
     std::vector<uint8_t> chi_one;       // [G]
     std::vector<int32_t> sp_perm;       // [n_sp][N]
 
-    // Rep/Sym tables on R coarse sublattices of br bits
+    // Rep/Sym tables on R coarse sublattices of br bits; too large for LDS
+    // (rep_global), they stay in device memory and are read through the caches
     int R = 0, br = 0;
+    bool rep_global = false;
     std::vector<uint16_t> rep;          // [R][2^br]
     std::vector<uint32_t> sym_off;      // [R*2^br + 1]
     std::vector<uint32_t> sym_list;     // (g << 16) | (sp << 1) | flip
@@ -66,11 +68,21 @@ struct HostTables {
     std::vector<ChiTerm> chis;
 };
 
+// Rep/Sym tables: at most this many bytes go to LDS; larger ones stay in
+// device memory (up to the second limit; the automatic choice takes at most
+// the third, which the L2 cache of one XCD holds twice).
+constexpr size_t kRepSymLdsMax = 64 * 1024;
+constexpr size_t kRepSymGlobalMax = 16u << 20;
+constexpr size_t kRepSymChooseMax = 2u << 20;
+
 // Byte layout of the table blob staged into LDS by the kernels.
 struct BlobLayout {
     uint32_t off_rep, off_symoff, off_symlist, off_atab, off_aent, off_pairs, off_chis, off_chi, off_sqrt, off_isqrt,
         off_chione, off_mlp;
     uint32_t aent_lg;    // log2 of the row stride (entries) of the SymmetryAction entries
+    // Rep/Sym tables in a separate device buffer (rep_global != 0): their
+    // offsets there and its size; off_rep/off_symoff/off_symlist are unused
+    uint32_t rep_global, g_rep, g_symoff, g_symlist, gbytes;
     uint32_t bytes;      // staged into LDS: up to the network pieces in use
     uint32_t reserved;   // allocated: room for the largest network expansion
 };
@@ -100,6 +112,8 @@ struct KParams {
     // learned lookup: {rep, x} records in basis order, one per representative
     // (real sectors; null until the index is trained)
     const uint64_t *lrec;
+    // Rep/Sym tables when they live in device memory (lay.rep_global)
+    const void *gtab;
 };
 
 // Thread-local error reporting.
@@ -115,7 +129,9 @@ ed_status check_invariant(const ed_model *m, const HostTables &T);
 void build_rep_sym(const HostTables &T, int n_sub, std::vector<uint16_t> &rep, std::vector<uint32_t> &sym_off,
                    std::vector<uint32_t> &sym_list);
 void build_pairs(const ed_model *m, HostTables &T);
-std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &lay);
+// LDS blob; with T.rep_global the Rep/Sym tables go to *gblob instead (if
+// given; their offsets are set in lay either way).
+std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &lay, std::vector<uint8_t> *gblob = nullptr);
 int choose_sublattices(const HostTables &T, int &R, int &A, std::string &why);
 
 // pwexpand.cpp

@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(kApplyThreads, 8) k_apply(KParams p, const dou
 {
     extern __shared__ __align__(16) unsigned char lds[];
     stage_blob(lds, p.blob, p.lay.bytes);
-    const Lds L = lds_view(lds, p.lay);
+    const Lds L = lds_view(lds, p.lay, static_cast<const unsigned char *>(p.gtab));
     const double beta = (MODE == 1) ? ls->beta_prev : 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int lane = threadIdx.x & 63;
@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(256) k_count(KParams p, unsigned long long *ou
 {
     extern __shared__ __align__(16) unsigned char lds[];
     stage_blob(lds, p.blob, p.lay.bytes);
-    const Lds L = lds_view(lds, p.lay);
+    const Lds L = lds_view(lds, p.lay, static_cast<const unsigned char *>(p.gtab));
     unsigned long long c = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.dim; i += stride) {
@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(256) k_enumerate(KParams p, const uint64_t *bi
 {
     extern __shared__ __align__(16) unsigned char lds[];
     stage_blob(lds, p.blob, p.lay.bytes);
-    const Lds L = lds_view(lds, p.lay);
+    const Lds L = lds_view(lds, p.lay, static_cast<const unsigned char *>(p.gtab));
     const int N = p.N, R = p.R, br = p.br, A = p.A, ba = p.ba;
     const uint32_t S = 1u << br, mr = S - 1u, ma = (1u << ba) - 1u;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;

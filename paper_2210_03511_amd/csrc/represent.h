@@ -13,7 +13,7 @@ namespace symed {
 
 struct Lds {
     const uint16_t *rep;
-    const uint16_t *symoff;
+    const uint32_t *symoff;
     const uint16_t *symlist;    // symmetry codes (sp << 1) | flip
     const uint16_t *atab;   // distinct SymmetryAction tables, 2^ba entries each
     const uint32_t *aent;   // [n_sp][2^aent_lg >= A]: (offset of the table in atab << 8) | shift of the source substate
@@ -27,12 +27,21 @@ struct Lds {
     PwView pw;
 };
 
-__host__ __device__ __forceinline__ Lds lds_view(const unsigned char *b, const BlobLayout &L)
+// Views of the tables: b is the staged blob (LDS), g the buffer that holds
+// the Rep/Sym tables when they are too large for LDS (L.rep_global).
+__host__ __device__ __forceinline__ Lds lds_view(const unsigned char *b, const BlobLayout &L,
+                                                 const unsigned char *g = nullptr)
 {
     Lds v;
-    v.rep = reinterpret_cast<const uint16_t *>(b + L.off_rep);
-    v.symoff = reinterpret_cast<const uint16_t *>(b + L.off_symoff);
-    v.symlist = reinterpret_cast<const uint16_t *>(b + L.off_symlist);
+    if (L.rep_global) {
+        v.rep = reinterpret_cast<const uint16_t *>(g + L.g_rep);
+        v.symoff = reinterpret_cast<const uint32_t *>(g + L.g_symoff);
+        v.symlist = reinterpret_cast<const uint16_t *>(g + L.g_symlist);
+    } else {
+        v.rep = reinterpret_cast<const uint16_t *>(b + L.off_rep);
+        v.symoff = reinterpret_cast<const uint32_t *>(b + L.off_symoff);
+        v.symlist = reinterpret_cast<const uint16_t *>(b + L.off_symlist);
+    }
     v.atab = reinterpret_cast<const uint16_t *>(b + L.off_atab);
     v.aent = reinterpret_cast<const uint32_t *>(b + L.off_aent);
     v.aent_lg = L.aent_lg;

@@ -225,22 +225,35 @@ void build_rep_sym(const HostTables &T, int n_sub, std::vector<uint16_t> &rep, s
         for (int X = 0; X < n_sub; ++X)
             if (p[X * b] / b == 0) GX[X].push_back(g);
     }
-    std::vector<uint32_t> img;
+    // The image of a substate is the OR of the images of its bits, so it is
+    // assembled from the images of its 8-bit chunks (one table per element;
+    // every caller keeps b <= 16, so at most two chunks).
+    const int nc = (b + 7) / 8;
+    std::vector<uint32_t> chunk, best;
     for (int X = 0; X < n_sub; ++X) {
+        const size_t ng = GX[X].size();
+        chunk.assign(ng * nc * 256, 0u);
+        for (size_t k = 0; k < ng; ++k) {
+            const int32_t *p = &T.sp_perm[(size_t)T.sp_of[GX[X][k]] * T.N];
+            for (int c = 0; c < nc; ++c)
+                for (uint32_t u = 0; u < 256; ++u)
+                    chunk[(k * nc + c) * 256 + u] = sub_image(p, X, b, (u << (8 * c)) & mask);
+        }
+        std::vector<uint32_t> fm(ng);
+        for (size_t k = 0; k < ng; ++k) fm[k] = T.flip[GX[X][k]] ? mask : 0u;
+        auto image = [&](size_t k, uint32_t s) {
+            const uint32_t *t = chunk.data() + k * nc * 256;
+            uint32_t v = t[s & 255u];
+            if (nc > 1) v |= t[256 + ((s >> 8) & 255u)];
+            return v ^ fm[k];
+        };
+        best.assign(S, ~0u);
+        for (size_t k = 0; k < ng; ++k)
+            for (uint32_t s = 0; s < S; ++s) best[s] = std::min(best[s], image(k, s));
         for (uint32_t s = 0; s < S; ++s) {
-            img.resize(GX[X].size());
-            uint32_t best = ~0u;
-            for (size_t k = 0; k < GX[X].size(); ++k) {
-                int g = GX[X][k];
-                const int32_t *p = &T.sp_perm[(size_t)T.sp_of[g] * T.N];
-                uint32_t v = sub_image(p, X, b, s);
-                if (T.flip[g]) v ^= mask;
-                img[k] = v;
-                best = std::min(best, v);
-            }
-            rep[(size_t)X * S + s] = (uint16_t)best;
-            for (size_t k = 0; k < GX[X].size(); ++k)
-                if (img[k] == best) {
+            rep[(size_t)X * S + s] = (uint16_t)best[s];
+            for (size_t k = 0; k < ng; ++k)
+                if (image(k, s) == best[s]) {
                     int g = GX[X][k];
                     sym_list.push_back(((uint32_t)g << 16) | ((uint32_t)T.sp_of[g] << 1) | T.flip[g]);
                 }
@@ -329,12 +342,28 @@ void build_pairs(const ed_model *m, HostTables &T)
 
 static size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &L)
+std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &L, std::vector<uint8_t> *gblob)
 {
-    size_t o = 0;
-    L.off_rep = (uint32_t)o;     o = align16(o + T.rep.size() * sizeof(uint16_t));
-    L.off_symoff = (uint32_t)o;  o = align16(o + T.sym_off.size() * sizeof(uint16_t));
-    L.off_symlist = (uint32_t)o; o = align16(o + T.sym_list.size() * sizeof(uint16_t));
+    // Rep u16, SymOff u32, SymList u16 (symmetry codes): in the LDS blob, or
+    // in a buffer of their own
+    size_t o = 0, g = 0;
+    size_t &rs = T.rep_global ? g : o;
+    L.rep_global = T.rep_global ? 1u : 0u;
+    const uint32_t r0 = (uint32_t)rs;    rs = align16(rs + T.rep.size() * sizeof(uint16_t));
+    const uint32_t r1 = (uint32_t)rs;    rs = align16(rs + T.sym_off.size() * sizeof(uint32_t));
+    const uint32_t r2 = (uint32_t)rs;    rs = align16(rs + T.sym_list.size() * sizeof(uint16_t));
+    L.off_rep = L.off_symoff = L.off_symlist = 0;
+    L.g_rep = L.g_symoff = L.g_symlist = 0;
+    if (T.rep_global) {
+        L.g_rep = r0;
+        L.g_symoff = r1;
+        L.g_symlist = r2;
+    } else {
+        L.off_rep = r0;
+        L.off_symoff = r1;
+        L.off_symlist = r2;
+    }
+    L.gbytes = (uint32_t)g;
     L.off_atab = (uint32_t)o;    o = align16(o + T.act_tab.size() * sizeof(uint16_t));
     // entry rows padded to a power-of-two stride (a shift instead of a multiply)
     L.aent_lg = 0;
@@ -353,12 +382,20 @@ std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &L)
     L.reserved = (uint32_t)o;
     std::vector<uint8_t> blob(o, 0);
     auto put = [&](uint32_t off, const void *src, size_t n) { if (n) std::memcpy(blob.data() + off, src, n); };
-    put(L.off_rep, T.rep.data(), T.rep.size() * sizeof(uint16_t));
-    // device form: 16-bit offsets, and for each symmetry its code (sp << 1) | flip
-    std::vector<uint16_t> off16(T.sym_off.begin(), T.sym_off.end()), code(T.sym_list.size());
+    // device form of the Sym list: for each symmetry its code (sp << 1) | flip
+    std::vector<uint16_t> code(T.sym_list.size());
     for (size_t k = 0; k < T.sym_list.size(); ++k) code[k] = (uint16_t)(T.sym_list[k] & 0xffffu);
-    put(L.off_symoff, off16.data(), off16.size() * sizeof(uint16_t));
-    put(L.off_symlist, code.data(), code.size() * sizeof(uint16_t));
+    if (!T.rep_global) {
+        put(L.off_rep, T.rep.data(), T.rep.size() * sizeof(uint16_t));
+        put(L.off_symoff, T.sym_off.data(), T.sym_off.size() * sizeof(uint32_t));
+        put(L.off_symlist, code.data(), code.size() * sizeof(uint16_t));
+    } else if (gblob) {
+        gblob->assign(g, 0);
+        auto gput = [&](uint32_t off, const void *src, size_t n) { if (n) std::memcpy(gblob->data() + off, src, n); };
+        gput(L.g_rep, T.rep.data(), T.rep.size() * sizeof(uint16_t));
+        gput(L.g_symoff, T.sym_off.data(), T.sym_off.size() * sizeof(uint32_t));
+        gput(L.g_symlist, code.data(), code.size() * sizeof(uint16_t));
+    }
     put(L.off_atab, T.act_tab.data(), T.act_tab.size() * sizeof(uint16_t));
     // device form of the entries: table offset in atab << 8 | right shift of
     // the source substate (offsets < 4096 << 12 = 2^24, shifts < 64)
@@ -393,13 +430,17 @@ std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &L)
     return blob;
 }
 
+// Bytes of the device Rep/Sym tables: Rep u16 and SymOff u32 per substate,
+// SymList u16 per entry.
+static size_t rep_sym_bytes(size_t n_rep, size_t n_list) { return n_rep * 2 + (n_rep + 1) * 4 + n_list * 2; }
+
 // Choose the decompositions: the SymmetryAction tables use the stable
 // contiguous decomposition with the fewest sublattices (fewest destination
 // steps per candidate) whose distinct tables fit (<= 12 bits per substate,
 // <= 16 sublattices, tables of <= 48 KiB together); the Rep/Sym
 // tables use the one with the fewest sublattices (fewest candidate
 // symmetries) that the action decomposition refines and whose tables fit
-// 64 KiB.
+// 64 KiB of LDS, or 2 MiB of device memory read through the caches.
 int choose_sublattices(const HostTables &T, int &R, int &A, std::string &why)
 {
     const int N = T.N;
@@ -420,7 +461,7 @@ int choose_sublattices(const HostTables &T, int &R, int &A, std::string &why)
         // the Rep/Sym decomposition must divide it: some stable one with small enough tables
         bool refinable = false;
         for (int r : stable)
-            if (ns % r == 0 && N / r <= 14) refinable = true;
+            if (ns % r == 0 && N / r <= 16) refinable = true;
         if (refinable) { bestA = ns; break; }
     }
     if (!bestA) {
@@ -431,19 +472,16 @@ int choose_sublattices(const HostTables &T, int &R, int &A, std::string &why)
     for (int ns : stable) {
         if (bestA % ns) continue;  // the action decomposition must refine this one
         int b = N / ns;
-        if (b > 14) continue;
+        if (b > 16) continue;
         size_t S = (size_t)1 << b;
-        // tables: rep u16, offsets u32, list u32 (estimate the list as G_X * S / 4 worst-case cap)
+        if (rep_sym_bytes(ns * S, 0) > kRepSymChooseMax) continue;
         std::vector<uint16_t> rep;
         std::vector<uint32_t> off, lst;
-        if (ns * S * 6 > 64 * 1024) continue;
         build_rep_sym(T, ns, rep, off, lst);
-        size_t bytes = rep.size() * 2 + off.size() * 2 + lst.size() * 2;
-        if (lst.size() > 65535) continue;
-        if (bytes <= 64 * 1024) { bestR = ns; break; }
+        if (rep_sym_bytes(rep.size(), lst.size()) <= kRepSymChooseMax) { bestR = ns; break; }
     }
     if (!bestR) {
-        why = "no stable decomposition gives Rep/Sym tables of at most 64 KiB";
+        why = "no stable decomposition gives Rep/Sym tables of at most 2 MiB";
         return 0;
     }
     R = bestR;
@@ -475,8 +513,11 @@ ed_status build_host_tables(const ed_model *m, const ed_group *g, int n_up, int 
     if (T.ba > 12 || A > 16)
         return fail(ED_EINVAL, "SymmetryAction tables need <= 12 bits per substate and <= 16 sublattices");
     build_rep_sym(T, R, T.rep, T.sym_off, T.sym_list);
-    if (T.sym_list.size() > 65535 || T.n_sp >= 32768)
-        return fail(ED_EINVAL, "Sym tables too large for 16-bit entries; choose more Rep sublattices");
+    if (T.n_sp >= 32768) return fail(ED_EINVAL, "too many distinct permutations for 16-bit symmetry codes");
+    const size_t rs_bytes = rep_sym_bytes(T.rep.size(), T.sym_list.size());
+    if (rs_bytes > kRepSymGlobalMax)
+        return fail(ED_EINVAL, "Rep/Sym tables of " + std::to_string(rs_bytes) + " B; choose more Rep sublattices");
+    T.rep_global = rs_bytes > kRepSymLdsMax;
     if ((st = build_act(T)) != ED_OK) return st;
     build_pairs(m, T);
     return ED_OK;

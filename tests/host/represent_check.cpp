@@ -22,9 +22,10 @@ int main(int argc, char **argv) {
   HostTables T;
   ed_status st = build_host_tables(&m, &g, n_up, R, A, T);
   if (st != ED_OK) { printf("build_host_tables failed %d\n", st); return 2; }
-  BlobLayout lay; std::vector<uint8_t> blob = pack_blob(T, lay);
+  BlobLayout lay; std::vector<uint8_t> gblob; std::vector<uint8_t> blob = pack_blob(T, lay, &gblob);
   std::vector<uint8_t> al(blob.size() + 16); std::memcpy(al.data(), blob.data(), blob.size());
-  Lds L = lds_view(al.data(), lay);
+  std::vector<uint8_t> gl(gblob.size() + 16); if (!gblob.empty()) std::memcpy(gl.data(), gblob.data(), gblob.size());
+  Lds L = lds_view(al.data(), lay, gl.data());
   // find_rep reports a symmetry by its code (sp << 1) | flip
   std::vector<int> g_of_code(2 * T.n_sp, 0);
   for (int e = 0; e < T.G; ++e) g_of_code[(T.sp_of[e] << 1) | T.flip[e]] = e;
