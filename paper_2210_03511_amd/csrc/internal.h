@@ -77,12 +77,12 @@ constexpr size_t kRepSymChooseMax = 2u << 20;
 
 // Byte layout of the table blob staged into LDS by the kernels.
 struct BlobLayout {
-    uint32_t off_rep, off_symoff, off_symlist, off_atab, off_aent, off_pairs, off_chis, off_chi, off_sqrt, off_isqrt,
-        off_chione, off_mlp;
+    uint32_t off_rent, off_symlist, off_atab, off_aent, off_pairs, off_chis, off_chi, off_sqrt, off_isqrt, off_chione,
+        off_mlp;
     uint32_t aent_lg;    // log2 of the row stride (entries) of the SymmetryAction entries
     // Rep/Sym tables in a separate device buffer (rep_global != 0): their
-    // offsets there and its size; off_rep/off_symoff/off_symlist are unused
-    uint32_t rep_global, g_rep, g_symoff, g_symlist, gbytes;
+    // offsets there and its size; off_rent/off_symlist are unused
+    uint32_t rep_global, g_rent, g_symlist, gbytes;
     uint32_t bytes;      // staged into LDS: up to the network pieces in use
     uint32_t reserved;   // allocated: room for the largest network expansion
 };

@@ -249,12 +249,12 @@ __global__ void __launch_bounds__(256) k_enumerate(KParams p, const uint64_t *bi
         while (s < send) {
             const uint32_t s0 = (uint32_t)(s >> (N - br)) & mr;
             int bad = -1;
-            if (L.rep[s0] != s0) {
+            if ((L.rent[s0].x & 0xffffu) != s0) {
                 bad = 0;
             } else {
                 for (int X = 1; X < R; ++X) {
                     const uint32_t sx = (uint32_t)(s >> (N - (X + 1) * br)) & mr;
-                    if (L.rep[X * S + sx] < s0) {
+                    if ((L.rent[X * S + sx].x & 0xffffu) < s0) {
                         bad = X;
                         break;
                     }
@@ -270,9 +270,10 @@ __global__ void __launch_bounds__(256) k_enumerate(KParams p, const uint64_t *bi
             for (int Y = 0; Y < R && isrep; ++Y) {
                 const uint32_t sy = (uint32_t)(s >> (N - (Y + 1) * br)) & mr;
                 const uint32_t idx = Y * S + sy;
-                if (L.rep[idx] != s0) continue;
-                const uint32_t k1 = L.symoff[idx + 1];
-                for (uint32_t q = L.symoff[idx]; q < k1; ++q) {
+                const uint2 e = L.rent[idx];
+                if ((e.x & 0xffffu) != s0) continue;
+                const uint32_t k1 = e.y + (e.x >> 16);
+                for (uint32_t q = e.y; q < k1; ++q) {
                     const uint32_t e = L.symlist[q];
                     const uint32_t sp = e >> 1;
                     const uint32_t *en = L.aent + ((size_t)sp << L.aent_lg);

@@ -12,8 +12,7 @@
 namespace symed {
 
 struct Lds {
-    const uint16_t *rep;
-    const uint32_t *symoff;
+    const uint2 *rent;          // per coarse substate: {Rep | count << 16, first Sym entry}
     const uint16_t *symlist;    // symmetry codes (sp << 1) | flip
     const uint16_t *atab;   // distinct SymmetryAction tables, 2^ba entries each
     const uint32_t *aent;   // [n_sp][2^aent_lg >= A]: (offset of the table in atab << 8) | shift of the source substate
@@ -34,12 +33,10 @@ __host__ __device__ __forceinline__ Lds lds_view(const unsigned char *b, const B
 {
     Lds v;
     if (L.rep_global) {
-        v.rep = reinterpret_cast<const uint16_t *>(g + L.g_rep);
-        v.symoff = reinterpret_cast<const uint32_t *>(g + L.g_symoff);
+        v.rent = reinterpret_cast<const uint2 *>(g + L.g_rent);
         v.symlist = reinterpret_cast<const uint16_t *>(g + L.g_symlist);
     } else {
-        v.rep = reinterpret_cast<const uint16_t *>(b + L.off_rep);
-        v.symoff = reinterpret_cast<const uint32_t *>(b + L.off_symoff);
+        v.rent = reinterpret_cast<const uint2 *>(b + L.off_rent);
         v.symlist = reinterpret_cast<const uint16_t *>(b + L.off_symlist);
     }
     v.atab = reinterpret_cast<const uint16_t *>(b + L.off_atab);
@@ -85,14 +82,18 @@ __host__ __device__ __forceinline__ Found find_rep(uint64_t t, const KParams &p,
 {
     const int N = p.N, R = p.R, br = p.br, A = p.A, ba = p.ba;
     const uint32_t S = 1u << br, mr = S - 1u, ma = (1u << ba) - 1u;
-    // MinRep, and in xm the coarse sublattices that attain it (R <= 16)
+    // MinRep, and in xm the coarse sublattices that attain it (R <= 16); e0
+    // keeps the entry of the first of them
     uint32_t minrep = 0xffffffffu, xm = 0;
+    uint2 e0 = make_uint2(0u, 0u);
     for (int X = 0; X < R; ++X) {
         uint32_t s = (uint32_t)(t >> (N - (X + 1) * br)) & mr;
-        const uint32_t r = L.rep[X * S + s];
+        const uint2 e = L.rent[X * S + s];
+        const uint32_t r = e.x & 0xffffu;
         if (r < minrep) {
             minrep = r;
             xm = 1u << X;
+            e0 = e;
         } else if (r == minrep) {
             xm |= 1u << X;
         }
@@ -105,13 +106,18 @@ __host__ __device__ __forceinline__ Found find_rep(uint64_t t, const KParams &p,
     const int d0 = A / R;
     uint64_t best = ~0ull;
     uint32_t bg = 0, cnt = 0;
+    bool first = true;
     while (xm) {
         const int X = __builtin_ctz(xm);
         xm &= xm - 1u;
-        uint32_t s = (uint32_t)(t >> (N - (X + 1) * br)) & mr;
-        uint32_t idx = X * S + s;
-        const uint32_t k1 = L.symoff[idx + 1];
-        for (uint32_t k = L.symoff[idx]; k < k1; ++k) {
+        uint2 e = e0;
+        if (!first) {
+            const uint32_t s = (uint32_t)(t >> (N - (X + 1) * br)) & mr;
+            e = L.rent[X * S + s];
+        }
+        first = false;
+        const uint32_t k1 = e.y + (e.x >> 16);
+        for (uint32_t k = e.y; k < k1; ++k) {
             const uint32_t e = L.symlist[k];
             const uint32_t sp = e >> 1;
             const uint32_t fm = (e & 1u) ? ma : 0u;  // spin flip complements every substate

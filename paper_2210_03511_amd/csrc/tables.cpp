@@ -344,24 +344,22 @@ static size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &L, std::vector<uint8_t> *gblob)
 {
-    // Rep u16, SymOff u32, SymList u16 (symmetry codes): in the LDS blob, or
-    // in a buffer of their own
+    // Rep/Sym entries {Rep | count << 16, first Sym entry} (8 B per substate)
+    // and SymList u16 (symmetry codes): in the LDS blob, or in a buffer of
+    // their own
     size_t o = 0, g = 0;
     size_t &rs = T.rep_global ? g : o;
     L.rep_global = T.rep_global ? 1u : 0u;
-    const uint32_t r0 = (uint32_t)rs;    rs = align16(rs + T.rep.size() * sizeof(uint16_t));
-    const uint32_t r1 = (uint32_t)rs;    rs = align16(rs + T.sym_off.size() * sizeof(uint32_t));
-    const uint32_t r2 = (uint32_t)rs;    rs = align16(rs + T.sym_list.size() * sizeof(uint16_t));
-    L.off_rep = L.off_symoff = L.off_symlist = 0;
-    L.g_rep = L.g_symoff = L.g_symlist = 0;
+    const uint32_t r0 = (uint32_t)rs;    rs = align16(rs + T.rep.size() * 2 * sizeof(uint32_t));
+    const uint32_t r1 = (uint32_t)rs;    rs = align16(rs + T.sym_list.size() * sizeof(uint16_t));
+    L.off_rent = L.off_symlist = 0;
+    L.g_rent = L.g_symlist = 0;
     if (T.rep_global) {
-        L.g_rep = r0;
-        L.g_symoff = r1;
-        L.g_symlist = r2;
+        L.g_rent = r0;
+        L.g_symlist = r1;
     } else {
-        L.off_rep = r0;
-        L.off_symoff = r1;
-        L.off_symlist = r2;
+        L.off_rent = r0;
+        L.off_symlist = r1;
     }
     L.gbytes = (uint32_t)g;
     L.off_atab = (uint32_t)o;    o = align16(o + T.act_tab.size() * sizeof(uint16_t));
@@ -382,18 +380,22 @@ std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &L, std::vector<u
     L.reserved = (uint32_t)o;
     std::vector<uint8_t> blob(o, 0);
     auto put = [&](uint32_t off, const void *src, size_t n) { if (n) std::memcpy(blob.data() + off, src, n); };
-    // device form of the Sym list: for each symmetry its code (sp << 1) | flip
+    // device form of the Sym list: for each symmetry its code (sp << 1) | flip;
+    // counts fit 16 bits since the group has at most 65535 elements
     std::vector<uint16_t> code(T.sym_list.size());
     for (size_t k = 0; k < T.sym_list.size(); ++k) code[k] = (uint16_t)(T.sym_list[k] & 0xffffu);
+    std::vector<uint32_t> rent(2 * T.rep.size());
+    for (size_t i = 0; i < T.rep.size(); ++i) {
+        rent[2 * i] = (uint32_t)T.rep[i] | ((T.sym_off[i + 1] - T.sym_off[i]) << 16);
+        rent[2 * i + 1] = T.sym_off[i];
+    }
     if (!T.rep_global) {
-        put(L.off_rep, T.rep.data(), T.rep.size() * sizeof(uint16_t));
-        put(L.off_symoff, T.sym_off.data(), T.sym_off.size() * sizeof(uint32_t));
+        put(L.off_rent, rent.data(), rent.size() * sizeof(uint32_t));
         put(L.off_symlist, code.data(), code.size() * sizeof(uint16_t));
     } else if (gblob) {
         gblob->assign(g, 0);
         auto gput = [&](uint32_t off, const void *src, size_t n) { if (n) std::memcpy(gblob->data() + off, src, n); };
-        gput(L.g_rep, T.rep.data(), T.rep.size() * sizeof(uint16_t));
-        gput(L.g_symoff, T.sym_off.data(), T.sym_off.size() * sizeof(uint32_t));
+        gput(L.g_rent, rent.data(), rent.size() * sizeof(uint32_t));
         gput(L.g_symlist, code.data(), code.size() * sizeof(uint16_t));
     }
     put(L.off_atab, T.act_tab.data(), T.act_tab.size() * sizeof(uint16_t));
@@ -430,9 +432,9 @@ std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &L, std::vector<u
     return blob;
 }
 
-// Bytes of the device Rep/Sym tables: Rep u16 and SymOff u32 per substate,
-// SymList u16 per entry.
-static size_t rep_sym_bytes(size_t n_rep, size_t n_list) { return n_rep * 2 + (n_rep + 1) * 4 + n_list * 2; }
+// Bytes of the device Rep/Sym tables: an 8 B entry per substate (Rep,
+// number of Sym entries, first Sym entry) and a u16 code per Sym entry.
+static size_t rep_sym_bytes(size_t n_rep, size_t n_list) { return n_rep * 8 + n_list * 2; }
 
 // Choose the decompositions: the SymmetryAction tables use the stable
 // contiguous decomposition with the fewest sublattices (fewest destination
