@@ -19,6 +19,8 @@ What each function follows (thesis sections / equations):
     products (site 0 = leftmost factor = most significant bit).
   * ``projector_basis``  - symmetry-adapted vectors sum_g conj(chi(g)) g|s>
     written out in the unsymmetrized basis.
+  * ``spin_correlations`` / ``structure_factor`` - <S_i.S_j> of a state
+    from the definition of the spin operators, and their Fourier sum.
   * ``lanczos``          - the real-symmetric two-vector step and the
     complex-Hermitian three-vector step ("The Lanczos algorithm"), no
     reorthogonalization; T-matrix eigenvalues by a library tridiagonal solver.
@@ -313,6 +315,37 @@ def unsym_sector_matrix(inst):
                    flips=np.zeros(1, np.uint8), chi=np.ones(1, complex))
     reps, stabs = enumerate_basis(triv)
     return reps, coo_matrix(triv, reps, stabs)
+
+
+def spin_correlations(inst, states, psi):
+    """C[i, j] = <psi|S_i . S_j|psi> for a normalized psi over the ascending
+    Sz configurations ``states`` (trivial group), from the definition
+    S_i . S_j = S^z_i S^z_j + (S^+_i S^-_j + S^-_i S^+_j) / 2, bit by bit;
+    C[i, i] = 3/4."""
+    n = inst.n_sites
+    s = np.asarray(states, np.uint64)
+    p = np.asarray(psi)
+    w = np.abs(p) ** 2
+    bits = [((s >> np.uint64(n - 1 - i)) & np.uint64(1)).astype(bool) for i in range(n)]
+    C = np.full((n, n), 0.75)
+    for i in range(n):
+        for j in range(i + 1, n):
+            same = bits[i] == bits[j]
+            zz = np.sum(w[same]) * 0.25 - np.sum(w[~same]) * 0.25
+            anti = np.nonzero(~same)[0]
+            t = s[anti] ^ (np.uint64(1) << np.uint64(n - 1 - i)) ^ (np.uint64(1) << np.uint64(n - 1 - j))
+            k = np.searchsorted(s, t)
+            flip = 0.5 * np.sum(np.conj(p[k]) * p[anti])
+            C[i, j] = C[j, i] = zz + flip.real
+    return C
+
+
+def structure_factor(C, coords, q):
+    """S(q) = (1/N) sum_{i,j} exp(2 pi i q.(r_i - r_j)) C[i, j], with r in
+    lattice coordinates and q in the matching reciprocal units."""
+    r = np.asarray(coords, float)
+    ph = np.exp(2j * np.pi * (r @ np.asarray([float(c) for c in q], float)))
+    return float(np.real(np.conj(ph) @ C @ ph)) / len(r)
 
 
 # ---------------------------------------------------------------------------

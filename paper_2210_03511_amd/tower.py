@@ -18,7 +18,10 @@ Ritz vector and expectation value runs in the HIP kernels behind the C ABI.
   tower;
 * ``total_spin`` - S from <S^2> = 3N/4 + 2 sum_{i<j} <S_i . S_j> of a state,
   through the expectation-value kernel with the all-pairs operator (which
-  every site permutation and the spin flip leave invariant).
+  every site permutation and the spin flip leave invariant);
+* ``structure_factor`` - S(q), the Fourier sum of the spin correlations (its
+  value at the ordering vector measures the order: M = (pi, pi) for the
+  Neel state), through the same kernel.
 """
 from __future__ import annotations
 
@@ -80,6 +83,24 @@ def total_spin(basis, psi, mode=0):
     bonds, J = all_pairs(n)
     ss = 0.75 * n + 2.0 * basis.expectation(psi, bonds, J, mode=mode).real
     return 0.5 * (math.sqrt(1.0 + 4.0 * max(ss, 0.0)) - 1.0), ss
+
+
+def structure_factor(basis, psi, coords, qs, mode=0):
+    """Spin structure factor S(q) = (1/N) sum_{i,j} exp(i q.(r_i - r_j))
+    <S_i . S_j> of a normalized state, averaged over the momenta ``qs``:
+    3/4 + (2/N) sum_{i<j} <cos(2 pi q.(r_i - r_j))>_qs <S_i . S_j>, one call of
+    the expectation kernel.  ``coords``: lattice coordinates of the sites;
+    ``qs``: q in the matching reciprocal units, and with it every momentum
+    the basis's point group maps it to (its star), so that the operator is
+    invariant.  For a state of full point symmetry every q of a star gives
+    the same S(q)."""
+    r = np.asarray(coords, float)
+    n = len(r)
+    bonds, _ = all_pairs(n)
+    d = r[bonds[:, 0]] - r[bonds[:, 1]]
+    Q = np.array([[float(c) for c in q] for q in qs], float)
+    J = (2.0 / n) * np.cos(2.0 * np.pi * (d @ Q.T)).mean(axis=1)
+    return 0.75 + basis.expectation(psi, bonds, J, mode=mode).real
 
 
 def _main(argv=None):

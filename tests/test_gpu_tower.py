@@ -105,3 +105,55 @@ def test_tower_square32_levels_and_total_spin(T):
         e_prev = e0
         del psi, v0
         b.free()
+
+
+def _ground(symed, torch, inst, n_iter, seed):
+    b = symed.Basis.build(inst)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    dt = torch.complex128 if inst.is_complex else torch.float64
+    v0 = torch.randn(b.dim, dtype=dt, device="cuda", generator=g)
+    e0, psi = b.ground_state(v0, min(n_iter, b.dim))
+    return b, e0, psi
+
+
+@pytest.mark.parametrize("J2", [0.0, 0.5])
+def test_structure_factor_square16_equals_oracle(T, J2):
+    """S(q) of the 16-site ground state (Gamma.A1.even) through the
+    expectation kernel against the oracle's correlations of the dense
+    full-Sz-sector ground state, at M, at the star of X and at Gamma."""
+    from paper_2210_03511_amd import symed
+    torch = _torch()
+    inst = L.square_j1j2(L.SQ16_L[0], L.SQ16_L[1], 1.0, J2, L.Q0, sublat_chain=L.SQ16_CHAIN)
+    b, e0, psi = _ground(symed, torch, inst, 120, 7)
+    states, H = O.unsym_sector_matrix(inst)
+    w, v = np.linalg.eigh(H.toarray())
+    assert w[1] > w[0] + 1e-6 and abs(e0 - w[0]) < 1e-10
+    C = O.spin_correlations(inst, states, v[:, 0])
+    pos = L.site_coords(inst)
+    for q in [L.Q0, (L.F(1, 2), L.F(1, 2)), (L.F(1, 2), L.F(0)), (L.F(1, 4), L.F(0))]:
+        star = L.momentum_star(inst, q)
+        exact = np.mean([O.structure_factor(C, pos, qq) for qq in star])
+        got = T.structure_factor(b, psi, pos, star)
+        _say("square16 J2", J2, "q", [str(c) for c in q], "star", len(star), "S", got, "oracle", exact)
+        assert abs(got - exact) < 1e-8      # Ritz-vector accuracy
+    b.free()
+
+
+def test_structure_factor_square32_frustration(T):
+    """Neel correlations at 32 sites: S(M) is largest at J2 = 0 and is
+    suppressed by the frustrating J2 = 0.5; the singlet has S(Gamma) = 0."""
+    from paper_2210_03511_amd import symed
+    torch = _torch()
+    M = (L.F(1, 2), L.F(1, 2))
+    sm = {}
+    for J2 in (0.0, 0.5):
+        inst = L.square32(J2=J2)
+        b, e0, psi = _ground(symed, torch, inst, 120, 11)
+        pos = L.site_coords(inst)
+        sm[J2] = T.structure_factor(b, psi, pos, L.momentum_star(inst, M))
+        s0 = T.structure_factor(b, psi, pos, [L.Q0])
+        _say("square32 J2", J2, "E0", e0, "S(M)", sm[J2], "S(Gamma)", s0)
+        assert abs(s0) < 1e-6
+        b.free()
+    assert sm[0.0] > sm[0.5] > 0.75

@@ -339,3 +339,44 @@ def test_ring4_correlations_closed_form():
     assert c[1] == pytest.approx(-0.5, abs=1e-13)
     assert c[2] == pytest.approx(0.25, abs=1e-13)
     assert 0.75 + 2 * c[1] + c[2] == pytest.approx(0.0, abs=1e-13)
+
+
+# --- structure factor -----------------------------------------------------------
+
+def _ground_state_full(inst):
+    states, H = O.unsym_sector_matrix(inst)
+    w, v = np.linalg.eigh(H.toarray())
+    return states, v[:, 0], w
+
+
+def test_structure_factor_ring4_closed_form():
+    # 4-site Heisenberg ring: singlet ground state with <S0.S1> = -1/2 and
+    # <S0.S2> = 1/4, so S(0) = 0, S(pi/2) = S(3 pi/2) = 1/2, S(pi) = 2
+    inst = L.chain(4, sublat=(2,))
+    states, psi, w = _ground_state_full(inst)
+    assert w[0] == pytest.approx(-2.0, abs=1e-12) and w[1] > w[0] + 1e-6
+    C = O.spin_correlations(inst, states, psi)
+    pos = L.site_coords(inst)
+    from fractions import Fraction as F
+    expect = {0: 0.0, 1: 0.5, 2: 2.0, 3: 0.5}
+    for m, sq in expect.items():
+        assert O.structure_factor(C, pos, (F(m, 4),)) == pytest.approx(sq, abs=1e-12)
+
+
+def test_structure_factor_sum_rule_and_singlet_square16():
+    # sum over all momenta of S(q) is 3N/4 for any state; a singlet has S(0) = 0
+    inst = L.square_j1j2(L.SQ16_L[0], L.SQ16_L[1], 1.0, 0.0, L.Q0, sublat_chain=L.SQ16_CHAIN)
+    states, H = O.unsym_sector_matrix(inst)
+    w, v = scipy.sparse.linalg.eigsh(H, k=1, which="SA")
+    psi = v[:, 0] / np.linalg.norm(v[:, 0])
+    C = O.spin_correlations(inst, states, psi)
+    # the correlations reproduce the energy: E = sum_b J_b C[i_b, j_b]
+    assert sum(J * C[i, j] for (i, j), J in zip(inst.bonds.tolist(), inst.bond_J)) == pytest.approx(w[0], abs=1e-10)
+    pos = L.site_coords(inst)
+    lat = inst.meta["lattice"]
+    total = sum(O.structure_factor(C, pos, q) for q in lat.momenta())
+    assert total == pytest.approx(0.75 * inst.n_sites, abs=1e-10)
+    assert O.structure_factor(C, pos, L.Q0) == pytest.approx(0.0, abs=1e-10)
+    # Neel correlations peak at M = (pi, pi)
+    sM = O.structure_factor(C, pos, (L.F(1, 2), L.F(1, 2)))
+    assert all(sM >= O.structure_factor(C, pos, q) for q in lat.momenta())

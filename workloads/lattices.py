@@ -574,3 +574,25 @@ def chain_distance_bonds(inst, r):
     lab = {p: i for i, p in enumerate(pos)}
     bonds = np.array([(lab[p], lab[(p + r) % n]) for p in range(n)], np.int32)
     return bonds, np.full(n, 1.0 / n)
+
+
+def site_coords(inst):
+    """Lattice coordinates of every site label: (N, 2) integer lattice
+    coordinates on a torus, or (N, 1) chain positions."""
+    if "lattice" in inst.meta:
+        return np.array(inst.meta["lattice"].coords, dtype=np.int64)
+    return np.array(inst.meta["positions"], dtype=np.int64)[:, None]
+
+
+def momentum_star(inst, q):
+    """The momenta P^T q (mod 1) over the point group of a torus instance, as
+    Fractions (q itself for a chain)."""
+    if "lattice" not in inst.meta:
+        return [tuple(q)]
+    out = []
+    for P in inst.meta["lattice"].pg:
+        qp = (P[0][0] * q[0] + P[1][0] * q[1], P[0][1] * q[0] + P[1][1] * q[1])
+        qp = tuple(c - (c.numerator // c.denominator) for c in qp)
+        if qp not in out:
+            out.append(qp)
+    return out
