@@ -1,4 +1,4 @@
-"""Tower-of-states sweeps over symmetry sectors (host orchestration only).
+"""Tower-of-states sweeps and order diagnostics (host orchestration only).
 
 The thesis reads magnetic order off the low-energy spectrum: the lowest
 level of every total spin S, labelled by momentum and point-group irrep,
@@ -42,7 +42,8 @@ def _start(dim, is_complex, seed):
 
 def sector_lowest(instances, n_iter=100, mode=0, seed=1, k=1):
     """[(E_0, ..., E_{k-1}), instance] for every non-empty sector: Lanczos
-    from a seeded normal start vector, lowest k eigenvalues of T."""
+    from a seeded normal start vector, lowest k eigenvalues of T.  mode 0
+    (plain lookup) or 2 (hashed table, built per sector)."""
     out = []
     for inst in instances:
         b = symed.Basis.build(inst)
