@@ -171,10 +171,12 @@ ed_status ed_basis_device_reps(const ed_basis *basis, const uint64_t **d_reps);
  * accumulates character x norm ratio x amplitude x x_j; no atomics).
  *   d_x, d_y: device vectors of length dim (f64 or interleaved c128); must
  *   not alias.  lookup_mode: 0 = plain (Limits + binary search), 1 = learned
- *   index (requires ed_index_train), 2 = hashed staging table (requires
- *   ed_hash_build; x is first copied into the table, which the basis owns,
- *   so calls with mode 2 on one basis must not overlap in time).  The result
- *   is the same in every mode, bit for bit.  Asynchronous on `stream`.
+ *   index (requires ed_index_train; in real sectors x is first copied into
+ *   the index's {representative, x} records), 2 = hashed staging table
+ *   (requires ed_hash_build; x is first copied into the table).  The basis
+ *   owns those records, so calls with mode 1 or 2 on one basis must not
+ *   overlap in time.  The result is the same in every mode, bit for bit.
+ *   Asynchronous on `stream`.
  */
 ed_status ed_apply_H(const ed_basis *basis, const void *d_x, void *d_y, int32_t lookup_mode, void *stream);
 
@@ -334,7 +336,9 @@ typedef struct {
 
 /*
  * Train the learned index of a built basis (device kernels; blocks until
- * done) and build its exact leaf table.  Afterwards lookup_mode / mode 1 is
+ * done) and build its exact leaf table.  Real sectors also get a record
+ * {representative, x} per state in basis order (16 B per state), from which
+ * the mode-1 H.v gather reads x_j.  Afterwards lookup_mode / mode 1 is
  * accepted by ed_apply_H, ed_lookup and ed_lanczos_run.  Retraining with the
  * same leaf count replaces the index.  Errors: ED_EINVAL, ED_ENOMEM,
  * ED_EDEVICE.
