@@ -139,6 +139,14 @@ def test_trained_network_gains_over_untrained(S):
     assert trained["mean_window"] < 0.2 * plain
     reps, _ = b.export()
     _check_agreement(S, torch, b, reps, inst)
+    # after retraining, the gather over the index's records still equals plain
+    x = torch.from_numpy(V.start_vector(len(reps), 8, inst.is_complex)).cuda()
+    y0 = torch.zeros_like(x)
+    y1 = torch.zeros_like(x)
+    b.apply_H(x, y0, mode=0)
+    b.apply_H(x, y1, mode=1)
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1)
 
 
 def test_learned_index_requires_training(S):
