@@ -85,7 +85,12 @@ def cpu_baseline(inst, budget_s):
             "rows_per_s": len(rows) / t}
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "k_apply_square40_counters.json")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def counters_path(config):
+    """Recorded FETCH_SIZE / WRITE_SIZE of the H.v kernel for a workload."""
+    return os.path.join(PROFILES, f"k_apply_{config}_counters.json")
 
 
 def kernel_sources_sha256():
@@ -104,9 +109,10 @@ def recorded_traffic(config, mode):
     """HBM bytes per launch of the H.v kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE passes, scaled by the copy calibration; None if
     there is no record for this workload and mode or the sources changed."""
-    if not os.path.exists(COUNTERS):
+    path = counters_path(config)
+    if not os.path.exists(path):
         return None
-    with open(COUNTERS) as f:
+    with open(path) as f:
         rec = json.load(f)
     if rec.get("config") != config or rec.get("sources_sha256") != kernel_sources_sha256():
         return None

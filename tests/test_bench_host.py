@@ -27,12 +27,12 @@ def test_algorithmic_bytes():
 def test_recorded_traffic_only_for_matching_sources(tmp_path, monkeypatch):
     rec = {"config": "square40", "sources_sha256": bench.kernel_sources_sha256(), "fetch_factor": 2.0,
            "write_factor": 1.0, "kernels": {"hash": {"fetch_kib": 10.0, "write_kib": 3.0}}}
-    p = tmp_path / "c.json"
+    p = tmp_path / "k_apply_square40_counters.json"
     p.write_text(json.dumps(rec))
-    monkeypatch.setattr(bench, "COUNTERS", str(p))
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
     assert bench.recorded_traffic("square40", 2) == (10.0 * 2.0 + 3.0) * 1024.0
     assert bench.recorded_traffic("square40", 0) is None          # no record for this lookup
-    assert bench.recorded_traffic("triangular36", 2) is None      # another workload
+    assert bench.recorded_traffic("triangular36", 2) is None      # no record for another workload
     rec["sources_sha256"] = "0" * 64
     p.write_text(json.dumps(rec))
     assert bench.recorded_traffic("square40", 2) is None          # sources changed since the counters
