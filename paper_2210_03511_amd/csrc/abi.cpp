@@ -688,6 +688,32 @@ ed_status ed_index_train(ed_basis *b, const ed_index_cfg *cfg_in, ed_index_stats
     HIP_OK(hipMemcpyAsync(&total, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     if (total >= (1ull << 32)) return fail(ED_EINVAL, "leaf bucket table too large");
+    // leaves whose largest bucket exceeds kMaxWindow keys get more buckets,
+    // a few rounds at most (bucket tables of the rounds are temporary)
+    {
+        uint32_t *d_factor = nullptr;
+        unsigned int *d_count = nullptr;
+        HIP_OK(tmp.alloc((void **)&d_factor, M * sizeof(uint32_t)));
+        HIP_OK(tmp.alloc((void **)&d_count, sizeof(unsigned int)));
+        HIP_OK(hipMemsetAsync(d_factor, 0, M * sizeof(uint32_t), st));
+        for (int round = 0; round < kRefineRounds; ++round) {
+            uint32_t *d_tsub = nullptr;
+            HIP_OK(tmp.alloc((void **)&d_tsub, (total + 1) * sizeof(uint32_t)));
+            HIP_OK(leaf_buckets(b->d_leaves, lg, b->d_reps, d_offsets, d_tsub, d_stats, st));
+            unsigned int refined = 0;
+            HIP_OK(hipMemsetAsync(d_count, 0, sizeof(unsigned int), st));
+            HIP_OK(leaf_refine(b->d_leaves, lg, d_tsub, kMaxWindow, d_factor, d_count, st));
+            HIP_OK(hipMemcpyAsync(&refined, d_count, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
+            HIP_OK(hipStreamSynchronize(st));
+            if (refined == 0) break;
+            HIP_OK(leaf_reshape(b->d_leaves, lg, b->d_reps, target, d_factor, d_sizes, st));
+            HIP_OK(launch_scan(d_sizes, d_offsets, M, d_total, st));
+            HIP_OK(hipMemcpyAsync(&total, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+            HIP_OK(hipStreamSynchronize(st));
+            if (total >= (1ull << 32)) return fail(ED_EINVAL, "leaf bucket table too large");
+        }
+        HIP_OK(hipMemsetAsync(d_stats, 0, 2 * sizeof(unsigned long long), st));
+    }
     if (total + 1 > b->sub_cap) {
         if ((s = dev_alloc(b, (void **)&b->d_sub, (total + 1) * sizeof(uint32_t))) != ED_OK) return s;
         b->sub_cap = total + 1;

@@ -2,11 +2,13 @@
 // (forward, backward, Adam) and the exact leaf-table build.
 //
 // The network maps a representative to an estimate of its normalized rank;
-// that estimate routes the key to one of 2^m leaves.  Each leaf records the
-// position range [lo, hi) of the keys routed to it and the largest distance
-// between a routed key's position and the leaf's linear interpolation, so a
-// binary search inside [pred - err, pred + err] finds every stored key, and
-// reports absence for every other key.  The plain Limits lookup remains the
+// that estimate routes the key to one of 2^m leaves.  The network is
+// monotone, so the keys routed to a leaf fill a position range [lo, hi).
+// Each leaf splits its range into buckets uniform in key space and records
+// where each bucket begins, so a binary search inside the key's bucket finds
+// every stored key and reports absence for every other key.  Leaves whose
+// largest bucket holds more than kMaxWindow keys get proportionally more
+// buckets, a few rounds at most.  The plain Limits lookup remains the
 // reference the learned lookup is compared with.
 #include <hip/hip_runtime.h>
 
@@ -18,6 +20,7 @@ namespace symed {
 namespace {
 
 constexpr int kTB = 64;  // samples per training block
+constexpr uint32_t kMaxRefine = 1024;  // largest bucket refinement factor of a leaf
 
 __device__ __forceinline__ uint64_t splitmix(uint64_t x)
 {
@@ -215,10 +218,12 @@ __global__ void __launch_bounds__(256) k_leaf_range(const float *pwg, int N, int
     }
 }
 
-// key-space bucket count of each leaf: about `target` routed keys per bucket,
-// at most one bucket per position of the range; sizes[b] = entries of the
-// leaf's bucket-begin array (nsub + 1, or 0 for an empty leaf)
-__global__ void k_leaf_shape(Leaf *leaves, uint64_t M, const uint64_t *reps, uint32_t target, uint32_t *sizes)
+// key-space bucket count of each leaf: about `target` keys per bucket, at
+// most one bucket per position of the range, both times the leaf's
+// refinement factor (0 = 1); sizes[b] = entries of the leaf's bucket-begin
+// array (nsub + 1, or 0 for an empty leaf)
+__global__ void k_leaf_shape(Leaf *leaves, uint64_t M, const uint64_t *reps, uint32_t target,
+                             const uint32_t *factor, uint32_t *sizes)
 {
     for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < M; b += (uint64_t)gridDim.x * blockDim.x) {
         Leaf L = leaves[b];
@@ -227,16 +232,17 @@ __global__ void k_leaf_shape(Leaf *leaves, uint64_t M, const uint64_t *reps, uin
             sizes[b] = 0;
             continue;
         }
-        const uint32_t count = L.nsub;
-        uint32_t nsub = (count + target - 1) / target;
+        const uint32_t count = L.hi - L.lo;
+        const uint32_t f = (factor && factor[b]) ? factor[b] : 1u;
+        uint64_t nsub = ((uint64_t)count + target - 1) / target * f;
         if (nsub < 1) nsub = 1;
-        if (nsub > L.hi - L.lo) nsub = L.hi - L.lo;
+        if (nsub > (uint64_t)count * f) nsub = (uint64_t)count * f;
         const uint64_t k0 = reps[L.lo], k1 = reps[L.hi - 1];
         L.kfirst = k0;
-        L.nsub = nsub;
+        L.nsub = (uint32_t)nsub;
         L.scale = (double)nsub / ((double)(k1 - k0) + 1.0);
         leaves[b] = L;
-        sizes[b] = nsub + 1;
+        sizes[b] = (uint32_t)nsub + 1;
     }
 }
 
@@ -276,6 +282,24 @@ __global__ void k_leaf_fill(const Leaf *leaves, uint64_t M, const uint64_t *reps
     }
     atomicAdd(&stats[0], sq);
     atomicMax(&stats[1], mx);
+}
+
+// Leaves whose largest bucket holds more than `window` keys: the
+// refinement factor grows by ceil(largest / window), up to kMaxRefine in
+// all; `count` receives the number of leaves refined.
+__global__ void k_leaf_refine(const Leaf *leaves, uint64_t M, const uint32_t *sub, uint32_t window,
+                              uint32_t *factor, unsigned int *count)
+{
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < M; b += (uint64_t)gridDim.x * blockDim.x) {
+        const Leaf L = leaves[b];
+        if (L.lo >= L.hi) continue;
+        uint32_t mx = 0;
+        for (uint32_t q = 0; q < L.nsub; ++q) mx = max(mx, sub[L.off + q + 1] - sub[L.off + q]);
+        const uint32_t f = factor[b] ? factor[b] : 1u;
+        if (mx <= window || f >= kMaxRefine || L.nsub >= (1u << 22)) continue;
+        factor[b] = min(kMaxRefine, f * ((mx + window - 1) / window));
+        atomicAdd(count, 1u);
+    }
 }
 
 // largest |network estimate * D - position| over all keys
@@ -370,8 +394,27 @@ hipError_t leaf_ranges(const float *d_pw, int N, int lg, const uint64_t *reps, i
     const uint64_t M = 1ull << lg;
     hipLaunchKernelGGL(k_leaf_init, dim3(1024), dim3(256), 0, st, lv, M);
     hipLaunchKernelGGL(k_leaf_range, dim3(blocks), dim3(256), 0, st, d_pw, N, lg, reps, D, lv);
-    hipLaunchKernelGGL(k_leaf_shape, dim3(1024), dim3(256), 0, st, lv, M, reps, target, d_sizes);
+    hipLaunchKernelGGL(k_leaf_shape, dim3(1024), dim3(256), 0, st, lv, M, reps, target, nullptr, d_sizes);
     hipLaunchKernelGGL(k_net_err, dim3(blocks), dim3(256), 0, st, d_pw, N, reps, D, d_net_err);
+    return hipGetLastError();
+}
+
+hipError_t leaf_reshape(void *d_leaves, int lg, const uint64_t *reps, uint32_t target, const uint32_t *d_factor,
+                        uint32_t *d_sizes, hipStream_t st)
+{
+    Leaf *lv = static_cast<Leaf *>(d_leaves);
+    const uint64_t M = 1ull << lg;
+    hipLaunchKernelGGL(k_leaf_shape, dim3(1024), dim3(256), 0, st, lv, M, reps, target, d_factor, d_sizes);
+    return hipGetLastError();
+}
+
+hipError_t leaf_refine(const void *d_leaves, int lg, const uint32_t *d_sub, uint32_t window, uint32_t *d_factor,
+                       unsigned int *d_count, hipStream_t st)
+{
+    const Leaf *lv = static_cast<const Leaf *>(d_leaves);
+    const uint64_t M = 1ull << lg;
+    hipLaunchKernelGGL(k_leaf_refine, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, lv, M, d_sub, window,
+                       d_factor, d_count);
     return hipGetLastError();
 }
 
