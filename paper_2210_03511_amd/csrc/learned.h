@@ -28,7 +28,7 @@ hipError_t leaf_refine(const void *d_leaves, int lg, const uint32_t *d_sub, uint
                        unsigned int *d_count, hipStream_t st);
 // Largest bucket the index build aims for (keys), and refinement rounds.
 constexpr uint32_t kMaxWindow = 64;
-constexpr int kRefineRounds = 4;
+constexpr int kRefineRounds = 6;
 hipError_t index_predict(const float *d_pw, int N, const uint64_t *keys, int64_t n, float *u, float *y, hipStream_t st);
 
 }  // namespace symed
