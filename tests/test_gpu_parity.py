@@ -364,3 +364,55 @@ def test_single_state_and_empty_sectors(S):
             call()
         assert err.value.status == S.ED_EINVAL
     e.free()
+
+
+@pytest.mark.parametrize("case", [(48, 3, 0, (2, 4, 8, 16)), (60, 57, 7, (2, 4, 12)), (63, 3, 0, (3, 9)),
+                                  (63, 60, 5, (3, 9)), (56, 53, 11, (2, 4, 8))], ids=str)
+def test_large_n_sparse_sectors(S, case):
+    """Up to 63 sites (the largest N of the 64-bit encoding), at Sz far from 0
+    so the oracle finishes in milliseconds; with most spins up the
+    representatives carry bits up to the top of the encoding.  The 48-, 56-
+    and 60-site rings keep their 12- to 15-bit Rep/Sym tables in device
+    memory.  Basis bit-exact, H.v against the oracle and identical in all
+    three lookups."""
+    torch = _torch()
+    N, n_up, k, sub = case
+    inst = L.chain(N, k=k, n_up=n_up, sublat=sub)
+    _say("large N", N, n_up, k)
+    reps_o, stabs_o = O.enumerate_basis(inst)
+    b = S.Basis.build(inst)
+    reps, stab = b.export()
+    assert np.array_equal(reps, reps_o) and np.array_equal(stab.astype(np.int64), stabs_o.astype(np.int64))
+    H = O.coo_matrix(inst, reps_o, stabs_o)
+    x = V.start_vector(len(reps), 21, inst.is_complex)
+    ref = H @ x
+    b.train_index(steps=200)
+    b.build_hash()
+    xt = _dev(torch, x)
+    ys = []
+    for mode in (0, 1, 2):
+        yt = torch.zeros_like(xt)
+        b.apply_H(xt, yt, mode=mode)
+        torch.cuda.synchronize()
+        ys.append(yt)
+        assert np.max(np.abs(yt.cpu().numpy() - ref)) < 1e-12
+    assert torch.equal(ys[0], ys[1]) and torch.equal(ys[0], ys[2])
+    keys = _dev(torch, reps.view(np.int64))
+    for mode in (0, 1, 2):
+        idx = torch.empty_like(keys)
+        b.lookup(keys, idx, mode=mode)
+        torch.cuda.synchronize()
+        assert np.array_equal(idx.cpu().numpy(), np.arange(len(reps)))
+    b.free()
+
+
+def test_no_admissible_decomposition_is_refused(S):
+    """A 48-site ring labelled by residues mod 2 and 4 only: 4 sublattices of
+    12 bits give more distinct SymmetryAction tables than 48 KiB hold, and
+    finer contiguous decompositions do not exist in that labelling.  The
+    build refuses it with ED_ENOTSTABLE and says why."""
+    _torch()
+    with pytest.raises(S.EdError) as e:
+        S.Basis.build(L.chain(48, n_up=3, sublat=(2, 4)))
+    assert e.value.status == S.ED_ENOTSTABLE
+    assert "SymmetryAction" in str(e.value)
