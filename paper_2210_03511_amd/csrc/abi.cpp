@@ -683,6 +683,8 @@ ed_status ed_index_train(ed_basis *b, const ed_index_cfg *cfg_in, ed_index_stats
     HIP_OK(tmp.alloc((void **)&d_stats, 2 * sizeof(unsigned long long)));
     HIP_OK(hipMemsetAsync(d_err, 0, sizeof(uint32_t), st));
     HIP_OK(hipMemsetAsync(d_stats, 0, 2 * sizeof(unsigned long long), st));
+    uint32_t *d_leaf_max = nullptr;
+    HIP_OK(tmp.alloc((void **)&d_leaf_max, M * sizeof(uint32_t)));
     HIP_OK(leaf_ranges(d_pw, N, lg, b->d_reps, b->dim, b->d_leaves, target, d_sizes, d_err, 8 * b->n_cu, st));
     HIP_OK(launch_scan(d_sizes, d_offsets, M, d_total, st));
     HIP_OK(hipMemcpyAsync(&total, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
@@ -691,18 +693,22 @@ ed_status ed_index_train(ed_basis *b, const ed_index_cfg *cfg_in, ed_index_stats
     // leaves whose largest bucket exceeds kMaxWindow keys get more buckets,
     // a few rounds at most (bucket tables of the rounds are temporary)
     {
-        uint32_t *d_factor = nullptr;
         unsigned int *d_count = nullptr;
-        HIP_OK(tmp.alloc((void **)&d_factor, M * sizeof(uint32_t)));
         HIP_OK(tmp.alloc((void **)&d_count, sizeof(unsigned int)));
+        uint32_t *d_factor = nullptr;
+        HIP_OK(tmp.alloc((void **)&d_factor, M * sizeof(uint32_t)));
         HIP_OK(hipMemsetAsync(d_factor, 0, M * sizeof(uint32_t), st));
+        uint32_t *d_tsub = nullptr;
+        uint64_t tsub_cap = 0;
         for (int round = 0; round < kRefineRounds; ++round) {
-            uint32_t *d_tsub = nullptr;
-            HIP_OK(tmp.alloc((void **)&d_tsub, (total + 1) * sizeof(uint32_t)));
-            HIP_OK(leaf_buckets(b->d_leaves, lg, b->d_reps, d_offsets, d_tsub, d_stats, st));
+            if (total + 1 > tsub_cap) {
+                HIP_OK(tmp.alloc((void **)&d_tsub, (total + 1) * sizeof(uint32_t)));
+                tsub_cap = total + 1;
+            }
+            HIP_OK(leaf_buckets(b->d_leaves, lg, b->d_reps, d_offsets, d_tsub, d_leaf_max, d_stats, st));
             unsigned int refined = 0;
             HIP_OK(hipMemsetAsync(d_count, 0, sizeof(unsigned int), st));
-            HIP_OK(leaf_refine(b->d_leaves, lg, d_tsub, kMaxWindow, d_factor, d_count, st));
+            HIP_OK(leaf_refine(b->d_leaves, lg, d_leaf_max, kMaxWindow, d_factor, d_count, st));
             HIP_OK(hipMemcpyAsync(&refined, d_count, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
             HIP_OK(hipStreamSynchronize(st));
             if (refined == 0) break;
@@ -718,7 +724,7 @@ ed_status ed_index_train(ed_basis *b, const ed_index_cfg *cfg_in, ed_index_stats
         if ((s = dev_alloc(b, (void **)&b->d_sub, (total + 1) * sizeof(uint32_t))) != ED_OK) return s;
         b->sub_cap = total + 1;
     }
-    HIP_OK(leaf_buckets(b->d_leaves, lg, b->d_reps, d_offsets, b->d_sub, d_stats, st));
+    HIP_OK(leaf_buckets(b->d_leaves, lg, b->d_reps, d_offsets, b->d_sub, d_leaf_max, d_stats, st));
     HIP_OK(hipMemcpyAsync(&net_err, d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HIP_OK(hipMemcpyAsync(hstats, d_stats, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     std::vector<uint32_t> hs(M);

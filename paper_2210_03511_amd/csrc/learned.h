@@ -17,14 +17,15 @@ hipError_t mlp_loss_grad(const float *d_params, int F, const float *d_X, const f
                          float *d_loss, float *d_gpart, float *d_lpart, hipStream_t st);
 hipError_t leaf_ranges(const float *d_pw, int N, int lg, const uint64_t *reps, int64_t D, void *d_leaves,
                        uint32_t target, uint32_t *d_sizes, uint32_t *d_net_err, int blocks, hipStream_t st);
+// Bucket begins at d_offsets, window statistics, largest bucket per leaf.
 hipError_t leaf_buckets(void *d_leaves, int lg, const uint64_t *reps, const uint64_t *d_offsets, uint32_t *d_sub,
-                        unsigned long long *d_stats, hipStream_t st);
+                        uint32_t *d_leaf_max, unsigned long long *d_stats, hipStream_t st);
 // Bucket counts again, with a refinement factor per leaf (0 = 1).
 hipError_t leaf_reshape(void *d_leaves, int lg, const uint64_t *reps, uint32_t target, const uint32_t *d_factor,
                         uint32_t *d_sizes, hipStream_t st);
 // Raise the factor of leaves whose largest bucket exceeds `window` keys;
 // *d_count += leaves raised.
-hipError_t leaf_refine(const void *d_leaves, int lg, const uint32_t *d_sub, uint32_t window, uint32_t *d_factor,
+hipError_t leaf_refine(const void *d_leaves, int lg, const uint32_t *d_leaf_max, uint32_t window, uint32_t *d_factor,
                        unsigned int *d_count, hipStream_t st);
 // Largest bucket the index build aims for (keys), and refinement rounds.
 constexpr uint32_t kMaxWindow = 64;

@@ -12,6 +12,8 @@
 // reference the learned lookup is compared with.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "learned.h"
 #include "learned_dev.h"
 
@@ -200,7 +202,7 @@ __global__ void k_leaf_init(Leaf *leaves, uint64_t M)
         leaves[b] = Leaf{0xffffffffu, 0u, 0u, 0u, 0ull, 0.0};
 }
 
-// position range and key count of every leaf (count kept in nsub for now)
+// position range of every leaf
 __global__ void __launch_bounds__(256) k_leaf_range(const float *pwg, int N, int lg, const uint64_t *reps, int64_t D,
                                                   Leaf *leaves)
 {
@@ -214,7 +216,6 @@ __global__ void __launch_bounds__(256) k_leaf_range(const float *pwg, int N, int
         leaf_of(pw_eval(pw, key_feature(reps[i], N)), lg, b, frac);
         atomicMin(&leaves[b].lo, (uint32_t)i);
         atomicMax(&leaves[b].hi, (uint32_t)(i + 1));
-        atomicAdd(&leaves[b].nsub, 1u);
     }
 }
 
@@ -252,49 +253,78 @@ __global__ void k_leaf_setoff(Leaf *leaves, uint64_t M, const uint64_t *offsets)
         leaves[b].off = (uint32_t)offsets[b];
 }
 
-// bucket begins of one leaf per thread: sub[off + q] = first position of
-// [lo, hi) whose key lies in bucket q or later; sub[off + nsub] = hi
-__global__ void k_leaf_fill(const Leaf *leaves, uint64_t M, const uint64_t *reps, uint32_t *sub,
-                            unsigned long long *stats)
+// Bucket begins, one wavefront per leaf, its lanes over the positions of the
+// leaf's range [lo, hi) (whatever leaf each position is routed to: the FP32
+// evaluation of the network can step back at a breakpoint, so neighbouring
+// ranges may overlap): sub[off + q] = first position of [lo, hi) whose key
+// lies in bucket q or later.  Position p writes the entries of the buckets
+// after its predecessor's up to its own, and the last position also those
+// after its own, ending with sub[off + nsub] = hi.
+__global__ void __launch_bounds__(256) k_leaf_fill(const Leaf *leaves, uint64_t M, const uint64_t *reps,
+                                                 uint32_t *sub)
 {
-    unsigned long long sq = 0, mx = 0;
-    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < M; b += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    for (uint64_t b = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; b < M; b += waves) {
         const Leaf L = leaves[b];
         if (L.lo >= L.hi) continue;
-        uint32_t next = 0, prev = L.lo;
-        for (uint32_t p = L.lo; p < L.hi; ++p) {
+        for (uint32_t p = L.lo + lane; p < L.hi; p += 64) {
             const uint32_t q = leaf_bucket(L, reps[p]);
-            while (next <= q) {
-                sub[L.off + next] = p;
-                ++next;
+            const int64_t q0 = (p == L.lo) ? -1 : (int64_t)leaf_bucket(L, reps[p - 1]);
+            for (int64_t r = q0 + 1; r <= (int64_t)q; ++r) sub[L.off + r] = p;
+            if (p + 1 == L.hi)
+                for (uint32_t r = q + 1; r <= L.nsub; ++r) sub[L.off + r] = L.hi;
+        }
+    }
+}
+
+// Bucket sizes, one wavefront per leaf, from the first position of each
+// bucket: the sum of their squares and their maximum (stats), and the
+// largest bucket of every leaf.
+__global__ void __launch_bounds__(256) k_leaf_stats(const Leaf *leaves, uint64_t M, const uint64_t *reps,
+                                                  const uint32_t *sub, uint32_t *leaf_max,
+                                                  unsigned long long *stats)
+{
+    __shared__ unsigned long long ssq[256];
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    unsigned long long sq = 0, mx = 0;
+    for (uint64_t b = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; b < M; b += waves) {
+        const Leaf L = leaves[b];
+        uint32_t lm = 0;
+        if (L.lo < L.hi) {
+            for (uint32_t p = L.lo + lane; p < L.hi; p += 64) {
+                const uint32_t q = leaf_bucket(L, reps[p]);
+                if (p != L.lo && leaf_bucket(L, reps[p - 1]) == q) continue;
+                const uint32_t w = sub[L.off + q + 1] - p;
+                sq += (unsigned long long)w * w;
+                lm = w > lm ? w : lm;
             }
         }
-        while (next <= L.nsub) {
-            sub[L.off + next] = L.hi;
-            ++next;
-        }
-        for (uint32_t q = 0; q < L.nsub; ++q) {
-            const unsigned long long w = sub[L.off + q + 1] - sub[L.off + q];
-            sq += w * w;
-            mx = w > mx ? w : mx;
-        }
-        (void)prev;
+        for (int o = 32; o > 0; o >>= 1) lm = max(lm, (uint32_t)__shfl_xor((int)lm, o, 64));
+        if (lane == 0) leaf_max[b] = lm;
+        mx = lm > mx ? lm : mx;
     }
-    atomicAdd(&stats[0], sq);
-    atomicMax(&stats[1], mx);
+    ssq[threadIdx.x] = sq;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) ssq[threadIdx.x] += ssq[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(&stats[0], ssq[0]);
+    if (lane == 0) atomicMax(&stats[1], mx);
 }
 
 // Leaves whose largest bucket holds more than `window` keys: the
 // refinement factor grows by ceil(largest / window), up to kMaxRefine in
 // all; `count` receives the number of leaves refined.
-__global__ void k_leaf_refine(const Leaf *leaves, uint64_t M, const uint32_t *sub, uint32_t window,
+__global__ void k_leaf_refine(const Leaf *leaves, uint64_t M, const uint32_t *leaf_max, uint32_t window,
                               uint32_t *factor, unsigned int *count)
 {
     for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < M; b += (uint64_t)gridDim.x * blockDim.x) {
         const Leaf L = leaves[b];
         if (L.lo >= L.hi) continue;
-        uint32_t mx = 0;
-        for (uint32_t q = 0; q < L.nsub; ++q) mx = max(mx, sub[L.off + q + 1] - sub[L.off + q]);
+        const uint32_t mx = leaf_max[b];
         const uint32_t f = factor[b] ? factor[b] : 1u;
         if (mx <= window || f >= kMaxRefine || L.nsub >= (1u << 22)) continue;
         factor[b] = min(kMaxRefine, f * ((mx + window - 1) / window));
@@ -408,23 +438,26 @@ hipError_t leaf_reshape(void *d_leaves, int lg, const uint64_t *reps, uint32_t t
     return hipGetLastError();
 }
 
-hipError_t leaf_refine(const void *d_leaves, int lg, const uint32_t *d_sub, uint32_t window, uint32_t *d_factor,
+hipError_t leaf_refine(const void *d_leaves, int lg, const uint32_t *d_leaf_max, uint32_t window, uint32_t *d_factor,
                        unsigned int *d_count, hipStream_t st)
 {
     const Leaf *lv = static_cast<const Leaf *>(d_leaves);
     const uint64_t M = 1ull << lg;
-    hipLaunchKernelGGL(k_leaf_refine, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, lv, M, d_sub, window,
+    hipLaunchKernelGGL(k_leaf_refine, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, lv, M, d_leaf_max, window,
                        d_factor, d_count);
     return hipGetLastError();
 }
 
 hipError_t leaf_buckets(void *d_leaves, int lg, const uint64_t *reps, const uint64_t *d_offsets, uint32_t *d_sub,
-                        unsigned long long *d_stats, hipStream_t st)
+                        uint32_t *d_leaf_max, unsigned long long *d_stats, hipStream_t st)
 {
     Leaf *lv = static_cast<Leaf *>(d_leaves);
     const uint64_t M = 1ull << lg;
+    // one wavefront per leaf, at most 65536 blocks of four
+    const unsigned blocks = (unsigned)std::min<uint64_t>((M + 3) / 4, 65536);
     hipLaunchKernelGGL(k_leaf_setoff, dim3(1024), dim3(256), 0, st, lv, M, d_offsets);
-    hipLaunchKernelGGL(k_leaf_fill, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, lv, M, reps, d_sub, d_stats);
+    hipLaunchKernelGGL(k_leaf_fill, dim3(blocks), dim3(256), 0, st, lv, M, reps, d_sub);
+    hipLaunchKernelGGL(k_leaf_stats, dim3(blocks), dim3(256), 0, st, lv, M, reps, d_sub, d_leaf_max, d_stats);
     return hipGetLastError();
 }
 
