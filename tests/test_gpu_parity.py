@@ -265,6 +265,9 @@ def test_square32_against_stored_oracle_values(S):
     inst = L.square32()
     b = S.Basis.build(inst)
     assert b.dim == gold["dim"]
+    # 16-bit coarse substates: the Rep/Sym tables (1.4 MB) stay out of LDS
+    info = b.info()
+    assert info["n_sub_rep"] == 2 and info["table_bytes"] < 64 * 1024
     reps, stab = b.export()
     assert int(np.sum(reps, dtype=np.uint64)) == gold["reps_sum_mod_2_64"]
     assert int(np.bitwise_xor.reduce(reps)) == gold["reps_xor"]
