@@ -292,7 +292,10 @@ ed_status ed_eigenvalues(const double *alpha, const double *beta, int32_t n, int
  * of its normalized position; the estimate routes the key to one of
  * 2^log2_leaves leaves.  Each leaf stores the position range of the keys
  * routed to it and splits that range into buckets uniform in key space
- * (about keys_per_bucket keys each) whose begin positions are tabulated; the
+ * (about keys_per_bucket keys each) whose begin positions are tabulated.
+ * Leaves whose largest bucket holds more than 64 keys get proportionally more
+ * buckets (a few rounds), so the search window is at most 64 keys unless a
+ * leaf reaches its refinement cap.  The
  * binary search inside the key's bucket finds every representative and
  * reports absence for every other key, so lookups agree exactly with the
  * plain Limits + binary search of the thesis (section on distributed memory
@@ -305,7 +308,7 @@ ed_status ed_eigenvalues(const double *alpha, const double *beta, int32_t n, int
  * Zero fields mean defaults (n_features = 1 (the only value accepted),
  * hidden = 32 (the only value accepted), steps = 3000, batch = 8192,
  * lr = 1e-2 with cosine decay, log2_leaves ~ log2(dim / 256) (at most 22),
- * keys_per_bucket = 2; 8 halves the table at some cost in speed).
+ * keys_per_bucket = 2; 4 halves the table at some cost in speed).
  */
 typedef struct {
     int32_t n_features;
