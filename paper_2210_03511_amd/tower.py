@@ -16,6 +16,11 @@ Ritz vector and expectation value runs in the HIP kernels behind the C ABI.
   (Lieb-Mattis, bipartite antiferromagnets) the lowest level at Sz = S has
   total spin exactly S, so the head of each list is the S-th level of the
   tower;
+* ``sector_levels`` / ``spin_levels`` - the lowest few levels of every
+  sector at Sz = S, and of them those of total spin exactly S: every level
+  of spin S' > S also lies at Sz = S + 1, so a level at Sz = S below the
+  lowest level of all sectors at Sz = S + 1 has spin S (this holds on any
+  lattice, frustrated or not);
 * ``total_spin`` - S from <S^2> = 3N/4 + 2 sum_{i<j} <S_i . S_j> of a state,
   through the expectation-value kernel with the all-pairs operator (which
   every site permutation and the spin flip leave invariant);
@@ -72,6 +77,80 @@ def lowest_by_spin(make_sectors, spins, n_iter=100, mode=0, seed=1):
     return table
 
 
+def good_ritz(alpha, beta, k, tol=1e-10):
+    """Lowest k distinct eigenvalues of the Lanczos T-matrix with the
+    spurious ones removed (Cullum and Willoughby's test, 1985).  Without
+    reorthogonalization T acquires, besides repeated copies of converged
+    eigenvalues, simple eigenvalues that belong to no eigenvalue of H; each
+    of those is also an eigenvalue of T with its first row and column
+    deleted, to rounding, because the start vector has no weight on it.  A
+    cluster of T eigenvalues equal to 1e-8 (relative) counts once; a simple
+    one closer than ``tol`` (relative to the largest |eigenvalue|) to an
+    eigenvalue of the reduced matrix is dropped."""
+    a = np.ascontiguousarray(alpha, np.float64)
+    b = np.ascontiguousarray(beta, np.float64)
+    n = len(a)
+    lam = symed.eigenvalues(a, b, n)
+    scale = max(1.0, float(np.max(np.abs(lam))))
+    mu = symed.eigenvalues(a[1:], b[1:], n - 1) if n > 1 else np.zeros(0)
+    out = []
+    i = 0
+    while i < n and len(out) < k:
+        j = i + 1
+        while j < n and lam[j] - lam[i] <= 1e-8 * scale:
+            j += 1
+        if j - i > 1 or len(mu) == 0 or np.min(np.abs(mu - lam[i])) > tol * scale:
+            out.append(float(lam[i]))
+        i = j
+    return out
+
+
+def sector_levels(instances, n_iter=100, k=3, mode=0, seed=1, label=None, check=10, log=None):
+    """For every non-empty sector: (label, [lowest k Ritz values], drift,
+    dim).  Lanczos runs min(n_iter, dim) steps from a seeded normal start
+    vector without reorthogonalization; ``good_ritz`` merges the copies of
+    converged levels and drops the spurious ones (one Krylov space sees each
+    eigenvalue once, so a sector's own degeneracies are never resolved
+    anyway).  ``drift``: largest change of the k values over the last
+    ``check`` steps, a convergence measure.  ``label(inst)``
+    names the sector (default: its name); ``log`` receives one line per
+    sector."""
+    import time
+    out = []
+    for inst in instances:
+        t0 = time.perf_counter()
+        b = symed.Basis.build(inst)
+        try:
+            if b.dim == 0:
+                continue
+            if mode == 2:
+                b.build_hash()
+            v0 = _start(b.dim, b.is_complex, seed)
+            a, beta, n, _ = b.lanczos(v0, min(n_iter, b.dim), mode=mode)
+            del v0
+            lv = good_ritz(a[:n], beta[:n], k)
+            drift = 0.0
+            if n > check + k:
+                prev = good_ritz(a[:n - check], beta[:n - check], len(lv))
+                drift = max(abs(x - y) for x, y in zip(lv, prev)) if len(prev) == len(lv) else float("inf")
+            name = label(inst) if label else inst.name
+            out.append((name, lv, drift, b.dim))
+            if log:
+                log(f"  {name:<22s} dim {b.dim:>11d}  {n:3d} steps  {time.perf_counter() - t0:6.1f} s  "
+                    f"drift {drift:.1e}  " + " ".join(f"{e:.8f}" for e in lv))
+        finally:
+            b.free()
+    return out
+
+
+def spin_levels(at_s, at_s1):
+    """Levels of total spin exactly S, sorted: [(E, label)] from
+    ``sector_levels`` output at Sz = S (``at_s``) that lie below the lowest
+    level of every sector at Sz = S + 1 (``at_s1``); also that cut."""
+    cut = min(lv[0] for _, lv, _, _ in at_s1)
+    return sorted((e, name) for name, lv, _, _ in at_s for e in lv if e < cut), cut
+
+
 def all_pairs(n_sites):
     """Bonds (i, j), i < j, of every pair of sites, coupling 1."""
     ij = np.array([(i, j) for i in range(n_sites) for j in range(i + 1, n_sites)], np.int32)
@@ -110,16 +189,41 @@ def _main(argv=None):
 
     from workloads import lattices as L
 
-    ap = argparse.ArgumentParser(description="Tower-of-states sweep of the square Heisenberg (J1-J2) model: the "
-                                             "lowest level of every one-dimensional sector at Sz = S.")
-    ap.add_argument("--sites", type=int, default=32, choices=[16, 32])
+    ap = argparse.ArgumentParser(description="Tower-of-states sweep: the low levels of every one-dimensional "
+                                             "sector at Sz = S, square J1-J2 (16, 32 sites) or triangular J1-J2 "
+                                             "(12, 36 sites, C6v).")
+    ap.add_argument("--lattice", default="square", choices=["square", "triangular"])
+    ap.add_argument("--sites", type=int, default=32, choices=[12, 16, 32, 36])
     ap.add_argument("--J2", type=float, default=0.0)
     ap.add_argument("--spins", type=int, nargs="+", default=[0, 1, 2, 3])
     ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--levels", type=int, default=1, help="levels per sector (more than 1: spin-resolved table)")
+    ap.add_argument("--next-steps", type=int, default=0, help="steps per sector at Sz = S + 1 (spin-resolved)")
     ap.add_argument("--mode", type=int, default=0, choices=[0, 2])
     ap.add_argument("--show", type=int, default=3, help="sectors listed per S")
     a = ap.parse_args(argv)
-    make = L.square32_sectors if a.sites == 32 else L.square16_sectors
+    make = {("square", 32): L.square32_sectors, ("square", 16): L.square16_sectors,
+            ("triangular", 12): L.triangular12_sectors, ("triangular", 36): L.triangular36_sectors}[(a.lattice, a.sites)]
+
+    def say(s):
+        print(s, flush=True)
+
+    if a.levels > 1:
+        # spin-resolved: k levels per sector at Sz = S, lowest levels at Sz = S + 1
+        for S in a.spins:
+            t0 = time.perf_counter()
+            say(f"Sz={S}: {a.levels} levels per sector, {a.steps} steps")
+            at_s = sector_levels(make(J2=a.J2, n_up=a.sites // 2 + S), a.steps, a.levels, a.mode,
+                                 label=L.sector_label, log=say)
+            say(f"Sz={S + 1}: lowest level per sector, {a.next_steps or a.steps} steps")
+            at_s1 = sector_levels(make(J2=a.J2, n_up=a.sites // 2 + S + 1), a.next_steps or a.steps, 1, a.mode,
+                                  label=L.sector_label, log=say)
+            rows, cut = spin_levels(at_s, at_s1)
+            say(f"S={S}: {len(rows)} levels of spin {S} below {cut:.8f} (lowest at Sz={S + 1}), "
+                f"{time.perf_counter() - t0:.1f} s")
+            for e, name in rows:
+                say(f"    {e:.8f}  {name}")
+        return
     for S in a.spins:
         t0 = time.perf_counter()
         rows = lowest_by_spin(lambda s: make(J2=a.J2, n_up=a.sites // 2 + s), [S], a.steps, a.mode)[S]

@@ -8,6 +8,11 @@
   the table's irrep, each level of spin S reappears at Sz < S (an SU(2)
   multiplet), and the Ritz vectors of these levels have <S^2> = S(S+1) from
   the expectation-value kernel with the all-pairs operator.
+* 12-site triangular (C6v): the lowest four levels of every sector at
+  Sz = 0..3 (Lanczos, spurious Ritz values removed by the Cullum-Willoughby
+  test) equal the oracle's dense spectra, and the spin-resolved levels
+  built from them hold the 120-degree tower table's irreps and
+  multiplicities for S = 0, 1, 2.
 """
 import json
 import os
@@ -21,7 +26,9 @@ from workloads import lattices as L
 
 pytestmark = pytest.mark.gpu
 
-GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")))["tos_neel_square"]
+_ALL = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")))
+GOLD = _ALL["tos_neel_square"]
+GOLD120 = _ALL["tos_120_triangular"]
 
 
 def _torch():
@@ -81,6 +88,37 @@ def test_tower_square32_neel_table(T):
             prev = [(e, _label(i)) for e, i in table[S - 1]]
             assert any(abs(e - rows[0][0]) < 1e-7 and lab == _label(rows[0][1]) for e, lab in prev)
     assert all(a < b for a, b in zip(lows, lows[1:]))
+
+
+def test_tower_triangular12_equals_oracle_and_120_table(T):
+    k = 4
+    at, labels = {}, {}
+    for sz in range(4):
+        secs = L.triangular12_sectors(J2=0.0, n_up=6 + sz)
+        at[sz] = T.sector_levels(secs, n_iter=200, k=k)
+        for inst in secs:
+            labels[inst.name] = L.sector_label(inst)
+            reps, stabs = O.enumerate_basis(inst)
+            if not len(reps):
+                continue
+            w = np.linalg.eigvalsh(O.coo_matrix(inst, reps, stabs).toarray())
+            exact = [e for i, e in enumerate(w) if i == 0 or e - w[i - 1] > 1e-8][:k]
+            got = next(lv for name, lv, _, _ in at[sz] if name == inst.name)
+            # the lowest level converges fully; the higher ones of the
+            # tiniest sectors (n_iter = dim) keep a rounding error near 1e-8
+            assert len(got) == len(exact) and abs(got[0] - exact[0]) < 1e-10, inst.name
+            assert np.allclose(got, exact, rtol=0, atol=1e-7), inst.name
+    for S in GOLD120["S"][:3]:
+        rows, cut = T.spin_levels(at[S], at[S + 1])
+        rows = [(e, labels[name]) for e, name in rows]
+        m = {lab: c[GOLD120["S"].index(S)] for lab, c in GOLD120["multiplicity"].items()}
+        n = sum(m.values())
+        _say("triangular12 S", S, "cut", round(cut, 6), [(round(e, 6), lab) for e, lab in rows[:n + 1]])
+        assert sorted(lab for _, lab in rows[:n]) == sorted(lab for lab, c in m.items() for _ in range(c))
+        # a gap above the tower: the next spin-S level, or the cut if no other
+        # level lies below it
+        nxt = rows[n][0] if len(rows) > n else cut
+        assert nxt > rows[n - 1][0] + 0.1
 
 
 def test_tower_square32_levels_and_total_spin(T):

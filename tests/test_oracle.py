@@ -289,6 +289,49 @@ def test_tower_of_states_square16_neel_table():
     assert all(a < b for a, b in zip(emin, emin[1:]))
 
 
+def _minus(a, b, tol=1e-8):
+    """Multiset difference of two eigenvalue lists: the levels of a left after
+    one matching level (within tol) is taken out for every level of b."""
+    left = sorted(a)
+    for x in b:
+        k = int(np.argmin(np.abs(np.array(left) - x)))
+        assert abs(left[k] - x) < tol
+        left.pop(k)
+    return left
+
+
+def test_tower_of_states_triangular12_120_table():
+    """The 12-site triangular Heisenberg antiferromagnet (C6v cluster with
+    the K points): its lowest levels of total spin S = 0, 1, 2 carry exactly
+    the irreps and multiplicities of the thesis's 120-degree tower table
+    (S = 3 needs a sublattice spin of at least 3, i.e. 18 sites or more), a
+    clear gap separates them from the next spin-S level, and the
+    unsymmetrized Sz spectra hold the same levels with K.A1 twice (K and K')
+    and nothing in between, so no two-dimensional irrep intrudes.  A level
+    at Sz = S has spin S when the same sector at Sz = S + 1 lacks it."""
+    g = GOLD["tos_120_triangular"]
+    n, top = 12, 3
+    spec, full = {}, {}
+    for sz in range(top + 1):
+        for inst in L.triangular12_sectors(J2=0.0, n_up=n // 2 + sz):
+            reps, stabs = O.enumerate_basis(inst)
+            if len(reps):
+                w = np.linalg.eigvalsh(O.coo_matrix(inst, reps, stabs).toarray())
+                spec.setdefault((sz, L.sector_label(inst)), []).extend(w)
+        full[sz] = np.linalg.eigvalsh(O.unsym_sector_matrix(inst)[1].toarray())
+    for S in range(top):
+        levels = sorted((e, lab) for (sz, lab), w in spec.items() if sz == S
+                        for e in _minus(w, spec.get((S + 1, lab), [])))
+        m = {k: v[g["S"].index(S)] for k, v in g["multiplicity"].items()}
+        tower = levels[:sum(m.values())]
+        assert sorted(lab for _, lab in tower) == sorted(k for k, c in m.items() for _ in range(c))
+        assert levels[len(tower)][0] > tower[-1][0] + 0.1
+        expanded = sorted(e for e, lab in tower for _ in range(2 if lab.startswith("K.") else 1))
+        spin_s = _minus(full[S], full[S + 1])
+        assert np.allclose(spin_s[:len(expanded)], expanded, atol=1e-9)
+        assert spin_s[len(expanded)] > expanded[-1] + 0.1
+
+
 # --- learned-index network reference -----------------------------------------
 
 def test_mlp_gradient_central_differences():

@@ -1,0 +1,47 @@
+"""Host logic of the tower-of-states sweep: removal of spurious Lanczos Ritz
+values (Cullum-Willoughby test) and the spin-S cut, on T-matrices from the
+oracle's Lanczos (no reorthogonalization) over every sector of the 12-site
+triangular cluster, against dense spectra."""
+import numpy as np
+
+from oracle import oracle as O
+from workloads import lattices as L
+
+
+def _distinct(w, k):
+    return [e for i, e in enumerate(w) if i == 0 or e - w[i - 1] > 1e-8][:k]
+
+
+def test_good_ritz_removes_spurious_values():
+    from paper_2210_03511_amd import tower as T
+    k, fixed = 4, 0
+    for sz in (0, 1):
+        for inst in L.triangular12_sectors(J2=0.0, n_up=6 + sz):
+            reps, stabs = O.enumerate_basis(inst)
+            if not len(reps):
+                continue
+            H = O.coo_matrix(inst, reps, stabs)
+            exact = _distinct(np.linalg.eigvalsh(H.toarray()), k)
+            for seed in range(3):
+                rng = np.random.default_rng(seed)
+                v0 = rng.standard_normal(len(reps))
+                if inst.is_complex:
+                    v0 = v0 + 1j * rng.standard_normal(len(reps))
+                a, b = O.lanczos(lambda v: H @ v, v0, len(reps), hermitian_complex=inst.is_complex)
+                bb = np.zeros(len(a))
+                bb[:min(len(b), len(a))] = b[:len(a)]
+                got = T.good_ritz(a, bb, k)
+                assert len(got) == len(exact) and abs(got[0] - exact[0]) < 1e-10, inst.name
+                assert np.allclose(got, exact, rtol=0, atol=1e-7), inst.name
+                plain = _distinct(T.symed.eigenvalues(a, bb, len(a)), k)
+                fixed += not np.allclose(plain, exact, rtol=0, atol=1e-7)
+    assert fixed > 0        # the cases include T-matrices with a spurious value
+
+
+def test_spin_levels_cut():
+    from paper_2210_03511_amd import tower as T
+    at_s = [("a", [-3.0, -1.0], 0.0, 10), ("b", [-2.5, -2.0], 0.0, 10)]
+    at_s1 = [("a", [-1.5], 0.0, 8), ("b", [-0.5], 0.0, 8)]
+    rows, cut = T.spin_levels(at_s, at_s1)
+    assert cut == -1.5
+    assert rows == [(-3.0, "a"), (-2.5, "b"), (-2.0, "b")]

@@ -320,12 +320,16 @@ TRI_CART = ((1.0, 0.0), (0.5, np.sqrt(3.0) / 2.0))
 
 def square_lattice(L1, L2, sublat_chain, mirrors=True):
     gens = [SQ_R90] + ([SQ_MX] if mirrors else [])
-    return Torus2D(L1, L2, gens, sublat_chain)
+    lat = Torus2D(L1, L2, gens, sublat_chain)
+    lat.kind = "square"
+    return lat
 
 
 def triangular_lattice(L1, L2, sublat_chain, mirrors=False):
     gens = [TRI_R60] + ([TRI_MY] if mirrors else [])
-    return Torus2D(L1, L2, gens, sublat_chain, cart=TRI_CART)
+    lat = Torus2D(L1, L2, gens, sublat_chain, cart=TRI_CART)
+    lat.kind = "triangular"
+    return lat
 
 
 def _irrep_by_name(little, name):
@@ -383,7 +387,8 @@ def triangular_j1j2chi(L1, L2, J1, J2, Jchi, q, irrep="A", flip=1, sublat_chain=
                     n_up=n // 2 if n_up is None else n_up, perms=perms, flips=flips, chi=chis,
                     sublat_options=lat.sublat_options,
                     sector=f"q={tuple(map(str, q))}.{irrep}.{_flipname(flip)}",
-                    meta=dict(lattice=lat, little=little, q=q))
+                    meta=dict(lattice=lat, little=little, q=q, irrep=0 if irrep in ("A", "A1") else irrep,
+                              flip=flip))
 
 
 def _flipname(flip):
@@ -475,17 +480,14 @@ def tri36_K(J2=0.1, Jchi=0.2, flip=1, sublat_chain=TRI36_CHAIN):
     return inst
 
 
-def square_sectors(L, chain, J2=0.5, n_up=None, name="square"):
+def _all_sectors(lat, make, n_up, name):
     """Every one-dimensional sector (k orbit x 1-D irrep of L_k, x flip parity
-    at Sz = 0) of the square J1-J2 model (J1 = 1) on the torus L at the given
-    number of up spins.  Away from Sz = 0 the spin flip is not a symmetry of
-    the sector, so it is left out of the group.  Two-dimensional irreps of the
-    little group are outside the one-dimensional method and not listed.
-    ``meta`` of each instance holds q, the irrep index (0 = A1, the trivial
-    irrep) and the flip parity (None away from Sz = 0)."""
-    lat = square_lattice(L[0], L[1], chain)
+    at Sz = 0) of a torus model at the given number of up spins; ``make(q,
+    irrep_index, flip)`` builds one instance.  Away from Sz = 0 the spin flip
+    is not a symmetry of the sector, so it is left out of the group.
+    Two-dimensional irreps of the little group are outside the
+    one-dimensional method and not listed."""
     n = lat.N
-    n_up = n // 2 if n_up is None else n_up
     flips = (1, -1) if 2 * n_up == n else (None,)
     seen = set()
     out = []
@@ -496,11 +498,67 @@ def square_sectors(L, chain, J2=0.5, n_up=None, name="square"):
         little = lat.little_group(q)
         for ir_i, _ in enumerate(one_dim_irreps(little)):
             for fl in flips:
-                inst = square_j1j2(L[0], L[1], 1.0, J2, q, irrep=ir_i, flip=fl, sublat_chain=chain, n_up=n_up)
+                inst = make(q, ir_i, fl)
                 inst.name = (f"{name}{n}_Sz{Fraction(2 * n_up - n, 2)}_q{float(q[0]):.3f}_{float(q[1]):.3f}_ir{ir_i}"
                              + ("" if fl is None else f"_{_flipname(fl)}"))
                 out.append(inst)
     return out
+
+
+def square_sectors(L, chain, J2=0.5, n_up=None, name="square"):
+    """Every one-dimensional sector of the square J1-J2 model (J1 = 1, point
+    group C4v) on the torus L at the given number of up spins.  ``meta`` of
+    each instance holds q, the irrep index (0 = A1, the trivial irrep) and
+    the flip parity (None away from Sz = 0)."""
+    lat = square_lattice(L[0], L[1], chain)
+    n_up = lat.N // 2 if n_up is None else n_up
+    return _all_sectors(lat, lambda q, ir, fl: square_j1j2(L[0], L[1], 1.0, J2, q, irrep=ir, flip=fl,
+                                                           sublat_chain=chain, n_up=n_up), n_up, name)
+
+
+def triangular_sectors(L, chain, J2=0.0, n_up=None, name="triangular"):
+    """Every one-dimensional sector of the triangular J1-J2 model (J1 = 1,
+    no chirality, point group C6v) on the torus L at the given number of up
+    spins; ``meta`` as for ``square_sectors``."""
+    lat = triangular_lattice(L[0], L[1], chain, mirrors=True)
+    n_up = lat.N // 2 if n_up is None else n_up
+    return _all_sectors(lat, lambda q, ir, fl: triangular_j1j2chi(L[0], L[1], 1.0, J2, 0.0, q, irrep=ir, flip=fl,
+                                                                  sublat_chain=chain, mirrors=True, n_up=n_up),
+                        n_up, name)
+
+
+def pg_character(inst, P):
+    """Character of the sector's point-group irrep on the little-group
+    element P (an integer matrix on lattice coordinates)."""
+    little = inst.meta["little"]
+    return one_dim_irreps(little)[inst.meta["irrep"]][P]
+
+
+def sector_label(inst):
+    """'<momentum>.<irrep>' of a torus sector in the thesis's tower-of-states
+    names: Gamma, M (square (1/2, 1/2); triangular the three edge centres), K
+    (triangular corners (1/3, 2/3), (2/3, 1/3)); the trivial irrep is A1.  On
+    the triangular lattice at Gamma the other one-dimensional irreps of C6v
+    are named by their characters on the 60-degree rotation and on the
+    mirror that contains the bond a1: A2 (+1, -1), B1 (-1, +1), B2 (-1, -1).
+    Other irreps are 'ir<index>'."""
+    lat = inst.meta["lattice"]
+    q = tuple(inst.meta["q"])
+    h = Fraction(1, 2)
+    names = {(Fraction(0), Fraction(0)): "Gamma"}
+    if lat.kind == "square":
+        names[(h, h)] = "M"
+    else:
+        names.update({(Fraction(0), h): "M", (h, Fraction(0)): "M", (h, h): "M",
+                      (Fraction(1, 3), Fraction(2, 3)): "K", (Fraction(2, 3), Fraction(1, 3)): "K"})
+    mom = names.get(q, "(" + ",".join(str(c) for c in q) + ")")
+    ir = inst.meta["irrep"]
+    if ir == 0:
+        return f"{mom}.A1"
+    if lat.kind == "triangular" and mom == "Gamma" and TRI_MY in inst.meta["little"]:
+        c = (round(pg_character(inst, TRI_R60).real), round(pg_character(inst, TRI_MY).real))
+        return "Gamma." + {(1, -1): "A2", (-1, 1): "B1", (-1, -1): "B2"}[c]
+    return f"{mom}.ir{ir}"
 
 
 def square32_sectors(J2=0.5, n_up=None):
@@ -517,6 +575,18 @@ def square32_sectors(J2=0.5, n_up=None):
 def square16_sectors(J2=0.0, n_up=None):
     """Every one-dimensional sector of the 16-site (4 x 4) square J1-J2 model."""
     return square_sectors(SQ16_L, SQ16_CHAIN, J2, n_up)
+
+
+def triangular12_sectors(J2=0.0, n_up=None):
+    """Every one-dimensional sector of the 12-site triangular J1-J2 model
+    (C6v, with the K points)."""
+    return triangular_sectors(TRI12_L, TRI12_CHAIN, J2, n_up)
+
+
+def triangular36_sectors(J2=0.0, n_up=None):
+    """Every one-dimensional sector of the 36-site (6 x 6) triangular J1-J2
+    model (C6v)."""
+    return triangular_sectors(TRI36_L, TRI36_CHAIN, J2, n_up)
 
 
 # ---------------------------------------------------------------------------
