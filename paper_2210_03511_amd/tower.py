@@ -143,11 +143,15 @@ def sector_levels(instances, n_iter=100, k=3, mode=0, seed=1, label=None, check=
     return out
 
 
-def spin_levels(at_s, at_s1):
+def spin_levels(at_s, at_s1, safety=1.0):
     """Levels of total spin exactly S, sorted: [(E, label)] from
     ``sector_levels`` output at Sz = S (``at_s``) that lie below the lowest
-    level of every sector at Sz = S + 1 (``at_s1``); also that cut."""
-    cut = min(lv[0] for _, lv, _, _ in at_s1)
+    level of every sector at Sz = S + 1 (``at_s1``); also that cut.  A Ritz
+    value lies above the level it approximates, so each sector's value at
+    Sz = S + 1 is first lowered by ``safety`` times its drift: a level of
+    higher spin whose copy at Sz = S + 1 is less converged stays above the
+    cut."""
+    cut = min(lv[0] - safety * drift for _, lv, drift, _ in at_s1)
     return sorted((e, name) for name, lv, _, _ in at_s for e in lv if e < cut), cut
 
 
