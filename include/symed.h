@@ -224,6 +224,17 @@ ed_status ed_lanczos_run(const ed_basis *basis, const void *d_v0, int32_t n_iter
  *   the imaginary part (0 up to rounding for Hermitian O; complex sectors
  *   only) to *im (may be NULL).  Allocates a vector of dim entries
  *   temporarily.  Blocks until done.
+ * ed_apply_op: d_y := O d_x for such an operator (same checks) and, when
+ *   d_z is not NULL, <z, y> = sum_i conj(z_i) y_i to *re and *im (im: complex
+ *   sectors; may be NULL).  Two calls give <psi|A B|psi> = <A psi, B psi>
+ *   for Hermitian invariant A and B: the four-spin bond-bond and six-spin
+ *   chirality-chirality correlations of the thesis's order parameters
+ *   (chapter on the triangular J1-J2-Jchi model, nematic and chirality
+ *   order parameters).  Vectors as in ed_apply_H (caller-owned, dim
+ *   entries, y must not alias x; z may be x, y or another vector);
+ *   lookup_mode 1 and 2 stage x into the basis's records, so calls on one
+ *   basis must not overlap.  Allocates O's tables temporarily.  Blocks
+ *   until done.
  */
 ed_status ed_ritz_vector(const double *alpha, const double *beta, int32_t n, int32_t k, double *lambda,
                          double *coef);
@@ -231,6 +242,8 @@ ed_status ed_lanczos_vector(const ed_basis *basis, const void *d_v0, int32_t n_i
                             const double *h_coef, void *d_psi, void *stream);
 ed_status ed_expectation(const ed_basis *basis, const ed_model *op, const void *d_psi, int32_t lookup_mode,
                          double *re, double *im, void *stream);
+ed_status ed_apply_op(const ed_basis *basis, const ed_model *op, const void *d_x, void *d_y, const void *d_z,
+                      int32_t lookup_mode, double *re, double *im, void *stream);
 
 /*
  * Hashed staging table (not in the thesis).  The gather needs, for every

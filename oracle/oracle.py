@@ -21,6 +21,11 @@ What each function follows (thesis sections / equations):
     written out in the unsymmetrized basis.
   * ``spin_correlations`` / ``structure_factor`` - <S_i.S_j> of a state
     from the definition of the spin operators, and their Fourier sum.
+  * ``chirality_correlation`` / ``bond_correlation`` - the summed
+    chirality-chirality and (connected) bond-bond correlations of the
+    chirality and nematic order parameters (chapter on the triangular
+    J1-J2-Jchi model), from explicit spin matrices; ``sector_state`` writes
+    a sector eigenvector out in the unsymmetrized basis.
   * ``lanczos``          - the real-symmetric two-vector step and the
     complex-Hermitian three-vector step ("The Lanczos algorithm"), no
     reorthogonalization; T-matrix eigenvalues by a library tridiagonal solver.
@@ -346,6 +351,72 @@ def structure_factor(C, coords, q):
     r = np.asarray(coords, float)
     ph = np.exp(2j * np.pi * (r @ np.asarray([float(c) for c in q], float)))
     return float(np.real(np.conj(ph) @ C @ ph)) / len(r)
+
+
+def _spin_matrices(n):
+    """S^a_i, a in x, y, z, as sparse 2^n matrices (site 0 leftmost)."""
+    assert n <= 14
+    return {a: [_site_op(m, i, n) for i in range(n)] for a, m in (("x", _SX), ("y", _SY), ("z", _SZ))}
+
+
+def bond_operator(S, i, j):
+    """S_i . S_j = sum_a S^a_i S^a_j."""
+    return sum(S[a][i] @ S[a][j] for a in "xyz")
+
+
+def chirality_operator(S, i, j, k):
+    """S_i . (S_j x S_k) = sum_abc eps_abc S^a_i S^b_j S^c_k."""
+    out = 0
+    for (a, b, c), e in (((("x", "y", "z"), 1), (("y", "z", "x"), 1), (("z", "x", "y"), 1),
+                          (("x", "z", "y"), -1), (("z", "y", "x"), -1), (("y", "x", "z"), -1))):
+        out = out + e * (S[a][i] @ S[b][j] @ S[c][k])
+    return out
+
+
+def sector_state(inst, k=0):
+    """The k-th lowest eigenvector of the symmetrized sector matrix written
+    out in the unsymmetrized Sz configurations (ascending): returns (states,
+    psi), psi normalized."""
+    reps, stabs = enumerate_basis(inst)
+    w, v = np.linalg.eigh(coo_matrix(inst, reps, stabs).toarray())
+    states, _ = unsym_sector_matrix(inst)
+    psi = projector_basis(inst, reps, states) @ v[:, k]
+    return states, psi / np.linalg.norm(psi)
+
+
+def _restricted(M, states):
+    idx = np.asarray(states, np.int64)
+    return M.tocsr()[idx][:, idx]
+
+
+def chirality_correlation(inst, states, psi, t0, triangles):
+    """sum_t <psi|chi_t0 chi_t|psi> over the triangles t (each (i, j, k)),
+    chi = S_i . (S_j x S_k): the summed scalar-chirality correlation of the
+    chirality order parameter (chapter on the triangular J1-J2-Jchi model),
+    from spin matrices."""
+    S = _spin_matrices(inst.n_sites)
+    p = np.asarray(psi, complex)
+    a = _restricted(chirality_operator(S, *t0), states) @ p
+    tot = 0.0
+    for t in triangles:
+        tot += np.vdot(a, _restricted(chirality_operator(S, *t), states) @ p)
+    return tot
+
+
+def bond_correlation(inst, states, psi, b0, bonds, connected=True):
+    """sum_b <psi|(S.S)_b0 (S.S)_b|psi> over the bonds b (each (i, j)), minus
+    <(S.S)_b0><(S.S)_b> when connected: the nematic order parameter's sum
+    over the bonds parallel to b0 (same chapter), from spin matrices."""
+    S = _spin_matrices(inst.n_sites)
+    p = np.asarray(psi, complex)
+    B0 = _restricted(bond_operator(S, *b0), states)
+    a = B0 @ p
+    e0 = np.vdot(p, a)
+    tot = 0.0
+    for b in bonds:
+        y = _restricted(bond_operator(S, *b), states) @ p
+        tot += np.vdot(a, y) - (e0 * np.vdot(p, y) if connected else 0.0)
+    return tot
 
 
 # ---------------------------------------------------------------------------

@@ -1,7 +1,7 @@
 // Ground-state vectors and expectation values (C ABI): the Ritz vector of
 // the tridiagonal T-matrix, a second Lanczos pass that accumulates the
-// eigenvector from the Lanczos vectors, and <psi|O|psi> for a symmetric
-// operator O evaluated with the H.v kernel on O's own pair table.
+// eigenvector from the Lanczos vectors, and O x and <psi|O|psi> for a
+// symmetric operator O evaluated with the H.v kernel on O's own pair table.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -131,11 +131,17 @@ ed_status ed_lanczos_vector(const ed_basis *cb, const void *d_v0, int32_t n_iter
     return done(ED_OK);
 }
 
-ed_status ed_expectation(const ed_basis *cb, const ed_model *op, const void *d_psi, int32_t lookup_mode,
-                         double *h_re, double *h_im, void *stream)
+}  // extern "C"
+
+namespace {
+
+// y = O x for an operator O of the same form as H (bonds, chirality
+// triangles) invariant under the basis's group: O's pair table replaces H's
+// in the H.v kernel.  Enqueued on `s`; the caller synchronizes.  d_blob
+// receives O's tables (freed by the caller).
+ed_status apply_op_enqueue(ed_basis *b, const ed_model *op, const void *d_x, void *d_y, int32_t lookup_mode,
+                           void **d_blob, hipStream_t s)
 {
-    ed_basis *b = const_cast<ed_basis *>(cb);
-    if (!b || !op || !d_psi || !h_re) return fail(ED_EINVAL, "bad arguments");
     if (!(lookup_mode == 0 || (lookup_mode == 1 && b->indexed) || (lookup_mode == 2 && b->hashed)))
         return fail(ED_EINVAL, "lookup_mode not available on this basis");
     if (op->n_sites != b->T.N) return fail(ED_EINVAL, "operator on another number of sites");
@@ -151,11 +157,6 @@ ed_status ed_expectation(const ed_basis *cb, const ed_model *op, const void *d_p
     bool chir = false;
     for (int t = 0; t < op->n_tri; ++t) chir |= op->tri_Jchi[t] != 0.0;
     if (chir && !b->T.is_complex) return fail(ED_EINVAL, "a chirality operator needs a complex sector");
-    if (b->dim == 0) {
-        *h_re = 0.0;
-        if (h_im) *h_im = 0.0;
-        return ED_OK;
-    }
     HostTables T2 = b->T;
     ed_status st = check_invariant(op, T2);
     if (st != ED_OK) return st;
@@ -167,39 +168,105 @@ ed_status ed_expectation(const ed_basis *cb, const ed_model *op, const void *d_p
         return fail(ED_EDEVICE, "device query");
     if ((int64_t)lay2.bytes + (b->lay.bytes - b->lay.off_mlp) + 256 > lds_max)
         return fail(ED_EINVAL, "operator tables exceed the LDS of one block");
-    const bool cplx = b->T.is_complex;
-    const size_t vbytes = (size_t)b->dim * sizeof(double) * (cplx ? 2 : 1);
-    const int nb = b->cfg.vec_blocks;
-    void *d_blob = nullptr, *d_y = nullptr;
-    double *d_part = nullptr;
-    auto cleanup = [&](ed_status r) {
-        (void)hipStreamSynchronize((hipStream_t)stream);
-        (void)hipFree(d_blob);
-        (void)hipFree(d_y);
-        (void)hipFree(d_part);
-        return r;
-    };
-    if (hipMalloc(&d_blob, blob.size()) != hipSuccess || hipMalloc(&d_y, vbytes) != hipSuccess ||
-        hipMalloc((void **)&d_part, 2 * nb * sizeof(double)) != hipSuccess)
-        return cleanup(fail(ED_ENOMEM, "operator workspace"));
-    hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipMemcpyAsync(d_blob, blob.data(), blob.size(), hipMemcpyHostToDevice, s);
+    if (hipMalloc(d_blob, blob.size()) != hipSuccess) return fail(ED_ENOMEM, "operator tables");
+    hipError_t e = hipMemcpyAsync(*d_blob, blob.data(), blob.size(), hipMemcpyHostToDevice, s);
     // the learned index network lives in the blob: carry it over
     if (e == hipSuccess && b->indexed) {
-        e = hipMemcpyAsync(static_cast<unsigned char *>(d_blob) + lay2.off_mlp,
+        e = hipMemcpyAsync(static_cast<unsigned char *>(*d_blob) + lay2.off_mlp,
                            static_cast<const unsigned char *>(b->d_blob) + b->lay.off_mlp, kPwFloats * sizeof(float),
                            hipMemcpyDeviceToDevice, s);
         lay2.bytes = lay2.off_mlp + (b->lay.bytes - b->lay.off_mlp);
     }
     KParams p = make_params(b);
     p.lay = lay2;
-    p.blob = d_blob;
+    p.blob = *d_blob;
     p.n_pairs = (int)T2.pairs.size();
     int bpc = 0, thr = 0;
     if (e == hipSuccess) e = prepare_kernels(p, &bpc, &thr);
-    if (e == hipSuccess) e = stage_input(b, lookup_mode, d_psi, s);
-    if (e == hipSuccess) e = launch_apply(p, b->cfg, d_psi, d_y, 0, lookup_mode, nullptr, nullptr, s);
-    if (e == hipSuccess) e = launch_dot(d_psi, d_y, b->dim, cplx, d_part, nb, s);
+    if (e == hipSuccess) e = stage_input(b, lookup_mode, d_x, s);
+    if (e == hipSuccess) e = launch_apply(p, b->cfg, d_x, d_y, 0, lookup_mode, nullptr, nullptr, s);
+    if (e != hipSuccess) return fail(ED_EDEVICE, std::string("operator apply: ") + hipGetErrorString(e));
+    return ED_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ed_status ed_apply_op(const ed_basis *cb, const ed_model *op, const void *d_x, void *d_y, const void *d_z,
+                      int32_t lookup_mode, double *h_re, double *h_im, void *stream)
+{
+    ed_basis *b = const_cast<ed_basis *>(cb);
+    if (!b || !op || !d_x || !d_y || (d_z && !h_re)) return fail(ED_EINVAL, "bad arguments");
+    if (d_x == d_y) return fail(ED_EINVAL, "y must not alias x");
+    if (d_z) {
+        *h_re = 0.0;
+        if (h_im) *h_im = 0.0;
+    }
+    if (b->dim == 0) return ED_OK;
+    const bool cplx = b->T.is_complex;
+    const int nb = b->cfg.vec_blocks;
+    hipStream_t s = (hipStream_t)stream;
+    void *d_blob = nullptr;
+    double *d_part = nullptr;
+    auto cleanup = [&](ed_status r) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(d_blob);
+        (void)hipFree(d_part);
+        return r;
+    };
+    if (d_z && hipMalloc((void **)&d_part, 2 * nb * sizeof(double)) != hipSuccess)
+        return cleanup(fail(ED_ENOMEM, "dot partials"));
+    ed_status st = apply_op_enqueue(b, op, d_x, d_y, lookup_mode, &d_blob, s);
+    if (st != ED_OK) return cleanup(st);
+    hipError_t e = hipSuccess;
+    std::vector<double> part(2 * nb, 0.0);
+    if (d_z) {
+        e = launch_dot(d_z, d_y, b->dim, cplx, d_part, nb, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(part.data(), d_part, (cplx ? 2 : 1) * nb * sizeof(double), hipMemcpyDeviceToHost, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return cleanup(fail(ED_EDEVICE, std::string("operator apply: ") + hipGetErrorString(e)));
+    if (d_z) {
+        double re = 0.0, im = 0.0;
+        for (int q = 0; q < nb; ++q) re += part[q];
+        if (cplx)
+            for (int q = 0; q < nb; ++q) im += part[nb + q];
+        *h_re = re;
+        if (h_im) *h_im = im;
+    }
+    return cleanup(ED_OK);
+}
+
+ed_status ed_expectation(const ed_basis *cb, const ed_model *op, const void *d_psi, int32_t lookup_mode,
+                         double *h_re, double *h_im, void *stream)
+{
+    ed_basis *b = const_cast<ed_basis *>(cb);
+    if (!b || !op || !d_psi || !h_re) return fail(ED_EINVAL, "bad arguments");
+    if (b->dim == 0) {
+        *h_re = 0.0;
+        if (h_im) *h_im = 0.0;
+        return ED_OK;
+    }
+    const bool cplx = b->T.is_complex;
+    const size_t vbytes = (size_t)b->dim * sizeof(double) * (cplx ? 2 : 1);
+    const int nb = b->cfg.vec_blocks;
+    void *d_blob = nullptr, *d_y = nullptr;
+    double *d_part = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    auto cleanup = [&](ed_status r) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(d_blob);
+        (void)hipFree(d_y);
+        (void)hipFree(d_part);
+        return r;
+    };
+    if (hipMalloc(&d_y, vbytes) != hipSuccess || hipMalloc((void **)&d_part, 2 * nb * sizeof(double)) != hipSuccess)
+        return cleanup(fail(ED_ENOMEM, "operator workspace"));
+    ed_status st = apply_op_enqueue(b, op, d_psi, d_y, lookup_mode, &d_blob, s);
+    if (st != ED_OK) return cleanup(st);
+    hipError_t e = launch_dot(d_psi, d_y, b->dim, cplx, d_part, nb, s);
     std::vector<double> part(2 * nb, 0.0);
     if (e == hipSuccess)
         e = hipMemcpyAsync(part.data(), d_part, (cplx ? 2 : 1) * nb * sizeof(double), hipMemcpyDeviceToHost, s);

@@ -26,7 +26,8 @@ EXPORTED = ["ed_last_error", "ed_version", "ed_basis_build", "ed_basis_free", "e
             "ed_basis_device_reps", "ed_apply_H", "ed_lookup", "ed_lanczos_run", "ed_eigenvalues",
             "ed_tables_inspect", "ed_index_train", "ed_index_info", "ed_mlp_loss_grad",
             "ed_index_predict", "ed_batch_create", "ed_batch_apply", "ed_batch_lanczos", "ed_batch_info",
-            "ed_batch_free", "ed_hash_build", "ed_ritz_vector", "ed_lanczos_vector", "ed_expectation", "ed_lanczos_resume"]
+            "ed_batch_free", "ed_hash_build", "ed_ritz_vector", "ed_lanczos_vector", "ed_expectation", "ed_lanczos_resume",
+            "ed_apply_op"]
 
 
 class EdError(RuntimeError):
@@ -150,6 +151,7 @@ def lib():
         L.ed_ritz_vector.argtypes = [vp, vp, i32, i32, vp, vp]
         L.ed_lanczos_vector.argtypes = [vp, vp, i32, i32, vp, vp, vp]
         L.ed_expectation.argtypes = [vp, ctypes.POINTER(_Model), vp, i32, vp, vp, vp]
+        L.ed_apply_op.argtypes = [vp, ctypes.POINTER(_Model), vp, vp, vp, i32, vp, vp, vp]
         L.ed_hash_build.argtypes = [vp, ctypes.POINTER(HashCfg), ctypes.POINTER(HashStats), vp]
         L.ed_batch_create.argtypes = [vp, i32, ctypes.POINTER(BatchCfg), vp, ctypes.POINTER(vp)]
         L.ed_batch_apply.argtypes = [vp, vp, vp, i32, vp]
@@ -322,21 +324,38 @@ class Basis:
                                        _stream_ptr(stream)))
         return lam, psi
 
-    def expectation(self, psi, bonds=None, bond_J=None, tris=None, tri_Jchi=None, mode=0, stream=None):
-        """<psi|O|psi> for O = sum J S_i.S_j (+ sum Jchi S_i.(S_j x S_k)); O must
-        be invariant under the basis's group.  Returns a complex number."""
+    def _op_model(self, bonds, bond_J, tris, tri_Jchi):
         bonds = np.ascontiguousarray(np.zeros((0, 2)) if bonds is None else bonds, np.int32).reshape(-1)
         bond_J = np.ascontiguousarray(np.zeros(0) if bond_J is None else bond_J, np.float64)
         tris = np.ascontiguousarray(np.zeros((0, 3)) if tris is None else tris, np.int32).reshape(-1)
         tri_Jchi = np.ascontiguousarray(np.zeros(0) if tri_Jchi is None else tri_Jchi, np.float64)
         n_sites = self.info()["n_sites"]
-        m = _Model(n_sites, len(bond_J), _np_ptr(bonds), _np_ptr(bond_J), len(tri_Jchi), _np_ptr(tris),
-                   _np_ptr(tri_Jchi))
+        keep = (bonds, bond_J, tris, tri_Jchi)
+        return _Model(n_sites, len(bond_J), _np_ptr(bonds), _np_ptr(bond_J), len(tri_Jchi), _np_ptr(tris),
+                      _np_ptr(tri_Jchi)), keep
+
+    def expectation(self, psi, bonds=None, bond_J=None, tris=None, tri_Jchi=None, mode=0, stream=None):
+        """<psi|O|psi> for O = sum J S_i.S_j (+ sum Jchi S_i.(S_j x S_k)); O must
+        be invariant under the basis's group.  Returns a complex number."""
+        m, keep = self._op_model(bonds, bond_J, tris, tri_Jchi)
         re = ctypes.c_double(0.0)
         im = ctypes.c_double(0.0)
         _check(lib().ed_expectation(self._h, ctypes.byref(m), _tensor_ptr(psi), int(mode), ctypes.byref(re),
                                     ctypes.byref(im), _stream_ptr(stream)))
+        del keep
         return complex(re.value, im.value)
+
+    def apply_op(self, x, y, bonds=None, bond_J=None, tris=None, tri_Jchi=None, z=None, mode=0, stream=None):
+        """y := O x for O as in ``expectation`` (device vectors of dim
+        entries); with a device vector z also returns <z, y> (complex)."""
+        m, keep = self._op_model(bonds, bond_J, tris, tri_Jchi)
+        re = ctypes.c_double(0.0)
+        im = ctypes.c_double(0.0)
+        _check(lib().ed_apply_op(self._h, ctypes.byref(m), _tensor_ptr(x), _tensor_ptr(y),
+                                 None if z is None else _tensor_ptr(z), int(mode), ctypes.byref(re), ctypes.byref(im),
+                                 _stream_ptr(stream)))
+        del keep
+        return None if z is None else complex(re.value, im.value)
 
     def build_hash(self, load=0.0, stream=None):
         """Build the hashed staging table (lookup mode 2); returns its stats."""

@@ -26,7 +26,13 @@ Ritz vector and expectation value runs in the HIP kernels behind the C ABI.
   every site permutation and the spin flip leave invariant);
 * ``structure_factor`` - S(q), the Fourier sum of the spin correlations (its
   value at the ordering vector measures the order: M = (pi, pi) for the
-  Neel state), through the same kernel.
+  Neel state), through the same kernel;
+* ``chirality_correlation`` / ``nematic`` - the thesis's order parameters
+  that tell tetrahedral from stripy order on the triangular lattice (chapter
+  on the J1-J2-Jchi model): the summed scalar-chirality correlation
+  X = sum_t <chi_0 chi_t> and the connected bond-bond sum
+  N = sum_{b || b0} <(S.S)_b0 (S.S)_b>_c, each from products
+  <A psi, B psi> of two symmetric operators applied by the library.
 """
 from __future__ import annotations
 
@@ -112,7 +118,8 @@ def sector_levels(instances, n_iter=100, k=3, mode=0, seed=1, label=None, check=
     converged levels and drops the spurious ones (one Krylov space sees each
     eigenvalue once, so a sector's own degeneracies are never resolved
     anyway).  ``drift``: largest change of the k values over the last
-    ``check`` steps, a convergence measure.  ``label(inst)``
+    ``check`` steps, a convergence measure (0 when the run spans the whole
+    Krylov space: all dim steps, or a breakdown).  ``label(inst)``
     names the sector (default: its name); ``log`` receives one line per
     sector."""
     import time
@@ -126,11 +133,12 @@ def sector_levels(instances, n_iter=100, k=3, mode=0, seed=1, label=None, check=
             if mode == 2:
                 b.build_hash()
             v0 = _start(b.dim, b.is_complex, seed)
-            a, beta, n, _ = b.lanczos(v0, min(n_iter, b.dim), mode=mode)
+            a, beta, n, broken = b.lanczos(v0, min(n_iter, b.dim), mode=mode)
             del v0
             lv = good_ritz(a[:n], beta[:n], k)
             drift = 0.0
-            if n > check + k:
+            # a run that spans the whole Krylov space (n = dim, or breakdown) is exact
+            if n > check + k and n < b.dim and not broken:
                 prev = good_ritz(a[:n - check], beta[:n - check], len(lv))
                 drift = max(abs(x - y) for x, y in zip(lv, prev)) if len(prev) == len(lv) else float("inf")
             name = label(inst) if label else inst.name
@@ -185,6 +193,55 @@ def structure_factor(basis, psi, coords, qs, mode=0):
     Q = np.array([[float(c) for c in q] for q in qs], float)
     J = (2.0 / n) * np.cos(2.0 * np.pi * (d @ Q.T)).mean(axis=1)
     return 0.75 + basis.expectation(psi, bonds, J, mode=mode).real
+
+
+def _op_args(op):
+    return dict(bonds=op.get("bonds"), bond_J=op.get("bond_J"), tris=op.get("tris"), tri_Jchi=op.get("tri_Jchi"))
+
+
+def product_expectation(basis, psi, A, B, mode=0):
+    """<psi|A B|psi> = <A psi, B psi> for Hermitian operators A and B, each
+    a dict of the ``expectation`` arguments (bonds, bond_J, tris,
+    tri_Jchi), both invariant under the basis's group.  The products and
+    the inner product run in the library (ed_apply_op)."""
+    import torch
+    a = torch.empty_like(psi)
+    if A is B:
+        return basis.apply_op(psi, a, z=a, mode=mode, **_op_args(A))      # |A psi|^2
+    basis.apply_op(psi, a, mode=mode, **_op_args(A))
+    b = torch.empty_like(psi)
+    return basis.apply_op(psi, b, z=a, mode=mode, **_op_args(B))
+
+
+def chirality_correlation(basis, psi, up, down, c6=True, mode=0):
+    """X = sum_t <chi_t0 chi_t> over all elementary triangles t (up and
+    down, counter-clockwise; t0 an up triangle) of a translation-invariant
+    normalized state.  Translations make it (1/N) <X_up X_all>, X_up and
+    X_all the chirality sums over the up and over all triangles.  With the
+    60-degree rotation in the group (``c6``), which swaps up and down
+    triangles, <X_up X_all> = <X_all X_all> / 2 = |X_all psi|^2 / 2, and
+    X_up need not be invariant; otherwise X_up must be."""
+    up = np.asarray(up, np.int32)
+    down = np.asarray(down, np.int32)
+    n = len(up)
+    all_ = dict(tris=np.concatenate([up, down]), tri_Jchi=np.ones(len(up) + len(down)))
+    if c6:
+        return product_expectation(basis, psi, all_, all_, mode).real / (2 * n)
+    return product_expectation(basis, psi, dict(tris=up, tri_Jchi=np.ones(n)), all_, mode).real / n
+
+
+def nematic(basis, psi, bonds, mode=0):
+    """N = sum_b <(S.S)_b0 (S.S)_b>_c over the bonds b parallel to b0, of a
+    translation-invariant normalized state: (<B^2> - <B>^2) / N with B the
+    sum of the N bonds ``bonds`` of one direction.  B must be invariant
+    under the basis's group: build the sector with the point-group elements
+    that keep that direction (a state of higher symmetry lies in the
+    trivial irrep of the smaller group)."""
+    bonds = np.asarray(bonds, np.int32)
+    Bop = dict(bonds=bonds, bond_J=np.ones(len(bonds)))
+    e = basis.expectation(psi, mode=mode, **_op_args(Bop)).real
+    b2 = product_expectation(basis, psi, Bop, Bop, mode).real
+    return (b2 - e * e) / len(bonds)
 
 
 def _main(argv=None):

@@ -132,3 +132,105 @@ def test_expectation_rejects_non_invariant_operator(S):
     assert e.value.status == S.ED_EINVAL
     with pytest.raises(S.EdError):
         b.expectation(psi, tris=np.array([[0, 1, 2]]), tri_Jchi=np.array([1.0]))
+
+
+# --- operator products: order parameters of the triangular J1-J2-Jchi chapter ---
+
+def _tri12(Jchi, J2=0.0, q=L.Q0, pg_gens=None, irrep="A", flip=1):
+    return L.triangular_j1j2chi(L.TRI12_L[0], L.TRI12_L[1], 1.0, J2, Jchi, q, irrep=irrep, flip=flip,
+                                sublat_chain=L.TRI12_CHAIN, pg_gens=pg_gens, name="triangular12")
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_apply_op_equals_oracle_matrix(S, cplx):
+    """y = O x through ed_apply_op (plain and hashed lookup) equals the
+    oracle's symmetrized matrix of O times x, and <z, y> is returned."""
+    torch = _torch()
+    if cplx:
+        inst = _tri12(0.3)                           # Gamma, C6: chirality makes the sector complex
+        up, down = L.triangles(inst)
+        op = dict(bonds=L.bonds_along(inst, (1, 0)).tolist() + L.bonds_along(inst, (0, 1)).tolist()
+                  + L.bonds_along(inst, (-1, 1)).tolist(), tris=np.concatenate([up, down]))
+        op["bond_J"] = np.full(len(op["bonds"]), 0.7)
+        op["tri_Jchi"] = np.full(len(op["tris"]), -1.3)
+    else:
+        inst = L.chain16()
+        op = dict(bonds=L.chain_distance_bonds(inst, 3)[0], bond_J=np.full(16, 0.5))
+    assert inst.is_complex == cplx
+    reps, stabs = O.enumerate_basis(inst)
+    M = O.coo_matrix(_op(inst, op["bonds"], op["bond_J"], op.get("tris"), op.get("tri_Jchi")), reps,
+                     stabs).toarray()
+    b = S.Basis.build(inst)
+    x = V.start_vector(b.dim, 31, cplx)
+    z = V.start_vector(b.dim, 32, cplx)
+    ref = M @ x
+    xd, zd = _dev(torch, x), _dev(torch, z)
+    outs = []
+    for mode in (0, 2):
+        if mode == 2:
+            b.build_hash()
+        y = torch.empty_like(xd)
+        dot = b.apply_op(xd, y, z=zd, mode=mode, **op)
+        got = y.cpu().numpy()
+        assert np.max(np.abs(got - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref)))
+        assert abs(dot - np.vdot(z, ref)) < 1e-10 * max(1.0, abs(np.vdot(z, ref)))
+        outs.append(got)
+    assert np.array_equal(outs[0], outs[1])                   # the lookup does not change the result
+    with pytest.raises(S.EdError):
+        b.apply_op(xd, xd, mode=0, **op)                      # y aliasing x is refused
+    b.free()
+
+
+@pytest.mark.parametrize("where", ["Gamma_C6", "K_C3"])
+def test_chirality_correlation_against_oracle(S, where):
+    """X = sum_t <chi_0 chi_t> of the sector ground state (12-site
+    triangular, J2 = 0.1, Jchi = 0.3): at Gamma (C6) from |X_all psi|^2 / 2N,
+    at K (little group C3) from <X_up psi, X_all psi> / N, against the
+    oracle's spin-matrix products on the same state."""
+    torch = _torch()
+    from paper_2210_03511_amd import tower as T
+    q = L.Q0 if where == "Gamma_C6" else (L.F(1, 3), L.F(2, 3))
+    inst = _tri12(0.3, J2=0.1, q=q)
+    assert (L.TRI_R60 in inst.meta["little"]) == (where == "Gamma_C6")
+    up, down = L.triangles(inst)
+    states, ref_psi = O.sector_state(inst)
+    ref = O.chirality_correlation(inst, states, ref_psi, tuple(up[0]), np.concatenate([up, down]))
+    b = S.Basis.build(inst)
+    e0, psi = b.ground_state(_dev(torch, V.start_vector(b.dim, 5, True)), b.dim)
+    got = T.chirality_correlation(b, psi, up, down, c6=where == "Gamma_C6")
+    print(where, "dim", b.dim, "E0", e0, "X", got, "oracle", ref.real, flush=True)
+    assert abs(ref.imag) < 1e-12
+    assert abs(got - ref.real) < 1e-9
+    b.free()
+
+
+def test_chirality_operator_refused_under_mirrors(S):
+    torch = _torch()
+    inst = _tri12(0.0, J2=0.1, irrep="A1")                    # C6v: the chirality is odd under the mirrors
+    up, down = L.triangles(inst)
+    b = S.Basis.build(inst)
+    psi = _dev(torch, V.start_vector(b.dim, 1, inst.is_complex))
+    with pytest.raises(S.EdError):
+        b.apply_op(psi, torch.empty_like(psi), tris=np.concatenate([up, down]), tri_Jchi=np.ones(2 * len(up)))
+    b.free()
+
+
+@pytest.mark.parametrize("J2", [0.0, 0.2])
+def test_nematic_against_oracle(S, J2):
+    """N = sum_{b || b0} <(S.S)_b0 (S.S)_b>_c of the ground state of the
+    12-site triangular J1-J2 model, bonds along a1, in the sector of the
+    point group {E, C2, the two mirrors that keep a1's direction} (which
+    leaves the bond sum along a1 invariant), against the oracle."""
+    torch = _torch()
+    from paper_2210_03511_amd import tower as T
+    inst = _tri12(0.0, J2=J2, pg_gens=[L.TRI_C2, L.TRI_MY])
+    assert len(inst.meta["little"]) == 4
+    bonds = L.bonds_along(inst, (1, 0))
+    states, ref_psi = O.sector_state(inst)
+    ref = O.bond_correlation(inst, states, ref_psi, tuple(bonds[0]), bonds)
+    b = S.Basis.build(inst)
+    e0, psi = b.ground_state(_dev(torch, V.start_vector(b.dim, 6, inst.is_complex)), min(b.dim, 200))
+    got = T.nematic(b, psi, bonds)
+    print("J2", J2, "dim", b.dim, "E0", e0, "N", got, "oracle", ref.real, flush=True)
+    assert abs(got - ref.real) < 1e-9
+    b.free()

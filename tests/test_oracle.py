@@ -423,3 +423,44 @@ def test_structure_factor_sum_rule_and_singlet_square16():
     # Neel correlations peak at M = (pi, pi)
     sM = O.structure_factor(C, pos, (L.F(1, 2), L.F(1, 2)))
     assert all(sM >= O.structure_factor(C, pos, q) for q in lat.momenta())
+
+
+# --- order-parameter correlations (triangular J1-J2-Jchi chapter) --------------
+
+def _triangle_instance(n_up):
+    return L.Instance("triangle", 3, np.zeros((0, 2), np.int32), np.zeros(0), np.array([[0, 1, 2]], np.int32),
+                      np.ones(1), n_up, np.arange(3, dtype=np.int32)[None], np.zeros(1, np.uint8),
+                      np.ones(1, complex), [1])
+
+
+def test_triangle_chirality_spectrum_and_correlation():
+    """Three spins 1/2: S_0.(S_1 x S_2) is +-sqrt(3)/4 on the two spin-1/2
+    doublets of definite chirality and 0 on the spin-3/2 quartet, so a
+    chiral eigenstate has <chi chi> = 3/16."""
+    S = O._spin_matrices(3)
+    X = O.chirality_operator(S, 0, 1, 2).toarray()
+    assert np.max(np.abs(X - X.conj().T)) < 1e-15
+    r = np.sqrt(3.0) / 4
+    assert np.allclose(np.linalg.eigvalsh(X), [-r, -r, 0, 0, 0, 0, r, r], atol=1e-14)
+    inst = _triangle_instance(2)
+    states, _ = O.unsym_sector_matrix(inst)
+    w, v = np.linalg.eigh(X[np.ix_(states.astype(np.int64), states.astype(np.int64))])
+    assert w[-1] == pytest.approx(r, abs=1e-14)
+    c = O.chirality_correlation(inst, states, v[:, -1], (0, 1, 2), [(0, 1, 2)])
+    assert c == pytest.approx(3.0 / 16, abs=1e-14)
+
+
+def test_bond_correlation_ring4_closed_forms():
+    """4-site ring ground state: the bond sum over the ring is H itself, so
+    for an eigenstate sum_b <(S.S)_b0 (S.S)_b>_c = <b0 H> - <b0><H> = 0; and
+    (S_0.S_1)^2 = 3/16 - (S_0.S_1)/2 for spins 1/2 gives 7/16 at
+    <S_0.S_1> = -1/2."""
+    inst = L.chain(4)
+    states, H = O.unsym_sector_matrix(inst)
+    w, v = np.linalg.eigh(H.toarray())
+    psi = v[:, 0]
+    b0 = tuple(inst.bonds[0])
+    assert O.bond_correlation(inst, states, psi, b0, inst.bonds) == pytest.approx(0.0, abs=1e-13)
+    sq = O.bond_correlation(inst, states, psi, b0, [b0], connected=False)
+    assert sq == pytest.approx(7.0 / 16, abs=1e-13)
+    assert O.bond_correlation(inst, states, psi, b0, inst.bonds, connected=False) == pytest.approx(1.0, abs=1e-13)

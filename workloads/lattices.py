@@ -315,6 +315,7 @@ SQ_R90 = ((0, -1), (1, 0))
 SQ_MX = ((-1, 0), (0, 1))
 TRI_R60 = ((0, -1), (1, 1))        # a1 -> a2, a2 -> a2 - a1
 TRI_MY = ((1, 1), (0, -1))         # a1 -> a1, a2 -> a1 - a2
+TRI_C2 = ((-1, 0), (0, -1))        # inversion through a site
 TRI_CART = ((1.0, 0.0), (0.5, np.sqrt(3.0) / 2.0))
 
 
@@ -325,8 +326,8 @@ def square_lattice(L1, L2, sublat_chain, mirrors=True):
     return lat
 
 
-def triangular_lattice(L1, L2, sublat_chain, mirrors=False):
-    gens = [TRI_R60] + ([TRI_MY] if mirrors else [])
+def triangular_lattice(L1, L2, sublat_chain, mirrors=False, pg_gens=None):
+    gens = pg_gens if pg_gens is not None else [TRI_R60] + ([TRI_MY] if mirrors else [])
     lat = Torus2D(L1, L2, gens, sublat_chain, cart=TRI_CART)
     lat.kind = "triangular"
     return lat
@@ -363,10 +364,12 @@ def square_j1j2(L1, L2, J1, J2, q, irrep="A1", flip=1, sublat_chain=None, mirror
 
 
 def triangular_j1j2chi(L1, L2, J1, J2, Jchi, q, irrep="A", flip=1, sublat_chain=None, mirrors=None,
-                       n_up=None, name="triangular"):
+                       n_up=None, name="triangular", pg_gens=None):
+    """Triangular J1-J2-Jchi model.  Point group: C6, with the mirrors when
+    Jchi = 0 (``mirrors``), or the group generated by ``pg_gens``."""
     if mirrors is None:
         mirrors = (Jchi == 0)
-    lat = triangular_lattice(L1, L2, sublat_chain, mirrors=mirrors)
+    lat = triangular_lattice(L1, L2, sublat_chain, mirrors=mirrors, pg_gens=pg_gens)
     vec1 = [(1, 0), (0, 1), (-1, 1)]
     vec2 = [(1, 1), (-1, 2), (-2, 1)]
     b1 = lat.bonds(vec1)
@@ -375,9 +378,8 @@ def triangular_j1j2chi(L1, L2, J1, J2, Jchi, q, irrep="A", flip=1, sublat_chain=
     bJ = [J1] * len(b1) + [J2] * len(b2)
     tris = []
     if Jchi != 0:
-        for r in lat.coords:
-            tris.append((lat.site(r), lat.site(_add(r, (1, 0))), lat.site(_add(r, (0, 1)))))
-            tris.append((lat.site(_add(r, (1, 0))), lat.site(_add(r, (1, 1))), lat.site(_add(r, (0, 1)))))
+        up, down = _triangles(lat)
+        tris = [t for pair in zip(up, down) for t in pair]
     little = lat.little_group(q)
     rho = _irrep_by_name(little, irrep)
     perms, flips, chis = build_group(lat, q, rho, flip, little)
@@ -389,6 +391,27 @@ def triangular_j1j2chi(L1, L2, J1, J2, Jchi, q, irrep="A", flip=1, sublat_chain=
                     sector=f"q={tuple(map(str, q))}.{irrep}.{_flipname(flip)}",
                     meta=dict(lattice=lat, little=little, q=q, irrep=0 if irrep in ("A", "A1") else irrep,
                               flip=flip))
+
+
+def _triangles(lat):
+    """Elementary triangles, counter-clockwise: up (r, r + a1, r + a2) and
+    down (r + a1, r + a1 + a2, r + a2), one of each per site r."""
+    up = [(lat.site(r), lat.site(_add(r, (1, 0))), lat.site(_add(r, (0, 1)))) for r in lat.coords]
+    down = [(lat.site(_add(r, (1, 0))), lat.site(_add(r, (1, 1))), lat.site(_add(r, (0, 1)))) for r in lat.coords]
+    return up, down
+
+
+def triangles(inst):
+    """(up, down) counter-clockwise elementary triangles of a triangular
+    instance, int32 arrays (N, 3) in its site labels."""
+    up, down = _triangles(inst.meta["lattice"])
+    return np.array(up, np.int32), np.array(down, np.int32)
+
+
+def bonds_along(inst, d):
+    """Bonds (r, r + d) for every site r of a torus instance, int32 (N, 2)."""
+    lat = inst.meta["lattice"]
+    return np.array([(lat.site(r), lat.site(_add(r, d))) for r in lat.coords], np.int32)
 
 
 def _flipname(flip):
