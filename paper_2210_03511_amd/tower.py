@@ -262,7 +262,13 @@ def _main(argv=None):
     ap.add_argument("--next-steps", type=int, default=0, help="steps per sector at Sz = S + 1 (spin-resolved)")
     ap.add_argument("--mode", type=int, default=0, choices=[0, 2])
     ap.add_argument("--show", type=int, default=3, help="sectors listed per S")
+    ap.add_argument("--order", action="store_true",
+                    help="triangular order parameters X and N of the Gamma ground state (with --Jchi)")
+    ap.add_argument("--Jchi", type=float, default=0.0)
     a = ap.parse_args(argv)
+    if a.order:
+        _order_main(a, L)
+        return
     make = {("square", 32): L.square32_sectors, ("square", 16): L.square16_sectors,
             ("triangular", 12): L.triangular12_sectors, ("triangular", 36): L.triangular36_sectors}[(a.lattice, a.sites)]
 
@@ -292,6 +298,46 @@ def _main(argv=None):
         print(f"S={S}: {len(rows)} sectors, {dt:.1f} s", flush=True)
         for e, inst in rows[: a.show]:
             print(f"    {e:.10f}  {inst.name}", flush=True)
+
+
+def _order_main(a, L):
+    """X (sector of C6: chirality needs Jchi != 0, a complex sector) and N
+    (sector of the point-group elements that keep a1's direction) of the
+    Gamma ground state of the triangular J1-J2-Jchi model."""
+    import time
+
+    import torch
+    Lt, ch = {12: (L.TRI12_L, L.TRI12_CHAIN), 36: (L.TRI36_L, L.TRI36_CHAIN)}[a.sites]
+
+    def ground(inst):
+        t0 = time.perf_counter()
+        b = symed.Basis.build(inst)
+        if a.mode == 2:
+            b.build_hash()
+        e0, psi = b.ground_state(_start(b.dim, b.is_complex, 1), min(a.steps, b.dim), mode=a.mode)
+        return b, e0, psi, time.perf_counter() - t0
+
+    if a.Jchi != 0.0:
+        inst = L.triangular_j1j2chi(Lt[0], Lt[1], 1.0, a.J2, a.Jchi, L.Q0, irrep="A", flip=1, sublat_chain=ch)
+        b, e0, psi, dt = ground(inst)
+        up, down = L.triangles(inst)
+        t0 = time.perf_counter()
+        x = chirality_correlation(b, psi, up, down, c6=True, mode=a.mode)
+        print(f"X: Gamma C6 sector, dim {b.dim}, E0 {e0:.10f} ({dt:.1f} s), X = {x:.8f} "
+              f"({time.perf_counter() - t0:.1f} s)", flush=True)
+        del psi
+        b.free()
+    gens = [L.TRI_C2] + ([L.TRI_MY] if a.Jchi == 0.0 else [])
+    inst = L.triangular_j1j2chi(Lt[0], Lt[1], 1.0, a.J2, a.Jchi, L.Q0, irrep="A", flip=1, sublat_chain=ch,
+                                pg_gens=gens)
+    b, e0, psi, dt = ground(inst)
+    t0 = time.perf_counter()
+    nem = nematic(b, psi, L.bonds_along(inst, (1, 0)), mode=a.mode)
+    print(f"N: Gamma sector of {len(inst.meta['little'])} point-group elements, dim {b.dim}, E0 {e0:.10f} "
+          f"({dt:.1f} s), N = {nem:.8f} ({time.perf_counter() - t0:.1f} s)", flush=True)
+    del psi
+    b.free()
+    torch.cuda.synchronize()
 
 
 if __name__ == "__main__":
