@@ -419,6 +419,20 @@ def bond_correlation(inst, states, psi, b0, bonds, connected=True):
     return tot
 
 
+def sector_resolvent(inst, psi, op_inst, z):
+    """G(z) = <psi|O^dag (z - H)^-1 O|psi> for a vector psi of the sector
+    (symmetrized basis, dense) and an operator O given as an instance with
+    the sector's group: the spectral sum sum_n |<n|O psi>|^2 / (z - E_n)
+    over the eigenpairs of the dense sector matrix (the quantity the
+    continued-fraction expansion approximates, outlook chapter)."""
+    reps, stabs = enumerate_basis(inst)
+    w, V = np.linalg.eigh(coo_matrix(inst, reps, stabs).toarray())
+    phi = coo_matrix(op_inst, reps, stabs).toarray() @ np.asarray(psi)
+    amp2 = np.abs(V.conj().T @ phi) ** 2
+    z = np.asarray(z, complex)
+    return (amp2[None, :] / (z.reshape(-1, 1) - w[None, :])).sum(axis=1).reshape(z.shape)
+
+
 # ---------------------------------------------------------------------------
 # Lanczos
 # ---------------------------------------------------------------------------

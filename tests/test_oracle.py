@@ -464,3 +464,20 @@ def test_bond_correlation_ring4_closed_forms():
     sq = O.bond_correlation(inst, states, psi, b0, [b0], connected=False)
     assert sq == pytest.approx(7.0 / 16, abs=1e-13)
     assert O.bond_correlation(inst, states, psi, b0, inst.bonds, connected=False) == pytest.approx(1.0, abs=1e-13)
+
+
+def test_resolvent_ring4_single_pole():
+    """O = H on the 4-site ring ground state: O psi = E0 psi, so the
+    resolvent has the single pole E0 with weight E0^2: 4 / (z + 2)."""
+    inst = L.chain(4)
+    reps, stabs = O.enumerate_basis(inst)
+    w, v = np.linalg.eigh(O.coo_matrix(inst, reps, stabs).toarray())
+    z = np.array([0.3 + 0.1j, -1.0 + 0.05j, 2.0 + 1.0j, -2.0 + 0.01j])
+    G = O.sector_resolvent(inst, v[:, 0], inst, z)
+    assert np.allclose(G, 4.0 / (z + 2.0), rtol=1e-13, atol=1e-13)
+    # the pairs (0, 2) and (1, 3) each form spin 1 in that state, so
+    # S_0.S_2 = S_1.S_3 = 1/4 on it: O = (S_0.S_2 + S_1.S_3)/2 (the distance-2
+    # bonds at weight 1/4, each pair twice) has the single pole E0, weight 1/16
+    b2, J2 = L.chain_distance_bonds(inst, 2)
+    G2 = O.sector_resolvent(inst, v[:, 0], _op_instance(inst, b2, J2), z)
+    assert np.allclose(G2, (1.0 / 16) / (z + 2.0), rtol=1e-13, atol=1e-13)
