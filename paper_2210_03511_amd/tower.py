@@ -267,10 +267,16 @@ def _main(argv=None):
     ap.add_argument("--Jchi", type=float, default=0.0)
     a = ap.parse_args(argv)
     if a.order:
+        if a.lattice != "triangular" or a.sites not in (12, 36):
+            ap.error("--order needs --lattice triangular and --sites 12 or 36")
         _order_main(a, L)
         return
-    make = {("square", 32): L.square32_sectors, ("square", 16): L.square16_sectors,
-            ("triangular", 12): L.triangular12_sectors, ("triangular", 36): L.triangular36_sectors}[(a.lattice, a.sites)]
+    makers = {("square", 32): L.square32_sectors, ("square", 16): L.square16_sectors,
+              ("triangular", 12): L.triangular12_sectors, ("triangular", 36): L.triangular36_sectors}
+    if (a.lattice, a.sites) not in makers:
+        ap.error(f"no {a.sites}-site {a.lattice} cluster; available: "
+                 + ", ".join(f"{lat} {n}" for lat, n in makers))
+    make = makers[(a.lattice, a.sites)]
 
     def say(s):
         print(s, flush=True)

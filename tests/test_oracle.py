@@ -481,3 +481,25 @@ def test_resolvent_ring4_single_pole():
     b2, J2 = L.chain_distance_bonds(inst, 2)
     G2 = O.sector_resolvent(inst, v[:, 0], _op_instance(inst, b2, J2), z)
     assert np.allclose(G2, (1.0 / 16) / (z + 2.0), rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_sector_state_is_symmetric_eigenvector(k):
+    """The k-th sector eigenvector written out in the Sz configurations is an
+    eigenvector of the unsymmetrized H with the same energy, and every group
+    element g maps it to chi(g) times itself: with the projector
+    sum_g conj(chi(g)) g, h P = chi(h) P.  Here for a complex sector (K
+    point, chirality on), where a wrong conjugation shows."""
+    inst = L.small_instances()[15]
+    assert inst.is_complex
+    reps, stabs = O.enumerate_basis(inst)
+    w = np.linalg.eigvalsh(O.coo_matrix(inst, reps, stabs).toarray())
+    states, psi = O.sector_state(inst, k)
+    _, Hs = O.unsym_sector_matrix(inst)
+    assert np.linalg.norm(Hs @ psi - w[k] * psi) < 1e-11
+    pos = {int(s): i for i, s in enumerate(states)}
+    for g in range(inst.n_elem):
+        img = O.apply_group_numpy(inst, g, states)
+        moved = np.zeros_like(psi)
+        moved[[pos[int(t)] for t in img]] = psi
+        assert np.linalg.norm(moved - inst.chi[g] * psi) < 1e-11
