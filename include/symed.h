@@ -235,6 +235,8 @@ ed_status ed_lanczos_run(const ed_basis *basis, const void *d_v0, int32_t n_iter
  *   lookup_mode 1 and 2 stage x into the basis's records, so calls on one
  *   basis must not overlap.  Allocates O's tables temporarily.  Blocks
  *   until done.
+ * On an empty sector (dim 0) ed_expectation and ed_apply_op return ED_OK at
+ *   once with *re = *im = 0, before the operator is checked.
  */
 ed_status ed_ritz_vector(const double *alpha, const double *beta, int32_t n, int32_t k, double *lambda,
                          double *coef);
