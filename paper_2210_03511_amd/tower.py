@@ -341,6 +341,14 @@ def _order_main(a, L):
     nem = nematic(b, psi, L.bonds_along(inst, (1, 0)), mode=a.mode)
     print(f"N: Gamma sector of {len(inst.meta['little'])} point-group elements, dim {b.dim}, E0 {e0:.10f} "
           f"({dt:.1f} s), N = {nem:.8f} ({time.perf_counter() - t0:.1f} s)", flush=True)
+    # S(q) over the whole C6v star of q (a union of orbits of the sector's group)
+    pg6v = L.triangular_lattice(Lt[0], Lt[1], ch, mirrors=True).pg
+    pos = L.site_coords(inst)
+    h, t = L.Fraction(1, 2), L.Fraction(1, 3)
+    for name, q in (("Gamma", L.Q0), ("K", (t, 2 * t)), ("M", (h, L.Fraction(0)))):
+        star = L.momentum_star(inst, q, pg6v)
+        print(f"   S({name}) = {structure_factor(b, psi, pos, star, mode=a.mode):.8f} (star of {len(star)})",
+              flush=True)
     del psi
     b.free()
     torch.cuda.synchronize()

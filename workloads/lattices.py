@@ -677,13 +677,13 @@ def site_coords(inst):
     return np.array(inst.meta["positions"], dtype=np.int64)[:, None]
 
 
-def momentum_star(inst, q):
-    """The momenta P^T q (mod 1) over the point group of a torus instance, as
-    Fractions (q itself for a chain)."""
+def momentum_star(inst, q, pg=None):
+    """The momenta P^T q (mod 1) over the point group of a torus instance
+    (or over the matrices ``pg``), as Fractions (q itself for a chain)."""
     if "lattice" not in inst.meta:
         return [tuple(q)]
     out = []
-    for P in inst.meta["lattice"].pg:
+    for P in (inst.meta["lattice"].pg if pg is None else pg):
         qp = (P[0][0] * q[0] + P[1][0] * q[1], P[0][1] * q[0] + P[1][1] * q[1])
         qp = tuple(c - (c.numerator // c.denominator) for c in qp)
         if qp not in out:
