@@ -262,6 +262,8 @@ def _main(argv=None):
     ap.add_argument("--next-steps", type=int, default=0, help="steps per sector at Sz = S + 1 (spin-resolved)")
     ap.add_argument("--mode", type=int, default=0, choices=[0, 2])
     ap.add_argument("--show", type=int, default=3, help="sectors listed per S")
+    ap.add_argument("--with-e", action="store_true",
+                    help="spin-resolved sweep: add the sectors of the 2-D irreps (E, E1, E2)")
     ap.add_argument("--order", action="store_true",
                     help="triangular order parameters X and N of the Gamma ground state (with --Jchi)")
     ap.add_argument("--Jchi", type=float, default=0.0)
@@ -277,6 +279,14 @@ def _main(argv=None):
         ap.error(f"no {a.sites}-site {a.lattice} cluster; available: "
                  + ", ".join(f"{lat} {n}" for lat, n in makers))
     make = makers[(a.lattice, a.sites)]
+    if a.with_e:
+        geo = {("square", 32): (L.SQ32_L, L.SQ32_CHAIN), ("square", 16): (L.SQ16_L, L.SQ16_CHAIN),
+               ("triangular", 12): (L.TRI12_L, L.TRI12_CHAIN),
+               ("triangular", 36): (L.TRI36_L, L.TRI36_CHAIN)}[(a.lattice, a.sites)]
+        base = make
+
+        def make(J2, n_up):
+            return base(J2=J2, n_up=n_up) + L.two_dim_sectors(a.lattice, geo[0], geo[1], J2=J2, n_up=n_up)
 
     def say(s):
         print(s, flush=True)

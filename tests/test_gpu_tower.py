@@ -12,7 +12,8 @@
   Sz = 0..3 (Lanczos, spurious Ritz values removed by the Cullum-Willoughby
   test) equal the oracle's dense spectra, and the spin-resolved levels
   built from them hold the 120-degree tower table's irreps and
-  multiplicities for S = 0, 1, 2.
+  multiplicities for S = 0, 1, 2; the sectors of the 2-D irreps (E1, E2 at
+  Gamma, E at K) give the oracle's levels too.
 """
 import json
 import os
@@ -119,6 +120,21 @@ def test_tower_triangular12_equals_oracle_and_120_table(T):
         # level lies below it
         nxt = rows[n][0] if len(rows) > n else cut
         assert nxt > rows[n - 1][0] + 0.1
+
+
+def test_two_dim_irrep_sectors_equal_oracle(T):
+    k = 4
+    for sz in (0, 1):
+        secs = L.two_dim_sectors("triangular", L.TRI12_L, L.TRI12_CHAIN, J2=0.1, n_up=6 + sz)
+        got = T.sector_levels(secs, n_iter=200, k=k, label=L.sector_label)
+        assert [g[0] for g in got] == [L.sector_label(i) for i in secs if len(O.enumerate_basis(i)[0])]
+        for (name, lv, _, _), inst in zip(got, [i for i in secs if len(O.enumerate_basis(i)[0])]):
+            reps, stabs = O.enumerate_basis(inst)
+            w = np.linalg.eigvalsh(O.coo_matrix(inst, reps, stabs).toarray())
+            exact = [e for i, e in enumerate(w) if i == 0 or e - w[i - 1] > 1e-8][:k]
+            _say("triangular12 Sz", sz, name, [round(e, 8) for e in lv])
+            assert len(lv) == len(exact) and abs(lv[0] - exact[0]) < 1e-10, inst.name
+            assert np.allclose(lv, exact, rtol=0, atol=1e-7), inst.name
 
 
 def test_tower_square32_levels_and_total_spin(T):

@@ -503,3 +503,45 @@ def test_sector_state_is_symmetric_eigenvector(k):
         moved = np.zeros_like(psi)
         moved[[pos[int(t)] for t in img]] = psi
         assert np.linalg.norm(moved - inst.chi[g] * psi) < 1e-11
+
+
+def _spectrum(insts):
+    out = []
+    for inst in insts:
+        reps, stabs = O.enumerate_basis(inst)
+        if len(reps):
+            out.extend(np.linalg.eigvalsh(O.coo_matrix(inst, reps, stabs).toarray()))
+    return np.sort(out)
+
+
+@pytest.mark.parametrize("kind,sz", [("triangular", 0), ("triangular", 1), ("square", 0), ("square", 1)])
+def test_two_dim_irreps_complete_the_spectrum(kind, sz):
+    """At every momentum whose little group is C_nv (n >= 3), the levels of
+    the one-dimensional sectors plus those of the rotation-subgroup sectors
+    of the two-dimensional irreps, each counted twice, are exactly the
+    spectrum of the same momentum with translations only (12-site
+    triangular: Gamma (E1, E2) and K (E); 16-site square: Gamma and M)."""
+    if kind == "triangular":
+        Lt, ch, J2, n = L.TRI12_L, L.TRI12_CHAIN, 0.1, 12
+        one = L.triangular_sectors(Lt, ch, J2=J2, n_up=n // 2 + sz)
+
+        def trans_only(q, fl):
+            return L.triangular_j1j2chi(Lt[0], Lt[1], 1.0, J2, 0.0, q, irrep="A", flip=fl, sublat_chain=ch,
+                                        pg_gens=[], n_up=n // 2 + sz)
+    else:
+        Lt, ch, J2, n = L.SQ16_L, L.SQ16_CHAIN, 0.3, 16
+        one = L.square_sectors(Lt, ch, J2=J2, n_up=n // 2 + sz)
+
+        def trans_only(q, fl):
+            return L.square_j1j2(Lt[0], Lt[1], 1.0, J2, q, irrep="A1", flip=fl, sublat_chain=ch, pg_gens=[],
+                                 n_up=n // 2 + sz)
+    two = L.two_dim_sectors(kind, Lt, ch, J2=J2, n_up=n // 2 + sz)
+    flips = (1, -1) if sz == 0 else (None,)
+    qs = sorted({tuple(i.meta["q"]) for i in two})
+    assert len(qs) == 2
+    for q in qs:
+        got = np.sort(np.concatenate([_spectrum([i for i in one if tuple(i.meta["q"]) == q]),
+                                      np.repeat(_spectrum([i for i in two if tuple(i.meta["q"]) == q]), 2)]))
+        ref = _spectrum([trans_only(q, fl) for fl in flips])
+        assert len(got) == len(ref) and np.allclose(got, ref, atol=1e-10), (kind, sz, q)
+        assert any(len(O.enumerate_basis(i)[0]) for i in two if tuple(i.meta["q"]) == q)

@@ -319,8 +319,8 @@ TRI_C2 = ((-1, 0), (0, -1))        # inversion through a site
 TRI_CART = ((1.0, 0.0), (0.5, np.sqrt(3.0) / 2.0))
 
 
-def square_lattice(L1, L2, sublat_chain, mirrors=True):
-    gens = [SQ_R90] + ([SQ_MX] if mirrors else [])
+def square_lattice(L1, L2, sublat_chain, mirrors=True, pg_gens=None):
+    gens = pg_gens if pg_gens is not None else [SQ_R90] + ([SQ_MX] if mirrors else [])
     lat = Torus2D(L1, L2, gens, sublat_chain)
     lat.kind = "square"
     return lat
@@ -343,8 +343,8 @@ def _irrep_by_name(little, name):
 
 
 def square_j1j2(L1, L2, J1, J2, q, irrep="A1", flip=1, sublat_chain=None, mirrors=True,
-                n_up=None, name="square"):
-    lat = square_lattice(L1, L2, sublat_chain, mirrors=mirrors)
+                n_up=None, name="square", pg_gens=None):
+    lat = square_lattice(L1, L2, sublat_chain, mirrors=mirrors, pg_gens=pg_gens)
     vec1 = [(1, 0), (0, 1)]
     vec2 = [(1, 1), (1, -1)]
     b1 = lat.bonds(vec1)
@@ -557,6 +557,17 @@ def pg_character(inst, P):
     return one_dim_irreps(little)[inst.meta["irrep"]][P]
 
 
+def _momentum_name(kind, q):
+    h = Fraction(1, 2)
+    names = {(Fraction(0), Fraction(0)): "Gamma"}
+    if kind == "square":
+        names[(h, h)] = "M"
+    else:
+        names.update({(Fraction(0), h): "M", (h, Fraction(0)): "M", (h, h): "M",
+                      (Fraction(1, 3), Fraction(2, 3)): "K", (Fraction(2, 3), Fraction(1, 3)): "K"})
+    return names.get(tuple(q), "(" + ",".join(str(c) for c in q) + ")")
+
+
 def sector_label(inst):
     """'<momentum>.<irrep>' of a torus sector in the thesis's tower-of-states
     names: Gamma, M (square (1/2, 1/2); triangular the three edge centres), K
@@ -564,17 +575,12 @@ def sector_label(inst):
     the triangular lattice at Gamma the other one-dimensional irreps of C6v
     are named by their characters on the 60-degree rotation and on the
     mirror that contains the bond a1: A2 (+1, -1), B1 (-1, +1), B2 (-1, -1).
-    Other irreps are 'ir<index>'."""
+    Sectors of ``two_dim_sectors`` carry their E label.  Other irreps are
+    'ir<index>'."""
+    if "label" in inst.meta:
+        return inst.meta["label"]
     lat = inst.meta["lattice"]
-    q = tuple(inst.meta["q"])
-    h = Fraction(1, 2)
-    names = {(Fraction(0), Fraction(0)): "Gamma"}
-    if lat.kind == "square":
-        names[(h, h)] = "M"
-    else:
-        names.update({(Fraction(0), h): "M", (h, Fraction(0)): "M", (h, h): "M",
-                      (Fraction(1, 3), Fraction(2, 3)): "K", (Fraction(2, 3), Fraction(1, 3)): "K"})
-    mom = names.get(q, "(" + ",".join(str(c) for c in q) + ")")
+    mom = _momentum_name(lat.kind, inst.meta["q"])
     ir = inst.meta["irrep"]
     if ir == 0:
         return f"{mom}.A1"
@@ -582,6 +588,61 @@ def sector_label(inst):
         c = (round(pg_character(inst, TRI_R60).real), round(pg_character(inst, TRI_MY).real))
         return "Gamma." + {(1, -1): "A2", (-1, 1): "B1", (-1, -1): "B2"}[c]
     return f"{mom}.ir{ir}"
+
+
+def two_dim_sectors(kind, L, chain, J2=0.0, n_up=None, name=None):
+    """Sectors that hold the levels of the two-dimensional irreps of the
+    point group, which the one-dimensional method cannot build directly.
+    Where the little group of q is C_nv with n >= 3 (Gamma and M of the
+    square lattice, Gamma and K of the triangular one), each 2-D irrep
+    restricted to the rotations C_n is the pair of 1-D irreps with
+    chi(R) = exp(+-2 pi i m / n), R the smallest rotation: m = 1 for E of
+    C3v and C4v, m = 1 (E1) and m = 2 (E2) for C6v.  One sector per pair is
+    built (the other holds the same levels), with the group T x| C_n
+    (x flip at Sz = 0); ``meta['label']`` is '<momentum>.E', '.E1' or '.E2'.
+    Each level of such a sector is one 2-D multiplet of the full group."""
+    if kind == "square":
+        full = square_lattice(L[0], L[1], chain, mirrors=True)
+        rot = square_lattice(L[0], L[1], chain, mirrors=False)
+        R, turns = SQ_R90, 4
+    else:
+        full = triangular_lattice(L[0], L[1], chain, mirrors=True)
+        rot = triangular_lattice(L[0], L[1], chain, mirrors=False)
+        R, turns = TRI_R60, 6
+    n = full.N
+    n_up = n // 2 if n_up is None else n_up
+    flips = (1, -1) if 2 * n_up == n else (None,)
+    seen = set()
+    out = []
+    for q in full.momenta():
+        if q in seen:
+            continue
+        seen |= _pg_orbit(full, q)
+        little = rot.little_group(q)
+        order = len(little)
+        if order < 3 or len(full.little_group(q)) != 2 * order:
+            continue
+        gen = ((1, 0), (0, 1))
+        for _ in range(turns // order):
+            gen = _matmul(R, gen)
+        irreps = one_dim_irreps(little)
+        mom = _momentum_name(kind, q)
+        for m in range(1, (order - 1) // 2 + 1):
+            target = np.exp(2j * np.pi * m / order)
+            idx = next(i for i, ir in enumerate(irreps) if abs(ir[gen] - target) < 1e-9)
+            lab = f"{mom}.E{m}" if order == 6 else f"{mom}.E"
+            for fl in flips:
+                if kind == "square":
+                    inst = square_j1j2(L[0], L[1], 1.0, J2, q, irrep=idx, flip=fl, sublat_chain=chain,
+                                       mirrors=False, n_up=n_up)
+                else:
+                    inst = triangular_j1j2chi(L[0], L[1], 1.0, J2, 0.0, q, irrep=idx, flip=fl, sublat_chain=chain,
+                                              mirrors=False, n_up=n_up)
+                inst.meta["label"] = lab
+                inst.name = (f"{name or kind}{n}_Sz{Fraction(2 * n_up - n, 2)}_{lab}"
+                             + ("" if fl is None else f"_{_flipname(fl)}"))
+                out.append(inst)
+    return out
 
 
 def square32_sectors(J2=0.5, n_up=None):
