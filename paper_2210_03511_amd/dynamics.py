@@ -24,7 +24,6 @@ from __future__ import annotations
 import numpy as np
 
 
-
 def continued_fraction(alpha, beta, z, weight=1.0):
     """weight / (z - a_0 - b_0^2 / (z - a_1 - ... - b_{n-2}^2 / (z - a_{n-1})))
     for the T-matrix with diagonal alpha[n] and off-diagonal beta[:n-1],

@@ -45,3 +45,16 @@ def test_spin_levels_cut():
     rows, cut = T.spin_levels(at_s, at_s1)
     assert cut == -1.5
     assert rows == [(-3.0, "a"), (-2.5, "b"), (-2.0, "b")]
+
+
+def test_spin_levels_cut_lowered_by_drift():
+    """A less converged copy of a higher-spin level at Sz = S + 1 (Ritz value
+    above the level, drift 0.01) must not let that level pass as spin S."""
+    from paper_2210_03511_amd import tower as T
+    at_s = [("a", [-3.0, -2.0005], 0.0, 10)]           # -2.0005: a spin-(S+1) level, converged at Sz = S
+    at_s1 = [("a", [-2.0], 0.01, 8)]                    # its copy at Sz = S + 1, not yet converged
+    rows, cut = T.spin_levels(at_s, at_s1)
+    assert cut == -2.01
+    assert rows == [(-3.0, "a")]
+    rows0, cut0 = T.spin_levels(at_s, at_s1, safety=0.0)
+    assert rows0 == [(-3.0, "a"), (-2.0005, "a")]       # without the margin it would pass
