@@ -13,7 +13,9 @@
   test) equal the oracle's dense spectra, and the spin-resolved levels
   built from them hold the 120-degree tower table's irreps and
   multiplicities for S = 0, 1, 2; the sectors of the 2-D irreps (E1, E2 at
-  Gamma, E at K) give the oracle's levels too.
+  Gamma, E at K) give the oracle's levels too; with chirality (J2 = 0.2,
+  Jchi = 0.5, point group C6) the spin-resolved levels hold the tetrahedral
+  tower table for S = 0..3.
 """
 import json
 import os
@@ -30,6 +32,7 @@ pytestmark = pytest.mark.gpu
 _ALL = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")))
 GOLD = _ALL["tos_neel_square"]
 GOLD120 = _ALL["tos_120_triangular"]
+GOLDTET = _ALL["tos_tetrahedral_triangular"]
 
 
 def _torch():
@@ -120,6 +123,33 @@ def test_tower_triangular12_equals_oracle_and_120_table(T):
         # level lies below it
         nxt = rows[n][0] if len(rows) > n else cut
         assert nxt > rows[n - 1][0] + 0.1
+
+
+def test_tower_triangular12_tetrahedral_table(T):
+    k = 4
+    at, labels = {}, {}
+    for sz in range(5):
+        secs = L.triangular_chiral_sectors(L.TRI12_L, L.TRI12_CHAIN, J2=0.2, Jchi=0.5, n_up=6 + sz)
+        at[sz] = T.sector_levels(secs, n_iter=200, k=k)
+        for inst in secs:
+            labels[inst.name] = L.sector_label(inst)
+            reps, stabs = O.enumerate_basis(inst)
+            if not len(reps):
+                continue
+            w = np.linalg.eigvalsh(O.coo_matrix(inst, reps, stabs).toarray())
+            exact = [e for i, e in enumerate(w) if i == 0 or e - w[i - 1] > 1e-8][:k]
+            got = next(lv for name, lv, _, _ in at[sz] if name == inst.name)
+            assert len(got) == len(exact) and abs(got[0] - exact[0]) < 1e-10, inst.name
+            assert np.allclose(got, exact, rtol=0, atol=1e-7), inst.name
+    for S in GOLDTET["S"]:
+        rows, cut = T.spin_levels(at[S], at[S + 1])
+        rows = [(e, labels[name]) for e, name in rows]
+        m = {lab: c[GOLDTET["S"].index(S)] for lab, c in GOLDTET["multiplicity"].items()}
+        n = sum(m.values())
+        _say("tetrahedral12 S", S, "cut", round(cut, 6), [(round(e, 6), lab) for e, lab in rows[:n + 1]])
+        assert sorted(lab for _, lab in rows[:n]) == sorted(lab for lab, c in m.items() for _ in range(c))
+        nxt = rows[n][0] if len(rows) > n else cut
+        assert nxt > rows[n - 1][0] + 0.2
 
 
 def test_two_dim_irrep_sectors_equal_oracle(T):

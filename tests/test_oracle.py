@@ -545,3 +545,27 @@ def test_two_dim_irreps_complete_the_spectrum(kind, sz):
         ref = _spectrum([trans_only(q, fl) for fl in flips])
         assert len(got) == len(ref) and np.allclose(got, ref, atol=1e-10), (kind, sz, q)
         assert any(len(O.enumerate_basis(i)[0]) for i in two if tuple(i.meta["q"]) == q)
+
+
+def test_tower_of_states_triangular12_tetrahedral_table():
+    """The 12-site triangular J1-J2-Jchi model at J2 = 0.2, Jchi = 0.5 (point
+    group C6): the lowest levels of total spin S = 0..3 carry exactly the
+    irreps and multiplicities of the thesis's tetrahedral tower table, with
+    a gap above 0.2 to the next spin-S level.  Spin S = levels at Sz = S
+    that the same sector lacks at Sz = S + 1."""
+    g = GOLD["tos_tetrahedral_triangular"]
+    n = 12
+    spec = {}
+    for sz in range(5):
+        for inst in L.triangular_chiral_sectors(L.TRI12_L, L.TRI12_CHAIN, J2=0.2, Jchi=0.5, n_up=n // 2 + sz):
+            reps, stabs = O.enumerate_basis(inst)
+            if len(reps):
+                w = np.linalg.eigvalsh(O.coo_matrix(inst, reps, stabs).toarray())
+                spec.setdefault((sz, L.sector_label(inst)), []).extend(w)
+    for S in g["S"]:
+        levels = sorted((e, lab) for (sz, lab), w in spec.items() if sz == S
+                        for e in _minus(w, spec.get((S + 1, lab), [])))
+        m = {k: v[g["S"].index(S)] for k, v in g["multiplicity"].items()}
+        n_tower = sum(m.values())
+        assert sorted(lab for _, lab in levels[:n_tower]) == sorted(k for k, c in m.items() for _ in range(c)), S
+        assert levels[n_tower][0] > levels[n_tower - 1][0] + 0.2

@@ -575,18 +575,28 @@ def sector_label(inst):
     the triangular lattice at Gamma the other one-dimensional irreps of C6v
     are named by their characters on the 60-degree rotation and on the
     mirror that contains the bond a1: A2 (+1, -1), B1 (-1, +1), B2 (-1, -1).
-    Sectors of ``two_dim_sectors`` carry their E label.  Other irreps are
-    'ir<index>'."""
+    Without mirrors (chirality on, point group C6) the trivial irrep is A;
+    at Gamma the others are named by chi(C6) = exp(2 pi i m / 6): B (m = 3),
+    E1a / E1b (m = 1 / 5), E2a / E2b (m = 2 / 4); at M (little group C2) the
+    odd one is B.  Sectors of ``two_dim_sectors`` carry their E label.  Other
+    irreps are 'ir<index>'."""
     if "label" in inst.meta:
         return inst.meta["label"]
     lat = inst.meta["lattice"]
     mom = _momentum_name(lat.kind, inst.meta["q"])
     ir = inst.meta["irrep"]
+    little = inst.meta["little"]
+    mirrored = any(P[0][0] * P[1][1] - P[0][1] * P[1][0] < 0 for P in little)
     if ir == 0:
-        return f"{mom}.A1"
-    if lat.kind == "triangular" and mom == "Gamma" and TRI_MY in inst.meta["little"]:
+        return f"{mom}.A1" if mirrored else f"{mom}.A"
+    if lat.kind == "triangular" and mom == "Gamma" and TRI_MY in little:
         c = (round(pg_character(inst, TRI_R60).real), round(pg_character(inst, TRI_MY).real))
         return "Gamma." + {(1, -1): "A2", (-1, 1): "B1", (-1, -1): "B2"}[c]
+    if lat.kind == "triangular" and mom == "Gamma" and TRI_R60 in little and not mirrored:
+        m = int(round(np.angle(pg_character(inst, TRI_R60)) * 6 / (2 * np.pi))) % 6
+        return "Gamma." + {3: "B", 1: "E1a", 5: "E1b", 2: "E2a", 4: "E2b"}[m]
+    if mom == "M" and not mirrored and TRI_C2 in little and len(little) == 2:
+        return "M.B"
     return f"{mom}.ir{ir}"
 
 
@@ -643,6 +653,17 @@ def two_dim_sectors(kind, L, chain, J2=0.0, n_up=None, name=None):
                              + ("" if fl is None else f"_{_flipname(fl)}"))
                 out.append(inst)
     return out
+
+
+def triangular_chiral_sectors(L, chain, J2=0.0, Jchi=0.0, n_up=None, name="triangular"):
+    """Every one-dimensional sector of the triangular J1-J2-Jchi model with
+    the point group C6 (the chirality is odd under the mirrors); every irrep
+    of C6 and of its little groups is one-dimensional."""
+    lat = triangular_lattice(L[0], L[1], chain, mirrors=False)
+    n_up = lat.N // 2 if n_up is None else n_up
+    return _all_sectors(lat, lambda q, ir, fl: triangular_j1j2chi(L[0], L[1], 1.0, J2, Jchi, q, irrep=ir, flip=fl,
+                                                                  sublat_chain=chain, mirrors=False, n_up=n_up),
+                        n_up, name)
 
 
 def square32_sectors(J2=0.5, n_up=None):
