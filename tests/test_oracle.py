@@ -425,6 +425,29 @@ def test_structure_factor_sum_rule_and_singlet_square16():
     assert all(sM >= O.structure_factor(C, pos, q) for q in lat.momenta())
 
 
+@pytest.mark.parametrize("J2,peak", [(0.0, "K"), (0.3, "M")])
+def test_structure_factor_triangular12_peaks(J2, peak):
+    """Lattice coordinates on the triangular lattice (a1, a2 at 60 degrees):
+    in the Gamma.A1 state of the 12-site cluster the sum rule gives 3N/4,
+    S(q) is the same over each star, and it peaks at K with 120-degree
+    correlations (J2 = 0) and at M on the stripy side (J2 = 0.3), as the
+    thesis states for these orders."""
+    inst = L.triangular_j1j2chi(L.TRI12_L[0], L.TRI12_L[1], 1.0, J2, 0.0, L.Q0, irrep="A1", flip=1,
+                                sublat_chain=L.TRI12_CHAIN)
+    states, psi = O.sector_state(inst)
+    C = O.spin_correlations(inst, states, psi)
+    pos = L.site_coords(inst)
+    S = {q: O.structure_factor(C, pos, q) for q in inst.meta["lattice"].momenta()}
+    assert sum(S.values()) == pytest.approx(0.75 * inst.n_sites, abs=1e-10)
+    stars = {"K": L.momentum_star(inst, (L.F(1, 3), L.F(2, 3))), "M": L.momentum_star(inst, (L.F(1, 2), L.F(0)))}
+    assert [len(stars["K"]), len(stars["M"])] == [2, 3]
+    for star in stars.values():
+        assert np.allclose([S[q] for q in star], S[star[0]], atol=1e-10)
+    top = max(S.values())
+    assert S[stars[peak][0]] == pytest.approx(top, abs=1e-12)
+    assert all(S[q] < top - 0.5 for q in S if q not in stars[peak])
+
+
 # --- order-parameter correlations (triangular J1-J2-Jchi chapter) --------------
 
 def _triangle_instance(n_up):
