@@ -592,3 +592,31 @@ def test_tower_of_states_triangular12_tetrahedral_table():
         n_tower = sum(m.values())
         assert sorted(lab for _, lab in levels[:n_tower]) == sorted(k for k, c in m.items() for _ in range(c)), S
         assert levels[n_tower][0] > levels[n_tower - 1][0] + 0.2
+
+
+def test_bond_and_chirality_correlations_eigenstate_identities():
+    """12-site triangular lattice.  With J2 = 0, H is the sum of the bonds of
+    all three directions, so in an eigenstate sum_b <(S.S)_b0 (S.S)_b>_c over
+    all bonds b vanishes.  With H = X_all (every triangle's chirality, point
+    group C6), an eigenstate of eigenvalue x has sum_t <chi_0 chi_t> =
+    <chi_0 X_all> = x <chi_0> = x^2 / 2N (the 2N triangles are equivalent
+    under translations and C6)."""
+    inst = L.triangular_j1j2chi(L.TRI12_L[0], L.TRI12_L[1], 1.0, 0.0, 0.0, L.Q0, irrep="A1", flip=1,
+                                sublat_chain=L.TRI12_CHAIN)
+    states, psi = O.sector_state(inst)
+    b0 = tuple(L.bonds_along(inst, (1, 0))[0])
+    assert abs(O.bond_correlation(inst, states, psi, b0, inst.bonds)) < 1e-10
+    # a sub-sum alone is not zero: the check is not trivially satisfied
+    assert abs(O.bond_correlation(inst, states, psi, b0, L.bonds_along(inst, (1, 0)))) > 1e-3
+    from dataclasses import replace
+    chiral = L.triangular_j1j2chi(L.TRI12_L[0], L.TRI12_L[1], 1.0, 0.0, 1.0, L.Q0, irrep="A", flip=1,
+                                  sublat_chain=L.TRI12_CHAIN)
+    up, down = L.triangles(chiral)
+    pure = replace(chiral, bonds=np.zeros((0, 2), np.int32), bond_J=np.zeros(0))
+    reps, stabs = O.enumerate_basis(pure)
+    x = np.linalg.eigvalsh(O.coo_matrix(pure, reps, stabs).toarray())[0]
+    states, psi = O.sector_state(pure)
+    X = O.chirality_correlation(pure, states, psi, tuple(up[0]), np.concatenate([up, down]))
+    assert abs(x) > 1.0
+    assert X.real == pytest.approx(x * x / (2 * 12), rel=1e-10)
+    assert abs(X.imag) < 1e-12
