@@ -1,6 +1,9 @@
 // CPU check of the device representative search (represent.h, compiled for
 // the host) against brute force over the whole group, for every state of a
-// small instance.  Built and run by tests/test_represent_host.py.
+// small instance, or for `samples` random states with n_up spins up
+// (SplitMix64 from `seed`, partial Fisher-Yates over the sites) when the
+// optional fourth and fifth arguments are given.  Built and run by
+// tests/test_represent_host.py.
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -31,8 +34,29 @@ int main(int argc, char **argv) {
   for (int e = 0; e < T.G; ++e) g_of_code[(T.sp_of[e] << 1) | T.flip[e]] = e;
   KParams p{}; p.N = N; p.R = T.R; p.br = T.br; p.A = T.A; p.ba = T.ba; p.maskN = (1ull << N) - 1;
   long long checked = 0, bad = 0;
-  for (uint64_t s = 0; s < (1ull << N); ++s) {
-    if (__builtin_popcountll(s) != n_up) continue;
+  const long long samples = argc > 4 ? atoll(argv[4]) : 0;
+  uint64_t rng = argc > 5 ? strtoull(argv[5], nullptr, 10) : 1;
+  auto next = [&rng]() {
+    uint64_t z = (rng += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  const uint64_t total = samples ? (uint64_t)samples : (N < 64 ? (1ull << N) : 0);
+  for (uint64_t it = 0; it < total; ++it) {
+    uint64_t s = it;
+    if (samples) {
+      int site[64];
+      for (int i = 0; i < N; ++i) site[i] = i;
+      s = 0;
+      for (int k = 0; k < n_up; ++k) {
+        int j = k + (int)(next() % (uint64_t)(N - k));
+        int t = site[k]; site[k] = site[j]; site[j] = t;
+        s |= 1ull << (N - 1 - site[k]);
+      }
+    } else if (__builtin_popcountll(s) != n_up) {
+      continue;
+    }
     uint64_t best = ~0ull; int cnt = 0;
     std::vector<uint64_t> img(G);
     for (int e = 0; e < G; ++e) {

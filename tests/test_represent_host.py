@@ -64,3 +64,34 @@ def test_representative_search_matches_brute_force(checker, inst, tmp_path):
             assert r.returncode == 0, (R, A, r.stdout[-500:])
             ran += 1
     assert ran >= 1
+
+
+def _large_cases():
+    t36, c36 = L.TRI36_L, L.TRI36_CHAIN
+    K = (L.F(1, 3), L.F(2, 3))
+    return [
+        ("triangular36 C6v Gamma.A1", L.triangular_j1j2chi(t36[0], t36[1], 1.0, 0.0, 0.0, L.Q0, irrep="A1", flip=1,
+                                                           sublat_chain=c36)),
+        ("triangular36 C6v K Sz=1", L.triangular_j1j2chi(t36[0], t36[1], 1.0, 0.0, 0.0, K, irrep="A1", flip=None,
+                                                         sublat_chain=c36, n_up=19)),
+        ("triangular36 {E, C2, mirrors}", L.triangular_j1j2chi(t36[0], t36[1], 1.0, 0.2, 0.0, L.Q0, irrep="A", flip=1,
+                                                               sublat_chain=c36, pg_gens=[L.TRI_C2, L.TRI_MY])),
+        ("triangular36 chiral C6", L.triangular_j1j2chi(t36[0], t36[1], 1.0, 0.1, 0.2, L.Q0, irrep="A", flip=1,
+                                                        sublat_chain=c36)),
+        ("triangular36 E2 sector", L.two_dim_sectors("triangular", t36, c36, J2=0.0, n_up=18)[2]),
+        ("square32 E sector", L.two_dim_sectors("square", L.SQ32_L, L.SQ32_CHAIN, J2=0.5, n_up=16)[0]),
+        ("square40", L.square40()),
+    ]
+
+
+@pytest.mark.parametrize("name,inst", _large_cases(), ids=lambda x: x if isinstance(x, str) else "")
+def test_representative_search_sampled_large_groups(checker, name, inst, tmp_path):
+    """The groups of the production-size sweeps and order parameters (36-site
+    C6v, its subgroup that keeps a1's direction, the chiral C6, the sectors
+    of 2-D irreps, the 40-site benchmark group), with the tables the library
+    chooses by itself: 20000 random configurations each against brute force."""
+    path = str(tmp_path / "inst.bin")
+    _write(inst, path)
+    r = subprocess.run([checker, path, "0", "0", "20000", "7"], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, (name, r.stdout[-500:])
+    assert "checked 20000 bad 0" in r.stdout, r.stdout
