@@ -95,3 +95,25 @@ def test_representative_search_sampled_large_groups(checker, name, inst, tmp_pat
     r = subprocess.run([checker, path, "0", "0", "20000", "7"], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, (name, r.stdout[-500:])
     assert "checked 20000 bad 0" in r.stdout, r.stdout
+
+
+def test_representative_search_sampled_all_decompositions_triangular36(checker, tmp_path):
+    """Every admissible explicit pair (R, A) of the 36-site C6v group at Gamma
+    (R sublattices for Rep/Sym, A for the action tables), 3000 random
+    configurations each."""
+    inst = L.triangular_j1j2chi(L.TRI36_L[0], L.TRI36_L[1], 1.0, 0.0, 0.0, L.Q0, irrep="A1", flip=1,
+                                sublat_chain=L.TRI36_CHAIN)
+    path = str(tmp_path / "inst.bin")
+    _write(inst, path)
+    ran = []
+    for R in (1, 4, 12, 36):
+        for A in (1, 4, 12, 36):
+            if A % R:
+                continue
+            r = subprocess.run([checker, path, str(R), str(A), "3000", "11"], capture_output=True, text=True,
+                               timeout=300)
+            if "build_host_tables failed" in r.stdout:
+                continue
+            assert r.returncode == 0 and "bad 0" in r.stdout, (R, A, r.stdout[-300:])
+            ran.append((R, A))
+    assert ran == [(4, 4), (4, 12), (12, 12)], ran      # 1: tables too large; 36: not in the chain
