@@ -93,8 +93,9 @@ typedef struct {
  *  n_sub_act:   sublattices of the SymmetryAction tables; a multiple of
  *               n_sub_rep (a refinement in the same contiguous labelling).
  *  prefix_bits: bits of the Limits prefix table of the plain index lookup.
- *  mem_limit_bytes: cap on device memory owned by the basis (0 = none);
- *               exceeding it fails with ED_ENOMEM.
+ *  mem_limit_bytes: cap on the device memory owned by the basis together
+ *               with the temporaries of the calls working on it while they
+ *               are held (0 = none); exceeding it fails with ED_ENOMEM.
  */
 typedef struct {
     int32_t n_sub_rep;
@@ -119,8 +120,8 @@ typedef struct {
     int64_t bytes_device;      /* device memory owned by the basis */
     int64_t table_bytes;       /* sublattice-coding tables (resident in LDS) */
     int64_t limits_bytes;      /* plain lookup prefix table */
-    int64_t index_bytes;       /* learned index (0 if not trained) */
-    int32_t index_max_err;     /* learned-index error bound (-1 if not trained) */
+    int64_t index_bytes;       /* learned index: network, segment and cell tables (0 if not trained) */
+    int32_t index_max_err;     /* learned index: largest search window (-1 if not trained) */
     int32_t lds_resident;      /* tables staged in LDS by the kernels */
     double build_seconds;      /* wall time of ed_basis_build */
     double limits_mean_window; /* plain lookup: mean Limits bucket over all keys */
@@ -299,31 +300,36 @@ ed_status ed_lanczos_resume(const ed_basis *basis, int32_t n_more, int32_t looku
 ed_status ed_eigenvalues(const double *alpha, const double *beta, int32_t n, int32_t k, double *evals);
 
 /*
- * Learned index over the ascending representative list.  A network with two
- * hidden layers of 32 units (float32 weights; half of each layer relu(z),
- * half min(z,0); weights kept non-negative, so the network is
- * non-decreasing) maps the key, read as a floating-point number u = (e + 1 +
- * mantissa) / (N + 1) with e the position of its leading one, to an estimate
- * of its normalized position; the estimate routes the key to one of
- * 2^log2_leaves leaves.  Each leaf stores the position range of the keys
- * routed to it and splits that range into buckets uniform in key space
- * (about keys_per_bucket keys each) whose begin positions are tabulated.
- * Leaves whose largest bucket holds more than 64 keys get proportionally more
- * buckets (a few rounds), so the search window is at most 64 keys unless a
- * leaf reaches its refinement cap.  The
- * binary search inside the key's bucket finds every representative and
- * reports absence for every other key, so lookups agree exactly with the
- * plain Limits + binary search of the thesis (section on distributed memory
- * parallelization, "Limits" map).
- * Training runs on the device with the library's own forward, backward and
- * Adam kernels on minibatches of (representative, position) pairs.
- * After training the one-input network is expanded exactly into its linear
- * pieces (at most 1090); the index build and all lookups evaluate it through
- * that expansion (a binary search over the breakpoints, in LDS).
- * Zero fields mean defaults (n_features = 1 (the only value accepted),
- * hidden = 32 (the only value accepted), steps = 3000, batch = 8192,
- * lr = 1e-2 with cosine decay, log2_leaves ~ log2(dim / 256) (at most 22),
- * keys_per_bucket = 2; 4 halves the table at some cost in speed).
+ * Learned index over the ascending representative list (not in the thesis;
+ * measured against its "Limits" prefix map, section on distributed-memory
+ * parallelization, which stays the plain lookup and the reference).
+ *  - Input: the rank of the key among all N-bit configurations with the
+ *    sector's number of up spins, in ascending order (combinatorial number
+ *    system), read as a fraction u of the largest rank in the basis.
+ *  - Network: 1 -> 32 -> 32 -> 1, float32 weights (half of each hidden layer
+ *    relu(z), half min(z,0); weights kept non-negative, so the network is
+ *    non-decreasing).  Trained on the device with the library's own forward,
+ *    backward and Adam kernels on minibatches of (key, position) pairs, then
+ *    expanded exactly into its linear pieces (at most 1090), which lookups
+ *    evaluate from LDS.  Its output picks one of 2^log2_segments segments.
+ *  - Segment: maps the rank linearly onto its cells; cells are allocated in
+ *    proportion to the keys routed to the segment (about keys_per_cell each).
+ *  - Cell: the position range [first, first + n) of its keys, a prediction
+ *    by linear interpolation inside the cell, and its recorded largest
+ *    errors below and above the prediction.  Segments whose cells need a
+ *    wider window than max_window get four times the cells, a few rounds at
+ *    most.
+ *  - Lookup: rank -> network -> segment -> cell -> prediction; the search
+ *    starts at the predicted position and stays inside the recorded window,
+ *    so every representative is found and every other key reported absent:
+ *    the lookups agree exactly with the plain Limits + binary search.
+ * routing selects what picks the segment: 0 = the trained network, 1 = the
+ * network at its initial weights (no training step), 2 = no network (the
+ * segment is the feature u itself); the tables below are built the same way,
+ * so the three can be compared.  Zero fields mean defaults (n_features = 1
+ * and hidden = 32, the only values accepted; steps = 3000, batch = 8192, lr =
+ * 1e-2 with cosine decay; log2_segments ~ log2(dim / 2048) within [4, 22];
+ * keys_per_cell = 64; max_window = 16).
  */
 typedef struct {
     int32_t n_features;
@@ -332,34 +338,44 @@ typedef struct {
     int32_t batch;
     float lr;
     uint32_t seed;
-    int32_t log2_leaves;
-    int32_t keys_per_bucket;
+    int32_t log2_segments;
+    int32_t keys_per_cell;
+    int32_t max_window;
+    int32_t routing;
 } ed_index_cfg;
 
 typedef struct {
-    int32_t max_err;           /* largest search window (keys in one bucket) */
-    int32_t n_leaves;
+    int32_t max_err;           /* largest search window of a representative (keys) */
+    int32_t n_segments;
     float final_loss;          /* last minibatch mean squared error (normalized positions) */
     float mlp_max_err;         /* max |network estimate * dim - position| over all keys */
-    int64_t mlp_bytes;         /* network weights */
-    int64_t leaf_bytes;        /* leaf table and bucket-begin table */
-    double train_seconds;      /* training + leaf build wall time */
-    double mean_window;        /* mean search window over all keys */
+    int64_t mlp_bytes;         /* network weights (float32) */
+    int64_t table_bytes;       /* segment and cell tables */
+    double train_seconds;      /* training + table build wall time */
+    double mean_window;        /* mean search window over all representatives (keys) */
     int32_t n_features;        /* network inputs (1) */
-    int32_t n_pieces;          /* linear pieces of the trained network */
-    int64_t used_leaves;       /* leaves with at least one key */
+    int32_t n_pieces;          /* linear pieces of the network */
+    int64_t used_segments;     /* segments with at least one key */
     float feature_offset;      /* network input x = (u - feature_offset) * feature_scale */
     float feature_scale;
+    int64_t n_cells;
+    int64_t refined_segments;  /* segments given more cells to meet max_window */
+    double mean_abs_err;       /* mean |predicted - true position| */
+    double frac_exact;         /* representatives whose prediction is their position */
+    double mean_lines;         /* mean 128-byte lines of 16-byte records spanned by the window */
+    int64_t lds_bytes;         /* expanded network and rank table (staged in LDS) */
+    int32_t routing;
+    int32_t reserved;
 } ed_index_stats;
 
 /*
  * Train the learned index of a built basis (device kernels; blocks until
- * done) and build its exact leaf table.  Real sectors also get a record
- * {representative, x} per state in basis order (16 B per state), from which
- * the mode-1 H.v gather reads x_j.  Afterwards lookup_mode / mode 1 is
- * accepted by ed_apply_H, ed_lookup and ed_lanczos_run.  Retraining with the
- * same leaf count replaces the index.  Errors: ED_EINVAL, ED_ENOMEM,
- * ED_EDEVICE.
+ * done) and build its segment and cell tables.  Real sectors also get a
+ * record {representative, x} per state in basis order (16 B per state), from
+ * which the mode-1 H.v gather reads x_j.  Afterwards lookup_mode / mode 1 is
+ * accepted by ed_apply_H, ed_lookup and ed_lanczos_run.  Training again
+ * replaces the index.  Temporaries count against the basis's memory cap.
+ * Errors: ED_EINVAL, ED_ENOMEM, ED_EDEVICE.
  */
 ed_status ed_index_train(ed_basis *basis, const ed_index_cfg *cfg, ed_index_stats *out, void *stream);
 
@@ -370,8 +386,10 @@ ed_status ed_index_info(const ed_basis *basis, ed_index_stats *out, float *h_par
 
 /*
  * Evaluate the trained index network (expanded form) on n keys: d_u[k] =
- * input feature of d_keys[k], d_y[k] = network output.  Device pointers
- * (uint64[n], float32[n], float32[n]); asynchronous on `stream`.
+ * input feature of d_keys[k], d_y[k] = network output (NaN for both when the
+ * key is not a configuration of the sector: wrong number of up spins or bits
+ * at or above N).  Device pointers (uint64[n], float32[n], float32[n]);
+ * asynchronous on `stream`.
  */
 ed_status ed_index_predict(const ed_basis *basis, const uint64_t *d_keys, int64_t n, float *d_u, float *d_y,
                            void *stream);

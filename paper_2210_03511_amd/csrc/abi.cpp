@@ -39,9 +39,42 @@ ed_status dev_alloc(ed_basis *b, void **ptr, size_t bytes)
     hipError_t e = hipMalloc(ptr, bytes ? bytes : 16);
     if (e != hipSuccess) return fail(ED_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
     b->bytes += (int64_t)bytes;
-    b->allocs.push_back(*ptr);
+    b->allocs.emplace_back(*ptr, (int64_t)bytes);
     return ED_OK;
 }
+
+void dev_release(ed_basis *b, void *ptr)
+{
+    if (!ptr) return;
+    for (size_t k = 0; k < b->allocs.size(); ++k)
+        if (b->allocs[k].first == ptr) {
+            (void)hipFree(ptr);
+            b->bytes -= b->allocs[k].second;
+            b->allocs.erase(b->allocs.begin() + (long)k);
+            return;
+        }
+}
+
+ed_status TmpPool::take(void **q, size_t bytes)
+{
+    if (basis && basis->mem_limit > 0 && basis->bytes + (int64_t)bytes > basis->mem_limit)
+        return fail(ED_ENOMEM, "device memory cap exceeded by temporaries (" + std::to_string(basis->bytes + bytes) +
+                                   " > " + std::to_string(basis->mem_limit) + " bytes)");
+    hipError_t e = hipMalloc(q, bytes ? bytes : 16);
+    if (e != hipSuccess) return fail(ED_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    ptrs.push_back(*q);
+    if (basis) {
+        basis->bytes += (int64_t)bytes;
+        held += (int64_t)bytes;
+    }
+    return ED_OK;
+}
+
+#define TAKE(pool, ptr, bytes)                                          \
+    do {                                                                \
+        ed_status _ts = (pool).take((void **)(ptr), (size_t)(bytes));   \
+        if (_ts != ED_OK) return _ts;                                   \
+    } while (0)
 
 // Persistent grids of the apply kernel: as many blocks per compute unit as
 // fit, except for a plain lookup over long Limits windows (more than 64 keys
@@ -79,11 +112,13 @@ KParams make_params(const ed_basis *b)
     p.stab = b->d_stab;
     p.limits = b->d_limits;
     p.dim = b->dim;
-    p.leaves = b->d_leaves;
-    p.sub = b->d_sub;
-    p.log2_leaves = b->log2_leaves;
-    p.mlp_F = b->mlp_F;
-    p.mlp_c = b->mlp_c;
+    p.lv.segs = static_cast<const Seg *>(b->d_segs);
+    p.lv.cells = static_cast<const uint2 *>(b->d_cells);
+    p.lv.n_cells = b->n_cells;
+    p.lv.lg = b->lg_segs;
+    p.lv.rk_W = T.N - T.n_up + 1;
+    p.lv.eq_K = b->eq_K;
+    p.lv.eq_invK = 1.0 / (double)b->eq_K;
     p.has_index = b->indexed ? 1 : 0;
     p.htab = b->d_htab;
     p.hslots = b->hslots;
@@ -121,7 +156,7 @@ void ed_basis_free(ed_basis *b)
     if (!b) return;
     for (auto &g : b->step_graph)
         if (g) (void)hipGraphExecDestroy(g);
-    for (void *p : b->allocs) (void)hipFree(p);
+    for (auto &a : b->allocs) (void)hipFree(a.first);
     if (b->own) (void)hipStreamDestroy(b->own);
     delete b;
 }
@@ -164,7 +199,7 @@ static ed_status build_impl(const ed_model *model, const ed_group *group, int32_
     set_grids(b, bpc);
     b->cfg.vec_blocks = 4 * b->n_cu;
 
-    TmpPool tmp;  // temporaries of the build
+    TmpPool tmp(b);  // temporaries of the build, charged to the memory cap while held
     // --- enumeration of the sector (two passes + scan) -------------------
     const int N = T.N;
     const uint64_t total = binom64(N, n_up);
@@ -172,20 +207,22 @@ static ed_status build_impl(const ed_model *model, const ed_group *group, int32_
     for (int n = 0; n < 64; ++n)
         for (int k = 0; k < 64; ++k) hb[n * 64 + k] = binom64(n, k);
     uint64_t *d_binom = nullptr;
-    HIP_OK(tmp.alloc((void **)&d_binom, hb.size() * sizeof(uint64_t)));
+    TAKE(tmp, &d_binom, hb.size() * sizeof(uint64_t));
     HIP_OK(hipMemcpy(d_binom, hb.data(), hb.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
     uint64_t len = std::max<uint64_t>(256, (total + (1ull << 24) - 1) >> 24);
     uint64_t n_chunks = (total + len - 1) / len;
     if (n_chunks == 0) n_chunks = 1;
     uint32_t *d_counts = nullptr;
     uint64_t *d_offsets = nullptr, *d_total = nullptr;
-    HIP_OK(tmp.alloc((void **)&d_counts, n_chunks * sizeof(uint32_t)));
-    HIP_OK(tmp.alloc((void **)&d_offsets, n_chunks * sizeof(uint64_t)));
-    HIP_OK(tmp.alloc((void **)&d_total, sizeof(uint64_t)));
+    uint64_t *d_scan = nullptr;
+    TAKE(tmp, &d_counts, n_chunks * sizeof(uint32_t));
+    TAKE(tmp, &d_offsets, n_chunks * sizeof(uint64_t));
+    TAKE(tmp, &d_total, sizeof(uint64_t));
+    TAKE(tmp, &d_scan, scan_tmp_words(n_chunks) * sizeof(uint64_t));
     int eblocks = (int)std::min<uint64_t>((n_chunks + 255) / 256, (uint64_t)b->n_cu * 16);
     if (eblocks < 1) eblocks = 1;
     HIP_OK(launch_enumerate(p, d_binom, total, len, n_chunks, d_counts, nullptr, nullptr, nullptr, false, eblocks, st));
-    HIP_OK(launch_scan(d_counts, d_offsets, n_chunks, d_total, st));
+    HIP_OK(launch_scan(d_counts, d_offsets, n_chunks, d_total, d_scan, st));
     uint64_t dim = 0;
     HIP_OK(hipMemcpyAsync(&dim, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
@@ -214,7 +251,7 @@ static ed_status build_impl(const ed_model *model, const ed_group *group, int32_
     // --- key-weighted Limits bucket statistics (search window of the plain lookup)
     {
         unsigned long long *d_ls = nullptr, hls[2] = {0, 0};
-        HIP_OK(tmp.alloc((void **)&d_ls, 2 * sizeof(unsigned long long)));
+        TAKE(tmp, &d_ls, 2 * sizeof(unsigned long long));
         HIP_OK(hipMemsetAsync(d_ls, 0, 2 * sizeof(unsigned long long), st));
         HIP_OK(launch_limits_stats(b->d_limits, pb, d_ls, st));
         HIP_OK(hipMemcpyAsync(hls, d_ls, sizeof(hls), hipMemcpyDeviceToHost, st));
@@ -227,7 +264,7 @@ static ed_status build_impl(const ed_model *model, const ed_group *group, int32_
     // --- element count ----------------------------------------------------
     p = make_params(b);
     unsigned long long *d_cnt = nullptr, cnt = 0;
-    HIP_OK(tmp.alloc((void **)&d_cnt, sizeof(unsigned long long)));
+    TAKE(tmp, &d_cnt, sizeof(unsigned long long));
     HIP_OK(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long), st));
     if (b->dim > 0) HIP_OK(launch_count_elements(p, d_cnt, 4 * b->n_cu, st));
     HIP_OK(hipMemcpyAsync(&cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, st));
@@ -271,7 +308,7 @@ ed_status ed_basis_info(const ed_basis *b, ed_basis_info_t *info)
     r.bytes_device = b->bytes;
     r.table_bytes = b->lay.bytes;
     r.limits_bytes = (int64_t)(((1ull << b->pbits) + 1) * sizeof(uint32_t));
-    r.index_bytes = b->indexed ? b->istats.mlp_bytes + b->istats.leaf_bytes : 0;
+    r.index_bytes = b->indexed ? b->istats.mlp_bytes + b->istats.table_bytes : 0;
     r.index_max_err = b->indexed ? b->istats.max_err : -1;
     r.lds_resident = 1;
     r.limits_mean_window = b->limits_mean_window;
@@ -374,6 +411,11 @@ static ed_status lanczos_workspace(ed_basis *b, int n_iter, int keep)
             HIP_OK(hipMemcpy(na, b->d_alpha, keep * sizeof(double), hipMemcpyDeviceToDevice));
             HIP_OK(hipMemcpy(nb, b->d_beta, keep * sizeof(double), hipMemcpyDeviceToDevice));
         }
+        // nothing queued may still read the old arrays (hipMemcpy above and
+        // the graph launches before it ran on other streams)
+        HIP_OK(hipStreamSynchronize(b->own));
+        dev_release(b, b->d_alpha);
+        dev_release(b, b->d_beta);
         b->d_alpha = na;
         b->d_beta = nb;
         b->lanczos_cap = cap;
@@ -597,41 +639,74 @@ ed_status ed_index_train(ed_basis *b, const ed_index_cfg *cfg_in, ed_index_stats
     if (b->dim < 1) return fail(ED_EINVAL, "empty sector");
     ed_index_cfg cfg{};
     if (cfg_in) cfg = *cfg_in;
-    const int N = b->T.N;
-    // one monotone input feature (the key read as a floating-point number)
+    const int N = b->T.N, n_up = b->T.n_up;
+    // one input feature (the rank read as a fraction of the largest rank)
     const int F = 1;
     if (cfg.n_features != 0 && cfg.n_features != 1) return fail(ED_EINVAL, "the index network has one input feature");
     if (cfg.hidden != 0 && cfg.hidden != kHidden) return fail(ED_EINVAL, "hidden width must be 32");
-    const int steps = cfg.steps > 0 ? cfg.steps : 3000;
+    if (cfg.routing < 0 || cfg.routing > 2) return fail(ED_EINVAL, "routing must be 0, 1 or 2");
+    const int steps = cfg.routing == 0 ? (cfg.steps > 0 ? cfg.steps : 3000) : 0;
     const int batch = cfg.batch > 0 ? cfg.batch : 8192;
     const float lr0 = cfg.lr > 0 ? cfg.lr : 1e-2f;
-    int lg = cfg.log2_leaves;
+    int lg = cfg.log2_segments;
     if (lg <= 0) {
-        // about 256 keys per leaf; the key-space buckets refine further
+        // about 2048 keys per segment
         lg = 4;
-        while (lg < 22 && (int64_t(1) << (lg + 8)) < b->dim) ++lg;
+        while (lg < 22 && (int64_t(1) << (lg + 11)) < b->dim) ++lg;
     }
-    if (lg < 1 || lg > 28) return fail(ED_EINVAL, "log2_leaves must be in [1, 28]");
+    if (lg < 1 || lg > 24) return fail(ED_EINVAL, "log2_segments must be in [1, 24]");
+    const uint32_t kpc = cfg.keys_per_cell > 0 ? (uint32_t)cfg.keys_per_cell : kKeysPerCell;
+    const uint32_t win = cfg.max_window > 0 ? (uint32_t)cfg.max_window : kMaxWindow;
+    if (kpc > (1u << 16)) return fail(ED_EINVAL, "keys_per_cell must be at most 65536");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = b->own;
     HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    TmpPool tmp(b);  // charged to the memory cap while held
+    ed_status s;
+
+    // --- rank table and equalizer (host) -------------------------------------
+    const int W = N - n_up + 1, nr = rank_table_entries(N, n_up);
+    std::vector<uint64_t> hr((size_t)std::max(nr, 1), 0);
+    for (int j = 0; j < n_up; ++j)
+        for (int q = 0; q < W; ++q) hr[(size_t)j * W + q] = binom64(q + j, j + 1);
+    // knots: ranks of the keys at positions floor(j (dim - 1) / K)
+    const int K = (int)std::max<int64_t>(1, std::min<int64_t>(kEqMax, b->dim - 1));
+    std::vector<uint64_t> heq(kEqBytes / 8, 0);
+    double *hinvw = reinterpret_cast<double *>(heq.data() + kEqMax + 1);
+    for (int j = 0; j <= K; ++j) {
+        const int64_t pos = (int64_t)((double)j * (double)(b->dim - 1) / (double)K);
+        uint64_t key = 0;
+        HIP_OK(hipMemcpy(&key, b->d_reps + std::min<int64_t>(pos, b->dim - 1), sizeof(uint64_t),
+                         hipMemcpyDeviceToHost));
+        heq[j] = sz_rank(key, hr.data(), W);
+        if (j > 0 && heq[j] <= heq[j - 1]) heq[j] = heq[j - 1] + 1;  // one key (dim 1): any width
+    }
+    for (int j = 0; j < K; ++j) hinvw[j] = 1.0 / (double)(heq[j + 1] - heq[j]);
+    if (!b->d_rank && (s = dev_alloc(b, (void **)&b->d_rank, kRankMaxEntries * sizeof(uint64_t))) != ED_OK) return s;
+    if (!b->d_eq && (s = dev_alloc(b, (void **)&b->d_eq, kEqBytes)) != ED_OK) return s;
+    HIP_OK(hipMemcpy(b->d_rank, hr.data(), (size_t)nr * sizeof(uint64_t), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(b->d_eq, heq.data(), kEqBytes, hipMemcpyHostToDevice));
+    const Equalizer eq{reinterpret_cast<const uint64_t *>(b->d_eq),
+                       reinterpret_cast<const double *>(b->d_eq + (kEqMax + 1) * 8), K, 1.0 / (double)K};
+    const RankFeat rf{b->d_rank, W, n_up, eq};
+
+    // --- network: training on (feature, position) samples ------------------
     const int NP = mlp_param_count(F, kHidden);
     const int nb = mlp_train_blocks(batch);
-    TmpPool tmp;
-    ed_status s;
     if (!b->d_params && (s = dev_alloc(b, (void **)&b->d_params, kMlpMaxParams * sizeof(float))) != ED_OK) return s;
-    float *d_m = nullptr, *d_v = nullptr, *d_gpart = nullptr, *d_lpart = nullptr, *d_loss = nullptr;
-    HIP_OK(tmp.alloc((void **)&d_m, NP * sizeof(float)));
-    HIP_OK(tmp.alloc((void **)&d_v, NP * sizeof(float)));
-    HIP_OK(tmp.alloc((void **)&d_gpart, (size_t)nb * NP * sizeof(float)));
-    HIP_OK(tmp.alloc((void **)&d_lpart, (size_t)nb * sizeof(float)));
-    HIP_OK(tmp.alloc((void **)&d_loss, sizeof(float)));
+    float *d_m = nullptr, *d_v = nullptr, *d_gpart = nullptr, *d_lpart = nullptr, *d_loss = nullptr, *d_ur = nullptr;
+    TAKE(tmp, &d_m, NP * sizeof(float));
+    TAKE(tmp, &d_v, NP * sizeof(float));
+    TAKE(tmp, &d_gpart, (size_t)nb * NP * sizeof(float));
+    TAKE(tmp, &d_lpart, (size_t)nb * sizeof(float));
+    TAKE(tmp, &d_loss, sizeof(float));
+    TAKE(tmp, &d_ur, 2 * sizeof(float));
     HIP_OK(hipMemsetAsync(b->d_params, 0, kMlpMaxParams * sizeof(float), st));
     HIP_OK(hipMemsetAsync(d_m, 0, NP * sizeof(float), st));
     HIP_OK(hipMemsetAsync(d_v, 0, NP * sizeof(float), st));
-    float *d_ur = nullptr, ur[2] = {0.f, 1.f};
-    HIP_OK(tmp.alloc((void **)&d_ur, 2 * sizeof(float)));
-    HIP_OK(feature_range(b->d_reps, b->dim, N, d_ur, st));
+    HIP_OK(hipMemsetAsync(d_loss, 0, sizeof(float), st));
+    float ur[2] = {0.f, 1.f};
+    HIP_OK(feature_range(b->d_reps, b->dim, rf, d_ur, st));
     HIP_OK(hipMemcpyAsync(ur, d_ur, 2 * sizeof(float), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     // input standardization x = (u - mu) * sc maps the keys' feature range to [-1, 1]
@@ -641,97 +716,147 @@ ed_status ed_index_train(ed_basis *b, const ed_index_cfg *cfg_in, ed_index_stats
     for (int t = 0; t < steps; ++t) {
         // cosine decay to 2% of the initial rate
         const float lr = lr0 * (0.02f + 0.98f * 0.5f * (1.0f + std::cos(3.14159265f * t / steps)));
-        HIP_OK(mlp_train_step(b->d_params, d_m, d_v, F, mu, sc, N, b->d_reps, b->dim, cfg.seed, t, batch, lr, d_gpart,
+        HIP_OK(mlp_train_step(b->d_params, d_m, d_v, F, mu, sc, rf, b->d_reps, b->dim, cfg.seed, t, batch, lr, d_gpart,
                               d_lpart, d_loss, st));
     }
     float loss = 0;
     HIP_OK(hipMemcpyAsync(&loss, d_loss, sizeof(float), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
-    // the network, expanded into its pieces, goes into the table blob (staged
-    // into LDS by the kernels)
+    // expanded form; routing 2 replaces the network by y = u (one piece)
     std::vector<float> hp(kMlpMaxParams), block;
     HIP_OK(hipMemcpy(hp.data(), b->d_params, NP * sizeof(float), hipMemcpyDeviceToHost));
-    double dev = 0.0;
-    const int pieces = expand_network(hp.data(), mu, sc, block, &dev);
-    double yscale = 1.0;
-    for (int q = 0; q < pieces; ++q) yscale = std::max(yscale, (double)std::fabs(block[kPwHeader + 2 * pieces + q]));
-    if (!(dev <= 1e-4 * yscale)) return fail(ED_EDEVICE, "network expansion disagrees with the network");
-    if (b->lay.off_mlp + block.size() * sizeof(float) > b->lay.reserved)
-        return fail(ED_EDEVICE, "network expansion larger than its reserved space");
-    float *d_pw = reinterpret_cast<float *>(static_cast<unsigned char *>(b->d_blob) + b->lay.off_mlp);
-    HIP_OK(hipMemcpyAsync(d_pw, block.data(), block.size() * sizeof(float), hipMemcpyHostToDevice, st));
-    // the kernels now stage the pieces too; the blocks per compute unit follow
-    b->lay.bytes = (uint32_t)((b->lay.off_mlp + block.size() * sizeof(float) + 15) & ~(size_t)15);
+    int pieces = 1;
+    if (cfg.routing == 2) {
+        block.assign((size_t)pw_floats(1), 0.0f);
+        block[0] = 1.0f;
+        block[kPwHeader + 1] = 1.0f;   // slope
+        block[kPwHeader + 2] = 0.0f;   // intercept
+    } else {
+        double dev = 0.0;
+        pieces = expand_network(hp.data(), mu, sc, block, &dev);
+        double yscale = 1.0;
+        for (int q = 0; q < pieces; ++q)
+            yscale = std::max(yscale, (double)std::fabs(block[kPwHeader + 2 * pieces + q]));
+        if (!(dev <= 1e-4 * yscale)) return fail(ED_EDEVICE, "network expansion disagrees with the network");
+    }
+    // blob: the pieces at off_mlp, the equalizer and the rank table right
+    // behind them (LDS)
+    const size_t off_rank = (b->lay.off_mlp + block.size() * sizeof(float) + 15) & ~(size_t)15;
+    if (off_rank + kEqBytes + (size_t)nr * sizeof(uint64_t) > b->lay.reserved)
+        return fail(ED_EDEVICE, "network expansion, equalizer and rank table larger than their reserved space");
+    // nothing may still run on the old index while it is replaced
+    HIP_OK(hipDeviceSynchronize());
+    unsigned char *blob = static_cast<unsigned char *>(b->d_blob);
+    const float *d_pw = reinterpret_cast<const float *>(blob + b->lay.off_mlp);
+    HIP_OK(hipMemcpyAsync(blob + b->lay.off_mlp, block.data(), block.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(blob + off_rank, heq.data(), kEqBytes, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(blob + off_rank + kEqBytes, hr.data(), (size_t)nr * sizeof(uint64_t),
+                          hipMemcpyHostToDevice, st));
+    HIP_OK(hipStreamSynchronize(st));  // the host copies are about to go
+    b->lay.off_rank = (uint32_t)off_rank;
+    b->lay.bytes = (uint32_t)((off_rank + kEqBytes + (size_t)nr * sizeof(uint64_t) + 15) & ~(size_t)15);
     {
         int bpc = 0, athreads = 0;
         HIP_OK(prepare_kernels(make_params(b), &bpc, &athreads));
         if (bpc < 1) return fail(ED_EINVAL, "tables and network exceed the LDS of one compute unit");
         set_grids(b, bpc);
     }
-    // exact leaf table: ranges, key-space buckets, bucket begins
-    if (b->d_leaves && b->log2_leaves != lg) return fail(ED_EINVAL, "index already trained with another leaf count");
-    if (!b->d_leaves && (s = dev_alloc(b, &b->d_leaves, (sizeof(Leaf) << lg))) != ED_OK) return s;
+
+    // --- segments and cells --------------------------------------------------
     const uint64_t M = 1ull << lg;
-    const uint32_t target = cfg.keys_per_bucket > 0 ? (uint32_t)cfg.keys_per_bucket : 2u;
-    uint32_t *d_sizes = nullptr, *d_err = nullptr, net_err = 0;
-    uint64_t *d_offsets = nullptr, *d_total = nullptr, total = 0;
-    unsigned long long *d_stats = nullptr, hstats[2] = {0, 0};
-    HIP_OK(tmp.alloc((void **)&d_sizes, M * sizeof(uint32_t)));
-    HIP_OK(tmp.alloc((void **)&d_offsets, M * sizeof(uint64_t)));
-    HIP_OK(tmp.alloc((void **)&d_total, sizeof(uint64_t)));
-    HIP_OK(tmp.alloc((void **)&d_err, sizeof(uint32_t)));
-    HIP_OK(tmp.alloc((void **)&d_stats, 2 * sizeof(unsigned long long)));
+    const int kblocks = 8 * b->n_cu;
+    if (b->d_segs && b->lg_segs != lg) {
+        dev_release(b, b->d_segs);
+        b->d_segs = nullptr;
+    }
+    if (!b->d_segs && (s = dev_alloc(b, &b->d_segs, M * sizeof(Seg))) != ED_OK) return s;
+    uint32_t *d_cnt = nullptr, *d_factor = nullptr, *d_sizes = nullptr, *d_err = nullptr, *d_bad = nullptr,
+             *d_maxwin = nullptr;
+    unsigned long long *d_rmin = nullptr, *d_rmax = nullptr, *d_stats = nullptr;
+    uint64_t *d_offsets = nullptr, *d_total = nullptr, *d_scan = nullptr;
+    unsigned int *d_count = nullptr;
+    TAKE(tmp, &d_cnt, M * sizeof(uint32_t));
+    TAKE(tmp, &d_factor, M * sizeof(uint32_t));
+    TAKE(tmp, &d_sizes, M * sizeof(uint32_t));
+    TAKE(tmp, &d_rmin, M * sizeof(unsigned long long));
+    TAKE(tmp, &d_rmax, M * sizeof(unsigned long long));
+    TAKE(tmp, &d_offsets, M * sizeof(uint64_t));
+    TAKE(tmp, &d_total, sizeof(uint64_t));
+    TAKE(tmp, &d_scan, scan_tmp_words(M) * sizeof(uint64_t));
+    TAKE(tmp, &d_err, sizeof(uint32_t));
+    TAKE(tmp, &d_bad, sizeof(uint32_t));
+    TAKE(tmp, &d_maxwin, sizeof(uint32_t));
+    TAKE(tmp, &d_count, sizeof(unsigned int));
+    TAKE(tmp, &d_stats, 5 * sizeof(unsigned long long));
+    HIP_OK(hipMemsetAsync(d_cnt, 0, M * sizeof(uint32_t), st));
+    HIP_OK(hipMemsetAsync(d_factor, 0, M * sizeof(uint32_t), st));
+    HIP_OK(hipMemsetAsync(d_rmin, 0xff, M * sizeof(unsigned long long), st));
+    HIP_OK(hipMemsetAsync(d_rmax, 0, M * sizeof(unsigned long long), st));
     HIP_OK(hipMemsetAsync(d_err, 0, sizeof(uint32_t), st));
-    HIP_OK(hipMemsetAsync(d_stats, 0, 2 * sizeof(unsigned long long), st));
-    uint32_t *d_leaf_max = nullptr;
-    HIP_OK(tmp.alloc((void **)&d_leaf_max, M * sizeof(uint32_t)));
-    HIP_OK(leaf_ranges(d_pw, N, lg, b->d_reps, b->dim, b->d_leaves, target, d_sizes, d_err, 8 * b->n_cu, st));
-    HIP_OK(launch_scan(d_sizes, d_offsets, M, d_total, st));
-    HIP_OK(hipMemcpyAsync(&total, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
-    if (total >= (1ull << 32)) return fail(ED_EINVAL, "leaf bucket table too large");
-    // leaves whose largest bucket exceeds kMaxWindow keys get more buckets,
-    // a few rounds at most (bucket tables of the rounds are temporary)
-    {
-        unsigned int *d_count = nullptr;
-        HIP_OK(tmp.alloc((void **)&d_count, sizeof(unsigned int)));
-        uint32_t *d_factor = nullptr;
-        HIP_OK(tmp.alloc((void **)&d_factor, M * sizeof(uint32_t)));
-        HIP_OK(hipMemsetAsync(d_factor, 0, M * sizeof(uint32_t), st));
-        uint32_t *d_tsub = nullptr;
-        uint64_t tsub_cap = 0;
-        for (int round = 0; round < kRefineRounds; ++round) {
-            if (total + 1 > tsub_cap) {
-                HIP_OK(tmp.alloc((void **)&d_tsub, (total + 1) * sizeof(uint32_t)));
-                tsub_cap = total + 1;
-            }
-            HIP_OK(leaf_buckets(b->d_leaves, lg, b->d_reps, d_offsets, d_tsub, d_leaf_max, d_stats, st));
-            unsigned int refined = 0;
-            HIP_OK(hipMemsetAsync(d_count, 0, sizeof(unsigned int), st));
-            HIP_OK(leaf_refine(b->d_leaves, lg, d_leaf_max, kMaxWindow, d_factor, d_count, st));
-            HIP_OK(hipMemcpyAsync(&refined, d_count, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
-            HIP_OK(hipStreamSynchronize(st));
-            if (refined == 0) break;
-            HIP_OK(leaf_reshape(b->d_leaves, lg, b->d_reps, target, d_factor, d_sizes, st));
-            HIP_OK(launch_scan(d_sizes, d_offsets, M, d_total, st));
-            HIP_OK(hipMemcpyAsync(&total, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-            HIP_OK(hipStreamSynchronize(st));
-            if (total >= (1ull << 32)) return fail(ED_EINVAL, "leaf bucket table too large");
+    HIP_OK(hipMemsetAsync(d_bad, 0, sizeof(uint32_t), st));
+    HIP_OK(hipMemsetAsync(d_maxwin, 0, sizeof(uint32_t), st));
+    HIP_OK(hipMemsetAsync(d_stats, 0, 5 * sizeof(unsigned long long), st));
+    HIP_OK(index_route(d_pw, rf, lg, b->d_reps, b->dim, d_cnt, d_rmin, d_rmax, d_err, kblocks, st));
+    // cell ranges and errors; segments with too wide a window get more cells
+    uint32_t *c_first = nullptr, *c_last = nullptr, *c_elo = nullptr, *c_ehi = nullptr;
+    uint64_t cap = 0, total = 0;
+    int rounds = 0;
+    for (;; ++rounds) {
+        HIP_OK(index_seg_shape(M, d_cnt, d_rmin, d_rmax, kpc, d_factor, b->d_segs, d_sizes, st));
+        HIP_OK(launch_scan(d_sizes, d_offsets, M, d_total, d_scan, st));
+        HIP_OK(hipMemcpyAsync(&total, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        if (total >= (1ull << 31)) return fail(ED_EINVAL, "cell table too large");
+        HIP_OK(index_seg_setoff(b->d_segs, M, d_offsets, st));
+        if (total > cap) {
+            cap = total + total / 2 + 1;
+            TAKE(tmp, &c_first, cap * sizeof(uint32_t));
+            TAKE(tmp, &c_last, cap * sizeof(uint32_t));
+            TAKE(tmp, &c_elo, cap * sizeof(uint32_t));
+            TAKE(tmp, &c_ehi, cap * sizeof(uint32_t));
         }
-        HIP_OK(hipMemsetAsync(d_stats, 0, 2 * sizeof(unsigned long long), st));
+        HIP_OK(index_cells(d_pw, rf, lg, b->d_reps, b->dim, b->d_segs, total, c_first, c_last, c_elo, c_ehi, kblocks,
+                           st));
+        if (rounds == kRefineRounds) break;
+        unsigned int refined = 0;
+        HIP_OK(hipMemsetAsync(d_count, 0, sizeof(unsigned int), st));
+        HIP_OK(index_refine(M, b->d_segs, d_sizes, c_first, c_last, c_elo, c_ehi, win, kMaxRefine, d_factor, d_count,
+                            st));
+        HIP_OK(hipMemcpyAsync(&refined, d_count, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        if (refined == 0) break;
     }
-    if (total + 1 > b->sub_cap) {
-        if ((s = dev_alloc(b, (void **)&b->d_sub, (total + 1) * sizeof(uint32_t))) != ED_OK) return s;
-        b->sub_cap = total + 1;
+    if (b->d_cells) {
+        dev_release(b, b->d_cells);
+        b->d_cells = nullptr;
+        b->n_cells = 0;
     }
-    HIP_OK(leaf_buckets(b->d_leaves, lg, b->d_reps, d_offsets, b->d_sub, d_leaf_max, d_stats, st));
+    if ((s = dev_alloc(b, &b->d_cells, total * sizeof(uint2))) != ED_OK) return s;
+    HIP_OK(index_pack(total, c_first, c_last, c_elo, c_ehi, b->d_cells, d_bad, st));
+    b->n_cells = total;
+    b->lg_segs = lg;
+    b->eq_K = K;
+    b->mlp_F = F;
+    uint32_t bad = 0, net_err = 0, max_win = 0;
+    unsigned long long hst[5] = {0, 0, 0, 0, 0};
+    HIP_OK(index_window_stats(d_pw, rf, lg, b->d_reps, b->dim, b->d_segs, b->d_cells, total, d_stats, d_maxwin, kblocks,
+                              st));
+    HIP_OK(hipMemcpyAsync(&bad, d_bad, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HIP_OK(hipMemcpyAsync(&net_err, d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(hstats, d_stats, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    std::vector<uint32_t> hs(M);
-    HIP_OK(hipMemcpyAsync(hs.data(), d_sizes, M * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(&max_win, d_maxwin, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(hst, d_stats, sizeof(hst), hipMemcpyDeviceToHost, st));
+    std::vector<uint32_t> hc(M), hf(M);
+    HIP_OK(hipMemcpyAsync(hc.data(), d_cnt, M * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(hf.data(), d_factor, M * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
-    int64_t used = 0;
-    for (uint32_t v : hs) used += v ? 1 : 0;
+    b->indexed = false;  // until the checks below pass
+    if (bad) return fail(ED_EINVAL, "a cell of the learned index covers 2^20 positions or more");
+    if (hst[4] != 0) return fail(ED_EDEVICE, "learned index build: a key lies outside its recorded window");
+    int64_t used = 0, refined_segs = 0;
+    for (uint64_t q = 0; q < M; ++q) {
+        used += hc[q] ? 1 : 0;
+        refined_segs += hf[q] > 1 ? 1 : 0;
+    }
     for (auto &g : b->step_graph)
         if (g) {
             (void)hipGraphExecDestroy(g);
@@ -746,23 +871,28 @@ ed_status ed_index_train(ed_basis *b, const ed_index_cfg *cfg_in, ed_index_stats
         HIP_OK(hipStreamSynchronize(st));
     }
     b->indexed = true;
-    b->log2_leaves = lg;
-    b->mlp_F = F;
-    b->mlp_c = 0;
+    const double D = (double)b->dim;
     ed_index_stats r{};
-    r.max_err = (int32_t)std::min<unsigned long long>(hstats[1], 0x7fffffffull);
-    r.n_leaves = 1 << lg;
+    r.max_err = (int32_t)max_win;
+    r.n_segments = (int32_t)M;
     r.final_loss = loss;
     r.mlp_max_err = (float)net_err;
     r.mlp_bytes = (int64_t)NP * sizeof(float);
-    r.leaf_bytes = ((int64_t)sizeof(Leaf) << lg) + (int64_t)(total + 1) * (int64_t)sizeof(uint32_t);
+    r.table_bytes = (int64_t)(M * sizeof(Seg) + total * sizeof(uint2));
     r.train_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    r.mean_window = (double)hstats[0] / (double)b->dim;
+    r.mean_window = (double)hst[0] / D;
     r.n_features = F;
     r.n_pieces = pieces;
-    r.feature_offset = mu;
-    r.feature_scale = sc;
-    r.used_leaves = used;
+    r.used_segments = used;
+    r.feature_offset = cfg.routing == 2 ? 0.0f : mu;
+    r.feature_scale = cfg.routing == 2 ? 1.0f : sc;
+    r.n_cells = (int64_t)total;
+    r.refined_segments = refined_segs;
+    r.mean_abs_err = (double)hst[1] / D;
+    r.frac_exact = (double)hst[2] / D;
+    r.mean_lines = (double)hst[3] / D;
+    r.lds_bytes = (int64_t)(b->lay.bytes - b->lay.off_mlp);
+    r.routing = cfg.routing;
     b->istats = r;
     if (out) *out = r;
     return ED_OK;
@@ -788,7 +918,10 @@ ed_status ed_index_predict(const ed_basis *b, const uint64_t *d_keys, int64_t n,
     if (n < 0 || (n > 0 && (!d_keys || !d_u || !d_y))) return fail(ED_EINVAL, "bad arguments");
     if (n == 0) return ED_OK;
     const float *d_pw = reinterpret_cast<const float *>(static_cast<const unsigned char *>(b->d_blob) + b->lay.off_mlp);
-    HIP_OK(index_predict(d_pw, b->T.N, d_keys, n, d_u, d_y, (hipStream_t)stream));
+    const Equalizer eq{reinterpret_cast<const uint64_t *>(b->d_eq),
+                       reinterpret_cast<const double *>(b->d_eq + (kEqMax + 1) * 8), b->eq_K, 1.0 / (double)b->eq_K};
+    const RankFeat rf{b->d_rank, b->T.N - b->T.n_up + 1, b->T.n_up, eq};
+    HIP_OK(index_predict(d_pw, rf, b->T.N, d_keys, n, d_u, d_y, (hipStream_t)stream));
     return ED_OK;
 }
 

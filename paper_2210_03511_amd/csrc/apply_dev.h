@@ -67,12 +67,11 @@ __device__ __forceinline__ int64_t lookup_plain(uint64_t key, const KParams &p)
 }
 
 // Index of a representative (ed_lookup): plain Limits + binary search, or the learned
-// index (network in LDS, leaf table, bounded binary search).
+// index (network and rank table in LDS, segment and cell tables, bounded search).
 template <bool LEARNED>
-__device__ __forceinline__ int64_t lookup(uint64_t key, const KParams &p, const PwView &pw)
+__device__ __forceinline__ int64_t lookup(uint64_t key, const KParams &p, const LearnedLds &li)
 {
-    if (LEARNED)
-        return lookup_learned(key, p.reps, pw, static_cast<const Leaf *>(p.leaves), p.sub, p.N, p.log2_leaves);
+    if (LEARNED) return lookup_learned(key, p.reps, p.lv, li, p.N, p.n_up);
     return lookup_plain(key, p);
 }
 
@@ -121,39 +120,35 @@ __device__ __forceinline__ bool hash_get(uint64_t key, const KParams &p, double 
     }
 }
 
-// x of key through the learned index (network -> leaf -> key-space bucket,
-// as in lookup_learned) over the records {rep, x} kept in basis order (real
-// sectors): the
-// binary search compares the record keys, and the record it ends on is read
-// whole, so x comes with the key that confirms the match.  false if absent.
-template <bool CPLX>
-__device__ __forceinline__ bool learned_get(uint64_t key, const KParams &p, const PwView &pw, double &xr, double &xi)
+// x of key through the learned index over the records {rep, x} kept in
+// basis order (real sectors): the search in the recorded window starts at
+// the predicted record, which is read whole, so when the prediction is exact
+// x comes with the key that confirms it; otherwise the search compares
+// record keys and the record it ends on is read whole.  false if absent.
+// Targets of H.v are sector configurations (n_up up spins below bit N).
+__device__ __forceinline__ bool learned_get(uint64_t key, const KParams &p, const Lds &L, double &xr)
 {
-    constexpr int S = hash_words<CPLX>();
-    const float y = pw_eval(pw, key_feature(key, p.N));
-    uint32_t b;
-    float frac;
-    leaf_of(y, p.log2_leaves, b, frac);
-    const Leaf L = static_cast<const Leaf *>(p.leaves)[b];
-    if (L.lo >= L.hi) return false;
-    const uint32_t q = leaf_bucket(L, key);
-    uint32_t lo = p.sub[L.off + q], hi = p.sub[L.off + q + 1];
-    const uint32_t end = hi;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (p.lrec[(uint64_t)mid * S] < key) lo = mid + 1; else hi = mid;
-    }
-    if (lo >= end) return false;
+    uint32_t pred, lo, hi;
+    if (!learned_window(key, p.lv, L.li, pred, lo, hi)) return false;
     const uint4 *rec = reinterpret_cast<const uint4 *>(p.lrec);
-    uint4 a = rec[CPLX ? 2 * (uint64_t)lo : lo];
-    uint4 c = make_uint4(0u, 0u, 0u, 0u);
-    if (CPLX) c = rec[2 * (uint64_t)lo + 1];
+    uint4 a = rec[pred];
     // whole-record load (see hash_get)
     asm("" : "+v"(a.x), "+v"(a.y), "+v"(a.z), "+v"(a.w));
-    if (CPLX) asm("" : "+v"(c.x), "+v"(c.y));
-    if ((((uint64_t)a.y << 32) | a.x) != key) return false;
+    uint64_t k = ((uint64_t)a.y << 32) | a.x;
+    if (k != key) {
+        uint32_t lo2 = lo, hi2 = hi + 1u;   // half-open
+        if (k < key) lo2 = pred + 1u; else hi2 = pred;
+        while (lo2 < hi2) {
+            const uint32_t mid = (lo2 + hi2) >> 1;
+            if (p.lrec[(uint64_t)mid * 2] < key) lo2 = mid + 1u; else hi2 = mid;
+        }
+        if (lo2 > hi) return false;
+        a = rec[lo2];
+        asm("" : "+v"(a.x), "+v"(a.y), "+v"(a.z), "+v"(a.w));
+        k = ((uint64_t)a.y << 32) | a.x;
+        if (k != key) return false;
+    }
     xr = __hiloint2double((int)a.w, (int)a.z);
-    if (CPLX) xi = __hiloint2double((int)c.y, (int)c.x);
     return true;
 }
 
@@ -240,9 +235,9 @@ __device__ __forceinline__ double apply_row(const KParams &p, const Lds &L, int6
                 if (LK == kLookupHash) {
                     if (!hash_get<CPLX>(f.rep, p, xr, xi)) continue;
                 } else if (LK == kLookupLearned && !CPLX) {
-                    if (!learned_get<CPLX>(f.rep, p, L.pw, xr, xi)) continue;
+                    if (!learned_get(f.rep, p, L, xr)) continue;
                 } else {
-                    const int64_t j = lookup<LK == kLookupLearned>(f.rep, p, L.pw);
+                    const int64_t j = lookup<LK == kLookupLearned>(f.rep, p, L.li);
                     if (j < 0) continue;
                     xr = CPLX ? x[2 * j] : x[j];
                     if (CPLX) xi = x[2 * j + 1];

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -46,10 +47,12 @@ struct ed_basis {
     void *d_gtab = nullptr;       // Rep/Sym tables when they do not fit LDS
     uint64_t *d_lrec = nullptr;   // {rep, x} records in basis order for the learned lookup (real sectors)
     float *d_params = nullptr;
-    void *d_leaves = nullptr;
-    uint32_t *d_sub = nullptr;
-    uint64_t sub_cap = 0;
-    int log2_leaves = 0, mlp_F = 0, mlp_c = 0;
+    uint64_t *d_rank = nullptr;   // rank table, device copy for the build kernels
+    unsigned char *d_eq = nullptr;  // equalizer (knots, inverse widths), device copy for the build kernels
+    void *d_segs = nullptr;       // Seg[2^lg_segs]
+    void *d_cells = nullptr;      // uint2[n_cells]
+    uint64_t n_cells = 0;
+    int lg_segs = 0, eq_K = 1, mlp_F = 0;
     ed_index_stats istats{};
     // hashed staging table
     bool hashed = false;
@@ -57,22 +60,30 @@ struct ed_basis {
     uint64_t hslots = 0;
     uint32_t *d_pos2slot = nullptr;
     ed_hash_stats hstats{};
-    std::vector<void *> allocs;
+    std::vector<std::pair<void *, int64_t>> allocs;  // every device allocation and its size
 };
 
 
 ed_status dev_alloc(ed_basis *b, void **ptr, size_t bytes);
+// Free one allocation of dev_alloc (no-op for NULL) and stop charging it to
+// the memory cap.
+void dev_release(ed_basis *b, void *ptr);
 
 // Temporary device buffers of one call, freed when the call returns (error
-// returns included).
+// returns included).  With a basis, they count against its memory cap while
+// they are held: take() fails with ED_ENOMEM beyond the cap.
 struct TmpPool {
     std::vector<void *> ptrs;
+    ed_basis *basis = nullptr;
+    int64_t held = 0;
     TmpPool() = default;
+    explicit TmpPool(ed_basis *b) : basis(b) {}
     TmpPool(const TmpPool &) = delete;
     TmpPool &operator=(const TmpPool &) = delete;
     ~TmpPool()
     {
         for (void *q : ptrs) (void)hipFree(q);
+        if (basis) basis->bytes -= held;
     }
     hipError_t alloc(void **q, size_t bytes)
     {
@@ -80,6 +91,7 @@ struct TmpPool {
         if (e == hipSuccess) ptrs.push_back(*q);
         return e;
     }
+    ed_status take(void **q, size_t bytes);
 };
 symed::KParams make_params(const ed_basis *b);
 // Copy of the H.v input into the records of lookup mode 1 (basis order, real

@@ -41,6 +41,19 @@ static ed_status balloc(ed_batch *b, void **p, size_t bytes)
     return ED_OK;
 }
 
+// Free an allocation of balloc that a larger one replaced (no-op for NULL).
+// The caller has drained the batch's stream.
+static void brelease(ed_batch *b, void *p)
+{
+    if (!p) return;
+    for (size_t k = 0; k < b->allocs.size(); ++k)
+        if (b->allocs[k] == p) {
+            (void)hipFree(p);
+            b->allocs.erase(b->allocs.begin() + (long)k);
+            return;
+        }
+}
+
 // tiles of every sector for a tile length; uploads descriptors and tile starts
 static ed_status layout_tiles(ed_batch *b, int64_t tile_rows)
 {
@@ -56,13 +69,16 @@ static ed_status layout_tiles(ed_batch *b, int64_t tile_rows)
     b->ntiles = tile0[n];
     // partials hold one value per tile, and one per block of the vector kernels
     const int64_t need = std::max<int64_t>(b->ntiles, b->vec_blocks);
-    if (need > b->partial_cap) {
-        ed_status st = balloc(b, (void **)&b->d_partials, need * sizeof(double));
-        if (st != ED_OK) return st;
-        b->partial_cap = need;
-    }
     // nothing of the batch may be in flight while its tiling changes
     HIP_OK(hipStreamSynchronize(b->own));
+    if (need > b->partial_cap) {
+        double *np = nullptr;
+        ed_status st = balloc(b, (void **)&np, need * sizeof(double));
+        if (st != ED_OK) return st;
+        brelease(b, b->d_partials);
+        b->d_partials = np;
+        b->partial_cap = need;
+    }
     HIP_OK(hipMemcpyAsync(b->d_tile0, tile0.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, b->own));
     HIP_OK(hipMemcpyAsync(b->d_desc, b->hdesc.data(), n * sizeof(SectorDesc), hipMemcpyHostToDevice, b->own));
     HIP_OK(hipStreamSynchronize(b->own));
@@ -279,6 +295,11 @@ ed_status ed_batch_lanczos(ed_batch *b, const void *const *d_v0, int32_t n_iter,
     if ((st = fit_lds(b)) != ED_OK) return st;
     const int n = (int)b->secs.size();
     if (n_iter > b->lanczos_cap) {
+        HIP_OK(hipStreamSynchronize(b->own));
+        for (int s = 0; s < (int)b->alpha.size(); ++s) {
+            brelease(b, b->alpha[s]);
+            brelease(b, b->beta[s]);
+        }
         b->alpha.assign(n, nullptr);
         b->beta.assign(n, nullptr);
         const int cap = std::max(n_iter, 256);

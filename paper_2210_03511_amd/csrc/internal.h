@@ -83,9 +83,11 @@ struct BlobLayout {
     // Rep/Sym tables in a separate device buffer (rep_global != 0): their
     // offsets there and its size; off_rent/off_symlist are unused
     uint32_t rep_global, g_rent, g_symlist, gbytes;
-    uint32_t bytes;      // staged into LDS: up to the network pieces in use
-    uint32_t reserved;   // allocated: room for the largest network expansion
+    uint32_t off_rank;   // learned index: equalizer, then rank table (after the network pieces; 0 until trained)
+    uint32_t bytes;      // staged into LDS: up to the network pieces and rank table in use
+    uint32_t reserved;   // allocated: room for the largest network expansion and rank table
 };
+
 
 // Parameters passed by value to the apply / enumeration kernels.
 struct KParams {
@@ -98,12 +100,9 @@ struct KParams {
     const uint16_t *stab;      // [dim]
     const uint32_t *limits;    // [2^pbits + 1]
     int64_t dim;
-    // learned index (network weights live in the LDS blob at lay.off_mlp)
-    const void *leaves;        // Leaf[2^log2_leaves]
-    const uint32_t *sub;       // key-space buckets of the leaves
-    int32_t log2_leaves;
-    int32_t mlp_F;             // input features
-    int32_t mlp_c;             // bits per feature chunk
+    // learned index: the network (expanded) and the rank table live in the
+    // LDS blob at lay.off_mlp and lay.off_rank; segments and cells here
+    LearnedView lv;
     int32_t has_index;
     // hashed staging table: records {rep, x} (real) or {rep, re, im, -}
     // (complex) in hslots slots, linear probing (null until built)

@@ -80,13 +80,16 @@ __global__ void __launch_bounds__(256) k_count(KParams p, unsigned long long *ou
 template <int LK>
 __global__ void __launch_bounds__(256) k_lookup(KParams p, const uint64_t *keys, int64_t n, int64_t *idx)
 {
-    __shared__ float spw[kPwFloats];
+    // the learned index's region of the blob (network, equalizer, rank table)
+    __shared__ __align__(16) unsigned char sli[kLearnedLdsMax];
     if (LK == kLookupLearned) {
-        const float *g = reinterpret_cast<const float *>(static_cast<const unsigned char *>(p.blob) + p.lay.off_mlp);
-        for (int q = threadIdx.x; q < kPwFloats; q += blockDim.x) spw[q] = g[q];
+        const unsigned char *blob = static_cast<const unsigned char *>(p.blob) + p.lay.off_mlp;
+        const uint32_t nb = p.lay.bytes - p.lay.off_mlp;
+        for (uint32_t q = threadIdx.x; q < nb / 16u; q += blockDim.x)
+            reinterpret_cast<uint4 *>(sli)[q] = reinterpret_cast<const uint4 *>(blob)[q];
         __syncthreads();
     }
-    const PwView pw = pw_view(spw);
+    const LearnedLds li = learned_lds(sli, 0u, LK == kLookupLearned ? p.lay.off_rank - p.lay.off_mlp : 0u);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
         const uint64_t key = keys[k];
@@ -95,9 +98,9 @@ __global__ void __launch_bounds__(256) k_lookup(KParams p, const uint64_t *keys,
         if (!(key & ~p.maskN)) {
             if (LK == kLookupHash) {
                 const bool in = p.is_complex ? hash_find<true>(key, p) >= 0 : hash_find<false>(key, p) >= 0;
-                r = in ? lookup<false>(key, p, pw) : -1;
+                r = in ? lookup<false>(key, p, li) : -1;
             } else {
-                r = lookup<LK == kLookupLearned>(key, p, pw);
+                r = lookup<LK == kLookupLearned>(key, p, li);
             }
         }
         idx[k] = r;
@@ -586,58 +589,45 @@ hipError_t launch_enumerate(const KParams &p, const uint64_t *d_binom, uint64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_scan(const uint32_t *d_in, uint64_t *d_out, uint64_t n, uint64_t *d_total, hipStream_t st)
+uint64_t scan_tmp_words(uint64_t n)
 {
-    // level 0: counts -> offsets within blocks, block sums
     const uint64_t per = (uint64_t)kScanThreads * kScanPer;
-    uint64_t nb = (n + per - 1) / per;
-    if (nb == 0) nb = 1;
-    uint64_t *sums = nullptr, *sums_off = nullptr;
-    hipError_t e = hipMalloc((void **)&sums, (nb + 1) * sizeof(uint64_t));
-    if (e != hipSuccess) return e;
-    e = hipMalloc((void **)&sums_off, (nb + 1) * sizeof(uint64_t));
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(kScanThreads), 0, st, d_in, d_out, n, sums);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (nb > 1) {
-        e = launch_scan_u64(sums, sums_off, nb, d_total, st);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_add_offsets, dim3((n + 255) / 256), dim3(256), 0, st, d_out, n, sums_off);
-    } else {
-        // single block: total = sums[0]
-        e = hipMemcpyAsync(d_total, sums, sizeof(uint64_t), hipMemcpyDeviceToDevice, st);
-        if (e != hipSuccess) return e;
-    }
-    e = hipStreamSynchronize(st);
-    (void)hipFree(sums);
-    (void)hipFree(sums_off);
-    return e;
+    const uint64_t nb = n > per ? (n + per - 1) / per : 1;
+    // block sums and their scanned offsets, then the next level's
+    return 2 * (nb + 1) + (nb > 1 ? scan_tmp_words(nb) : 0);
 }
 
-hipError_t launch_scan_u64(const uint64_t *d_in, uint64_t *d_out, uint64_t n, uint64_t *d_total, hipStream_t st)
+// Exclusive scan, one level: per-block scans, then the block sums are
+// scanned (recursively) and added back.  tmp holds scan_tmp_words(n) words.
+template <typename T>
+static hipError_t scan_level(const T *d_in, uint64_t *d_out, uint64_t n, uint64_t *d_total, uint64_t *tmp,
+                             hipStream_t st)
 {
     const uint64_t per = (uint64_t)kScanThreads * kScanPer;
-    uint64_t nb = (n + per - 1) / per;
-    if (nb == 0) nb = 1;
-    uint64_t *sums = nullptr, *sums_off = nullptr;
-    hipError_t e = hipMalloc((void **)&sums, (nb + 1) * sizeof(uint64_t));
+    const uint64_t nb = n > per ? (n + per - 1) / per : 1;
+    uint64_t *sums = tmp, *sums_off = tmp + nb + 1;
+    if (sizeof(T) == sizeof(uint32_t))
+        hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(kScanThreads), 0, st,
+                           reinterpret_cast<const uint32_t *>(d_in), d_out, n, sums);
+    else
+        hipLaunchKernelGGL(k_scan_u64_block, dim3(nb), dim3(kScanThreads), 0, st,
+                           reinterpret_cast<const uint64_t *>(d_in), d_out, n, sums);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = hipMalloc((void **)&sums_off, (nb + 1) * sizeof(uint64_t));
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_u64_block, dim3(nb), dim3(kScanThreads), 0, st, d_in, d_out, n, sums);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     if (nb > 1) {
-        e = launch_scan_u64(sums, sums_off, nb, d_total, st);
+        e = scan_level<uint64_t>(sums, sums_off, nb, d_total, tmp + 2 * (nb + 1), st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_add_offsets, dim3((n + 255) / 256), dim3(256), 0, st, d_out, n, sums_off);
-    } else {
-        e = hipMemcpyAsync(d_total, sums, sizeof(uint64_t), hipMemcpyDeviceToDevice, st);
-        if (e != hipSuccess) return e;
+        return hipGetLastError();
     }
-    e = hipStreamSynchronize(st);
-    (void)hipFree(sums);
-    (void)hipFree(sums_off);
-    return e;
+    // single block: total = sums[0]
+    return hipMemcpyAsync(d_total, sums, sizeof(uint64_t), hipMemcpyDeviceToDevice, st);
+}
+
+hipError_t launch_scan(const uint32_t *d_in, uint64_t *d_out, uint64_t n, uint64_t *d_total, uint64_t *d_tmp,
+                       hipStream_t st)
+{
+    return scan_level<uint32_t>(d_in, d_out, n, d_total, d_tmp, st);
 }
 
 hipError_t launch_limits(const uint64_t *d_reps, int64_t dim, int N, int pbits, uint32_t *d_limits, hipStream_t st)

@@ -25,7 +25,11 @@ struct LaunchCfg {
 hipError_t launch_enumerate(const KParams &p, const uint64_t *d_binom, uint64_t total, uint64_t chunk_len,
                             uint64_t n_chunks, uint32_t *d_counts, const uint64_t *d_offsets, uint64_t *d_reps,
                             uint16_t *d_stab, bool write, int blocks, hipStream_t st);
-hipError_t launch_scan(const uint32_t *d_in, uint64_t *d_out, uint64_t n, uint64_t *d_total, hipStream_t st);
+// Exclusive scan of n u32 counts into u64 offsets, the total to *d_total;
+// d_tmp: scan_tmp_words(n) words of device memory.  Asynchronous on st.
+hipError_t launch_scan(const uint32_t *d_in, uint64_t *d_out, uint64_t n, uint64_t *d_total, uint64_t *d_tmp,
+                       hipStream_t st);
+uint64_t scan_tmp_words(uint64_t n);
 hipError_t launch_limits(const uint64_t *d_reps, int64_t dim, int N, int pbits, uint32_t *d_limits, hipStream_t st);
 hipError_t launch_limits_stats(const uint32_t *d_limits, int pbits, unsigned long long *d_stats, hipStream_t st);
 hipError_t launch_count_elements(const KParams &p, unsigned long long *d_count, int blocks, hipStream_t st);
@@ -59,7 +63,6 @@ hipError_t launch_axpy_coef(double *psi, const double *v, int64_t n2, const doub
                             int blocks, hipStream_t st);
 // partials[0..blocks) = Re <a|b> per block; complex: partials[blocks..2 blocks) = Im
 hipError_t launch_dot(const void *a, const void *b, int64_t n, bool cplx, double *partials, int blocks, hipStream_t st);
-hipError_t launch_scan_u64(const uint64_t *d_in, uint64_t *d_out, uint64_t n, uint64_t *d_total, hipStream_t st);
 hipError_t prepare_kernels(const KParams &p, int *apply_blocks_per_cu, int *apply_threads);
 hipError_t launch_lstate_init(LState *ls, hipStream_t st);
 

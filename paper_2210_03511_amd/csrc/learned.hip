@@ -1,15 +1,16 @@
 // Learned index over the sorted representative list: training kernels
-// (forward, backward, Adam) and the exact leaf-table build.
+// (forward, backward, Adam) and the build of the tables below the network.
 //
-// The network maps a representative to an estimate of its normalized rank;
-// that estimate routes the key to one of 2^m leaves.  The network is
-// monotone, so the keys routed to a leaf fill a position range [lo, hi).
-// Each leaf splits its range into buckets uniform in key space and records
-// where each bucket begins, so a binary search inside the key's bucket finds
-// every stored key and reports absence for every other key.  Leaves whose
-// largest bucket holds more than kMaxWindow keys get proportionally more
-// buckets, a few rounds at most.  The plain Limits lookup remains the
-// reference the learned lookup is compared with.
+// The network maps the rank of a representative (among all configurations
+// with its number of up spins) to an estimate of its normalized position;
+// the estimate picks one of 2^lg segments.  Each segment maps ranks linearly
+// onto cells, which are allocated in proportion to the keys routed to the
+// segment; each cell records the position range of its keys, predicts a
+// position by linear interpolation inside the cell, and records its largest
+// errors below and above the prediction.  A segment whose cells need a
+// window wider than the target gets four times the cells, a few rounds at
+// most.  Every stored key lies in the window of its own cell, so a search
+// there is exact; the plain Limits lookup remains the reference.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,7 +23,6 @@ namespace symed {
 namespace {
 
 constexpr int kTB = 64;  // samples per training block
-constexpr uint32_t kMaxRefine = 1024;  // largest bucket refinement factor of a leaf
 
 __device__ __forceinline__ uint64_t splitmix(uint64_t x)
 {
@@ -65,8 +65,8 @@ __global__ void k_mlp_init(float *P, int F, uint64_t seed)
 // Sampling mode (X == nullptr): sample s draws position j = hash(seed, step,
 // s) mod D and uses (key = reps[j], t = (j + 1/2) / D).  Explicit mode: X[s][F],
 // T[s].
-__global__ void __launch_bounds__(kTB) k_fwdbwd(const float *__restrict__ Pg, int F, float mu, float sc, int N,
-                                               const uint64_t *__restrict__ reps, int64_t D, uint64_t seed,
+__global__ void __launch_bounds__(kTB) k_fwdbwd(const float *__restrict__ Pg, int F, float mu, float sc,
+                                               RankFeat rf, const uint64_t *__restrict__ reps, int64_t D, uint64_t seed,
                                                int step, const float *__restrict__ X, const float *__restrict__ T,
                                                int64_t n_total, float inv_total, float *gpart, float *lpart)
 {
@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(kTB) k_fwdbwd(const float *__restrict__ Pg, in
         } else {
             const uint64_t h = splitmix(seed ^ ((uint64_t)step << 32) ^ (uint64_t)s);
             const uint64_t j = h % (uint64_t)D;
-            x[0] = (key_feature(reps[j], N) - mu) * sc;
+            x[0] = (equalize(sz_rank(reps[j], rf.binom, rf.W), rf.eq) - mu) * sc;
             t = (float)(((double)j + 0.5) / (double)D);
         }
     } else {
@@ -196,189 +196,250 @@ __global__ void k_adam(float *P, float *m, float *v, const float *gpart, const f
     P[p] = w;
 }
 
-__global__ void k_leaf_init(Leaf *leaves, uint64_t M)
+// Stage the network pieces and the rank table into LDS.
+__device__ __forceinline__ void stage_index(float *spw, uint64_t *srank, const float *pwg, const RankFeat &rf)
 {
-    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < M; b += (uint64_t)gridDim.x * blockDim.x)
-        leaves[b] = Leaf{0xffffffffu, 0u, 0u, 0u, 0ull, 0.0};
+    for (int q = threadIdx.x; q < kPwFloats; q += blockDim.x) spw[q] = pwg[q];
+    const int nr = rf.n_up * rf.W;
+    for (int q = threadIdx.x; q < nr; q += blockDim.x) srank[q] = rf.binom[q];
+    __syncthreads();
 }
 
-// position range of every leaf
-__global__ void __launch_bounds__(256) k_leaf_range(const float *pwg, int N, int lg, const uint64_t *reps, int64_t D,
-                                                  Leaf *leaves)
+__device__ __forceinline__ void reduce_u64_add(unsigned long long v, unsigned long long *out)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(out, v);
+}
+
+__device__ __forceinline__ void reduce_u32_max(uint32_t v, uint32_t *out)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, v);
+}
+
+// Segment of every key: key count and rank range of each segment, and the
+// largest |network estimate * D - position| (the network's own error).
+__global__ void __launch_bounds__(256) k_route(const float *pwg, RankFeat rf, int lg, const uint64_t *reps, int64_t D,
+                                             uint32_t *cnt, unsigned long long *rmin, unsigned long long *rmax,
+                                             uint32_t *net_err)
 {
     __shared__ float spw[kPwFloats];
-    for (int q = threadIdx.x; q < kPwFloats; q += blockDim.x) spw[q] = pwg[q];
-    __syncthreads();
-    const PwView pw = pw_view(spw);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D; i += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t b;
-        float frac;
-        leaf_of(pw_eval(pw, key_feature(reps[i], N)), lg, b, frac);
-        atomicMin(&leaves[b].lo, (uint32_t)i);
-        atomicMax(&leaves[b].hi, (uint32_t)(i + 1));
-    }
-}
-
-// key-space bucket count of each leaf: about `target` keys per bucket, at
-// most one bucket per position of the range, both times the leaf's
-// refinement factor (0 = 1); sizes[b] = entries of the leaf's bucket-begin
-// array (nsub + 1, or 0 for an empty leaf)
-__global__ void k_leaf_shape(Leaf *leaves, uint64_t M, const uint64_t *reps, uint32_t target,
-                             const uint32_t *factor, uint32_t *sizes)
-{
-    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < M; b += (uint64_t)gridDim.x * blockDim.x) {
-        Leaf L = leaves[b];
-        if (L.lo >= L.hi) {
-            leaves[b] = Leaf{0u, 0u, 0u, 0u, 0ull, 0.0};
-            sizes[b] = 0;
-            continue;
-        }
-        const uint32_t count = L.hi - L.lo;
-        const uint32_t f = (factor && factor[b]) ? factor[b] : 1u;
-        uint64_t nsub = ((uint64_t)count + target - 1) / target * f;
-        if (nsub < 1) nsub = 1;
-        if (nsub > (uint64_t)count * f) nsub = (uint64_t)count * f;
-        const uint64_t k0 = reps[L.lo], k1 = reps[L.hi - 1];
-        L.kfirst = k0;
-        L.nsub = (uint32_t)nsub;
-        L.scale = (double)nsub / ((double)(k1 - k0) + 1.0);
-        leaves[b] = L;
-        sizes[b] = (uint32_t)nsub + 1;
-    }
-}
-
-__global__ void k_leaf_setoff(Leaf *leaves, uint64_t M, const uint64_t *offsets)
-{
-    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < M; b += (uint64_t)gridDim.x * blockDim.x)
-        leaves[b].off = (uint32_t)offsets[b];
-}
-
-// Bucket begins, one wavefront per leaf, its lanes over the positions of the
-// leaf's range [lo, hi) (whatever leaf each position is routed to: the FP32
-// evaluation of the network can step back at a breakpoint, so neighbouring
-// ranges may overlap): sub[off + q] = first position of [lo, hi) whose key
-// lies in bucket q or later.  Position p writes the entries of the buckets
-// after its predecessor's up to its own, and the last position also those
-// after its own, ending with sub[off + nsub] = hi.
-__global__ void __launch_bounds__(256) k_leaf_fill(const Leaf *leaves, uint64_t M, const uint64_t *reps,
-                                                 uint32_t *sub)
-{
-    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    const uint32_t lane = threadIdx.x & 63u;
-    for (uint64_t b = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; b < M; b += waves) {
-        const Leaf L = leaves[b];
-        if (L.lo >= L.hi) continue;
-        for (uint32_t p = L.lo + lane; p < L.hi; p += 64) {
-            const uint32_t q = leaf_bucket(L, reps[p]);
-            const int64_t q0 = (p == L.lo) ? -1 : (int64_t)leaf_bucket(L, reps[p - 1]);
-            for (int64_t r = q0 + 1; r <= (int64_t)q; ++r) sub[L.off + r] = p;
-            if (p + 1 == L.hi)
-                for (uint32_t r = q + 1; r <= L.nsub; ++r) sub[L.off + r] = L.hi;
-        }
-    }
-}
-
-// Bucket sizes, one wavefront per leaf, from the first position of each
-// bucket: the sum of their squares and their maximum (stats), and the
-// largest bucket of every leaf.
-__global__ void __launch_bounds__(256) k_leaf_stats(const Leaf *leaves, uint64_t M, const uint64_t *reps,
-                                                  const uint32_t *sub, uint32_t *leaf_max,
-                                                  unsigned long long *stats)
-{
-    __shared__ unsigned long long ssq[256];
-    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    const uint32_t lane = threadIdx.x & 63u;
-    unsigned long long sq = 0, mx = 0;
-    for (uint64_t b = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; b < M; b += waves) {
-        const Leaf L = leaves[b];
-        uint32_t lm = 0;
-        if (L.lo < L.hi) {
-            for (uint32_t p = L.lo + lane; p < L.hi; p += 64) {
-                const uint32_t q = leaf_bucket(L, reps[p]);
-                if (p != L.lo && leaf_bucket(L, reps[p - 1]) == q) continue;
-                const uint32_t w = sub[L.off + q + 1] - p;
-                sq += (unsigned long long)w * w;
-                lm = w > lm ? w : lm;
-            }
-        }
-        for (int o = 32; o > 0; o >>= 1) lm = max(lm, (uint32_t)__shfl_xor((int)lm, o, 64));
-        if (lane == 0) leaf_max[b] = lm;
-        mx = lm > mx ? lm : mx;
-    }
-    ssq[threadIdx.x] = sq;
-    __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) ssq[threadIdx.x] += ssq[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicAdd(&stats[0], ssq[0]);
-    if (lane == 0) atomicMax(&stats[1], mx);
-}
-
-// Leaves whose largest bucket holds more than `window` keys: the
-// refinement factor grows by ceil(largest / window), up to kMaxRefine in
-// all; `count` receives the number of leaves refined.
-__global__ void k_leaf_refine(const Leaf *leaves, uint64_t M, const uint32_t *leaf_max, uint32_t window,
-                              uint32_t *factor, unsigned int *count)
-{
-    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < M; b += (uint64_t)gridDim.x * blockDim.x) {
-        const Leaf L = leaves[b];
-        if (L.lo >= L.hi) continue;
-        const uint32_t mx = leaf_max[b];
-        const uint32_t f = factor[b] ? factor[b] : 1u;
-        if (mx <= window || f >= kMaxRefine || L.nsub >= (1u << 22)) continue;
-        factor[b] = min(kMaxRefine, f * ((mx + window - 1) / window));
-        atomicAdd(count, 1u);
-    }
-}
-
-// largest |network estimate * D - position| over all keys
-__global__ void __launch_bounds__(256) k_net_err(const float *pwg, int N, const uint64_t *reps, int64_t D,
-                                               uint32_t *net_err)
-{
-    __shared__ float spw[kPwFloats];
-    for (int q = threadIdx.x; q < kPwFloats; q += blockDim.x) spw[q] = pwg[q];
-    __syncthreads();
+    __shared__ uint64_t srank[kRankMaxEntries];
+    stage_index(spw, srank, pwg, rf);
     const PwView pw = pw_view(spw);
     uint32_t worst = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D; i += (int64_t)gridDim.x * blockDim.x) {
-        const float y = pw_eval(pw, key_feature(reps[i], N));
+        const uint64_t rank = sz_rank(reps[i], srank, rf.W);
+        const float y = pw_eval(pw, equalize(rank, rf.eq));
+        const uint32_t s = seg_of(y, lg);
+        atomicAdd(&cnt[s], 1u);
+        atomicMin(&rmin[s], (unsigned long long)rank);
+        atomicMax(&rmax[s], (unsigned long long)rank);
         const double dy = fabs((double)y * (double)D - (double)i);
-        const uint32_t me = dy > 4.0e9 ? 0xffffffffu : (uint32_t)dy;
-        worst = max(worst, me);
+        worst = max(worst, dy > 4.0e9 ? 0xffffffffu : (uint32_t)dy);
     }
-    for (int o = 32; o > 0; o >>= 1) worst = max(worst, (uint32_t)__shfl_xor((int)worst, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(net_err, worst);
+    reduce_u32_max(worst, net_err);
 }
 
-// u and the expanded network output for given keys (verification)
-__global__ void __launch_bounds__(256) k_predict(const float *pwg, int N, const uint64_t *keys, int64_t n, float *u,
-                                               float *y)
+// Cells of every segment: about keys_per_cell keys per cell times the
+// segment's refinement factor; sizes[s] = its cell count (0: no key).
+__global__ void k_seg_shape(uint64_t M, const uint32_t *cnt, const unsigned long long *rmin,
+                            const unsigned long long *rmax, uint32_t keys_per_cell, const uint32_t *factor, Seg *segs,
+                            uint32_t *sizes)
+{
+    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < M; s += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t n = cnt[s];
+        if (n == 0) {
+            segs[s] = Seg{~0ull, 0.0f, 0u};  // every rank lies below r0: absent
+            sizes[s] = 0;
+            continue;
+        }
+        const uint64_t f = factor[s] ? factor[s] : 1u;
+        uint64_t nc = ((uint64_t)n + keys_per_cell - 1) / keys_per_cell * f;
+        const uint64_t span = (uint64_t)(rmax[s] - rmin[s]) + 1;
+        if (nc > span) nc = span;  // no more cells than ranks
+        // scale rounded down, so the segment's last key stays in its last cell
+        const double x = (double)nc / (double)span;
+        float sf = (float)x;
+        if ((double)sf > x) sf = nextafterf(sf, 0.0f);
+        segs[s] = Seg{(uint64_t)rmin[s], sf, 0u};
+        sizes[s] = (uint32_t)nc;
+    }
+}
+
+__global__ void k_seg_setoff(Seg *segs, uint64_t M, const uint64_t *offsets)
+{
+    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < M; s += (uint64_t)gridDim.x * blockDim.x)
+        segs[s].cell0 = (uint32_t)offsets[s];
+}
+
+__global__ void k_cell_clear(uint32_t *first, uint32_t *last, uint32_t *elo, uint32_t *ehi, uint64_t n)
+{
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (uint64_t)gridDim.x * blockDim.x) {
+        first[c] = 0xffffffffu;
+        last[c] = 0u;
+        elo[c] = 0u;
+        ehi[c] = 0u;
+    }
+}
+
+// Cell of every key, as the lookup computes it.
+__device__ __forceinline__ uint64_t key_cell(uint64_t key, const PwView &pw, const uint64_t *srank,
+                                             const RankFeat &rf, int lg, const Seg *segs, uint64_t n_cells,
+                                             double &frac)
+{
+    const uint64_t rank = sz_rank(key, srank, rf.W);
+    const float y = pw_eval(pw, equalize(rank, rf.eq));
+    const Seg S = segs[seg_of(y, lg)];
+    uint64_t ci = 0;
+    frac = 0.0;
+    (void)cell_of(rank, S, n_cells, ci, frac);  // a routed key is never below its segment's r0
+    return ci;
+}
+
+// Position range of the keys of every cell (pass 0), then the largest
+// errors of the cell's interpolation below and above (pass 1).
+template <int PASS>
+__global__ void __launch_bounds__(256) k_cell_pass(const float *pwg, RankFeat rf, int lg, const uint64_t *reps,
+                                                 int64_t D, const Seg *segs, uint64_t n_cells, uint32_t *first,
+                                                 uint32_t *last, uint32_t *elo, uint32_t *ehi)
 {
     __shared__ float spw[kPwFloats];
-    for (int q = threadIdx.x; q < kPwFloats; q += blockDim.x) spw[q] = pwg[q];
-    __syncthreads();
+    __shared__ uint64_t srank[kRankMaxEntries];
+    stage_index(spw, srank, pwg, rf);
+    const PwView pw = pw_view(spw);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D; i += (int64_t)gridDim.x * blockDim.x) {
+        double frac;
+        const uint64_t ci = key_cell(reps[i], pw, srank, rf, lg, segs, n_cells, frac);
+        if (PASS == 0) {
+            atomicMin(&first[ci], (uint32_t)i);
+            atomicMax(&last[ci], (uint32_t)i);
+        } else {
+            const uint32_t pred = first[ci] + cell_offset(last[ci] - first[ci] + 1u, frac);
+            if (pred > (uint32_t)i) atomicMax(&elo[ci], pred - (uint32_t)i);
+            else if (pred < (uint32_t)i) atomicMax(&ehi[ci], (uint32_t)i - pred);
+        }
+    }
+}
+
+// One wavefront per segment: the widest window among its cells; segments
+// wider than `window` keys get four times the cells (factor up to fmax, and
+// at most 2^24 cells per segment).  *count += segments refined.
+__global__ void __launch_bounds__(256) k_seg_refine(uint64_t M, const Seg *segs, const uint32_t *sizes,
+                                                  const uint32_t *first, const uint32_t *last, const uint32_t *elo,
+                                                  const uint32_t *ehi, uint32_t window, uint32_t fmax,
+                                                  uint32_t *factor, unsigned int *count)
+{
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    for (uint64_t s = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; s < M; s += waves) {
+        const uint32_t nc = sizes[s], c0 = segs[s].cell0;
+        uint32_t w = 0;
+        for (uint32_t c = lane; c < nc; c += 64) {
+            const uint32_t g = c0 + c;
+            if (first[g] > last[g]) continue;  // empty cell
+            const uint32_t n = last[g] - first[g] + 1u;
+            w = max(w, min(n, elo[g] + ehi[g] + 1u));
+        }
+        for (int o = 32; o > 0; o >>= 1) w = max(w, (uint32_t)__shfl_xor((int)w, o, 64));
+        if (lane == 0 && w > window) {
+            const uint32_t f = factor[s] ? factor[s] : 1u;
+            if (f < fmax && (uint64_t)nc * 4u <= (1u << 24)) {
+                factor[s] = f * 4u;
+                atomicAdd(count, 1u);
+            }
+        }
+    }
+}
+
+// Final cells {first, n | elo << 20 | ehi << 26}; *bad = 1 if a cell covers
+// 2^20 positions or more.
+__global__ void k_cell_pack(uint64_t n_cells, const uint32_t *first, const uint32_t *last, const uint32_t *elo,
+                            const uint32_t *ehi, uint2 *cells, uint32_t *bad)
+{
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells;
+         c += (uint64_t)gridDim.x * blockDim.x) {
+        if (first[c] > last[c]) {
+            cells[c] = make_uint2(0u, 0u);
+            continue;
+        }
+        const uint32_t n = last[c] - first[c] + 1u;
+        if (n >= (1u << kCellNBits)) atomicMax(bad, 1u);
+        cells[c] = make_uint2(first[c], cell_meta(n, elo[c], ehi[c]));
+    }
+}
+
+// Windows of the finished index, key by key, as the lookup sees them:
+// stats[0] = sum of window sizes, [1] = sum |prediction - position|, [2] =
+// exact predictions, [3] = sum of 128-byte record lines spanned by the
+// window ({rep, x} records of 16 bytes), [4] = keys outside their window
+// (must be 0); max_win = largest window.
+__global__ void __launch_bounds__(256) k_window_stats(const float *pwg, RankFeat rf, int lg, const uint64_t *reps,
+                                                    int64_t D, const Seg *segs, const uint2 *cells, uint64_t n_cells,
+                                                    unsigned long long *stats, uint32_t *max_win)
+{
+    __shared__ float spw[kPwFloats];
+    __shared__ uint64_t srank[kRankMaxEntries];
+    stage_index(spw, srank, pwg, rf);
+    const PwView pw = pw_view(spw);
+    unsigned long long sw = 0, se = 0, sx = 0, sl = 0, so = 0;
+    uint32_t mw = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D; i += (int64_t)gridDim.x * blockDim.x) {
+        double frac;
+        const uint64_t ci = key_cell(reps[i], pw, srank, rf, lg, segs, n_cells, frac);
+        uint32_t pred, lo, hi;
+        cell_window(cells[ci], frac, pred, lo, hi);
+        const uint32_t w = hi - lo + 1u;
+        sw += w;
+        se += pred > (uint32_t)i ? pred - (uint32_t)i : (uint32_t)i - pred;
+        sx += pred == (uint32_t)i;
+        sl += (hi >> 3) - (lo >> 3) + 1u;
+        so += ((uint32_t)i < lo || (uint32_t)i > hi);
+        mw = max(mw, w);
+    }
+    reduce_u64_add(sw, &stats[0]);
+    reduce_u64_add(se, &stats[1]);
+    reduce_u64_add(sx, &stats[2]);
+    reduce_u64_add(sl, &stats[3]);
+    reduce_u64_add(so, &stats[4]);
+    reduce_u32_max(mw, max_win);
+}
+
+// u and the expanded network output for given keys (verification); keys
+// that are not sector configurations give NaN
+__global__ void __launch_bounds__(256) k_predict(const float *pwg, RankFeat rf, int N, const uint64_t *keys, int64_t n,
+                                               float *u, float *y)
+{
+    __shared__ float spw[kPwFloats];
+    __shared__ uint64_t srank[kRankMaxEntries];
+    stage_index(spw, srank, pwg, rf);
     const PwView pw = pw_view(spw);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const float uu = key_feature(keys[i], N);
+        const uint64_t k = keys[i];
+        if (__popcll(k) != rf.n_up || (N < 64 && (k >> N))) {
+            u[i] = __int_as_float(0x7fc00000);
+            y[i] = __int_as_float(0x7fc00000);
+            continue;
+        }
+        const float uu = equalize(sz_rank(k, srank, rf.W), rf.eq);
         u[i] = uu;
         y[i] = pw_eval(pw, uu);
     }
 }
 
-__global__ void k_feature_range(const uint64_t *reps, int64_t D, int N, float *out)
+__global__ void k_feature_range(const uint64_t *reps, int64_t D, RankFeat rf, float *out)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        out[0] = key_feature(reps[0], N);
-        out[1] = key_feature(reps[D - 1], N);
+        out[0] = equalize(sz_rank(reps[0], rf.binom, rf.W), rf.eq);
+        out[1] = equalize(sz_rank(reps[D - 1], rf.binom, rf.W), rf.eq);
     }
 }
 
 }  // namespace
 
-hipError_t feature_range(const uint64_t *reps, int64_t D, int N, float *d_out, hipStream_t st)
+hipError_t feature_range(const uint64_t *reps, int64_t D, const RankFeat &rf, float *d_out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_feature_range, dim3(1), dim3(64), 0, st, reps, D, N, d_out);
+    hipLaunchKernelGGL(k_feature_range, dim3(1), dim3(64), 0, st, reps, D, rf, d_out);
     return hipGetLastError();
 }
 
@@ -392,13 +453,13 @@ hipError_t mlp_init(float *d_params, int F, uint64_t seed, hipStream_t st)
 
 int mlp_train_blocks(int batch) { return (batch + kTB - 1) / kTB; }
 
-hipError_t mlp_train_step(float *d_params, float *d_m, float *d_v, int F, float mu, float sc, int N,
+hipError_t mlp_train_step(float *d_params, float *d_m, float *d_v, int F, float mu, float sc, const RankFeat &rf,
                           const uint64_t *reps, int64_t D, uint64_t seed, int step, int batch, float lr, float *d_gpart,
                           float *d_lpart, float *d_loss, hipStream_t st)
 {
     const int nb = mlp_train_blocks(batch);
     const int NP = mlp_param_count(F, kHidden);
-    hipLaunchKernelGGL(k_fwdbwd, dim3(nb), dim3(kTB), 0, st, d_params, F, mu, sc, N, reps, D, seed, step, nullptr,
+    hipLaunchKernelGGL(k_fwdbwd, dim3(nb), dim3(kTB), 0, st, d_params, F, mu, sc, rf, reps, D, seed, step, nullptr,
                        nullptr, (int64_t)batch, 1.0f / (float)batch, d_gpart, d_lpart);
     hipLaunchKernelGGL(k_adam, dim3((NP + 255) / 256), dim3(256), 0, st, d_params, d_m, d_v, d_gpart, d_lpart, nb,
                        NP, lr, 0.9f, 0.999f, 1e-8f, step + 1, nullptr, d_loss, F, 1);
@@ -410,63 +471,84 @@ hipError_t mlp_loss_grad(const float *d_params, int F, const float *d_X, const f
 {
     const int nb = (int)((n + kTB - 1) / kTB);
     const int NP = mlp_param_count(F, kHidden);
-    hipLaunchKernelGGL(k_fwdbwd, dim3(nb), dim3(kTB), 0, st, d_params, F, 0.0f, 1.0f, 64, nullptr, (int64_t)1, 0ull, 0,
-                       d_X, d_T, n, 1.0f / (float)n, d_gpart, d_lpart);
+    hipLaunchKernelGGL(k_fwdbwd, dim3(nb), dim3(kTB), 0, st, d_params, F, 0.0f, 1.0f, RankFeat{}, nullptr,
+                       (int64_t)1, 0ull, 0, d_X, d_T, n, 1.0f / (float)n, d_gpart, d_lpart);
     hipLaunchKernelGGL(k_adam, dim3((NP + 255) / 256), dim3(256), 0, st, const_cast<float *>(d_params), nullptr,
                        nullptr, d_gpart, d_lpart, nb, NP, 0.0f, 0.0f, 0.0f, 0.0f, 1, d_grad, d_loss, F, 0);
     return hipGetLastError();
 }
 
-hipError_t leaf_ranges(const float *d_pw, int N, int lg, const uint64_t *reps, int64_t D, void *d_leaves,
-                       uint32_t target, uint32_t *d_sizes, uint32_t *d_net_err, int blocks, hipStream_t st)
+hipError_t index_route(const float *d_pw, const RankFeat &rf, int lg, const uint64_t *reps, int64_t D, uint32_t *cnt,
+                       unsigned long long *rmin, unsigned long long *rmax, uint32_t *net_err, int blocks,
+                       hipStream_t st)
 {
-    Leaf *lv = static_cast<Leaf *>(d_leaves);
-    const uint64_t M = 1ull << lg;
-    hipLaunchKernelGGL(k_leaf_init, dim3(1024), dim3(256), 0, st, lv, M);
-    hipLaunchKernelGGL(k_leaf_range, dim3(blocks), dim3(256), 0, st, d_pw, N, lg, reps, D, lv);
-    hipLaunchKernelGGL(k_leaf_shape, dim3(1024), dim3(256), 0, st, lv, M, reps, target, nullptr, d_sizes);
-    hipLaunchKernelGGL(k_net_err, dim3(blocks), dim3(256), 0, st, d_pw, N, reps, D, d_net_err);
+    hipLaunchKernelGGL(k_route, dim3(blocks), dim3(256), 0, st, d_pw, rf, lg, reps, D, cnt, rmin, rmax, net_err);
     return hipGetLastError();
 }
 
-hipError_t leaf_reshape(void *d_leaves, int lg, const uint64_t *reps, uint32_t target, const uint32_t *d_factor,
-                        uint32_t *d_sizes, hipStream_t st)
+hipError_t index_seg_shape(uint64_t M, const uint32_t *cnt, const unsigned long long *rmin,
+                           const unsigned long long *rmax, uint32_t keys_per_cell, const uint32_t *factor, void *segs,
+                           uint32_t *sizes, hipStream_t st)
 {
-    Leaf *lv = static_cast<Leaf *>(d_leaves);
-    const uint64_t M = 1ull << lg;
-    hipLaunchKernelGGL(k_leaf_shape, dim3(1024), dim3(256), 0, st, lv, M, reps, target, d_factor, d_sizes);
+    hipLaunchKernelGGL(k_seg_shape, dim3(1024), dim3(256), 0, st, M, cnt, rmin, rmax, keys_per_cell, factor,
+                       static_cast<Seg *>(segs), sizes);
     return hipGetLastError();
 }
 
-hipError_t leaf_refine(const void *d_leaves, int lg, const uint32_t *d_leaf_max, uint32_t window, uint32_t *d_factor,
-                       unsigned int *d_count, hipStream_t st)
+hipError_t index_seg_setoff(void *segs, uint64_t M, const uint64_t *offsets, hipStream_t st)
 {
-    const Leaf *lv = static_cast<const Leaf *>(d_leaves);
-    const uint64_t M = 1ull << lg;
-    hipLaunchKernelGGL(k_leaf_refine, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, lv, M, d_leaf_max, window,
-                       d_factor, d_count);
+    hipLaunchKernelGGL(k_seg_setoff, dim3(1024), dim3(256), 0, st, static_cast<Seg *>(segs), M, offsets);
     return hipGetLastError();
 }
 
-hipError_t leaf_buckets(void *d_leaves, int lg, const uint64_t *reps, const uint64_t *d_offsets, uint32_t *d_sub,
-                        uint32_t *d_leaf_max, unsigned long long *d_stats, hipStream_t st)
+hipError_t index_cells(const float *d_pw, const RankFeat &rf, int lg, const uint64_t *reps, int64_t D, const void *segs,
+                       uint64_t n_cells, uint32_t *first, uint32_t *last, uint32_t *elo, uint32_t *ehi, int blocks,
+                       hipStream_t st)
 {
-    Leaf *lv = static_cast<Leaf *>(d_leaves);
-    const uint64_t M = 1ull << lg;
-    // one wavefront per leaf, at most 65536 blocks of four
+    const Seg *sg = static_cast<const Seg *>(segs);
+    hipLaunchKernelGGL(k_cell_clear, dim3(1024), dim3(256), 0, st, first, last, elo, ehi, n_cells);
+    hipLaunchKernelGGL(k_cell_pass<0>, dim3(blocks), dim3(256), 0, st, d_pw, rf, lg, reps, D, sg, n_cells, first, last,
+                       elo, ehi);
+    hipLaunchKernelGGL(k_cell_pass<1>, dim3(blocks), dim3(256), 0, st, d_pw, rf, lg, reps, D, sg, n_cells, first, last,
+                       elo, ehi);
+    return hipGetLastError();
+}
+
+hipError_t index_refine(uint64_t M, const void *segs, const uint32_t *sizes, const uint32_t *first,
+                        const uint32_t *last, const uint32_t *elo, const uint32_t *ehi, uint32_t window, uint32_t fmax,
+                        uint32_t *factor, unsigned int *count, hipStream_t st)
+{
+    // one wavefront per segment, at most 65536 blocks of four
     const unsigned blocks = (unsigned)std::min<uint64_t>((M + 3) / 4, 65536);
-    hipLaunchKernelGGL(k_leaf_setoff, dim3(1024), dim3(256), 0, st, lv, M, d_offsets);
-    hipLaunchKernelGGL(k_leaf_fill, dim3(blocks), dim3(256), 0, st, lv, M, reps, d_sub);
-    hipLaunchKernelGGL(k_leaf_stats, dim3(blocks), dim3(256), 0, st, lv, M, reps, d_sub, d_leaf_max, d_stats);
+    hipLaunchKernelGGL(k_seg_refine, dim3(blocks), dim3(256), 0, st, M, static_cast<const Seg *>(segs), sizes, first,
+                       last, elo, ehi, window, fmax, factor, count);
     return hipGetLastError();
 }
 
-hipError_t index_predict(const float *d_pw, int N, const uint64_t *keys, int64_t n, float *u, float *y, hipStream_t st)
+hipError_t index_pack(uint64_t n_cells, const uint32_t *first, const uint32_t *last, const uint32_t *elo,
+                      const uint32_t *ehi, void *cells, uint32_t *bad, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cell_pack, dim3(1024), dim3(256), 0, st, n_cells, first, last, elo, ehi,
+                       static_cast<uint2 *>(cells), bad);
+    return hipGetLastError();
+}
+
+hipError_t index_window_stats(const float *d_pw, const RankFeat &rf, int lg, const uint64_t *reps, int64_t D,
+                              const void *segs, const void *cells, uint64_t n_cells, unsigned long long *stats,
+                              uint32_t *max_win, int blocks, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_window_stats, dim3(blocks), dim3(256), 0, st, d_pw, rf, lg, reps, D,
+                       static_cast<const Seg *>(segs), static_cast<const uint2 *>(cells), n_cells, stats, max_win);
+    return hipGetLastError();
+}
+
+hipError_t index_predict(const float *d_pw, const RankFeat &rf, int N, const uint64_t *keys, int64_t n, float *u,
+                         float *y, hipStream_t st)
 {
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_predict, dim3((unsigned)blocks), dim3(256), 0, st, d_pw, N, keys, n, u, y);
+    hipLaunchKernelGGL(k_predict, dim3((unsigned)blocks), dim3(256), 0, st, d_pw, rf, N, keys, n, u, y);
     return hipGetLastError();
 }
 

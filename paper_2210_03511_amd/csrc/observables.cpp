@@ -108,11 +108,11 @@ ed_status ed_lanczos_vector(const ed_basis *cb, const void *d_v0, int32_t n_iter
     const bool cplx = b->T.is_complex;
     const int64_t n2 = b->dim * (cplx ? 2 : 1);
     double *d_coef = nullptr;
-    if (hipMalloc(&d_coef, n_iter * sizeof(double)) != hipSuccess) return fail(ED_ENOMEM, "coefficients");
+    TmpPool tmp(b);
+    if ((st = tmp.take((void **)&d_coef, n_iter * sizeof(double))) != ED_OK) return st;
     hipStream_t s = b->own;
     auto done = [&](ed_status r) {
-        (void)hipStreamSynchronize(s);
-        (void)hipFree(d_coef);
+        (void)hipStreamSynchronize(s);  // before the pool frees the coefficients
         return r;
     };
     if ((st = lanczos_start(b, d_v0, stream)) != ED_OK) return done(st);
@@ -135,12 +135,13 @@ ed_status ed_lanczos_vector(const ed_basis *cb, const void *d_v0, int32_t n_iter
 
 namespace {
 
-// y = O x for an operator O of the same form as H (bonds, chirality
-// triangles) invariant under the basis's group: O's pair table replaces H's
-// in the H.v kernel.  Enqueued on `s`; the caller synchronizes.  d_blob
-// receives O's tables (freed by the caller).
-ed_status apply_op_enqueue(ed_basis *b, const ed_model *op, const void *d_x, void *d_y, int32_t lookup_mode,
-                           void **d_blob, hipStream_t s)
+// Tables of an operator O of the same form as H (bonds, chirality
+// triangles), which must be invariant under the basis's group: O's pair
+// table in place of H's, in a blob laid out like the basis's (lay2).  The
+// learned index network, which lives in the blob, is carried over by
+// op_apply.  Host only.
+ed_status op_tables(const ed_basis *b, const ed_model *op, int32_t lookup_mode, std::vector<uint8_t> &blob,
+                    BlobLayout &lay2, int &n_pairs)
 {
     if (!(lookup_mode == 0 || (lookup_mode == 1 && b->indexed) || (lookup_mode == 2 && b->hashed)))
         return fail(ED_EINVAL, "lookup_mode not available on this basis");
@@ -161,31 +162,74 @@ ed_status apply_op_enqueue(ed_basis *b, const ed_model *op, const void *d_x, voi
     ed_status st = check_invariant(op, T2);
     if (st != ED_OK) return st;
     build_pairs(op, T2);
-    BlobLayout lay2{};
-    std::vector<uint8_t> blob = pack_blob(T2, lay2);
+    lay2 = BlobLayout{};
+    blob = pack_blob(T2, lay2);
+    n_pairs = (int)T2.pairs.size();
     int lds_max = 0;
     if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device) != hipSuccess)
         return fail(ED_EDEVICE, "device query");
     if ((int64_t)lay2.bytes + (b->lay.bytes - b->lay.off_mlp) + 256 > lds_max)
         return fail(ED_EINVAL, "operator tables exceed the LDS of one block");
-    if (hipMalloc(d_blob, blob.size()) != hipSuccess) return fail(ED_ENOMEM, "operator tables");
-    hipError_t e = hipMemcpyAsync(*d_blob, blob.data(), blob.size(), hipMemcpyHostToDevice, s);
-    // the learned index network lives in the blob: carry it over
-    if (e == hipSuccess && b->indexed) {
-        e = hipMemcpyAsync(static_cast<unsigned char *>(*d_blob) + lay2.off_mlp,
-                           static_cast<const unsigned char *>(b->d_blob) + b->lay.off_mlp, kPwFloats * sizeof(float),
-                           hipMemcpyDeviceToDevice, s);
+    // the learned index's network pieces and rank table are copied in behind
+    // the tables, at the same offsets relative to off_mlp
+    if (b->indexed) {
+        lay2.off_rank = lay2.off_mlp + (b->lay.off_rank - b->lay.off_mlp);
         lay2.bytes = lay2.off_mlp + (b->lay.bytes - b->lay.off_mlp);
     }
+    return ED_OK;
+}
+
+// Bytes of device memory an operator blob takes (tables, and the carried
+// network pieces).
+size_t op_blob_bytes(const ed_basis *b, const std::vector<uint8_t> &blob, const BlobLayout &lay2)
+{
+    size_t n = blob.size();
+    if (b->indexed) n = std::max(n, (size_t)lay2.bytes);
+    return (n + 255) & ~(size_t)255;
+}
+
+// y = O x, enqueued on s with O's blob copied to d_blob (op_blob_bytes of
+// device memory); the caller synchronizes before the host blob or d_blob go.
+ed_status op_apply(ed_basis *b, const std::vector<uint8_t> &blob, const BlobLayout &lay2, int n_pairs, void *d_blob,
+                   const void *d_x, void *d_y, int32_t lookup_mode, hipStream_t s)
+{
+    hipError_t e = hipMemcpyAsync(d_blob, blob.data(), blob.size(), hipMemcpyHostToDevice, s);
+    // the learned index's network and rank table live in the blob: carry them over
+    if (e == hipSuccess && b->indexed)
+        e = hipMemcpyAsync(static_cast<unsigned char *>(d_blob) + lay2.off_mlp,
+                           static_cast<const unsigned char *>(b->d_blob) + b->lay.off_mlp,
+                           b->lay.bytes - b->lay.off_mlp, hipMemcpyDeviceToDevice, s);
     KParams p = make_params(b);
     p.lay = lay2;
-    p.blob = *d_blob;
-    p.n_pairs = (int)T2.pairs.size();
+    p.blob = d_blob;
+    p.n_pairs = n_pairs;
     int bpc = 0, thr = 0;
     if (e == hipSuccess) e = prepare_kernels(p, &bpc, &thr);
     if (e == hipSuccess) e = stage_input(b, lookup_mode, d_x, s);
     if (e == hipSuccess) e = launch_apply(p, b->cfg, d_x, d_y, 0, lookup_mode, nullptr, nullptr, s);
     if (e != hipSuccess) return fail(ED_EDEVICE, std::string("operator apply: ") + hipGetErrorString(e));
+    return ED_OK;
+}
+
+// <z, y> = sum conj(z_i) y_i from the per-block partials of the dot kernel
+// (d_part: 2 * vec_blocks doubles); synchronizes s.
+ed_status op_dot(ed_basis *b, const void *d_z, const void *d_y, double *d_part, double *h_re, double *h_im,
+                 hipStream_t s)
+{
+    const bool cplx = b->T.is_complex;
+    const int nb = b->cfg.vec_blocks;
+    std::vector<double> part(2 * nb, 0.0);
+    hipError_t e = launch_dot(d_z, d_y, b->dim, cplx, d_part, nb, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(part.data(), d_part, (cplx ? 2 : 1) * nb * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(ED_EDEVICE, std::string("dot product: ") + hipGetErrorString(e));
+    double re = 0.0, im = 0.0;
+    for (int q = 0; q < nb; ++q) re += part[q];
+    if (cplx)
+        for (int q = 0; q < nb; ++q) im += part[nb + q];
+    *h_re = re;
+    if (h_im) *h_im = im;
     return ED_OK;
 }
 
@@ -204,39 +248,21 @@ ed_status ed_apply_op(const ed_basis *cb, const ed_model *op, const void *d_x, v
         if (h_im) *h_im = 0.0;
     }
     if (b->dim == 0) return ED_OK;
-    const bool cplx = b->T.is_complex;
-    const int nb = b->cfg.vec_blocks;
     hipStream_t s = (hipStream_t)stream;
+    std::vector<uint8_t> blob;
+    BlobLayout lay2{};
+    int n_pairs = 0;
+    ed_status st = op_tables(b, op, lookup_mode, blob, lay2, n_pairs);
+    if (st != ED_OK) return st;
+    TmpPool tmp(b);
     void *d_blob = nullptr;
     double *d_part = nullptr;
-    auto cleanup = [&](ed_status r) {
-        (void)hipStreamSynchronize(s);
-        (void)hipFree(d_blob);
-        (void)hipFree(d_part);
-        return r;
-    };
-    if (d_z && hipMalloc((void **)&d_part, 2 * nb * sizeof(double)) != hipSuccess)
-        return cleanup(fail(ED_ENOMEM, "dot partials"));
-    ed_status st = apply_op_enqueue(b, op, d_x, d_y, lookup_mode, &d_blob, s);
-    if (st != ED_OK) return cleanup(st);
-    hipError_t e = hipSuccess;
-    std::vector<double> part(2 * nb, 0.0);
-    if (d_z) {
-        e = launch_dot(d_z, d_y, b->dim, cplx, d_part, nb, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(part.data(), d_part, (cplx ? 2 : 1) * nb * sizeof(double), hipMemcpyDeviceToHost, s);
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return cleanup(fail(ED_EDEVICE, std::string("operator apply: ") + hipGetErrorString(e)));
-    if (d_z) {
-        double re = 0.0, im = 0.0;
-        for (int q = 0; q < nb; ++q) re += part[q];
-        if (cplx)
-            for (int q = 0; q < nb; ++q) im += part[nb + q];
-        *h_re = re;
-        if (h_im) *h_im = im;
-    }
-    return cleanup(ED_OK);
+    if ((st = tmp.take(&d_blob, op_blob_bytes(b, blob, lay2))) != ED_OK) return st;
+    if (d_z && (st = tmp.take((void **)&d_part, 2 * b->cfg.vec_blocks * sizeof(double))) != ED_OK) return st;
+    st = op_apply(b, blob, lay2, n_pairs, d_blob, d_x, d_y, lookup_mode, s);
+    if (st == ED_OK && d_z) st = op_dot(b, d_z, d_y, d_part, h_re, h_im, s);
+    (void)hipStreamSynchronize(s);  // before the pool and the host blob go
+    return st;
 }
 
 ed_status ed_expectation(const ed_basis *cb, const ed_model *op, const void *d_psi, int32_t lookup_mode,
@@ -251,34 +277,22 @@ ed_status ed_expectation(const ed_basis *cb, const ed_model *op, const void *d_p
     }
     const bool cplx = b->T.is_complex;
     const size_t vbytes = (size_t)b->dim * sizeof(double) * (cplx ? 2 : 1);
-    const int nb = b->cfg.vec_blocks;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<uint8_t> blob;
+    BlobLayout lay2{};
+    int n_pairs = 0;
+    ed_status st = op_tables(b, op, lookup_mode, blob, lay2, n_pairs);
+    if (st != ED_OK) return st;
+    TmpPool tmp(b);
     void *d_blob = nullptr, *d_y = nullptr;
     double *d_part = nullptr;
-    hipStream_t s = (hipStream_t)stream;
-    auto cleanup = [&](ed_status r) {
-        (void)hipStreamSynchronize(s);
-        (void)hipFree(d_blob);
-        (void)hipFree(d_y);
-        (void)hipFree(d_part);
-        return r;
-    };
-    if (hipMalloc(&d_y, vbytes) != hipSuccess || hipMalloc((void **)&d_part, 2 * nb * sizeof(double)) != hipSuccess)
-        return cleanup(fail(ED_ENOMEM, "operator workspace"));
-    ed_status st = apply_op_enqueue(b, op, d_psi, d_y, lookup_mode, &d_blob, s);
-    if (st != ED_OK) return cleanup(st);
-    hipError_t e = launch_dot(d_psi, d_y, b->dim, cplx, d_part, nb, s);
-    std::vector<double> part(2 * nb, 0.0);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(part.data(), d_part, (cplx ? 2 : 1) * nb * sizeof(double), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return cleanup(fail(ED_EDEVICE, std::string("expectation: ") + hipGetErrorString(e)));
-    double re = 0.0, im = 0.0;
-    for (int q = 0; q < nb; ++q) re += part[q];
-    if (cplx)
-        for (int q = 0; q < nb; ++q) im += part[nb + q];
-    *h_re = re;
-    if (h_im) *h_im = im;
-    return cleanup(ED_OK);
+    if ((st = tmp.take(&d_y, vbytes)) != ED_OK) return st;
+    if ((st = tmp.take((void **)&d_part, 2 * b->cfg.vec_blocks * sizeof(double))) != ED_OK) return st;
+    if ((st = tmp.take(&d_blob, op_blob_bytes(b, blob, lay2))) != ED_OK) return st;
+    st = op_apply(b, blob, lay2, n_pairs, d_blob, d_psi, d_y, lookup_mode, s);
+    if (st == ED_OK) st = op_dot(b, d_psi, d_y, d_part, h_re, h_im, s);
+    (void)hipStreamSynchronize(s);
+    return st;
 }
 
 }  // extern "C"

@@ -23,7 +23,7 @@ struct Lds {
     const double *sqrtt;
     const double *isqrtt;
     const uint8_t *chione;
-    PwView pw;
+    LearnedLds li;  // learned index: network pieces, equalizer, rank table
 };
 
 // Views of the tables: b is the staged blob (LDS), g the buffer that holds
@@ -48,7 +48,7 @@ __host__ __device__ __forceinline__ Lds lds_view(const unsigned char *b, const B
     v.sqrtt = reinterpret_cast<const double *>(b + L.off_sqrt);
     v.isqrtt = reinterpret_cast<const double *>(b + L.off_isqrt);
     v.chione = b + L.off_chione;
-    v.pw = pw_view(reinterpret_cast<const float *>(b + L.off_mlp));
+    v.li = learned_lds(b, L.off_mlp, L.off_rank);
     return v;
 }
 

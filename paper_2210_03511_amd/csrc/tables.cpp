@@ -373,10 +373,13 @@ std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &L, std::vector<u
     L.off_sqrt = (uint32_t)o;    o = align16(o + (size_t)(T.G + 1) * sizeof(double));
     L.off_isqrt = (uint32_t)o;   o = align16(o + (size_t)(T.G + 1) * sizeof(double));
     L.off_chione = (uint32_t)o;  o = align16(o + (size_t)2 * T.n_sp);
-    // space for the learned-index network in expanded form (filled after training)
+    // space for the learned index, filled after training: the network in
+    // expanded form, then the equalizer and the rank table right behind the
+    // pieces in use
     L.off_mlp = (uint32_t)o;
+    L.off_rank = 0;
     L.bytes = (uint32_t)align16(o + kPwHeader * sizeof(float));   // no network yet: header only
-    o = align16(o + (size_t)kPwFloats * sizeof(float));
+    o = o + (size_t)kLearnedLdsMax;
     L.reserved = (uint32_t)o;
     std::vector<uint8_t> blob(o, 0);
     auto put = [&](uint32_t off, const void *src, size_t n) { if (n) std::memcpy(blob.data() + off, src, n); };

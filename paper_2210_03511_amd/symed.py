@@ -69,15 +69,23 @@ class BasisInfo(ctypes.Structure):
 class IndexCfg(ctypes.Structure):
     _fields_ = [("n_features", ctypes.c_int32), ("hidden", ctypes.c_int32), ("steps", ctypes.c_int32),
                 ("batch", ctypes.c_int32), ("lr", ctypes.c_float), ("seed", ctypes.c_uint32),
-                ("log2_leaves", ctypes.c_int32), ("keys_per_bucket", ctypes.c_int32)]
+                ("log2_segments", ctypes.c_int32), ("keys_per_cell", ctypes.c_int32),
+                ("max_window", ctypes.c_int32), ("routing", ctypes.c_int32)]
+
+
+# routing of the learned index: what picks the segment
+ROUTE_TRAINED, ROUTE_UNTRAINED, ROUTE_NONE = 0, 1, 2
 
 
 class IndexStats(ctypes.Structure):
-    _fields_ = [("max_err", ctypes.c_int32), ("n_leaves", ctypes.c_int32), ("final_loss", ctypes.c_float),
-                ("mlp_max_err", ctypes.c_float), ("mlp_bytes", ctypes.c_int64), ("leaf_bytes", ctypes.c_int64),
+    _fields_ = [("max_err", ctypes.c_int32), ("n_segments", ctypes.c_int32), ("final_loss", ctypes.c_float),
+                ("mlp_max_err", ctypes.c_float), ("mlp_bytes", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
                 ("train_seconds", ctypes.c_double), ("mean_window", ctypes.c_double),
-                ("n_features", ctypes.c_int32), ("n_pieces", ctypes.c_int32), ("used_leaves", ctypes.c_int64),
-                ("feature_offset", ctypes.c_float), ("feature_scale", ctypes.c_float)]
+                ("n_features", ctypes.c_int32), ("n_pieces", ctypes.c_int32), ("used_segments", ctypes.c_int64),
+                ("feature_offset", ctypes.c_float), ("feature_scale", ctypes.c_float),
+                ("n_cells", ctypes.c_int64), ("refined_segments", ctypes.c_int64), ("mean_abs_err", ctypes.c_double),
+                ("frac_exact", ctypes.c_double), ("mean_lines", ctypes.c_double), ("lds_bytes", ctypes.c_int64),
+                ("routing", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -306,9 +314,10 @@ class Basis:
         n = nd.value
         return a[:n], b[:n], n, st == ED_EBREAKDOWN
 
-    def train_index(self, n_features=0, hidden=32, steps=0, batch=0, lr=0.0, seed=1, log2_leaves=0,
-                    keys_per_bucket=0, stream=None):
-        cfg = IndexCfg(n_features, hidden, steps, batch, lr, seed, log2_leaves, keys_per_bucket)
+    def train_index(self, n_features=0, hidden=32, steps=0, batch=0, lr=0.0, seed=1, log2_segments=0,
+                    keys_per_cell=0, max_window=0, routing=ROUTE_TRAINED, stream=None):
+        cfg = IndexCfg(n_features, hidden, steps, batch, lr, seed, log2_segments, keys_per_cell, max_window,
+                       routing)
         stats = IndexStats()
         _check(lib().ed_index_train(self._h, ctypes.byref(cfg), ctypes.byref(stats), _stream_ptr(stream)))
         return stats.as_dict()

@@ -1,7 +1,8 @@
 """Learned index: gradients of the training kernels against the float64
 oracle network, exact agreement of learned and plain lookups (every query,
-found or absent), identical H.v and Lanczos results, and the gain of the
-trained network over an untrained one."""
+found or absent), identical H.v and Lanczos results, the recorded windows
+(every representative inside the window of its own cell), and the gain of
+the trained network over an untrained one and over no network."""
 import sys
 
 import numpy as np
@@ -99,6 +100,8 @@ def test_learned_lookup_is_exact(S, inst):
     st = b.train_index(steps=600)
     _say("  stats", st)
     assert st["max_err"] <= 64
+    assert st["mean_window"] <= st["max_err"]
+    assert 0.0 <= st["frac_exact"] <= 1.0 and st["mean_lines"] >= 1.0
     reps, _ = b.export()
     _check_agreement(S, torch, b, reps, inst)
     # H.v identical to the plain lookup (same targets, same accumulation order)
@@ -121,23 +124,50 @@ def test_learned_lookup_is_exact(S, inst):
     b.free()
 
 
+@pytest.mark.parametrize("routing", [1, 2], ids=["untrained", "no-network"])
+def test_every_routing_is_exact(S, routing):
+    """The tables below the network are built for whatever picks the
+    segment, so the untrained network and no network at all give exact
+    lookups too (only slower ones)."""
+    torch = _torch()
+    inst = L.square32()
+    b = S.Basis.build(inst)
+    st = b.train_index(routing=routing)
+    _say("  routing", routing, st)
+    assert st["routing"] == routing
+    reps, _ = b.export()
+    _check_agreement(S, torch, b, reps, inst)
+    x = torch.from_numpy(V.start_vector(len(reps), 6)).cuda()
+    y0 = torch.zeros_like(x)
+    y1 = torch.zeros_like(x)
+    b.apply_H(x, y0, mode=0)
+    b.apply_H(x, y1, mode=1)
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1)
+    b.free()
+
+
 def test_trained_network_gains_over_untrained(S):
-    """The trained network shrinks the search windows of the same leaf and
-    bucket tables (the buckets alone, behind an untrained network, already
-    beat the plain Limits prefix table), and both beat the plain lookup."""
+    """Same segment and cell tables behind three routings, built to the same
+    window bound.  The trained network fills more segments than the untrained
+    one, misplaces keys by far less, and so needs far fewer cells (the
+    refinement makes up for bad routing with table size); every routing keeps
+    its windows within the bound and beats the plain Limits window."""
     torch = _torch()
     inst = L.square32()
     b = S.Basis.build(inst)
     plain = b.info()["limits_mean_window"]
-    untrained = b.train_index(steps=1, lr=1e-9, log2_leaves=15)
-    trained = b.train_index(steps=1500, log2_leaves=15)
-    _say("plain", plain)
-    _say("untrained", untrained)
-    _say("trained", trained)
-    assert trained["final_loss"] < 0.05 * untrained["final_loss"]
-    assert trained["used_leaves"] > 4 * untrained["used_leaves"]
-    assert trained["mean_window"] < 0.8 * untrained["mean_window"]
-    assert trained["mean_window"] < 0.2 * plain
+    none = b.train_index(routing=2, log2_segments=12)
+    untrained = b.train_index(routing=1, log2_segments=12)
+    trained = b.train_index(steps=1500, log2_segments=12)
+    for name, st in (("plain", plain), ("none", none), ("untrained", untrained), ("trained", trained)):
+        _say(name, st)
+    for st in (none, untrained, trained):
+        assert st["max_err"] <= 64
+        assert st["mean_window"] < 0.2 * plain
+    assert trained["mlp_max_err"] < 0.1 * untrained["mlp_max_err"]
+    assert trained["used_segments"] > 2 * untrained["used_segments"]
+    assert trained["table_bytes"] < 0.5 * untrained["table_bytes"]
     reps, _ = b.export()
     _check_agreement(S, torch, b, reps, inst)
     # after retraining, the gather over the index's records still equals plain
@@ -150,6 +180,55 @@ def test_trained_network_gains_over_untrained(S):
     assert torch.equal(y0, y1)
 
 
+def _time_apply(torch, b, x, y, mode, reps=2):
+    b.apply_H(x, y, mode=mode)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.apply_H(x, y, mode=mode)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    return min(ts)
+
+
+def test_trained_network_gains_at_square40(S):
+    """At the 40-site benchmark sector (430,909,650 states), H.v through the
+    trained network runs at more elements per second than through the
+    untrained network, with the tables below built the same way, and the
+    index (network, segments, cells) is smaller than the plain lookup's
+    Limits table."""
+    torch = _torch()
+    inst = L.square40()
+    b = S.Basis.build(inst)
+    info = b.info()
+    n_el = info["n_elements"]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(21)
+    x = torch.randn(b.dim, dtype=torch.float64, device="cuda", generator=g)
+    y0 = torch.zeros_like(x)
+    y1 = torch.zeros_like(x)
+    rate = {}
+    for name, routing in (("none", 2), ("untrained", 1), ("trained", 0)):
+        st = b.train_index(routing=routing)
+        t = _time_apply(torch, b, x, y1, 1)
+        rate[name] = n_el / t
+        _say(" ", name, "H.v", round(t, 3), "s", f"{rate[name]:.3e} el/s", {k: st[k] for k in (
+            "mean_window", "max_err", "mean_abs_err", "frac_exact", "mean_lines", "n_cells", "table_bytes",
+            "used_segments", "refined_segments")})
+    assert st["table_bytes"] + st["mlp_bytes"] < info["limits_bytes"]
+    assert rate["trained"] > rate["untrained"]
+    b.apply_H(x, y0, mode=0)
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1)
+    del x, y0, y1
+    b.free()
+
+
 def test_learned_index_requires_training(S):
     torch = _torch()
     b = S.Basis.build(L.chain16())
@@ -159,15 +238,15 @@ def test_learned_index_requires_training(S):
         b.apply_H(x, y, mode=1)
 
 
-def test_large_leaf_table_stays_in_bounds(S):
-    """2^24 leaves: the network output near 1 must map to the last leaf (the
-    float value of 2^24 - 0.5 rounds up to 2^24, so the leaf index is clamped
-    as an integer)."""
+def test_large_segment_table_stays_in_bounds(S):
+    """2^24 segments: the network output near 1 must map to the last segment
+    (the float value of 2^24 - 0.5 rounds up to 2^24, so the segment index is
+    clamped as an integer)."""
     torch = _torch()
     inst = L.square32()
     b = S.Basis.build(inst)
-    st = b.train_index(steps=300, log2_leaves=24)
-    assert st["n_leaves"] == 1 << 24
+    st = b.train_index(steps=300, log2_segments=24)
+    assert st["n_segments"] == 1 << 24
     reps, _ = b.export()
     _check_agreement(S, torch, b, reps, inst)
 
@@ -204,7 +283,7 @@ def test_learned_full_size_equals_plain(S, make):
     b = S.Basis.build(inst)
     st = b.train_index()
     _say("  max_err", st["max_err"], "mean window", round(st["mean_window"], 2))
-    assert st["max_err"] <= 64                 # leaves with larger buckets are refined
+    assert st["max_err"] <= 64                 # segments with wider windows are refined
     g = torch.Generator(device="cuda")
     g.manual_seed(12)
     dt = torch.complex128 if inst.is_complex else torch.float64

@@ -197,6 +197,39 @@ def test_memory_cap(S):
     assert e.value.status == S.ED_ENOMEM
 
 
+def test_memory_cap_counts_build_temporaries(S):
+    """The cap counts the build's temporaries (chunk counts and offsets,
+    scan sums) while they are held: a cap of exactly what the finished basis
+    owns fails with ED_ENOMEM; one with room for the temporaries succeeds and
+    the basis then owns the same bytes as without a cap."""
+    inst = L.small_instances()[13]
+    b = S.Basis.build(inst)
+    owned = b.info()["bytes_device"]
+    b.free()
+    with pytest.raises(S.EdError) as e:
+        S.Basis.build(inst, mem_limit_bytes=owned)
+    assert e.value.status == S.ED_ENOMEM
+    b2 = S.Basis.build(inst, mem_limit_bytes=owned + (64 << 20))
+    assert b2.info()["bytes_device"] == owned
+    b2.free()
+
+
+def test_lanczos_arrays_are_replaced_not_kept(S):
+    """Growing the alpha/beta arrays frees the old ones: after a 300-step run
+    the basis owns the first run's bytes plus the growth of the two arrays
+    (256 -> 512 entries each), not both generations."""
+    torch = _torch()
+    inst = L.chain16()
+    b = S.Basis.build(inst)
+    v0 = _dev(torch, V.start_vector(b.dim, 1002))
+    b.lanczos(v0, 10)
+    before = b.info()["bytes_device"]
+    b.lanczos(v0, 300)
+    after = b.info()["bytes_device"]
+    assert after - before == 2 * (512 - 256) * 8
+    b.free()
+
+
 # --- benchmark-size sectors --------------------------------------------------
 
 def _sampled_rows(inst, count, seed):
@@ -207,17 +240,20 @@ def _sampled_rows(inst, count, seed):
 
 
 def _large_parity(S, inst, n_rows, seed, opts=None):
+    """H.v of the full sector on oracle-sampled rows, in every lookup mode
+    (plain, learned, hashed), against the oracle's gather form."""
     torch = _torch()
     _say("large", inst.name, inst.sector)
     b = S.Basis.build(inst, **(opts or {}))
     info = b.info()
     _say("  built", info["dim"], "in", round(info["build_seconds"], 2), "s")
     assert info["dim"] == O.character_formula_dim(inst)
-    d = info["dim"]
-    # ascending order on the device copy, checked in chunks on the host
+    # ascending order on the device copy, checked on the host
     reps, _ = b.export()
     assert np.all(reps[1:] > reps[:-1])
     rows = _sampled_rows(inst, n_rows, seed)
+    _say("  sampled rows", len(rows))
+    assert len(rows) >= 0.9 * n_rows
     # oracle rows are sector representatives: they must be in the GPU basis
     kt = _dev(torch, rows.view(np.int64))
     it = torch.empty_like(kt)
@@ -226,32 +262,67 @@ def _large_parity(S, inst, n_rows, seed, opts=None):
     idx = it.cpu().numpy()
     assert (idx >= 0).all()
     assert np.array_equal(reps[idx], rows)
-    # H.v on those rows with x(s) = hash(s)
-    x = V.state_vector(reps, 4242, inst.is_complex)
-    xt = _dev(torch, x)
-    yt = torch.zeros_like(xt)
-    b.apply_H(xt, yt)
-    torch.cuda.synchronize()
-    y = yt.cpu().numpy()[idx]
     yo, ok, ne = O.rows_apply(inst, rows, lambda t: V.state_vector(t, 4242, inst.is_complex))
     assert ok.all()
-    err = np.max(np.abs(y - (yo if inst.is_complex else yo.real)))
-    _say("  rows", len(rows), "max err", err)
-    assert err < 1e-12
+    ref = yo if inst.is_complex else yo.real
+    _say("  oracle elements", int(ne.sum()))
+    # H.v on those rows with x(s) = hash(s), in all three lookups
+    x = V.state_vector(reps, 4242, inst.is_complex)
     del reps
+    xt = _dev(torch, x)
+    del x
+    b.train_index()
+    b.build_hash()
+    it_t = torch.from_numpy(idx).cuda()
+    for mode in (0, 1, 2):
+        yt = torch.zeros_like(xt)
+        b.apply_H(xt, yt, mode=mode)
+        y = yt[it_t].cpu().numpy()
+        del yt
+        err = np.max(np.abs(y - ref))
+        _say("  mode", mode, "rows", len(rows), "max err", err)
+        assert err < 1e-12
+    del xt
     b.free()
 
 
 def test_square32_full_size(S):
-    _large_parity(S, L.square32(), 3000, 2001)
+    _large_parity(S, L.square32(), 100_000, 2001)
 
 
 def test_triangular36_full_size(S):
-    _large_parity(S, L.tri36_K(), 1500, 3001)
+    _large_parity(S, L.tri36_K(), 100_000, 3001)
 
 
 def test_square40_full_size(S):
-    _large_parity(S, L.square40(), 1500, 5001)
+    _large_parity(S, L.square40(), 100_000, 5001)
+
+
+def test_square32_every_16th_row(S):
+    """The whole 32-site sector at every 16th row (74,030 rows, about 4.9
+    million matrix elements), element by element against the oracle's
+    gather form, in every lookup mode."""
+    torch = _torch()
+    inst = L.square32()
+    b = S.Basis.build(inst)
+    reps, _ = b.export()
+    rows_idx = np.arange(0, len(reps), 16)
+    rows = reps[rows_idx]
+    yo, ok, ne = O.rows_apply(inst, rows, lambda t: V.state_vector(t, 4242))
+    assert ok.all()
+    _say("  every 16th row:", len(rows), "rows,", int(ne.sum()), "elements")
+    xt = _dev(torch, V.state_vector(reps, 4242))
+    b.train_index()
+    b.build_hash()
+    it_t = torch.from_numpy(rows_idx).cuda()
+    for mode in (0, 1, 2):
+        yt = torch.zeros_like(xt)
+        b.apply_H(xt, yt, mode=mode)
+        y = yt[it_t].cpu().numpy()
+        err = np.max(np.abs(y - yo.real))
+        _say("  mode", mode, "max err", err)
+        assert err < 1e-12
+    b.free()
 
 
 def test_square32_against_stored_oracle_values(S):
