@@ -11,6 +11,10 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 
+def test_host_cpu_model_is_named():
+    assert isinstance(bench.host_cpu_model(), str) and bench.host_cpu_model()
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=300)
@@ -25,12 +29,12 @@ def test_algorithmic_bytes():
 
 
 def test_recorded_traffic_only_for_matching_sources(tmp_path, monkeypatch):
-    rec = {"config": "square40", "sources_sha256": bench.kernel_sources_sha256(), "fetch_factor": 2.0,
-           "write_factor": 1.0, "kernels": {"hash": {"fetch_kib": 10.0, "write_kib": 3.0}}}
+    rec = {"config": "square40", "sources_sha256": bench.kernel_sources_sha256(),
+           "kernels": {"hash": {"dram_read_bytes": 10240.0, "dram_write_bytes": 3072.0}}}
     p = tmp_path / "k_apply_square40_counters.json"
     p.write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
-    assert bench.recorded_traffic("square40", 2) == (10.0 * 2.0 + 3.0) * 1024.0
+    assert bench.recorded_traffic("square40", 2) == 10240.0 + 3072.0
     assert bench.recorded_traffic("square40", 0) is None          # no record for this lookup
     assert bench.recorded_traffic("triangular36", 2) is None      # no record for another workload
     rec["sources_sha256"] = "0" * 64

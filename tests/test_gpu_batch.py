@@ -233,3 +233,51 @@ def test_batch_hash_lookup(S):
     for a, b in zip(r0, r2):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
     batch.free()
+
+
+def test_all_46_sectors_batched_lanczos_against_stored_oracle_energies(S):
+    """All 46 one-dimensional sectors of the 32-site square J1-J2 model
+    (150,281,582 states, 22 of them complex) in one batch: 100 graph-replayed
+    Lanczos steps of every sector.  Two sectors against energies the oracle
+    stored (tests/golden/make_golden.py, make_golden_batch.py), to 1e-10
+    relative: Gamma.A1.even from the start vector of seed 2002, and the
+    smallest complex sector, (0, 1/4).1.even, from seed 4001 + 10; every
+    other sector starts from seed 4001 + its number.  The lowest level over
+    all sectors lies in Gamma.A1.even."""
+    import json
+    import os
+    torch = _torch()
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    g_real = json.load(open(os.path.join(here, "square32_gamma_a1_even.json")))
+    g_cplx = json.load(open(os.path.join(here, "square32_batch_complex.json")))
+    insts = L.square32_sectors()
+    assert len(insts) == 46 and sum(i.is_complex for i in insts) == 22
+    bases = [S.Basis.build(i) for i in insts]
+    dims = [b.dim for b in bases]
+    assert sum(dims) == 150_281_582
+    assert dims[0] == g_real["dim"] and dims[g_cplx["sector_index"]] == g_cplx["dim"]
+    assert insts[g_cplx["sector_index"]].sector == g_cplx["sector"]
+    for b in bases:
+        b.build_hash()
+    batch = S.Batch(bases)
+    seeds = [4001 + k for k in range(len(insts))]
+    seeds[0] = g_real["lanczos_seed"]
+    assert seeds[g_cplx["sector_index"]] == g_cplx["lanczos_seed"]
+    v0s = [_dev(torch, V.start_vector(d, s, i.is_complex)) for d, s, i in zip(dims, seeds, insts)]
+    res = batch.lanczos(v0s, 100, mode=2)
+    e0 = []
+    for (a, b, n, broken), inst in zip(res, insts):
+        assert n == 100 and not broken, inst.sector
+        e0.append(float(S.eigenvalues(a, b, 1)[0]))
+    k = g_cplx["sector_index"]
+    _say("  Gamma.A1.even", repr(e0[0]), "stored", g_real["E0_after_100"])
+    _say("  ", insts[k].sector, repr(e0[k]), "stored", g_cplx["E0_after_100"])
+    assert abs(e0[0] - g_real["E0_after_100"]) <= 1e-10 * abs(g_real["E0_after_100"])
+    assert abs(e0[k] - g_cplx["E0_after_100"]) <= 1e-10 * abs(g_cplx["E0_after_100"])
+    a, b, _, _ = res[k]
+    assert np.max(np.abs(a[:10] - np.array(g_cplx["alpha_first10"]))) < 1e-10
+    assert np.max(np.abs(b[:10] - np.array(g_cplx["beta_first10"]))) < 1e-10
+    assert int(np.argmin(e0)) == 0
+    batch.free()
+    for b in bases:
+        b.free()
