@@ -249,6 +249,24 @@ ed_status ed_apply_op(const ed_basis *basis, const ed_model *op, const void *d_x
                       int32_t lookup_mode, double *re, double *im, void *stream);
 
 /*
+ * ed_apply_op without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same y := O x and <z, y> as
+ * ed_apply_op, with the same arguments, checks and results, but the
+ * operator's tables (at most 224 KiB) and the dot partials (at most 32 KiB)
+ * live in a static 256 KiB device array of the library instead of
+ * temporaries.  Each device the library runs on holds its own copy of that
+ * array until the process ends; its address is looked up at the first call
+ * on a device.  The basis must live on the current device.  All calls on one
+ * device share the array and leave their contents in it: calls of this
+ * entry point that overlap in time on one device race (as do mode 1 and 2
+ * calls on one basis, see ed_apply_H).  Tables larger than the array fail
+ * with ED_EINVAL before anything runs.  Blocks until done.
+ */
+ed_status ed_apply_op_noalloc(const ed_basis *basis, const ed_model *op, const void *d_x, void *d_y,
+                              const void *d_z, int32_t lookup_mode, double *re, double *im, void *stream);
+
+/*
  * Hashed staging table (not in the thesis).  The gather needs, for every
  * target, only x at the target's position.  This table holds records
  * {representative, x} (real) or {representative, Re x, Im x, unused}

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -233,6 +234,37 @@ ed_status op_dot(ed_basis *b, const void *d_z, const void *d_y, double *d_part, 
     return ED_OK;
 }
 
+// Scratch memory of ed_apply_op_noalloc: the operator's table blob, then
+// the dot partials, on every device the library runs on (each holds its own
+// copy until the process ends).  Host code never uses the array's name as an
+// address: the device address of each device's copy comes from
+// hipGetSymbolAddress at the first call on that device.
+constexpr size_t kScratchBytes = 256u << 10;
+constexpr size_t kScratchPartials = 32u << 10;     // dot partials at the end
+constexpr size_t kScratchBlob = kScratchBytes - kScratchPartials;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up once per
+// device, with that device current).
+static ed_status scratch_address(int device, unsigned char **out)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(ED_EINVAL, "device index out of range for the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(ED_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = static_cast<unsigned char *>(g_scratch_ptr[device]);
+    return ED_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -292,6 +324,41 @@ ed_status ed_expectation(const ed_basis *cb, const ed_model *op, const void *d_p
     st = op_apply(b, blob, lay2, n_pairs, d_blob, d_psi, d_y, lookup_mode, s);
     if (st == ED_OK) st = op_dot(b, d_psi, d_y, d_part, h_re, h_im, s);
     (void)hipStreamSynchronize(s);
+    return st;
+}
+
+ed_status ed_apply_op_noalloc(const ed_basis *cb, const ed_model *op, const void *d_x, void *d_y, const void *d_z,
+                              int32_t lookup_mode, double *h_re, double *h_im, void *stream)
+{
+    ed_basis *b = const_cast<ed_basis *>(cb);
+    if (!b || !op || !d_x || !d_y || (d_z && !h_re)) return fail(ED_EINVAL, "bad arguments");
+    if (d_x == d_y) return fail(ED_EINVAL, "y must not alias x");
+    if (d_z) {
+        *h_re = 0.0;
+        if (h_im) *h_im = 0.0;
+    }
+    if (b->dim == 0) return ED_OK;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<uint8_t> blob;
+    BlobLayout lay2{};
+    int n_pairs = 0;
+    ed_status st = op_tables(b, op, lookup_mode, blob, lay2, n_pairs);
+    if (st != ED_OK) return st;
+    const size_t need = op_blob_bytes(b, blob, lay2);
+    if (need > kScratchBlob)
+        return fail(ED_EINVAL, "operator tables (" + std::to_string(need) + " B) exceed the scratch space of " +
+                                   std::to_string(kScratchBlob) + " B");
+    if (d_z && 2 * (size_t)b->cfg.vec_blocks * sizeof(double) > kScratchPartials)
+        return fail(ED_EINVAL, "dot partials exceed the scratch space of " + std::to_string(kScratchPartials) + " B");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(ED_EDEVICE, "hipGetDevice");
+    if (dev != b->device) return fail(ED_EINVAL, "the basis lives on another device than the current one");
+    unsigned char *base = nullptr;
+    if ((st = scratch_address(dev, &base)) != ED_OK) return st;
+    st = op_apply(b, blob, lay2, n_pairs, base, d_x, d_y, lookup_mode, s);
+    if (st == ED_OK && d_z)
+        st = op_dot(b, d_z, d_y, reinterpret_cast<double *>(base + kScratchBlob), h_re, h_im, s);
+    (void)hipStreamSynchronize(s);  // before the host blob goes
     return st;
 }
 

@@ -27,7 +27,7 @@ EXPORTED = ["ed_last_error", "ed_version", "ed_basis_build", "ed_basis_free", "e
             "ed_tables_inspect", "ed_index_train", "ed_index_info", "ed_mlp_loss_grad",
             "ed_index_predict", "ed_batch_create", "ed_batch_apply", "ed_batch_lanczos", "ed_batch_info",
             "ed_batch_free", "ed_hash_build", "ed_ritz_vector", "ed_lanczos_vector", "ed_expectation", "ed_lanczos_resume",
-            "ed_apply_op"]
+            "ed_apply_op", "ed_apply_op_noalloc"]
 
 
 class EdError(RuntimeError):
@@ -160,6 +160,7 @@ def lib():
         L.ed_lanczos_vector.argtypes = [vp, vp, i32, i32, vp, vp, vp]
         L.ed_expectation.argtypes = [vp, ctypes.POINTER(_Model), vp, i32, vp, vp, vp]
         L.ed_apply_op.argtypes = [vp, ctypes.POINTER(_Model), vp, vp, vp, i32, vp, vp, vp]
+        L.ed_apply_op_noalloc.argtypes = [vp, ctypes.POINTER(_Model), vp, vp, vp, i32, vp, vp, vp]
         L.ed_hash_build.argtypes = [vp, ctypes.POINTER(HashCfg), ctypes.POINTER(HashStats), vp]
         L.ed_batch_create.argtypes = [vp, i32, ctypes.POINTER(BatchCfg), vp, ctypes.POINTER(vp)]
         L.ed_batch_apply.argtypes = [vp, vp, vp, i32, vp]
@@ -363,6 +364,19 @@ class Basis:
         _check(lib().ed_apply_op(self._h, ctypes.byref(m), _tensor_ptr(x), _tensor_ptr(y),
                                  None if z is None else _tensor_ptr(z), int(mode), ctypes.byref(re), ctypes.byref(im),
                                  _stream_ptr(stream)))
+        del keep
+        return None if z is None else complex(re.value, im.value)
+
+    def apply_op_noalloc(self, x, y, bonds=None, bond_J=None, tris=None, tri_Jchi=None, z=None, mode=0,
+                         stream=None):
+        """``apply_op`` through ed_apply_op_noalloc: the operator's tables and
+        the dot partials go to the library's static device scratch array."""
+        m, keep = self._op_model(bonds, bond_J, tris, tri_Jchi)
+        re = ctypes.c_double(0.0)
+        im = ctypes.c_double(0.0)
+        _check(lib().ed_apply_op_noalloc(self._h, ctypes.byref(m), _tensor_ptr(x), _tensor_ptr(y),
+                                         None if z is None else _tensor_ptr(z), int(mode), ctypes.byref(re),
+                                         ctypes.byref(im), _stream_ptr(stream)))
         del keep
         return None if z is None else complex(re.value, im.value)
 
