@@ -430,32 +430,52 @@ ed_status ed_mlp_loss_grad(int32_t n_features, const float *d_params, const floa
  * them at once: the rows of all sectors are cut into equal tiles, every
  * block of one persistent grid walks the tiles round-robin and stages the
  * tables of a tile's sector into LDS when it changes sector.  One Lanczos
- * step of all sectors is captured once as a HIP graph and replayed.  The
- * tile length is chosen by timing one batched H.v per candidate (2048,
- * 8192, 32768, 131072 rows) unless fixed by tile_rows with autotune = 0.
- * Real and complex sectors may be mixed; lookup_mode 1 needs a trained
- * learned index in every sector, lookup_mode 2 the hashed staging table in
- * every sector (the input vectors are copied into the tables first, so
- * mode-2 calls must not overlap with other calls on those sectors).
+ * step of all sectors is captured once as a HIP graph and replayed.  Real
+ * and complex sectors may be mixed; lookup_mode 1 needs a trained learned
+ * index in every sector, lookup_mode 2 the hashed staging table in every
+ * sector (the input vectors are copied into the tables first, so mode-2
+ * calls must not overlap with other calls on those sectors).
+ *
+ * Launch shape: the tile length and the blocks per compute unit of the
+ * persistent grid.  With autotune (the default when tile_rows is 0), the
+ * first call in a lookup mode times one batched H.v in that mode for every
+ * candidate (tile lengths 2048, 8192 and 32768 rows, with one block per
+ * compute unit or as many as fit) and keeps the fastest for that mode.  With
+ * cache_path, choices are looked up in that text file first and appended to
+ * it after a tuning, keyed by a fingerprint of the batch (device, lookup
+ * mode, and every sector's dimension, group order, element count,
+ * decompositions and table size): a later batch of the same sectors reuses
+ * them without timing.  Each sector's rows are always summed by one lane in
+ * term order, so H.v does not depend on the launch shape; the Lanczos
+ * reductions are summed per tile, so their rounding does (a cached choice
+ * reproduces the tuned run bit for bit).  Concurrent writers of one cache
+ * file are not coordinated.
  */
 typedef struct ed_batch ed_batch;
 
 typedef struct {
-    int32_t tile_rows;
+    int32_t tile_rows;          /* fixed tile length (used with autotune = 0) */
     int32_t autotune;
-    int32_t reserved[2];
+    int32_t blocks_per_cu;      /* fixed blocks per compute unit (0: as many as fit) */
+    int32_t reserved;
+    const char *cache_path;     /* tuning cache file, or NULL */
 } ed_batch_cfg;
 
 typedef struct {
     int32_t n_sectors;
-    int32_t tile_rows;          /* chosen tile length */
+    int32_t tile_rows;          /* tile length in use */
     int64_t n_tiles;
     int64_t total_dim;
     int64_t total_elements;     /* matrix entries evaluated per batched H.v */
-    int32_t apply_blocks;       /* persistent grid */
-    int32_t n_candidates;       /* autotuning: candidates timed */
+    int32_t apply_blocks;       /* persistent grid in use */
+    int32_t n_candidates;       /* candidates timed by the last tuning (0: none) */
     int32_t tune_rows[8];
+    int32_t tune_blocks[8];     /* blocks per compute unit of each candidate */
     double tune_seconds[8];     /* one batched H.v per candidate */
+    int32_t tune_mode;          /* lookup mode of the last choice (-1: none) */
+    int32_t cache_hit;          /* the last choice came from the cache file */
+    int32_t blocks_per_cu;      /* in use */
+    int32_t reserved;
 } ed_batch_info_t;
 
 /* Create a batch of n sectors (n <= 256); stream: hipStream_t or NULL.
@@ -478,6 +498,31 @@ ed_status ed_batch_info(const ed_batch *batch, ed_batch_info_t *info);
 
 /* Release the batch (not its sectors).  NULL is ignored. */
 void ed_batch_free(ed_batch *batch);
+
+/*
+ * Decomposition tuner.  The representative does not depend on the
+ * sublattice decomposition (any admissible pair gives the same basis), but
+ * the cost of the search does.  For every pair (n_sub_rep, n_sub_act) of
+ * stable contiguous decompositions with n_sub_rep dividing n_sub_act (at
+ * most 16 pairs, finest first), build the sector, prepare lookup_mode
+ * (trained index or hashed table with default settings), time one H.v after
+ * a warm-up, free it, and return the fastest pair.  Pairs the build refuses
+ * (tables too large) are reported with a time of -1.  With cache_path a
+ * stored choice (same model, group, characters, Sz sector, lookup mode and
+ * device) is returned without timing, and a new choice is appended.
+ * Blocks until done; allocates and frees device memory.
+ */
+typedef struct {
+    int32_t n_candidates;
+    int32_t cache_hit;
+    int32_t sub_rep[16];
+    int32_t sub_act[16];
+    double seconds[16];
+} ed_tune_report;
+
+ed_status ed_tune_decomposition(const ed_model *model, const ed_group *group, int32_t n_up, int32_t lookup_mode,
+                                const char *cache_path, void *stream, int32_t *n_sub_rep, int32_t *n_sub_act,
+                                ed_tune_report *report);
 
 /*
  * Host-only inspection of the sublattice-coding tables for one

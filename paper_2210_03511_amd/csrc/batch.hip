@@ -36,8 +36,10 @@ __device__ __forceinline__ int sector_of(const int64_t *tile0, int nsec, int64_t
 
 // lanczos = 0: y_s = H_s x_s.  lanczos = 1: w_s <- H_s v_s - beta_s w_s
 // (real sectors) or w_s <- H_s v_s (complex sectors), partial <w|v> per tile.
+// As for the single-sector kernel, the register budget allows 8 waves per
+// SIMD, so two blocks share a compute unit when the tables leave room.
 template <int LK>
-__global__ void __launch_bounds__(kApplyThreads) k_batch_apply(const SectorDesc *__restrict__ secs, int nsec,
+__global__ void __launch_bounds__(kApplyThreads, 8) k_batch_apply(const SectorDesc *__restrict__ secs, int nsec,
                                                              const int64_t *__restrict__ tile0g, int64_t ntiles,
                                                              int64_t tile_rows, int lanczos, double *partials)
 {

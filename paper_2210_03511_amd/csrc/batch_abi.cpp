@@ -9,6 +9,7 @@
 
 #include "basis.h"
 #include "batch.h"
+#include "tune.h"
 
 using namespace symed;
 
@@ -31,6 +32,12 @@ struct ed_batch {
     hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
     std::vector<void *> allocs;
     ed_batch_info_t info{};
+    // launch shape: fixed, or chosen per lookup mode (tile rows, blocks per CU)
+    bool autotune = true;
+    int max_bpc = 1;
+    int64_t choice_rows[3] = {0, 0, 0};
+    int choice_bpc[3] = {0, 0, 0};
+    std::string cache_path;
 };
 
 static ed_status balloc(ed_batch *b, void **p, size_t bytes)
@@ -57,6 +64,7 @@ static void brelease(ed_batch *b, void *p)
 // tiles of every sector for a tile length; uploads descriptors and tile starts
 static ed_status layout_tiles(ed_batch *b, int64_t tile_rows)
 {
+    b->info.tile_rows = (int32_t)tile_rows;
     const int n = (int)b->secs.size();
     std::vector<int64_t> tile0(n + 1, 0);
     for (int s = 0; s < n; ++s) {
@@ -87,7 +95,119 @@ static ed_status layout_tiles(ed_batch *b, int64_t tile_rows)
             (void)hipGraphExecDestroy(g);
             g = nullptr;
         }
+    b->info.n_tiles = b->ntiles;
     return ED_OK;
+}
+
+// Launch shape: tiles of tile_rows rows on a persistent grid of bpc blocks
+// per compute unit (captured steps hold the old shape and are dropped).
+static ed_status set_shape(ed_batch *b, int64_t tile_rows, int bpc)
+{
+    bpc = std::max(1, std::min(bpc, b->max_bpc));
+    if (tile_rows != b->tile_rows) {
+        ed_status st = layout_tiles(b, tile_rows);
+        if (st != ED_OK) return st;
+    }
+    if (bpc * b->n_cu != b->apply_blocks) {
+        HIP_OK(hipStreamSynchronize(b->own));
+        b->apply_blocks = bpc * b->n_cu;
+        for (auto &g : b->graph)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+    }
+    b->info.apply_blocks = b->apply_blocks;
+    b->info.blocks_per_cu = bpc;
+    return ED_OK;
+}
+
+// Fingerprint of a batch for the tuning cache: device, and every sector's
+// shape, decompositions and table size.
+static uint64_t batch_fingerprint(const ed_batch *b)
+{
+    uint64_t h = device_fingerprint(b->device);
+    for (const ed_basis *s : b->secs) {
+        const int64_t v[] = {s->dim, s->n_elements, s->T.G, s->T.N, s->T.R, s->T.A, s->T.is_complex, s->lay.bytes,
+                             s->lay.rep_global};
+        h = fnv1a(v, sizeof v, h);
+    }
+    return h;
+}
+
+static ed_status batch_apply_impl(ed_batch *b, const void *const *d_x, void *const *d_y, int32_t lookup_mode,
+                                  void *stream);
+
+// The launch shape for a lookup mode: fixed, the choice made earlier, the
+// cache file's, or the fastest of the candidates timed now in that mode.
+static ed_status ensure_shape(ed_batch *b, int mode)
+{
+    if (!b->autotune) return ED_OK;
+    if (b->choice_rows[mode] > 0) return set_shape(b, b->choice_rows[mode], b->choice_bpc[mode]);
+    const uint64_t fp = batch_fingerprint(b);
+    int64_t rows = 0, bpc = 0;
+    ed_status st;
+    if (tune_cache_lookup(b->cache_path.c_str(), "batch", fp, mode, rows, bpc) && rows > 0 && bpc >= 1) {
+        b->choice_rows[mode] = rows;
+        b->choice_bpc[mode] = (int)bpc;
+        b->info.tune_mode = mode;
+        b->info.cache_hit = 1;
+        b->info.n_candidates = 0;
+        return set_shape(b, rows, (int)bpc);
+    }
+    // time one batched H.v in this mode per candidate (after a warm-up)
+    const int n = (int)b->secs.size();
+    std::vector<const void *> xs(n);
+    std::vector<void *> ys(n);
+    for (int s = 0; s < n; ++s) {
+        xs[s] = b->v[s];
+        ys[s] = b->w[s];
+    }
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    const int64_t rows_c[] = {2048, 8192, 32768};
+    std::vector<int> bpcs = {b->max_bpc};
+    if (b->max_bpc > 1) bpcs.push_back(1);
+    double best = 1e300;
+    int64_t best_rows = rows_c[0];
+    int best_bpc = b->max_bpc, k = 0;
+    st = ED_OK;
+    for (int64_t r : rows_c) {
+        for (int c : bpcs) {
+            if (st == ED_OK) st = set_shape(b, r, c);
+            if (st == ED_OK) st = batch_apply_impl(b, xs.data(), ys.data(), mode, b->own);
+            if (st != ED_OK) break;
+            float ms = 0;
+            if (hipEventRecord(e0, b->own) != hipSuccess) st = fail(ED_EDEVICE, "event");
+            if (st == ED_OK) st = batch_apply_impl(b, xs.data(), ys.data(), mode, b->own);
+            if (st == ED_OK && (hipEventRecord(e1, b->own) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                st = fail(ED_EDEVICE, "event timing");
+            if (st != ED_OK) break;
+            if (k < 8) {
+                b->info.tune_rows[k] = (int32_t)r;
+                b->info.tune_blocks[k] = c;
+                b->info.tune_seconds[k] = ms / 1e3;
+                ++k;
+            }
+            if (ms / 1e3 < best) {
+                best = ms / 1e3;
+                best_rows = r;
+                best_bpc = c;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != ED_OK) return st;
+    b->info.n_candidates = k;
+    b->info.tune_mode = mode;
+    b->info.cache_hit = 0;
+    b->choice_rows[mode] = best_rows;
+    b->choice_bpc[mode] = best_bpc;
+    (void)tune_cache_store(b->cache_path.c_str(), "batch", fp, mode, best_rows, best_bpc, best);
+    return set_shape(b, best_rows, best_bpc);
 }
 
 // The tables a sector stages into LDS grow when its learned index is trained
@@ -104,8 +224,10 @@ static ed_status fit_lds(ed_batch *b)
         return fail(ED_EINVAL, "batched kernel does not fit on a compute unit");
     HIP_OK(hipStreamSynchronize(b->own));
     b->lds = need;
-    b->apply_blocks = bpc * b->n_cu;
+    b->max_bpc = bpc;
+    b->apply_blocks = std::min(b->apply_blocks, bpc * b->n_cu);
     b->info.apply_blocks = b->apply_blocks;
+    b->info.blocks_per_cu = b->apply_blocks / b->n_cu;
     for (auto &g : b->graph)
         if (g) {
             (void)hipGraphExecDestroy(g);
@@ -205,49 +327,15 @@ ed_status ed_batch_create(ed_basis *const *sectors, int32_t n, const ed_batch_cf
     b->info.n_sectors = n;
     b->info.total_dim = total;
     b->info.total_elements = elements;
-    // tile length: given, or chosen by timing one batched H.v per candidate
-    const int64_t cands[] = {2048, 8192, 32768, 131072};
-    if (cfg.tile_rows > 0 && !cfg.autotune) {
-        if ((st = layout_tiles(b, cfg.tile_rows)) != ED_OK) return cleanup(st);
-    } else {
-        (void)hipStreamSynchronize(b->own);
-        std::vector<const void *> xs(n);
-        std::vector<void *> ys(n);
-        for (int s = 0; s < n; ++s) {
-            xs[s] = b->v[s];
-            ys[s] = b->w[s];
-        }
-        hipEvent_t e0, e1;
-        (void)hipEventCreate(&e0);
-        (void)hipEventCreate(&e1);
-        double best = 1e300;
-        int64_t best_rows = cands[0];
-        int k = 0;
-        for (int64_t rows : cands) {
-            if ((st = layout_tiles(b, rows)) != ED_OK) return cleanup(st);
-            if ((st = ed_batch_apply(b, xs.data(), ys.data(), 0, b->own)) != ED_OK) return cleanup(st);
-            (void)hipEventRecord(e0, b->own);
-            if ((st = ed_batch_apply(b, xs.data(), ys.data(), 0, b->own)) != ED_OK) return cleanup(st);
-            (void)hipEventRecord(e1, b->own);
-            (void)hipEventSynchronize(e1);
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            b->info.tune_rows[k] = (int32_t)rows;
-            b->info.tune_seconds[k] = ms / 1e3;
-            ++k;
-            if (ms / 1e3 < best) {
-                best = ms / 1e3;
-                best_rows = rows;
-            }
-        }
-        b->info.n_candidates = k;
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        if ((st = layout_tiles(b, best_rows)) != ED_OK) return cleanup(st);
-    }
-    b->info.tile_rows = (int32_t)b->tile_rows;
-    b->info.n_tiles = b->ntiles;
-    b->info.apply_blocks = b->apply_blocks;
+    // launch shape: fixed, or chosen per lookup mode at its first use
+    b->max_bpc = bpc;
+    b->autotune = !(cfg.tile_rows > 0 && !cfg.autotune);
+    b->cache_path = cfg.cache_path ? cfg.cache_path : "";
+    b->info.tune_mode = -1;
+    const int64_t rows0 = cfg.tile_rows > 0 ? cfg.tile_rows : 8192;
+    const int bpc0 = cfg.blocks_per_cu > 0 ? cfg.blocks_per_cu : bpc;
+    if ((st = set_shape(b, rows0, bpc0)) != ED_OK) return cleanup(st);
+    b->tile_rows = rows0;
     *out = b;
     return ED_OK;
 }
@@ -265,6 +353,18 @@ ed_status ed_batch_apply(ed_batch *b, const void *const *d_x, void *const *d_y, 
     ed_status st = check_mode(b, lookup_mode);
     if (st != ED_OK) return st;
     if ((st = fit_lds(b)) != ED_OK) return st;
+    // tuning runs on the batch's own stream: work already queued on `stream` goes first
+    if (b->autotune && b->choice_rows[lookup_mode] == 0) HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    if ((st = ensure_shape(b, lookup_mode)) != ED_OK) return st;
+    return batch_apply_impl(b, d_x, d_y, lookup_mode, stream);
+}
+
+}  // extern "C"
+
+static ed_status batch_apply_impl(ed_batch *b, const void *const *d_x, void *const *d_y, int32_t lookup_mode,
+                                  void *stream)
+{
+    ed_status st = ED_OK;
     const int n = (int)b->secs.size();
     bool changed = false;
     for (int s = 0; s < n; ++s) {
@@ -283,8 +383,10 @@ ed_status ed_batch_apply(ed_batch *b, const void *const *d_x, void *const *d_y, 
     HIP_OK(launch_batch_apply(b->d_desc, n, b->d_tile0, b->ntiles, b->tile_rows, 0, lookup_mode, b->d_partials,
                               b->apply_blocks, b->lds, b->vec_blocks, stm));
     if (changed) HIP_OK(hipStreamSynchronize(stm));  // the host descriptor copy must outlive the transfer
-    return ED_OK;
+    return st;
 }
+
+extern "C" {
 
 ed_status ed_batch_lanczos(ed_batch *b, const void *const *d_v0, int32_t n_iter, int32_t lookup_mode,
                            double *h_alpha, double *h_beta, int32_t *n_done, void *stream)
@@ -293,6 +395,8 @@ ed_status ed_batch_lanczos(ed_batch *b, const void *const *d_v0, int32_t n_iter,
     ed_status st = check_mode(b, lookup_mode);
     if (st != ED_OK) return st;
     if ((st = fit_lds(b)) != ED_OK) return st;
+    HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    if ((st = ensure_shape(b, lookup_mode)) != ED_OK) return st;
     const int n = (int)b->secs.size();
     if (n_iter > b->lanczos_cap) {
         HIP_OK(hipStreamSynchronize(b->own));

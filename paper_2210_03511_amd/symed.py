@@ -27,7 +27,7 @@ EXPORTED = ["ed_last_error", "ed_version", "ed_basis_build", "ed_basis_free", "e
             "ed_tables_inspect", "ed_index_train", "ed_index_info", "ed_mlp_loss_grad",
             "ed_index_predict", "ed_batch_create", "ed_batch_apply", "ed_batch_lanczos", "ed_batch_info",
             "ed_batch_free", "ed_hash_build", "ed_ritz_vector", "ed_lanczos_vector", "ed_expectation", "ed_lanczos_resume",
-            "ed_apply_op", "ed_apply_op_noalloc"]
+            "ed_apply_op", "ed_apply_op_noalloc", "ed_tune_decomposition"]
 
 
 class EdError(RuntimeError):
@@ -104,21 +104,35 @@ class HashStats(ctypes.Structure):
 
 
 class BatchCfg(ctypes.Structure):
-    _fields_ = [("tile_rows", ctypes.c_int32), ("autotune", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+    _fields_ = [("tile_rows", ctypes.c_int32), ("autotune", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("cache_path", ctypes.c_char_p)]
 
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [("n_sectors", ctypes.c_int32), ("tile_rows", ctypes.c_int32), ("n_tiles", ctypes.c_int64),
                 ("total_dim", ctypes.c_int64), ("total_elements", ctypes.c_int64), ("apply_blocks", ctypes.c_int32),
                 ("n_candidates", ctypes.c_int32), ("tune_rows", ctypes.c_int32 * 8),
-                ("tune_seconds", ctypes.c_double * 8)]
+                ("tune_blocks", ctypes.c_int32 * 8), ("tune_seconds", ctypes.c_double * 8),
+                ("tune_mode", ctypes.c_int32), ("cache_hit", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         n = self.n_candidates
         d["tune_rows"] = list(self.tune_rows)[:n]
+        d["tune_blocks"] = list(self.tune_blocks)[:n]
         d["tune_seconds"] = list(self.tune_seconds)[:n]
         return d
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("n_candidates", ctypes.c_int32), ("cache_hit", ctypes.c_int32), ("sub_rep", ctypes.c_int32 * 16),
+                ("sub_act", ctypes.c_int32 * 16), ("seconds", ctypes.c_double * 16)]
+
+    def as_dict(self):
+        n = self.n_candidates
+        return {"n_candidates": n, "cache_hit": self.cache_hit,
+                "candidates": [(self.sub_rep[k], self.sub_act[k], self.seconds[k]) for k in range(n)]}
 
 
 _LIB = None
@@ -168,6 +182,9 @@ def lib():
         L.ed_batch_info.argtypes = [vp, ctypes.POINTER(BatchInfo)]
         L.ed_batch_free.argtypes = [vp]
         L.ed_batch_free.restype = None
+        L.ed_tune_decomposition.argtypes = [ctypes.POINTER(_Model), ctypes.POINTER(_Group), i32, i32,
+                                            ctypes.c_char_p, vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                            ctypes.POINTER(TuneReport)]
         for name in EXPORTED:
             if hasattr(L, name) and name not in ("ed_last_error", "ed_version", "ed_basis_free", "ed_batch_free"):
                 getattr(L, name).restype = ctypes.c_int
@@ -410,11 +427,12 @@ class Batch:
     """Several built sectors run together: one persistent launch per H.v and
     one captured HIP graph per Lanczos step.  The sectors must outlive it."""
 
-    def __init__(self, sectors, tile_rows=0, autotune=True, stream=None):
+    def __init__(self, sectors, tile_rows=0, autotune=True, blocks_per_cu=0, cache_path=None, stream=None):
         self.sectors = list(sectors)
         n = len(self.sectors)
         hs = (ctypes.c_void_p * n)(*[s._h.value for s in self.sectors])
-        cfg = BatchCfg(int(tile_rows), 1 if autotune else 0, (ctypes.c_int32 * 2)(0, 0))
+        self._cache = None if cache_path is None else str(cache_path).encode()
+        cfg = BatchCfg(int(tile_rows), 1 if autotune else 0, int(blocks_per_cu), 0, self._cache)
         h = ctypes.c_void_p()
         _check(lib().ed_batch_create(hs, n, ctypes.byref(cfg), _stream_ptr(stream), ctypes.byref(h)))
         self._h = h
@@ -478,6 +496,21 @@ def ritz_vector(alpha, beta, k=0):
     _check(lib().ed_ritz_vector(_np_ptr(a), _np_ptr(b) if len(b) else None, len(a), int(k), ctypes.byref(lam),
                                 _np_ptr(coef)))
     return lam.value, coef
+
+
+def tune_decomposition(inst, mode=0, cache_path=None, stream=None):
+    """Fastest admissible pair (n_sub_rep, n_sub_act) for a sector by timing
+    one H.v per pair in lookup mode `mode` (ed_tune_decomposition); returns
+    (n_sub_rep, n_sub_act, report)."""
+    arr = _arrays_from(inst)
+    r = ctypes.c_int32(0)
+    a = ctypes.c_int32(0)
+    rep = TuneReport()
+    path = None if cache_path is None else str(cache_path).encode()
+    _check(lib().ed_tune_decomposition(ctypes.byref(arr.model), ctypes.byref(arr.group), int(inst.n_up), int(mode),
+                                       path, _stream_ptr(stream), ctypes.byref(r), ctypes.byref(a),
+                                       ctypes.byref(rep)))
+    return r.value, a.value, rep.as_dict()
 
 
 def eigenvalues(alpha, beta, k=1):

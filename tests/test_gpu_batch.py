@@ -57,9 +57,7 @@ def test_batch_apply_matches_single_and_oracle(S, tile_rows, autotune):
     info = batch.info()
     assert info["n_sectors"] == len(insts)
     assert info["total_dim"] == sum(b.dim for b in bases)
-    if autotune:
-        assert info["n_candidates"] >= 2 and info["tile_rows"] in info["tune_rows"]
-    else:
+    if not autotune:
         assert info["tile_rows"] == tile_rows
     xs, ys, refs = [], [], []
     for k, (inst, b) in enumerate(zip(insts, bases)):
@@ -72,9 +70,15 @@ def test_batch_apply_matches_single_and_oracle(S, tile_rows, autotune):
         refs.append(yt)
     batch.apply_H(xs, ys)
     torch.cuda.synchronize()
+    if autotune:
+        # tuned at the first call, in the lookup mode of that call
+        info = batch.info()
+        assert info["tune_mode"] == 0 and info["n_candidates"] >= 3 and not info["cache_hit"]
+        assert info["tile_rows"] in info["tune_rows"]
     for inst, b, x, y, r in zip(insts, bases, xs, ys, refs):
         assert torch.equal(y, r), f"{inst.name} {inst.sector}"
-        reps, stabs = b.export()
+        reps, stabs = O.enumerate_basis(inst)
+        assert np.array_equal(b.export()[0], reps)
         H = O.coo_matrix(inst, reps, stabs)
         assert np.max(np.abs(y.cpu().numpy() - H @ x.cpu().numpy())) < 1e-12
     # a second call with other vectors reuses the batch
@@ -107,7 +111,8 @@ def test_batch_lanczos(S):
         assert np.max(np.abs(beta[:m] - b1[:m])) < 1e-10
         e = S.eigenvalues(a, beta, 1)[0]
         e1 = S.eigenvalues(a1, b1, 1)[0]
-        reps, stabs = b.export()
+        reps, stabs = O.enumerate_basis(inst)
+        assert np.array_equal(b.export()[0], reps)
         H = O.coo_matrix(inst, reps, stabs)
         ao, bo = O.lanczos(lambda v: H @ v, v0s[k].cpu().numpy(), n_iter, hermitian_complex=inst.is_complex)
         eo = O.tmatrix_eigs(ao, bo)[0]
@@ -281,3 +286,72 @@ def test_all_46_sectors_batched_lanczos_against_stored_oracle_energies(S):
     batch.free()
     for b in bases:
         b.free()
+
+
+def test_autotune_in_running_mode_and_cache_reuse(S, tmp_path):
+    """The launch shape is tuned in the lookup mode that runs (tile length x
+    blocks per compute unit), stored in the cache file, and a second batch of
+    the same sectors reuses it without timing: same shape, and every Lanczos
+    coefficient bit for bit equal to the first batch's."""
+    torch = _torch()
+    insts = [L.square32_sectors()[k] for k in (0, 3, 10)]
+    bases = [S.Basis.build(i) for i in insts]
+    for b in bases:
+        b.build_hash()
+    cache = tmp_path / "tune.txt"
+    v0s = [_dev(torch, V.start_vector(b.dim, 4001 + k, i.is_complex)) for k, (i, b) in enumerate(zip(insts, bases))]
+    b1 = S.Batch(bases, cache_path=cache)
+    assert b1.info()["tune_mode"] == -1                    # nothing tuned before the first call
+    r1 = b1.lanczos(v0s, 20, mode=2)
+    i1 = b1.info()
+    _say("  tuned", i1)
+    assert i1["tune_mode"] == 2 and not i1["cache_hit"] and i1["n_candidates"] >= 3
+    assert (i1["tile_rows"], i1["blocks_per_cu"]) in zip(i1["tune_rows"], i1["tune_blocks"])
+    assert cache.exists() and "batch" in cache.read_text()
+    b1.free()
+    b2 = S.Batch(bases, cache_path=cache)
+    r2 = b2.lanczos(v0s, 20, mode=2)
+    i2 = b2.info()
+    assert i2["cache_hit"] and i2["n_candidates"] == 0 and i2["tune_mode"] == 2
+    assert (i2["tile_rows"], i2["blocks_per_cu"]) == (i1["tile_rows"], i1["blocks_per_cu"])
+    for a, b in zip(r1, r2):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    # another mode is tuned on its own
+    y = [torch.zeros_like(v) for v in v0s]
+    b2.apply_H(v0s, y, mode=0)
+    assert b2.info()["tune_mode"] == 0 and not b2.info()["cache_hit"]
+    b2.free()
+    # a fixed shape equal to the choice gives the same coefficients too
+    b3 = S.Batch(bases, tile_rows=i1["tile_rows"], autotune=False, blocks_per_cu=i1["blocks_per_cu"])
+    r3 = b3.lanczos(v0s, 20, mode=2)
+    for a, b in zip(r1, r3):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    b3.free()
+
+
+def test_decomposition_tuner(S, tmp_path):
+    """Every admissible (n_sub_rep, n_sub_act) pair is timed; the choice is
+    the fastest one, a second call returns it from the cache, and a basis
+    built with it is the automatic one."""
+    torch = _torch()
+    inst = L.square32()
+    cache = tmp_path / "tune.txt"
+    R, A, rep = S.tune_decomposition(inst, mode=2, cache_path=cache)
+    _say("  decomposition", R, A, rep)
+    timed = [(r, a, t) for r, a, t in rep["candidates"] if t >= 0]
+    assert len(timed) >= 2 and not rep["cache_hit"]
+    assert (R, A) == min(timed, key=lambda c: c[2])[:2]
+    R2, A2, rep2 = S.tune_decomposition(inst, mode=2, cache_path=cache)
+    assert (R2, A2) == (R, A) and rep2["cache_hit"] and rep2["n_candidates"] == 0
+    b = S.Basis.build(inst, n_sub_rep=R, n_sub_act=A)
+    b0 = S.Basis.build(inst)
+    assert np.array_equal(b.export()[0], b0.export()[0])
+    x = _dev(torch, V.start_vector(b.dim, 12))
+    y = torch.zeros_like(x)
+    y0 = torch.zeros_like(x)
+    b.apply_H(x, y)
+    b0.apply_H(x, y0)
+    torch.cuda.synchronize()
+    assert torch.equal(y, y0)
+    b.free()
+    b0.free()
