@@ -29,6 +29,11 @@ What each function follows (thesis sections / equations):
   * ``lanczos``          - the real-symmetric two-vector step and the
     complex-Hermitian three-vector step ("The Lanczos algorithm"), no
     reorthogonalization; T-matrix eigenvalues by a library tridiagonal solver.
+  * ``sun_*``            - SU(d) permutation models (chapter on SU(N) chiral
+    spin liquids: H = J sum P_ij + i K3 sum (P_ijk - P_ijk^-1), d colors per
+    site, fixed color counts): the same definitions as above - orbit minima,
+    stabilizers, push-form matrix - over configurations written with two
+    bits per site, in plain numpy.
   * ``mlp_*``            - float64 reference of the learned-index network
     (two hidden layers of 32 units, half relu(z) and half min(z, 0);
     forward, loss, analytic backward) used to check the GPU training
@@ -535,3 +540,209 @@ def mlp_loss_grad(params, X, t):
 
 def binom(n, k):
     return comb(n, k)
+
+
+# ---------------------------------------------------------------------------
+# SU(d) permutation models (chapter on SU(N) chiral spin liquids)
+#
+# A configuration of n sites with colors 0..d-1 is the integer
+# sum_i color_i 4^(n-1-i): two bits per site, site 0 most significant, as
+# for spin 1/2 with one bit.  The exchange P_ij swaps the colors of sites i
+# and j; the ring exchange P_ijk moves the color of i to j, of j to k and of
+# k to i.  H = sum_b J_b P_b + sum_t K_t i (P_t - P_t^-1).
+# ---------------------------------------------------------------------------
+
+def sun_digits(keys, n):
+    """Colors [len(keys), n] of the configurations (site 0 first)."""
+    keys = np.asarray(keys, np.uint64)
+    return np.stack([((keys >> np.uint64(2 * (n - 1 - i))) & np.uint64(3)).astype(np.int64) for i in range(n)],
+                    axis=1).reshape(len(keys), n)
+
+
+def sun_keys(digits):
+    digits = np.asarray(digits, np.int64)
+    n = digits.shape[1]
+    k = np.zeros(digits.shape[0], np.uint64)
+    for i in range(n):
+        k = (k << np.uint64(2)) | digits[:, i].astype(np.uint64)
+    return k
+
+
+def sun_states(n, d, counts):
+    """All configurations with counts[c] sites of color c, ascending."""
+    assert sum(counts) == n and len(counts) == d
+    # multiset permutations, built color by color (plain recursion over sites)
+    res = []
+
+    def rec(prefix, left):
+        if len(prefix) == n:
+            res.append(list(prefix))
+            return
+        for c in range(d):
+            if left[c]:
+                left[c] -= 1
+                prefix.append(c)
+                rec(prefix, left)
+                prefix.pop()
+                left[c] += 1
+
+    rec([], list(counts))
+    keys = sun_keys(np.array(res, np.int64).reshape(-1, n))
+    return np.sort(keys)
+
+
+def sun_act(perm, keys, n):
+    """Keys after the site permutation (the color at site i moves to perm[i])."""
+    dg = sun_digits(keys, n)
+    out = np.empty_like(dg)
+    out[:, np.asarray(perm)] = dg
+    return sun_keys(out)
+
+
+def sun_rep_many(inst, keys):
+    """Representative (orbit minimum), the first group element reaching it,
+    stabilizer size and whether chi is trivial on the stabilizer."""
+    keys = np.asarray(keys, np.uint64)
+    n = inst.n_sites
+    imgs = np.stack([sun_act(inst.perms[g], keys, n) for g in range(inst.n_elem)], axis=1)
+    g = np.argmin(imgs, axis=1)
+    rep = imgs[np.arange(len(keys)), g]
+    fixed = imgs == keys[:, None]
+    stab = fixed.sum(axis=1)
+    chi_fixed = np.where(fixed, inst.chi[None, :], 1.0)
+    triv = np.all(np.abs(chi_fixed - 1.0) < 1e-9, axis=1)
+    return rep, g, stab, triv
+
+
+def sun_enumerate_basis(inst):
+    """Ascending sector representatives and stabilizer sizes."""
+    st = sun_states(inst.n_sites, inst.local_dim, inst.counts)
+    rep, g, stab, triv = sun_rep_many(inst, st)
+    keep = (rep == st) & triv
+    return st[keep], stab[keep].astype(np.int32)
+
+
+def sun_terms(inst, keys):
+    """Every non-branching piece applied to the configurations: a list of
+    (targets, amplitudes); a piece that leaves a configuration unchanged is
+    diagonal."""
+    n = inst.n_sites
+    dg = sun_digits(keys, n)
+    out = []
+    for (i, j), J in zip(inst.bonds.reshape(-1, 2), inst.bond_J):
+        t = dg.copy()
+        t[:, i], t[:, j] = dg[:, j], dg[:, i]
+        out.append((sun_keys(t), np.full(len(keys), complex(J))))
+    for (i, j, k), K in zip(inst.tris.reshape(-1, 3), inst.tri_Jchi):
+        fwd = dg.copy()
+        fwd[:, j], fwd[:, k], fwd[:, i] = dg[:, i], dg[:, j], dg[:, k]
+        bwd = dg.copy()
+        bwd[:, i], bwd[:, j], bwd[:, k] = dg[:, j], dg[:, k], dg[:, i]
+        out.append((sun_keys(fwd), np.full(len(keys), 1j * K)))
+        out.append((sun_keys(bwd), np.full(len(keys), -1j * K)))
+    return out
+
+
+def sun_coo_matrix(inst, reps, stabs):
+    """Symmetrized Hamiltonian in the sector basis (push form), scipy CSR:
+    H[i, j] += conj(chi(g)) sqrt(|Stab rep_i| / |Stab rep_j|) h for every
+    piece h taking rep_j to a configuration whose representative rep_i =
+    g(target) lies in the sector."""
+    reps = np.asarray(reps, np.uint64)
+    dim = len(reps)
+    rows, cols, vals = [], [], []
+    for tgt, h in sun_terms(inst, reps):
+        rt, g, st, tv = sun_rep_many(inst, tgt)
+        i = np.searchsorted(reps, rt)
+        ok = tv & (i < dim)
+        ok[ok] &= reps[i[ok]] == rt[ok]
+        j = np.nonzero(ok)[0]
+        v = np.conj(inst.chi[g[j]]) * np.sqrt(st[j] / stabs[j]) * h[j]
+        rows.append(i[j])
+        cols.append(j)
+        vals.append(v)
+    rows, cols, vals = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    if not inst.is_complex:
+        vals = vals.real
+    return scipy.sparse.csr_matrix((vals, (rows, cols)), shape=(dim, dim))
+
+
+def sun_rows_apply(inst, rows, xfun):
+    """Pull form y(rep_i) = sum chi(g) sqrt(|Stab t~| / |Stab rep_i|) conj(h) x(t~)
+    over the pieces of the given sector representatives (Hermiticity)."""
+    rows = np.asarray(rows, np.uint64)
+    _, _, srow, _ = sun_rep_many(inst, rows)
+    y = np.zeros(len(rows), complex)
+    for tgt, h in sun_terms(inst, rows):
+        rt, g, st, tv = sun_rep_many(inst, tgt)
+        c = np.where(tv, inst.chi[g] * np.sqrt(st / srow) * np.conj(h), 0.0)
+        y += c * np.where(tv, xfun(rt), 0.0)
+    return y
+
+
+def sun_character_formula_dim(inst):
+    """dim = |G|^-1 sum_g conj(chi(g)) Fix(g), Fix(g) = colorings constant on
+    the cycles of g with the sector's color counts (dynamic programming over
+    the cycles)."""
+    d, counts = inst.local_dim, tuple(inst.counts)
+    tot = 0j
+    for g in range(inst.n_elem):
+        lens = _cycles(inst.perms[g])
+        ways = {tuple([0] * d): 1}
+        for L in lens:
+            nxt = {}
+            for used, w in ways.items():
+                for c in range(d):
+                    u = list(used)
+                    u[c] += L
+                    if u[c] <= counts[c]:
+                        nxt[tuple(u)] = nxt.get(tuple(u), 0) + w
+            ways = nxt
+        tot += np.conj(inst.chi[g]) * ways.get(counts, 0)
+    v = tot / inst.n_elem
+    assert abs(v.imag) < 1e-9 and abs(v.real - round(v.real)) < 1e-9
+    return int(round(v.real))
+
+
+def sun_full_matrix(inst):
+    """H on all configurations with the sector's color counts (no symmetry):
+    the exchange and ring operators as permutations of the configurations."""
+    st = sun_states(inst.n_sites, inst.local_dim, inst.counts)
+    M = np.zeros((len(st), len(st)), complex)
+    for tgt, h in sun_terms(inst, st):
+        i = np.searchsorted(st, tgt)
+        np.add.at(M, (i, np.arange(len(st))), h)
+    return st, M
+
+
+def sun_kron_operator(n, d, sites, cyc):
+    """The permutation of colors on `sites` as a d^n x d^n matrix from
+    Kronecker products (site 0 = leftmost factor): cyc = 2 gives P_ij, cyc =
+    3 the ring P_ijk (color of i -> j -> k -> i)."""
+    dim = d ** n
+    M = np.zeros((dim, dim))
+    for col in range(dim):
+        dig = [(col // d ** (n - 1 - s)) % d for s in range(n)]
+        new = list(dig)
+        if cyc == 2:
+            i, j = sites
+            new[i], new[j] = dig[j], dig[i]
+        else:
+            i, j, k = sites
+            new[j], new[k], new[i] = dig[i], dig[j], dig[k]
+        row = sum(c * d ** (n - 1 - s) for s, c in enumerate(new))
+        M[row, col] = 1.0
+    return M
+
+
+def sun_projector_basis(inst, reps):
+    """Symmetry-adapted vectors sum_g conj(chi(g)) g|rep>, normalized, written
+    out on the configurations of the sector (columns)."""
+    st = sun_states(inst.n_sites, inst.local_dim, inst.counts)
+    B = np.zeros((len(st), len(reps)), complex)
+    for c, r in enumerate(np.asarray(reps, np.uint64)):
+        for g in range(inst.n_elem):
+            img = sun_act(inst.perms[g], np.array([r], np.uint64), inst.n_sites)[0]
+            B[np.searchsorted(st, img), c] += np.conj(inst.chi[g])
+        B[:, c] /= np.linalg.norm(B[:, c])
+    return st, B

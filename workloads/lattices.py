@@ -45,6 +45,12 @@ class Instance:
     sublat_options: list       # N_sub values contiguous in this labelling
     sector: str = ""
     meta: dict = field(default_factory=dict)
+    # SU(d) permutation models (thesis chapter on SU(N) chiral spin liquids):
+    # d colors per site, bond_J multiplies the exchange P_ij and tri_Jchi the
+    # ring term i (P_ijk - P_ijk^-1); counts[c] sites carry color c.  0: the
+    # spin-1/2 model above.
+    local_dim: int = 0
+    counts: tuple = ()
 
     def __post_init__(self):
         n = self.n_sites
@@ -53,6 +59,9 @@ class Instance:
         assert self.perms.ndim == 2 and self.perms.shape[1] == n
         assert len(self.flips) == len(self.chi) == self.perms.shape[0]
         assert self.bonds.size == 0 or (self.bonds.min() >= 0 and self.bonds.max() < n)
+        if self.local_dim:
+            assert 2 <= self.local_dim <= 4 and len(self.counts) == self.local_dim and sum(self.counts) == n
+            assert not np.any(self.flips)
 
     @property
     def n_elem(self) -> int:
@@ -771,3 +780,52 @@ def momentum_star(inst, q, pg=None):
         if qp not in out:
             out.append(qp)
     return out
+
+
+# ---------------------------------------------------------------------------
+# SU(N) permutation models: N colors per site (local dimension d = N)
+# ---------------------------------------------------------------------------
+
+def _sun_name(counts):
+    return "c" + "-".join(str(c) for c in counts)
+
+
+def sun_chain(N, d, counts, J=1.0, K3=0.0, k=0, reflection=False, sublat=(2, 4)):
+    """Periodic SU(d) chain: J sum_i P_{i,i+1} (+ K3 on the triangles
+    (i, i+1, i+2) when K3 != 0); translations with chi(T_n) = exp(2 pi i k n / N)."""
+    base = chain(N, J=J, k=k, flip=None, sublat=sublat, reflection=reflection)
+    lab = {p: i for i, p in enumerate(base.meta["positions"])}
+    tris = np.zeros((0, 3), np.int32)
+    if K3 != 0:
+        tris = np.array([(lab[p], lab[(p + 1) % N], lab[(p + 2) % N]) for p in range(N)], np.int32)
+    return Instance(name=f"su{d}chain{N}", n_sites=N, bonds=base.bonds, bond_J=base.bond_J, tris=tris,
+                    tri_Jchi=np.full(len(tris), float(K3)), n_up=0, perms=base.perms, flips=base.flips,
+                    chi=base.chi, sublat_options=base.sublat_options,
+                    sector=f"k={k}.{_sun_name(counts)}", meta=base.meta, local_dim=d, counts=tuple(counts))
+
+
+def sun_triangular(L1, L2, d, counts, J=1.0, K3=0.0, q=None, irrep="A", sublat_chain=None, pg_gens=None,
+                   name="su_triangular"):
+    """SU(d) Heisenberg model with imaginary ring exchange on the triangular
+    lattice, H = J sum_<ij> P_ij + i K3 sum_(ijk) (P_ijk - P_ijk^-1), the
+    ring term on every elementary triangle (up and down), counter-clockwise.
+    Point group C6 (the ring term is odd under the mirrors) unless pg_gens
+    is given."""
+    q = Q0 if q is None else q
+    lat = triangular_lattice(L1, L2, sublat_chain, mirrors=(K3 == 0) if pg_gens is None else False,
+                             pg_gens=pg_gens)
+    bonds = lat.bonds([(1, 0), (0, 1), (-1, 1)])
+    tris = []
+    if K3 != 0:
+        up, down = _triangles(lat)
+        tris = [t for pair in zip(up, down) for t in pair]
+    little = lat.little_group(q)
+    rho = _irrep_by_name(little, irrep)
+    perms, flips, chis = build_group(lat, q, rho, None, little)
+    return Instance(name=f"{name}{lat.N}", n_sites=lat.N, bonds=np.array(bonds, np.int32),
+                    bond_J=np.full(len(bonds), float(J)), tris=np.array(tris, np.int32).reshape(-1, 3),
+                    tri_Jchi=np.full(len(tris), float(K3)), n_up=0, perms=perms, flips=flips, chi=chis,
+                    sublat_options=lat.sublat_options,
+                    sector=f"q={tuple(map(str, q))}.{irrep}.{_sun_name(counts)}",
+                    meta=dict(lattice=lat, little=little, q=q, irrep=0 if irrep in ("A", "A1") else irrep),
+                    local_dim=d, counts=tuple(counts))
