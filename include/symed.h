@@ -128,6 +128,8 @@ typedef struct {
     int64_t limits_max_window; /* plain lookup: largest Limits bucket */
     int32_t apply_blocks;      /* persistent grid of the H.v kernel */
     int32_t apply_threads;     /* its block size */
+    int32_t n_colors;          /* SU(d) bases: d; spin-1/2 bases: 0 */
+    int32_t reserved;
 } ed_basis_info_t;
 
 /*
@@ -144,6 +146,35 @@ typedef struct {
  */
 ed_status ed_basis_build(const ed_model *model, const ed_group *group, int32_t n_up,
                          const ed_options *opts, void *stream, ed_basis **out);
+
+/*
+ * SU(d) permutation model in a color-count sector (thesis, chapter on SU(N)
+ * chiral spin liquids, the SU(N) Heisenberg model with imaginary ring
+ * exchange on elementary triangles):
+ *     H = sum_b J_b P_ij + sum_t K_t i (P_ijk - P_ijk^-1),
+ * P_ij exchanging the colors of sites i and j, P_ijk moving the color of i to
+ * j, of j to k and of k to i.  The model struct is read with that meaning:
+ * bond_J are the exchange couplings J_b, tri_Jchi the ring couplings K_t of the
+ * oriented triangles tri_sites.  For d = 2, P_ij = 2 S_i.S_j + 1/2 and
+ * i (P_ijk - P_ijk^-1) = 4 S_i.(S_j x S_k).
+ *   n_colors: d in [2, 4]; counts: int32[n_colors] (host), the number of
+ *   sites of each color, adding up to n_sites <= 31.
+ * A site holds its color in two bits: a configuration is the integer
+ * sum_i color_i 4^(n_sites-1-i) (site 0 most significant).  The group (no
+ * spin-flip elements) acts on sites; representatives, stabilizers, norms,
+ * basis order, sublattice stability and vectors follow the spin-1/2
+ * conventions above, read on these integers.  ed_options counts sublattices
+ * as for spin-1/2 bases (a sublattice of m sites is a 2m-bit substate);
+ * prefix_bits counts bits of the 2 n_sites-bit keys.
+ * The returned basis works with ed_apply_H, ed_lookup, ed_hash_build,
+ * ed_lanczos_*, ed_basis_info/export/device_reps (lookup modes 0 and 2);
+ * ed_index_train, the spin-1/2 observables (ed_apply_op*, ed_expectation)
+ * and batches reject it with ED_EINVAL.
+ * Errors: as ed_basis_build; ED_EINVAL also for counts that do not add up to
+ * n_sites, flip elements, or more than 2^58 configurations in the sector.
+ */
+ed_status ed_basis_build_colors(const ed_model *model, const ed_group *group, int32_t n_colors, const int32_t *counts,
+                                const ed_options *opts, void *stream, ed_basis **out);
 
 /* Release everything the basis owns (tables, representatives, indexes,
  * captured graphs).  NULL is ignored. */

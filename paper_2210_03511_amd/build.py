@@ -15,7 +15,7 @@ ARCH = os.environ.get("SYMED_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.join(ROOT, "include"),
          "-I", CSRC, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
 SOURCES = ["kernels.hip", "tables.cpp", "abi.cpp", "learned.hip", "pwexpand.cpp", "batch.hip", "batch_abi.cpp",
-           "observables.cpp", "tune.cpp"]
+           "observables.cpp", "tune.cpp", "colors.hip"]
 
 
 def _compile(src):

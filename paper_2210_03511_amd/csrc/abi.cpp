@@ -105,6 +105,8 @@ KParams make_params(const ed_basis *b)
     p.is_complex = T.is_complex ? 1 : 0;
     p.pbits = b->pbits;
     p.n_up = T.n_up;
+    p.n_colors = T.n_colors;
+    p.n_moves = (int)T.moves.size();
     p.maskN = (T.N == 64) ? ~0ull : ((1ull << T.N) - 1);
     p.lay = b->lay;
     p.blob = b->d_blob;
@@ -161,13 +163,31 @@ void ed_basis_free(ed_basis *b)
     delete b;
 }
 
-static ed_status build_impl(const ed_model *model, const ed_group *group, int32_t n_up, const ed_options *opts,
-                            hipStream_t st, ed_basis *b)
+// Number of configurations with the given color counts, n! / prod counts!;
+// 0 if it exceeds 2^58 (the enumeration's rank arithmetic multiplies it by n).
+static uint64_t multinomial64(int n_colors, const int32_t *counts)
+{
+    unsigned __int128 r = 1;
+    int k = 0;
+    for (int c = 0; c < n_colors; ++c)
+        for (int q = 1; q <= counts[c]; ++q) {
+            ++k;
+            r = r * (unsigned)k / (unsigned)q;   // exact: r is an integer multiple of C(k, q) here
+            if (r >> 58) return 0;
+        }
+    return (uint64_t)r;
+}
+
+// n_colors == 0: spin-1/2 model in the sector of n_up up spins; otherwise an
+// SU(n_colors) permutation model in the sector of the given color counts.
+static ed_status build_impl(const ed_model *model, const ed_group *group, int32_t n_up, int n_colors,
+                            const int32_t *color_counts, const ed_options *opts, hipStream_t st, ed_basis *b)
 {
     auto t0 = std::chrono::steady_clock::now();
     ed_options o{};
     if (opts) o = *opts;
-    ed_status s = build_host_tables(model, group, n_up, o.n_sub_rep, o.n_sub_act, b->T);
+    ed_status s = n_colors ? build_color_tables(model, group, n_colors, color_counts, o.n_sub_rep, o.n_sub_act, b->T)
+                           : build_host_tables(model, group, n_up, o.n_sub_rep, o.n_sub_act, b->T);
     if (s != ED_OK) return s;
     HostTables &T = b->T;
     b->mem_limit = o.mem_limit_bytes;
@@ -202,7 +222,8 @@ static ed_status build_impl(const ed_model *model, const ed_group *group, int32_
     TmpPool tmp(b);  // temporaries of the build, charged to the memory cap while held
     // --- enumeration of the sector (two passes + scan) -------------------
     const int N = T.N;
-    const uint64_t total = binom64(N, n_up);
+    const uint64_t total = n_colors ? multinomial64(n_colors, color_counts) : binom64(N, n_up);
+    if (n_colors && total == 0) return fail(ED_EINVAL, "color sector with more than 2^58 configurations");
     std::vector<uint64_t> hb(64 * 64, 0);
     for (int n = 0; n < 64; ++n)
         for (int k = 0; k < 64; ++k) hb[n * 64 + k] = binom64(n, k);
@@ -221,7 +242,12 @@ static ed_status build_impl(const ed_model *model, const ed_group *group, int32_
     TAKE(tmp, &d_scan, scan_tmp_words(n_chunks) * sizeof(uint64_t));
     int eblocks = (int)std::min<uint64_t>((n_chunks + 255) / 256, (uint64_t)b->n_cu * 16);
     if (eblocks < 1) eblocks = 1;
-    HIP_OK(launch_enumerate(p, d_binom, total, len, n_chunks, d_counts, nullptr, nullptr, nullptr, false, eblocks, st));
+    if (n_colors)
+        HIP_OK(launch_enumerate_colors(p, color_counts, n_colors, T.n_sites, total, len, n_chunks, d_counts, nullptr,
+                                       nullptr, nullptr, false, eblocks, st));
+    else
+        HIP_OK(launch_enumerate(p, d_binom, total, len, n_chunks, d_counts, nullptr, nullptr, nullptr, false, eblocks,
+                                st));
     HIP_OK(launch_scan(d_counts, d_offsets, n_chunks, d_total, d_scan, st));
     uint64_t dim = 0;
     HIP_OK(hipMemcpyAsync(&dim, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
@@ -231,8 +257,12 @@ static ed_status build_impl(const ed_model *model, const ed_group *group, int32_
     if ((s = dev_alloc(b, (void **)&b->d_reps, dim * sizeof(uint64_t))) != ED_OK) return s;
     if ((s = dev_alloc(b, (void **)&b->d_stab, dim * sizeof(uint16_t))) != ED_OK) return s;
     p = make_params(b);
-    HIP_OK(launch_enumerate(p, d_binom, total, len, n_chunks, d_counts, d_offsets, b->d_reps, b->d_stab, true, eblocks,
-                            st));
+    if (n_colors)
+        HIP_OK(launch_enumerate_colors(p, color_counts, n_colors, T.n_sites, total, len, n_chunks, d_counts, d_offsets,
+                                       b->d_reps, b->d_stab, true, eblocks, st));
+    else
+        HIP_OK(launch_enumerate(p, d_binom, total, len, n_chunks, d_counts, d_offsets, b->d_reps, b->d_stab, true,
+                                eblocks, st));
     HIP_OK(hipStreamSynchronize(st));
 
     // --- Limits prefix table --------------------------------------------
@@ -274,13 +304,13 @@ static ed_status build_impl(const ed_model *model, const ed_group *group, int32_
     return ED_OK;
 }
 
-ed_status ed_basis_build(const ed_model *model, const ed_group *group, int32_t n_up, const ed_options *opts,
-                         void *stream, ed_basis **out)
+static ed_status build_any(const ed_model *model, const ed_group *group, int32_t n_up, int n_colors,
+                           const int32_t *color_counts, const ed_options *opts, void *stream, ed_basis **out)
 {
     if (!out) return fail(ED_EINVAL, "out must not be NULL");
     ed_basis *b = new (std::nothrow) ed_basis();
     if (!b) return fail(ED_ENOMEM, "host allocation failed");
-    ed_status s = build_impl(model, group, n_up, opts, (hipStream_t)stream, b);
+    ed_status s = build_impl(model, group, n_up, n_colors, color_counts, opts, (hipStream_t)stream, b);
     if (s != ED_OK) {
         std::string msg = g_err;
         (void)hipDeviceSynchronize();  // nothing of the failed build may still run when it is freed
@@ -292,13 +322,27 @@ ed_status ed_basis_build(const ed_model *model, const ed_group *group, int32_t n
     return ED_OK;
 }
 
+ed_status ed_basis_build(const ed_model *model, const ed_group *group, int32_t n_up, const ed_options *opts,
+                         void *stream, ed_basis **out)
+{
+    return build_any(model, group, n_up, 0, nullptr, opts, stream, out);
+}
+
+ed_status ed_basis_build_colors(const ed_model *model, const ed_group *group, int32_t n_colors, const int32_t *counts,
+                                const ed_options *opts, void *stream, ed_basis **out)
+{
+    if (n_colors < 2 || n_colors > 4) return fail(ED_EINVAL, "n_colors must be in [2, 4]");
+    return build_any(model, group, 0, n_colors, counts, opts, stream, out);
+}
+
 ed_status ed_basis_info(const ed_basis *b, ed_basis_info_t *info)
 {
     if (!b || !info) return fail(ED_EINVAL, "NULL argument");
     ed_basis_info_t r{};
     r.dim = b->dim;
     r.is_complex = b->T.is_complex ? 1 : 0;
-    r.n_sites = b->T.N;
+    r.n_sites = b->T.n_colors ? b->T.n_sites : b->T.N;
+    r.n_colors = b->T.n_colors;
     r.n_elem = b->T.G;
     r.n_sub_rep = b->T.R;
     r.n_sub_act = b->T.A;
@@ -637,6 +681,7 @@ ed_status ed_index_train(ed_basis *b, const ed_index_cfg *cfg_in, ed_index_stats
 {
     if (!b) return fail(ED_EINVAL, "NULL basis");
     if (b->dim < 1) return fail(ED_EINVAL, "empty sector");
+    if (b->T.n_colors) return fail(ED_EINVAL, "the learned index ranks spin-1/2 configurations; not for SU(d) bases");
     ed_index_cfg cfg{};
     if (cfg_in) cfg = *cfg_in;
     const int N = b->T.N, n_up = b->T.n_up;

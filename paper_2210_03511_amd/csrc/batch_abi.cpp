@@ -267,6 +267,8 @@ ed_status ed_batch_create(ed_basis *const *sectors, int32_t n, const ed_batch_cf
 {
     if (!sectors || !out || n < 1) return fail(ED_EINVAL, "bad arguments");
     if (n > kMaxSectors) return fail(ED_EINVAL, "at most 256 sectors per batch");
+    for (int k = 0; k < n; ++k)
+        if (sectors[k] && sectors[k]->T.n_colors) return fail(ED_EINVAL, "batches hold spin-1/2 sectors only");
     // work queued on the caller's stream (e.g. the sectors' builds) comes first
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return fail(ED_EDEVICE, "stream");
     ed_batch_cfg cfg{};

@@ -35,6 +35,21 @@ struct ChiTerm {
     double c;
 };
 
+// One move of an SU(d) permutation term on configurations with two bits
+// per site (site i's color in the digit at bit offset 2 (n - 1 - i)):
+//   kind 0: exchange of the colors of sites (0, 1), <t|H|s> = amp (J);
+//   kind 1: cyclic move of three colors, site 0 -> 1 -> 2 -> 0, <t|H|s> = +i amp;
+//   kind 2: the inverse cyclic move, <t|H|s> = -i amp
+// (a ring term i K (P_ijk - P_ijk^-1) contributes one move of kind 1 and one
+// of kind 2 with amp = K).  A move that leaves s unchanged contributes amp
+// to the diagonal (kind 0) or nothing (kinds 1 and 2 cancel).
+struct ColorMove {
+    uint8_t sh[3];   // bit offsets of the three (kind 0: two) digits
+    uint8_t kind;
+    uint32_t pad;
+    double amp;
+};
+
 // Everything the kernels need, built on the host.
 struct HostTables {
     int N = 0, n_up = 0;
@@ -66,6 +81,12 @@ struct HostTables {
 
     std::vector<PairTerm> pairs;
     std::vector<ChiTerm> chis;
+
+    // SU(d) permutation models (n_colors > 0): N = 2 * n_sites bits, the group
+    // acts on digit pairs; sector = color counts; terms are moves, no pairs
+    int n_colors = 0, n_sites = 0;
+    int counts[4] = {0, 0, 0, 0};
+    std::vector<ColorMove> moves;
 };
 
 // Rep/Sym tables: at most this many bytes go to LDS; larger ones stay in
@@ -84,6 +105,7 @@ struct BlobLayout {
     // offsets there and its size; off_rent/off_symlist are unused
     uint32_t rep_global, g_rent, g_symlist, gbytes;
     uint32_t off_rank;   // learned index: equalizer, then rank table (after the network pieces; 0 until trained)
+    uint32_t off_moves;  // SU(d) models: the ColorMove list
     uint32_t bytes;      // staged into LDS: up to the network pieces and rank table in use
     uint32_t reserved;   // allocated: room for the largest network expansion and rank table
 };
@@ -93,6 +115,7 @@ struct BlobLayout {
 struct KParams {
     int N, R, br, A, ba, n_pairs, G, is_complex;
     int pbits, n_up;
+    int n_colors, n_moves;   // SU(d) models: colors and moves (0 for spin-1/2 models)
     uint64_t maskN;
     BlobLayout lay;
     const void *blob;          // device copy of the LDS blob (16-byte aligned)
@@ -132,6 +155,9 @@ void build_pairs(const ed_model *m, HostTables &T);
 // given; their offsets are set in lay either way).
 std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &lay, std::vector<uint8_t> *gblob = nullptr);
 int choose_sublattices(const HostTables &T, int &R, int &A, std::string &why);
+// SU(d) permutation model with colors counts[0..n_colors) (tables.cpp)
+ed_status build_color_tables(const ed_model *m, const ed_group *g, int n_colors, const int32_t *counts, int n_sub_rep,
+                             int n_sub_act, HostTables &T);
 
 // pwexpand.cpp
 int expand_network(const float *params, float mu, float sc, std::vector<float> &block, double *max_dev);

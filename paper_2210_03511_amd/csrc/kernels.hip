@@ -239,8 +239,7 @@ __global__ void __launch_bounds__(256) k_enumerate(KParams p, const uint64_t *bi
     extern __shared__ __align__(16) unsigned char lds[];
     stage_blob(lds, p.blob, p.lay.bytes);
     const Lds L = lds_view(lds, p.lay, static_cast<const unsigned char *>(p.gtab));
-    const int N = p.N, R = p.R, br = p.br, A = p.A, ba = p.ba;
-    const uint32_t S = 1u << br, mr = S - 1u, ma = (1u << ba) - 1u;
+    const int N = p.N, br = p.br;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_chunks; c += stride) {
         const uint64_t r0 = c * len;
@@ -250,50 +249,15 @@ __global__ void __launch_bounds__(256) k_enumerate(KParams p, const uint64_t *bi
         uint64_t k = WRITE ? offsets[c] : 0;
         uint32_t found = 0;
         while (s < send) {
-            const uint32_t s0 = (uint32_t)(s >> (N - br)) & mr;
-            int bad = -1;
-            if ((L.rent[s0].x & 0xffffu) != s0) {
-                bad = 0;
-            } else {
-                for (int X = 1; X < R; ++X) {
-                    const uint32_t sx = (uint32_t)(s >> (N - (X + 1) * br)) & mr;
-                    if ((L.rent[X * S + sx].x & 0xffffu) < s0) {
-                        bad = X;
-                        break;
-                    }
-                }
-            }
+            const int bad = rep_prefix_fail(s, p, L);
             if (bad >= 0) {
                 const int sh = N - (bad + 1) * br;
                 s = next_with_popcount(((s >> sh) + 1) << sh, p.n_up, N);
                 continue;
             }
-            bool isrep = true, triv = true;
             uint32_t stab = 0;
-            for (int Y = 0; Y < R && isrep; ++Y) {
-                const uint32_t sy = (uint32_t)(s >> (N - (Y + 1) * br)) & mr;
-                const uint32_t idx = Y * S + sy;
-                const uint2 e = L.rent[idx];
-                if ((e.x & 0xffffu) != s0) continue;
-                const uint32_t k1 = e.y + (e.x >> 16);
-                for (uint32_t q = e.y; q < k1; ++q) {
-                    const uint32_t e = L.symlist[q];
-                    const uint32_t sp = e >> 1;
-                    const uint32_t *en = L.aent + ((size_t)sp << L.aent_lg);
-                    uint64_t v = 0;
-                    for (int d = 0; d < A; ++d) v = (v << ba) | act_image(en, L.atab, s, d, ma);
-                    if (e & 1u) v ^= p.maskN;
-                    if (v < s) {
-                        isrep = false;
-                        break;
-                    }
-                    if (v == s) {
-                        ++stab;
-                        if (!L.chione[e]) triv = false;
-                    }
-                }
-            }
-            if (isrep && triv) {
+            bool triv = true;
+            if (rep_check(s, p, L, stab, triv) && triv) {
                 if (WRITE) {
                     out_reps[k] = s;
                     out_stab[k] = (uint16_t)stab;
@@ -645,6 +609,7 @@ hipError_t launch_limits_stats(const uint32_t *d_limits, int pbits, unsigned lon
 
 hipError_t launch_count_elements(const KParams &p, unsigned long long *d_count, int blocks, hipStream_t st)
 {
+    if (p.n_colors) return launch_count_colors(p, d_count, blocks, st);
     if (p.is_complex)
         hipLaunchKernelGGL(k_count<true>, dim3(blocks), dim3(256), p.lay.bytes, st, p, d_count);
     else
@@ -655,6 +620,7 @@ hipError_t launch_count_elements(const KParams &p, unsigned long long *d_count, 
 hipError_t launch_apply(const KParams &p, const LaunchCfg &c, const void *x, void *y, int mode, int lookup_kind,
                         const LState *ls, double *partials, hipStream_t st)
 {
+    if (p.n_colors) return launch_apply_colors(p, c, x, y, mode, lookup_kind, ls, partials, st);
     const size_t lds = apply_lds_bytes(p);
     const double *xd = static_cast<const double *>(x);
     double *yd = static_cast<double *>(y);
@@ -827,6 +793,8 @@ hipError_t prepare_kernels(const KParams &p, int *apply_blocks_per_cu, int *appl
             granted = lds;
         }
     }
+    *apply_threads = kApplyThreads;
+    if (p.n_colors) return prepare_color_kernels(p, apply_blocks_per_cu);
     int nb = 0;
     const void *ka = p.is_complex ? (const void *)k_apply<true, 0, 1> : (const void *)k_apply<false, 0, 1>;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ka, kApplyThreads, lds);

@@ -68,4 +68,15 @@ hipError_t launch_lstate_init(LState *ls, hipStream_t st);
 
 size_t apply_lds_bytes(const KParams &p);
 
+// SU(d) permutation models (colors.hip)
+hipError_t launch_enumerate_colors(const KParams &p, const int32_t *counts, int n_colors, int n_sites, uint64_t total,
+                                   uint64_t chunk_len, uint64_t n_chunks, uint32_t *d_counts,
+                                   const uint64_t *d_offsets, uint64_t *d_reps, uint16_t *d_stab, bool write,
+                                   int blocks, hipStream_t st);
+hipError_t launch_count_colors(const KParams &p, unsigned long long *d_count, int blocks, hipStream_t st);
+// lookup_kind 0 (plain) or 2 (hashed staging table)
+hipError_t launch_apply_colors(const KParams &p, const LaunchCfg &c, const void *x, void *y, int mode, int lookup_kind,
+                               const LState *ls, double *partials, hipStream_t st);
+hipError_t prepare_color_kernels(const KParams &p, int *apply_blocks_per_cu);
+
 }  // namespace symed

@@ -144,6 +144,7 @@ namespace {
 ed_status op_tables(const ed_basis *b, const ed_model *op, int32_t lookup_mode, std::vector<uint8_t> &blob,
                     BlobLayout &lay2, int &n_pairs)
 {
+    if (b->T.n_colors) return fail(ED_EINVAL, "spin-1/2 operators do not act on an SU(d) basis");
     if (!(lookup_mode == 0 || (lookup_mode == 1 && b->indexed) || (lookup_mode == 2 && b->hashed)))
         return fail(ED_EINVAL, "lookup_mode not available on this basis");
     if (op->n_sites != b->T.N) return fail(ED_EINVAL, "operator on another number of sites");

@@ -23,6 +23,7 @@ struct Lds {
     const double *sqrtt;
     const double *isqrtt;
     const uint8_t *chione;
+    const ColorMove *moves;  // SU(d) models
     LearnedLds li;  // learned index: network pieces, equalizer, rank table
 };
 
@@ -48,6 +49,7 @@ __host__ __device__ __forceinline__ Lds lds_view(const unsigned char *b, const B
     v.sqrtt = reinterpret_cast<const double *>(b + L.off_sqrt);
     v.isqrtt = reinterpret_cast<const double *>(b + L.off_isqrt);
     v.chione = b + L.off_chione;
+    v.moves = reinterpret_cast<const ColorMove *>(b + L.off_moves);
     v.li = learned_lds(b, L.off_mlp, L.off_rank);
     return v;
 }
@@ -150,6 +152,58 @@ __host__ __device__ __forceinline__ Found find_rep(uint64_t t, const KParams &p,
         }
     }
     return Found{best, bg, cnt};
+}
+
+// Enumeration tests (algorithm "Preparation of the distributed and
+// symmetrized Hilbert space"): the first coarse sublattice X at which s fails
+// the prefix test of a representative, or -1.  The identity is in G_0, so a
+// representative has Rep_0(s_0) = s_0 and Rep_X(s_X) >= s_0 for every coarse
+// sublattice X; a failed test on X rejects every configuration that shares
+// sublattices 0..X with s.
+__host__ __device__ __forceinline__ int rep_prefix_fail(uint64_t s, const KParams &p, const Lds &L)
+{
+    const int N = p.N, R = p.R, br = p.br;
+    const uint32_t S = 1u << br, mr = S - 1u;
+    const uint32_t s0 = (uint32_t)(s >> (N - br)) & mr;
+    if ((L.rent[s0].x & 0xffffu) != s0) return 0;
+    for (int X = 1; X < R; ++X) {
+        const uint32_t sx = (uint32_t)(s >> (N - (X + 1) * br)) & mr;
+        if ((L.rent[X * S + sx].x & 0xffffu) < s0) return X;
+    }
+    return -1;
+}
+
+// Full test of a configuration that passed the prefix test: every symmetry
+// of Sym_Y of a coarse sublattice Y with Rep_Y(s_Y) = s_0 is applied; s is a
+// representative iff no image is smaller.  stab counts the images equal to
+// s (the stabilizer), triv is false if chi is not 1 on one of them.
+__host__ __device__ __forceinline__ bool rep_check(uint64_t s, const KParams &p, const Lds &L, uint32_t &stab,
+                                                   bool &triv)
+{
+    const int N = p.N, R = p.R, br = p.br, A = p.A, ba = p.ba;
+    const uint32_t S = 1u << br, mr = S - 1u, ma = (1u << ba) - 1u;
+    const uint32_t s0 = (uint32_t)(s >> (N - br)) & mr;
+    stab = 0;
+    triv = true;
+    for (int Y = 0; Y < R; ++Y) {
+        const uint32_t sy = (uint32_t)(s >> (N - (Y + 1) * br)) & mr;
+        const uint2 e = L.rent[Y * S + sy];
+        if ((e.x & 0xffffu) != s0) continue;
+        const uint32_t k1 = e.y + (e.x >> 16);
+        for (uint32_t q = e.y; q < k1; ++q) {
+            const uint32_t c = L.symlist[q];
+            const uint32_t *en = L.aent + ((size_t)(c >> 1) << L.aent_lg);
+            uint64_t v = 0;
+            for (int d = 0; d < A; ++d) v = (v << ba) | act_image(en, L.atab, s, d, ma);
+            if (c & 1u) v ^= p.maskN;
+            if (v < s) return false;
+            if (v == s) {
+                ++stab;
+                if (!L.chione[c]) triv = false;
+            }
+        }
+    }
+    return true;
 }
 
 }  // namespace symed

@@ -369,6 +369,7 @@ std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &L, std::vector<u
     L.off_aent = (uint32_t)o;    o = align16(o + ((size_t)T.n_sp << L.aent_lg) * sizeof(uint32_t));
     L.off_pairs = (uint32_t)o;   o = align16(o + T.pairs.size() * sizeof(PairTerm));
     L.off_chis = (uint32_t)o;    o = align16(o + T.chis.size() * sizeof(ChiTerm));
+    L.off_moves = (uint32_t)o;   o = align16(o + T.moves.size() * sizeof(ColorMove));
     L.off_chi = (uint32_t)o;     o = align16(o + (size_t)2 * T.n_sp * sizeof(double) * (T.is_complex ? 2 : 1));
     L.off_sqrt = (uint32_t)o;    o = align16(o + (size_t)(T.G + 1) * sizeof(double));
     L.off_isqrt = (uint32_t)o;   o = align16(o + (size_t)(T.G + 1) * sizeof(double));
@@ -413,6 +414,7 @@ std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &L, std::vector<u
     put(L.off_aent, ent32.data(), ent32.size() * sizeof(uint32_t));
     put(L.off_pairs, T.pairs.data(), T.pairs.size() * sizeof(PairTerm));
     put(L.off_chis, T.chis.data(), T.chis.size() * sizeof(ChiTerm));
+    put(L.off_moves, T.moves.data(), T.moves.size() * sizeof(ColorMove));
     // characters and the "chi == 1" flags by symmetry code (sp << 1) | flip
     const int w = T.is_complex ? 2 : 1;
     std::vector<double> chi((size_t)2 * T.n_sp * w, 0.0);
@@ -525,6 +527,99 @@ ed_status build_host_tables(const ed_model *m, const ed_group *g, int n_up, int 
     T.rep_global = rs_bytes > kRepSymLdsMax;
     if ((st = build_act(T)) != ED_OK) return st;
     build_pairs(m, T);
+    return ED_OK;
+}
+
+// SU(d) permutation model H = sum_b J_b P_ij + sum_t K_t i (P_ijk - P_ijk^-1)
+// (thesis, chapter on SU(N) chiral spin liquids: the SU(N) Heisenberg model
+// with imaginary ring exchange on elementary triangles).  A site holds a
+// color 0..d-1 in two bits, so a configuration of n sites is a 2n-bit integer
+// (site 0 in the most significant digit) and a site permutation is a
+// permutation of bit positions, 2i + t -> 2 perm(i) + t.  The sublattice
+// coding tables, the representative search and the index lookups are those
+// of the spin-1/2 case on these 2n bit positions; only the sector (color
+// counts instead of a number of up spins) and the terms differ.
+// The ring term is totally antisymmetric in (i, j, k), like the scalar
+// chirality (for d = 2 it equals 4 S_i.(S_j x S_k)), so the invariance check
+// of the spin-1/2 model applies to the site-level model unchanged.
+ed_status build_color_tables(const ed_model *m, const ed_group *g, int n_colors, const int32_t *counts, int n_sub_rep,
+                             int n_sub_act, HostTables &T)
+{
+    if (!m || !g) return fail(ED_EINVAL, "model and group must not be NULL");
+    if (n_colors < 2 || n_colors > 4) return fail(ED_EINVAL, "n_colors must be in [2, 4]");
+    if (!counts) return fail(ED_EINVAL, "counts must not be NULL");
+    const int n = m->n_sites;
+    if (n < 1 || 2 * n > 62) return fail(ED_EINVAL, "n_sites must be in [1, 31] for two bits per site");
+    int sum = 0;
+    for (int c = 0; c < n_colors; ++c) {
+        if (counts[c] < 0) return fail(ED_EINVAL, "negative color count");
+        sum += counts[c];
+    }
+    if (sum != n) return fail(ED_EINVAL, "color counts must add up to n_sites");
+    if (g->n_elem >= 1 && g->flip)
+        for (int e = 0; e < g->n_elem; ++e)
+            if (g->flip[e]) return fail(ED_EINVAL, "spin-flip elements are not defined for SU(d) models");
+    // site level: group closure, characters, invariance of the terms
+    HostTables S;
+    ed_status st = validate_and_copy_group(m, g, 0, S);
+    if (st != ED_OK) return st;
+
+    // bit level: the same group acting on the 2n bit positions, no terms
+    const int N = 2 * n, G = g->n_elem;
+    std::vector<int32_t> bperm((size_t)G * N);
+    for (int e = 0; e < G; ++e)
+        for (int i = 0; i < n; ++i)
+            for (int t = 0; t < 2; ++t) bperm[(size_t)e * N + 2 * i + t] = 2 * g->perm[(size_t)e * n + i] + t;
+    std::vector<uint8_t> bflip(G, 0);
+    ed_group bg{G, bperm.data(), bflip.data(), g->chi_re, g->chi_im};
+    ed_model bm{N, 0, nullptr, nullptr, 0, nullptr, nullptr};
+    if ((st = build_host_tables(&bm, &bg, 0, n_sub_rep, n_sub_act, T)) != ED_OK) return st;
+    T.n_colors = n_colors;
+    T.n_sites = n;
+    for (int c = 0; c < 4; ++c) T.counts[c] = c < n_colors ? counts[c] : 0;
+
+    // moves: exchange couplings summed per unordered pair; ring couplings
+    // summed per triangle, each taken in the rotation that starts at its
+    // smallest site, with the sign of K reversed for the opposite orientation
+    std::map<std::pair<int, int>, double> J;
+    for (int b = 0; b < m->n_bonds; ++b) {
+        const int i = m->bond_sites[2 * b], j = m->bond_sites[2 * b + 1];
+        J[{std::min(i, j), std::max(i, j)}] += m->bond_J[b];
+    }
+    std::map<std::array<int, 3>, double> K;
+    for (int t = 0; t < m->n_tri; ++t) {
+        const int32_t *v = m->tri_sites + 3 * t;
+        int r = 0;
+        for (int q = 1; q < 3; ++q)
+            if (v[q] < v[r]) r = q;
+        const int a = v[r], b = v[(r + 1) % 3], c = v[(r + 2) % 3];
+        if (b < c) K[{a, b, c}] += m->tri_Jchi[t];
+        else K[{a, c, b}] -= m->tri_Jchi[t];
+    }
+    auto off = [n](int i) { return (uint8_t)(2 * (n - 1 - i)); };
+    T.moves.clear();
+    for (auto &kv : J) {
+        if (kv.second == 0.0) continue;
+        ColorMove mv{};
+        mv.sh[0] = off(kv.first.first);
+        mv.sh[1] = off(kv.first.second);
+        mv.kind = 0;
+        mv.amp = kv.second;
+        T.moves.push_back(mv);
+    }
+    bool ring = false;
+    for (auto &kv : K) {
+        if (kv.second == 0.0) continue;
+        ring = true;
+        for (uint8_t kind = 1; kind <= 2; ++kind) {
+            ColorMove mv{};
+            for (int q = 0; q < 3; ++q) mv.sh[q] = off(kv.first[q]);
+            mv.kind = kind;
+            mv.amp = kv.second;
+            T.moves.push_back(mv);
+        }
+    }
+    T.is_complex = T.is_complex || ring;
     return ED_OK;
 }
 

@@ -27,7 +27,7 @@ EXPORTED = ["ed_last_error", "ed_version", "ed_basis_build", "ed_basis_free", "e
             "ed_tables_inspect", "ed_index_train", "ed_index_info", "ed_mlp_loss_grad",
             "ed_index_predict", "ed_batch_create", "ed_batch_apply", "ed_batch_lanczos", "ed_batch_info",
             "ed_batch_free", "ed_hash_build", "ed_ritz_vector", "ed_lanczos_vector", "ed_expectation", "ed_lanczos_resume",
-            "ed_apply_op", "ed_apply_op_noalloc", "ed_tune_decomposition"]
+            "ed_apply_op", "ed_apply_op_noalloc", "ed_tune_decomposition", "ed_basis_build_colors"]
 
 
 class EdError(RuntimeError):
@@ -60,7 +60,7 @@ class BasisInfo(ctypes.Structure):
                 ("index_bytes", ctypes.c_int64), ("index_max_err", ctypes.c_int32), ("lds_resident", ctypes.c_int32),
                 ("build_seconds", ctypes.c_double), ("limits_mean_window", ctypes.c_double),
                 ("limits_max_window", ctypes.c_int64), ("apply_blocks", ctypes.c_int32),
-                ("apply_threads", ctypes.c_int32)]
+                ("apply_threads", ctypes.c_int32), ("n_colors", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -154,6 +154,8 @@ def lib():
         L.ed_version.restype = ctypes.c_char_p
         L.ed_basis_build.argtypes = [ctypes.POINTER(_Model), ctypes.POINTER(_Group), i32, ctypes.POINTER(_Options),
                                      vp, ctypes.POINTER(vp)]
+        L.ed_basis_build_colors.argtypes = [ctypes.POINTER(_Model), ctypes.POINTER(_Group), i32, vp,
+                                            ctypes.POINTER(_Options), vp, ctypes.POINTER(vp)]
         L.ed_basis_free.argtypes = [vp]
         L.ed_basis_free.restype = None
         L.ed_basis_info.argtypes = [vp, ctypes.POINTER(BasisInfo)]
@@ -251,12 +253,20 @@ class Basis:
     @classmethod
     def build(cls, inst, n_sub_rep=0, n_sub_act=0, prefix_bits=0, mem_limit_bytes=0, stream=None):
         """Build the basis of a problem description with attributes n_sites,
-        bonds, bond_J, tris, tri_Jchi, perms, flips, chi, n_up."""
+        bonds, bond_J, tris, tri_Jchi, perms, flips, chi, n_up; with
+        local_dim > 0 (and counts) an SU(local_dim) permutation model in the
+        sector of those color counts (ed_basis_build_colors)."""
         arr = _arrays_from(inst)
         opts = _Options(n_sub_rep, n_sub_act, prefix_bits, 0, mem_limit_bytes)
         h = ctypes.c_void_p()
-        _check(lib().ed_basis_build(ctypes.byref(arr.model), ctypes.byref(arr.group), int(inst.n_up),
-                                    ctypes.byref(opts), _stream_ptr(stream), ctypes.byref(h)))
+        d = int(getattr(inst, "local_dim", 0) or 0)
+        if d:
+            counts = np.ascontiguousarray(np.asarray(inst.counts, np.int32))
+            _check(lib().ed_basis_build_colors(ctypes.byref(arr.model), ctypes.byref(arr.group), d, _np_ptr(counts),
+                                               ctypes.byref(opts), _stream_ptr(stream), ctypes.byref(h)))
+        else:
+            _check(lib().ed_basis_build(ctypes.byref(arr.model), ctypes.byref(arr.group), int(inst.n_up),
+                                        ctypes.byref(opts), _stream_ptr(stream), ctypes.byref(h)))
         return cls(h.value)
 
     def free(self):

@@ -57,3 +57,16 @@ def random_sector_states(n_sites, n_up, count, seed):
             v |= 1 << (n_sites - 1 - int(q))
         out[k] = v
     return out
+
+
+def random_color_states(n_sites, counts, count, seed):
+    """Uniformly random configurations of an SU(d) color-count sector, two
+    bits per site (site 0 in the most significant digit): a random
+    permutation of the multiset of colors."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    base = np.repeat(np.arange(len(counts)), counts)
+    w = np.uint64(4) ** np.arange(n_sites - 1, -1, -1, dtype=np.uint64)
+    out = np.zeros(count, np.uint64)
+    for k in range(count):
+        out[k] = np.sum(g.permutation(base).astype(np.uint64) * w, dtype=np.uint64)
+    return out
