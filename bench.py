@@ -27,6 +27,12 @@ sys.path.insert(0, ROOT)
 
 # MI355X peaks used for the roofline
 HBM_PEAK_GBS = 8000.0
+PROGRESS = False
+
+
+def progress(*a):
+    if PROGRESS:
+        print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def parse():
@@ -41,6 +47,7 @@ def parse():
     ap.add_argument("--apply-reps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--progress", action="store_true", help="print a line to stderr after each stage")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device copy of this size first (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -104,7 +111,8 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 def counters_path(config):
     """Recorded DRAM byte counters of the H.v kernel for a workload."""
-    return os.path.join(PROFILES, f"k_apply_{config}_counters.json")
+    kernel = "k_batch_apply" if config == "square32_batch" else "k_apply"
+    return os.path.join(PROFILES, f"{kernel}_{config}_counters.json")
 
 
 def kernel_sources_sha256():
@@ -119,11 +127,10 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def recorded_traffic(config, mode):
-    """DRAM bytes per launch of the H.v kernel from the committed rocprofv3
-    passes (TCC_EA0_RDREQ_DRAM_32B and TCC_EA0_WRREQ_WRITE_DRAM_32B, both in
-    32-byte units); None if there is no record for this workload and mode or
-    the sources changed since it was taken."""
+def recorded_counters(config, mode):
+    """Counters of the H.v kernel from the committed rocprofv3 passes for a
+    workload and lookup mode; None if there is no record or the sources
+    changed since it was taken."""
     path = counters_path(config)
     if not os.path.exists(path):
         return None
@@ -131,10 +138,33 @@ def recorded_traffic(config, mode):
         rec = json.load(f)
     if rec.get("config") != config or rec.get("sources_sha256") != kernel_sources_sha256():
         return None
-    k = rec["kernels"].get({0: "plain", 1: "learned", 2: "hash"}[mode])
+    return rec["kernels"].get({0: "plain", 1: "learned", 2: "hash"}[mode])
+
+
+def recorded_traffic(config, mode):
+    """DRAM bytes per launch of the H.v kernel (TCC_EA0_RDREQ_DRAM_32B and
+    TCC_EA0_WRREQ_WRITE_DRAM_32B, both in 32-byte units, checked against a
+    1 GiB copy in the same runs); None without a current record."""
+    k = recorded_counters(config, mode)
     if not k:
         return None
     return float(k["dram_read_bytes"] + k["dram_write_bytes"])
+
+
+# wave64 VALU instructions per second: one per compute unit per cycle
+VALU_PEAK = 256 * 2.4e9
+
+
+def valu_bound(config, mode, t):
+    """Second bound of the H.v kernel: its recorded VALU instruction count
+    (SQ_INSTS_VALU) against the issue rate of 256 compute units at 2.4 GHz,
+    over the launch time t measured here; None without a current record."""
+    k = recorded_counters(config, mode)
+    if not k or not k.get("sq", {}).get("SQ_INSTS_VALU"):
+        return None
+    v = k["sq"]["SQ_INSTS_VALU"]
+    return {"bound": "alu", "achieved": v / t / 1e9, "peak": VALU_PEAK / 1e9, "unit": "G VALU wave-instructions/s",
+            "frac": v / t / VALU_PEAK, "instructions": v}
 
 
 def alg_bytes_of(D, n_off, cplx):
@@ -164,6 +194,7 @@ def main_batch(args):
     big = 0
     sub_r, sub_a, drep = S.tune_decomposition(insts[big], mode=max(modes), cache_path=cache)
     t_dtune = time.perf_counter() - t0
+    progress("decomposition tuned", sub_r, sub_a)
     t0 = time.perf_counter()
     bases = []
     for i in insts:
@@ -173,12 +204,14 @@ def main_batch(args):
             bases.append(S.Basis.build(i))
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
+    progress("46 bases built", round(t_build, 2), "s")
     infos = [b.info() for b in bases]
     t_train = t_hash = None
     if 1 in modes:
         t0 = time.perf_counter()
         for b in bases:
             b.train_index()
+            progress("index trained, dim", b.dim)
         t_train = time.perf_counter() - t0
     if 2 in modes:
         t0 = time.perf_counter()
@@ -188,6 +221,7 @@ def main_batch(args):
     t0 = time.perf_counter()
     batch = S.Batch(bases, cache_path=cache)
     t_tune = time.perf_counter() - t0
+    progress("batch created")
     v0s = [torch.from_numpy(V.start_vector(inf["dim"], 4001 + k, bool(inf["is_complex"]))).cuda()
            for k, inf in enumerate(infos)]
     ys = [torch.empty_like(v) for v in v0s]
@@ -212,6 +246,7 @@ def main_batch(args):
             torch.cuda.synchronize()
             ts.append(e0.elapsed_time(e1) / 1e3)
         apply_t[m] = float(np.mean(ts))
+        progress("batched H.v timed, mode", m, round(apply_t[m], 4), "s")
     del ys
     step_t, e_min = {}, {}
     for m in modes:
@@ -267,8 +302,9 @@ def main_batch(args):
                                     "candidates": drep["candidates"], "tune_s": t_dtune},
                   "autotune": {name(m): tuned[m] for m in modes}, "cache_reuse": reuse},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_batch_apply", "alg_bytes_per_launch": alg, "avg_launch_s": apply_t[best]},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic("square32_batch", best),
+                     "kernel": f"k_batch_apply ({name(best)} lookup)", "alg_bytes_per_launch": alg,
+                     "avg_launch_s": apply_t[best]},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(insts[0], args.cpu_seconds)
@@ -278,6 +314,8 @@ def main_batch(args):
 
 def main():
     args = parse()
+    global PROGRESS
+    PROGRESS = args.progress
     if args.gpus != 1:
         print(f"bench.py measures one MI355X; --gpus {args.gpus} is not supported: the library runs on one GPU "
               f"(rows would shard by contiguous blocks with an all-gather of the new vector per step, which is "
@@ -302,6 +340,7 @@ def main():
     basis = S.Basis.build(inst)
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
+    progress("basis built", round(t_build, 2), "s")
     info = basis.info()
     D = info["dim"]
     cplx = bool(info["is_complex"])
@@ -316,9 +355,11 @@ def main():
         train["wall_seconds"] = time.perf_counter() - t0
         modes.append(1)
         info = basis.info()
+        progress("index trained")
     if args.lookup in ("hash", "all"):
         hashed = basis.build_hash()
         modes.append(2)
+        progress("hash table built")
 
     v0 = V.start_vector(D, seed, cplx)
     v0t = torch.from_numpy(v0).cuda()
@@ -341,6 +382,7 @@ def main():
             torch.cuda.synchronize()
             ts.append(e0.elapsed_time(e1) / 1e3)
         apply_t[m] = float(np.mean(ts))
+        progress("H.v timed, mode", m, round(apply_t[m], 4), "s")
     del y
 
     # Lanczos steps: warmup, then exactly K timed steps per mode
@@ -355,6 +397,7 @@ def main():
         torch.cuda.synchronize()
         step_t[m] = (time.perf_counter() - t0) / max(n, 1)
         energies[m] = float(S.eigenvalues(a, b, 1)[0])
+        progress("Lanczos timed, mode", m)
 
     # the metric compares the learned lookup with the plain one: the headline
     # is the learned mode when it ran, else the fastest mode that did
@@ -373,7 +416,8 @@ def main():
                 "kernel": f"k_apply ({name[m]} lookup)", "alg_bytes_per_launch": alg_bytes, "avg_launch_s": t,
                 # algorithmic bytes over counted DRAM bytes, and the counted rate
                 "gather_efficiency": None if traffic is None else alg_bytes / traffic,
-                "counted_GBps": None if traffic is None else traffic / t / 1e9}
+                "counted_GBps": None if traffic is None else traffic / t / 1e9,
+                "valu": valu_bound(args.config, m, t)}
 
     t_apply = apply_t[head]
     out = {

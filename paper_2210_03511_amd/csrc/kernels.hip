@@ -26,15 +26,16 @@ constexpr int kVecThreads = 256;
 // same Lanczos coefficients.
 // At least 8 waves per SIMD (two 1024-thread blocks per CU when the tables
 // leave room in LDS): the register budget is capped at 64 per lane, which
-// every variant meets without spilling.
-template <bool CPLX, int MODE, int LK>
+// every variant meets without spilling.  RG = 0 when the Rep/Sym tables are
+// in LDS (their reads are then LDS reads, not flat loads), 1 otherwise.
+template <bool CPLX, int MODE, int LK, int RG>
 __global__ void __launch_bounds__(kApplyThreads, 8) k_apply(KParams p, const double *__restrict__ x,
                                                        double *__restrict__ y, const LState *ls,
                                                        double *partials)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     stage_blob(lds, p.blob, p.lay.bytes);
-    const Lds L = lds_view(lds, p.lay, static_cast<const unsigned char *>(p.gtab));
+    const Lds L = lds_view_t<RG>(lds, p.lay, static_cast<const unsigned char *>(p.gtab));
     const double beta = (MODE == 1) ? ls->beta_prev : 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int lane = threadIdx.x & 63;
@@ -231,14 +232,14 @@ __device__ __forceinline__ uint64_t next_with_popcount(uint64_t t, int k, int N)
 // identity is in G_0, so a representative has Rep_0(s_0) = s_0 and
 // Rep_X(s_X) >= s_0 for every coarse sublattice X; a failed test on X
 // rejects every configuration sharing sublattices 0..X, which are skipped.
-template <bool WRITE>
+template <bool WRITE, int RG>
 __global__ void __launch_bounds__(256) k_enumerate(KParams p, const uint64_t *binom, uint64_t total, uint64_t len,
                                                  uint64_t n_chunks, uint32_t *counts, const uint64_t *offsets,
                                                  uint64_t *out_reps, uint16_t *out_stab)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     stage_blob(lds, p.blob, p.lay.bytes);
-    const Lds L = lds_view(lds, p.lay, static_cast<const unsigned char *>(p.gtab));
+    const Lds L = lds_view_t<RG>(lds, p.lay, static_cast<const unsigned char *>(p.gtab));
     const int N = p.N, br = p.br;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_chunks; c += stride) {
@@ -544,12 +545,17 @@ hipError_t launch_enumerate(const KParams &p, const uint64_t *d_binom, uint64_t 
                             uint16_t *d_stab, bool write, int blocks, hipStream_t st)
 {
     const size_t lds = p.lay.bytes;
-    if (write)
-        hipLaunchKernelGGL(k_enumerate<true>, dim3(blocks), dim3(256), lds, st, p, d_binom, total, chunk_len,
-                           n_chunks, d_counts, d_offsets, d_reps, d_stab);
-    else
-        hipLaunchKernelGGL(k_enumerate<false>, dim3(blocks), dim3(256), lds, st, p, d_binom, total, chunk_len,
-                           n_chunks, d_counts, d_offsets, d_reps, d_stab);
+#define SYMED_ENUM(W, RG)                                                                                   \
+    hipLaunchKernelGGL((k_enumerate<W, RG>), dim3(blocks), dim3(256), lds, st, p, d_binom, total, chunk_len, \
+                       n_chunks, d_counts, d_offsets, d_reps, d_stab)
+    if (p.lay.rep_global) {
+        if (write) SYMED_ENUM(true, 1);
+        else SYMED_ENUM(false, 1);
+    } else {
+        if (write) SYMED_ENUM(true, 0);
+        else SYMED_ENUM(false, 0);
+    }
+#undef SYMED_ENUM
     return hipGetLastError();
 }
 
@@ -625,7 +631,11 @@ hipError_t launch_apply(const KParams &p, const LaunchCfg &c, const void *x, voi
     const double *xd = static_cast<const double *>(x);
     double *yd = static_cast<double *>(y);
     dim3 g(c.lookup_blocks[lookup_kind]), b(kApplyThreads);
-#define SYMED_APPLY(C, M, K) hipLaunchKernelGGL((k_apply<C, M, K>), g, b, lds, st, p, xd, yd, ls, partials)
+#define SYMED_APPLY(C, M, K)                                                                      \
+    do {                                                                                          \
+        if (p.lay.rep_global) hipLaunchKernelGGL((k_apply<C, M, K, 1>), g, b, lds, st, p, xd, yd, ls, partials); \
+        else hipLaunchKernelGGL((k_apply<C, M, K, 0>), g, b, lds, st, p, xd, yd, ls, partials);   \
+    } while (0)
 #define SYMED_APPLY_K(C, M)                                                        \
     do {                                                                           \
         if (lookup_kind == kLookupHash) SYMED_APPLY(C, M, kLookupHash);             \
@@ -770,14 +780,14 @@ hipError_t prepare_kernels(const KParams &p, int *apply_blocks_per_cu, int *appl
 {
     const size_t lds = apply_lds_bytes(p);
     hipError_t e;
-    const void *ks[] = {(const void *)k_apply<false, 0, 0>, (const void *)k_apply<false, 1, 0>,
-                        (const void *)k_apply<true, 0, 0>,  (const void *)k_apply<true, 2, 0>,
-                        (const void *)k_apply<false, 0, 1>, (const void *)k_apply<false, 1, 1>,
-                        (const void *)k_apply<true, 0, 1>,  (const void *)k_apply<true, 2, 1>,
-                        (const void *)k_apply<false, 0, 2>, (const void *)k_apply<false, 1, 2>,
-                        (const void *)k_apply<true, 0, 2>,  (const void *)k_apply<true, 2, 2>,
-                        (const void *)k_count<false>,       (const void *)k_count<true>,
-                        (const void *)k_enumerate<false>,   (const void *)k_enumerate<true>};
+#define SYMED_K4(RG, K)                                                                             \
+    (const void *)k_apply<false, 0, K, RG>, (const void *)k_apply<false, 1, K, RG>,                   \
+        (const void *)k_apply<true, 0, K, RG>, (const void *)k_apply<true, 2, K, RG>
+    const void *ks[] = {SYMED_K4(0, 0), SYMED_K4(0, 1), SYMED_K4(0, 2), SYMED_K4(1, 0), SYMED_K4(1, 1),
+                        SYMED_K4(1, 2), (const void *)k_count<false>, (const void *)k_count<true>,
+                        (const void *)k_enumerate<false, 0>, (const void *)k_enumerate<true, 0>,
+                        (const void *)k_enumerate<false, 1>, (const void *)k_enumerate<true, 1>};
+#undef SYMED_K4
     {
         // the limit is per kernel, shared by every basis in the process: it
         // only ever grows, so a later basis with smaller tables cannot
@@ -796,7 +806,9 @@ hipError_t prepare_kernels(const KParams &p, int *apply_blocks_per_cu, int *appl
     *apply_threads = kApplyThreads;
     if (p.n_colors) return prepare_color_kernels(p, apply_blocks_per_cu);
     int nb = 0;
-    const void *ka = p.is_complex ? (const void *)k_apply<true, 0, 1> : (const void *)k_apply<false, 0, 1>;
+    const void *ka = p.lay.rep_global
+                         ? (p.is_complex ? (const void *)k_apply<true, 0, 1, 1> : (const void *)k_apply<false, 0, 1, 1>)
+                         : (p.is_complex ? (const void *)k_apply<true, 0, 1, 0> : (const void *)k_apply<false, 0, 1, 0>);
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ka, kApplyThreads, lds);
     if (e != hipSuccess) return e;
     *apply_blocks_per_cu = nb;

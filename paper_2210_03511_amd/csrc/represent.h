@@ -29,11 +29,16 @@ struct Lds {
 
 // Views of the tables: b is the staged blob (LDS), g the buffer that holds
 // the Rep/Sym tables when they are too large for LDS (L.rep_global).
-__host__ __device__ __forceinline__ Lds lds_view(const unsigned char *b, const BlobLayout &L,
-                                                 const unsigned char *g = nullptr)
+// RG = 0: the Rep/Sym tables are in the blob (L.rep_global must be 0), so
+// every pointer derives from b and the compiler issues LDS reads for them;
+// RG = 1: decided from L.rep_global at run time (generic pointers, flat
+// loads).
+template <int RG>
+__host__ __device__ __forceinline__ Lds lds_view_t(const unsigned char *b, const BlobLayout &L,
+                                                   const unsigned char *g)
 {
     Lds v;
-    if (L.rep_global) {
+    if (RG && L.rep_global) {
         v.rent = reinterpret_cast<const uint2 *>(g + L.g_rent);
         v.symlist = reinterpret_cast<const uint16_t *>(g + L.g_symlist);
     } else {
@@ -52,6 +57,12 @@ __host__ __device__ __forceinline__ Lds lds_view(const unsigned char *b, const B
     v.moves = reinterpret_cast<const ColorMove *>(b + L.off_moves);
     v.li = learned_lds(b, L.off_mlp, L.off_rank);
     return v;
+}
+
+__host__ __device__ __forceinline__ Lds lds_view(const unsigned char *b, const BlobLayout &L,
+                                                 const unsigned char *g = nullptr)
+{
+    return lds_view_t<1>(b, L, g);
 }
 
 // Substate that a symmetry puts at fine destination d of the configuration

@@ -40,3 +40,15 @@ def test_recorded_traffic_only_for_matching_sources(tmp_path, monkeypatch):
     rec["sources_sha256"] = "0" * 64
     p.write_text(json.dumps(rec))
     assert bench.recorded_traffic("square40", 2) is None          # sources changed since the counters
+
+
+def test_valu_bound_from_recorded_instructions(tmp_path, monkeypatch):
+    rec = {"config": "square40", "sources_sha256": bench.kernel_sources_sha256(),
+           "kernels": {"hash": {"dram_read_bytes": 1.0, "dram_write_bytes": 1.0,
+                                "sq": {"SQ_INSTS_VALU": 0.5 * 256 * 2.4e9}}}}
+    (tmp_path / "k_apply_square40_counters.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
+    v = bench.valu_bound("square40", 2, 1.0)          # half a second of issue in a one-second launch
+    assert v["bound"] == "alu" and abs(v["frac"] - 0.5) < 1e-12
+    assert bench.valu_bound("square40", 0, 1.0) is None
+    assert bench.counters_path("square32_batch").endswith("k_batch_apply_square32_batch_counters.json")
