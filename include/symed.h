@@ -307,8 +307,9 @@ ed_status ed_apply_op_noalloc(const ed_basis *basis, const ed_model *op, const v
  * copied into the records; a lookup then probes from the home slot, and the
  * line that confirms the key also holds x_j.  Memory: slots x 16 (real) or
  * 32 (complex) bytes plus 4 bytes per state.  load: fraction of occupied
- * slots, in [0.05, 0.95]; 0 = default: 0.25, or the smallest load in
- * hundredths that keeps the slot count below 4e9.  Needs n_sites < 64.  A second
+ * slots, in [0.05, 0.95]; 0 = default: 0.15 (real sectors) or 0.25
+ * (complex sectors), or the smallest load in hundredths that keeps the slot
+ * count below 4e9.  Needs n_sites < 64.  A second
  * call with the same load returns the stats; another load is refused.
  * Blocks until built.
  */

@@ -594,10 +594,14 @@ ed_status ed_hash_build(ed_basis *b, const ed_hash_cfg *cfg_in, ed_hash_stats *o
     if (!b) return fail(ED_EINVAL, "NULL basis");
     ed_hash_cfg cfg{};
     if (cfg_in) cfg = *cfg_in;
-    // Default: a quarter of the slots occupied (about 1.17 probes per lookup),
-    // or the smallest load whose slot count still fits in 32 bits.
+    // Default: 15 % of the slots occupied for 16-byte records (about 1.09
+    // probes per lookup; at 40 sites 3.5 % faster than a quarter, for 18 GB
+    // more), a quarter for the 32-byte complex records (at 36 sites a load of
+    // 0.15 is 5 % slower), or the smallest load whose slot count still fits
+    // in 32 bits.
+    const double base = b->T.is_complex ? 0.25 : 0.15;
     const double load = cfg.load != 0.0 ? cfg.load
-                                         : std::max(0.25, std::ceil((double)b->dim / 4.0e9 * 100.0) / 100.0);
+                                         : std::max(base, std::ceil((double)b->dim / 4.0e9 * 100.0) / 100.0);
     if (!(load >= 0.05 && load <= 0.95)) return fail(ED_EINVAL, "load must lie in [0.05, 0.95]");
     if (b->T.N >= 64) return fail(ED_EINVAL, "the hashed table needs N < 64 (all-ones marks an empty slot)");
     if (b->dim == 0) return fail(ED_EINVAL, "empty sector");

@@ -15,7 +15,7 @@ struct Lds {
     const uint2 *rent;          // per coarse substate: {Rep | count << 16, first Sym entry}
     const uint16_t *symlist;    // symmetry codes (sp << 1) | flip
     const uint16_t *atab;   // distinct SymmetryAction tables, 2^ba entries each
-    const uint32_t *aent;   // [n_sp][2^aent_lg >= A]: (offset of the table in atab << 8) | shift of the source substate
+    const uint32_t *aent;   // [n_sp][2^aent_lg >= A]: (byte offset of the table in atab << 8) | shift of the source substate
     uint32_t aent_lg;
     const PairTerm *pairs;
     const ChiTerm *chis;
@@ -66,15 +66,15 @@ __host__ __device__ __forceinline__ Lds lds_view(const unsigned char *b, const B
 }
 
 // Substate that a symmetry puts at fine destination d of the configuration
-// t (spin flip not applied); en: the symmetry's A entries, each the offset
-// of its table in atab (<< 8) and the right shift that brings the source
-// substate of t to the low bits.
+// t (spin flip not applied); en: the symmetry's A entries, each the byte
+// offset of its table in atab (<< 8) and the right shift that brings the
+// source substate of t to the low bits.
 __host__ __device__ __forceinline__ uint32_t act_image(const uint32_t *en, const uint16_t *atab, uint64_t t, int d,
                                                       uint32_t ma)
 {
     const uint32_t ent = en[d];
     const uint32_t ss = (uint32_t)(t >> (ent & 63u)) & ma;
-    return atab[(ent >> 8) + ss];
+    return *reinterpret_cast<const uint16_t *>(reinterpret_cast<const unsigned char *>(atab) + (ent >> 8) + 2u * ss);
 }
 
 struct Found {
@@ -83,41 +83,24 @@ struct Found {
     uint32_t cnt;  // number of group elements reaching the representative = |Stab|
 };
 
-// Representative of t by sublattice coding (algorithm "Sublattice coding
-// algorithm for finding the representative"): MinRep over the coarse
-// sublattices, then every symmetry in Sym_Y of each sublattice Y attaining
-// MinRep is applied through the SymmetryAction tables of the fine
-// decomposition (destination-major, so the image is assembled most
-// significant sublattice first).  All minimizers lie among these candidates
-// and each group element is a candidate at most once, so the number of
-// candidates reaching the minimum is the stabilizer size.
-__host__ __device__ __forceinline__ Found find_rep(uint64_t t, const KParams &p, const Lds &L)
+// Candidate scan of find_rep in words of type V.  Every candidate maps its
+// sublattice onto the most significant coarse sublattice with image MinRep,
+// so the fine destinations 0..d0-1 agree for all candidates; images are
+// compared from destination d0 on and a candidate is dropped at the first
+// destination where it exceeds the best so far.  V = uint64_t carries the
+// MinRep prefix in the image; V = uint32_t (when the W = (A - d0) * ba bits
+// from destination d0 on number at most 31) carries only those bits, with
+// the all-ones start value above every image, and the prefix is put back at
+// the end.
+template <typename V>
+__host__ __device__ __forceinline__ Found scan_candidates(uint64_t t, const KParams &p, const Lds &L, uint32_t minrep,
+                                                          uint32_t xm, uint2 e0)
 {
     const int N = p.N, R = p.R, br = p.br, A = p.A, ba = p.ba;
     const uint32_t S = 1u << br, mr = S - 1u, ma = (1u << ba) - 1u;
-    // MinRep, and in xm the coarse sublattices that attain it (R <= 16); e0
-    // keeps the entry of the first of them
-    uint32_t minrep = 0xffffffffu, xm = 0;
-    uint2 e0 = make_uint2(0u, 0u);
-    for (int X = 0; X < R; ++X) {
-        uint32_t s = (uint32_t)(t >> (N - (X + 1) * br)) & mr;
-        const uint2 e = L.rent[X * S + s];
-        const uint32_t r = e.x & 0xffffu;
-        if (r < minrep) {
-            minrep = r;
-            xm = 1u << X;
-            e0 = e;
-        } else if (r == minrep) {
-            xm |= 1u << X;
-        }
-    }
-    // Every candidate maps its sublattice onto the most significant coarse
-    // sublattice with image MinRep, so the fine destinations 0..d0-1 agree
-    // for all candidates; images are compared from destination d0 on and a
-    // candidate is dropped at the first destination where it exceeds the
-    // best so far.
     const int d0 = A / R;
-    uint64_t best = ~0ull;
+    const V start = sizeof(V) == 8 ? (V)minrep : (V)0;
+    V best = ~(V)0;
     uint32_t bg = 0, cnt = 0;
     bool first = true;
     while (xm) {
@@ -135,11 +118,11 @@ __host__ __device__ __forceinline__ Found find_rep(uint64_t t, const KParams &p,
             const uint32_t sp = e >> 1;
             const uint32_t fm = (e & 1u) ? ma : 0u;  // spin flip complements every substate
             const uint32_t *en = L.aent + ((size_t)sp << L.aent_lg);
-            uint64_t v = minrep;
-            uint64_t bp = 0;
+            V v = start;
+            V bp = 0;
             int d = d0;
             for (; d < A; ++d) {
-                v = (v << ba) | (act_image(en, L.atab, t, d, ma) ^ fm);
+                v = (v << ba) | (V)(act_image(en, L.atab, t, d, ma) ^ fm);
                 bp = best >> ((A - 1 - d) * ba);
                 if (v != bp) break;
             }
@@ -156,13 +139,46 @@ __host__ __device__ __forceinline__ Found find_rep(uint64_t t, const KParams &p,
                 continue;
             }
             if (v > bp) continue;
-            for (++d; d < A; ++d) v = (v << ba) | (act_image(en, L.atab, t, d, ma) ^ fm);
+            for (++d; d < A; ++d) v = (v << ba) | (V)(act_image(en, L.atab, t, d, ma) ^ fm);
             best = v;
             bg = e;
             cnt = 1;
         }
     }
-    return Found{best, bg, cnt};
+    const uint64_t rep = sizeof(V) == 8 ? (uint64_t)best : (((uint64_t)minrep << ((A - d0) * ba)) | (uint64_t)best);
+    return Found{rep, bg, cnt};
+}
+
+// Representative of t by sublattice coding (algorithm "Sublattice coding
+// algorithm for finding the representative"): MinRep over the coarse
+// sublattices, then every symmetry in Sym_Y of each sublattice Y attaining
+// MinRep is applied through the SymmetryAction tables of the fine
+// decomposition (destination-major, so the image is assembled most
+// significant sublattice first).  All minimizers lie among these candidates
+// and each group element is a candidate at most once, so the number of
+// candidates reaching the minimum is the stabilizer size.
+__host__ __device__ __forceinline__ Found find_rep(uint64_t t, const KParams &p, const Lds &L)
+{
+    const int N = p.N, R = p.R, br = p.br;
+    const uint32_t S = 1u << br, mr = S - 1u;
+    // MinRep, and in xm the coarse sublattices that attain it (R <= 16); e0
+    // keeps the entry of the first of them
+    uint32_t minrep = 0xffffffffu, xm = 0;
+    uint2 e0 = make_uint2(0u, 0u);
+    for (int X = 0; X < R; ++X) {
+        uint32_t s = (uint32_t)(t >> (N - (X + 1) * br)) & mr;
+        const uint2 e = L.rent[X * S + s];
+        const uint32_t r = e.x & 0xffffu;
+        if (r < minrep) {
+            minrep = r;
+            xm = 1u << X;
+            e0 = e;
+        } else if (r == minrep) {
+            xm |= 1u << X;
+        }
+    }
+    if ((p.A - p.A / R) * p.ba <= 31) return scan_candidates<uint32_t>(t, p, L, minrep, xm, e0);
+    return scan_candidates<uint64_t>(t, p, L, minrep, xm, e0);
 }
 
 // Enumeration tests (algorithm "Preparation of the distributed and

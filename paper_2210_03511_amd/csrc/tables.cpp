@@ -403,13 +403,15 @@ std::vector<uint8_t> pack_blob(const HostTables &T, BlobLayout &L, std::vector<u
         gput(L.g_symlist, code.data(), code.size() * sizeof(uint16_t));
     }
     put(L.off_atab, T.act_tab.data(), T.act_tab.size() * sizeof(uint16_t));
-    // device form of the entries: table offset in atab << 8 | right shift of
-    // the source substate (offsets < 4096 << 12 = 2^24, shifts < 64)
+    // device form of the entries: byte offset of the table in atab << 8 |
+    // right shift of the source substate (byte offsets < 2^24: the blob
+    // fits LDS; shifts < 64)
     std::vector<uint32_t> ent32((size_t)T.n_sp << L.aent_lg, 0u);
     for (int sp = 0; sp < T.n_sp; ++sp)
         for (int d = 0; d < T.A; ++d) {
             const uint32_t e = T.act_ent[(size_t)sp * T.A + d], X = e & 15u;
-            ent32[((size_t)sp << L.aent_lg) + d] = (((e >> 4) << T.ba) << 8) | (uint32_t)(T.N - (int)(X + 1) * T.ba);
+            const uint32_t byte_off = ((e >> 4) << T.ba) * (uint32_t)sizeof(uint16_t);
+            ent32[((size_t)sp << L.aent_lg) + d] = (byte_off << 8) | (uint32_t)(T.N - (int)(X + 1) * T.ba);
         }
     put(L.off_aent, ent32.data(), ent32.size() * sizeof(uint32_t));
     put(L.off_pairs, T.pairs.data(), T.pairs.size() * sizeof(PairTerm));
