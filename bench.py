@@ -258,7 +258,9 @@ def main_batch(args):
         torch.cuda.synchronize()
         step_t[m] = (time.perf_counter() - t0) / args.steps
         e_min[m] = min(float(S.eigenvalues(a, b, 1)[0]) for a, b, n, br in res)
-    best = min(modes, key=lambda m: step_t[m])
+    # the metric compares the learned lookup with the plain one: the headline
+    # is the learned mode when it ran, else the fastest mode that did
+    best = 1 if 1 in modes else min(modes, key=lambda m: step_t[m])
     # a second batch of the same sectors takes its launch shape from the cache
     a_ref = batch.lanczos(v0s, 3, mode=best)
     batch2 = S.Batch(bases, cache_path=cache)
@@ -272,8 +274,16 @@ def main_batch(args):
     binfo = batch.info()
     n_el = binfo["total_elements"]
     alg = sum(alg_bytes_of(inf["dim"], inf["n_offdiag"], bool(inf["is_complex"])) for inf in infos)
-    achieved = alg / apply_t[best] / 1e9
     name = {0: "plain", 1: "learned", 2: "hash"}.get
+
+    def batch_roofline(m):
+        t = apply_t[m]
+        traffic = recorded_traffic("square32_batch", m)
+        return {"bound": "hbm", "achieved": alg / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": alg / t / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": f"k_batch_apply ({name(m)} lookup)", "alg_bytes_per_launch": alg, "avg_launch_s": t,
+                "gather_efficiency": None if traffic is None else alg / traffic,
+                "counted_GBps": None if traffic is None else traffic / t / 1e9}
     dims = [inf["dim"] for inf in infos]
     out = {
         "metric": "H\u00b7v elements/s & s per Lanczos step, batched sectors: learned vs plain lookup",
@@ -301,10 +311,8 @@ def main_batch(args):
                   "decomposition": {"n_sub_rep": sub_r, "n_sub_act": sub_a, "tuned_on": insts[big].sector,
                                     "candidates": drep["candidates"], "tune_s": t_dtune},
                   "autotune": {name(m): tuned[m] for m in modes}, "cache_reuse": reuse},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic("square32_batch", best),
-                     "kernel": f"k_batch_apply ({name(best)} lookup)", "alg_bytes_per_launch": alg,
-                     "avg_launch_s": apply_t[best]},
+        "roofline": batch_roofline(best),
+        "roofline_by_mode": {name(m): batch_roofline(m) for m in modes},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(insts[0], args.cpu_seconds)
