@@ -6,10 +6,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def build():
-    src = os.path.join(_HERE, "oracle.c")
+    srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "fast.c")]
     out = os.path.join(_HERE, "liboracle.so")
     tmp = out + ".tmp"
-    cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", src, "-o", tmp, "-lm"]
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-I", _HERE] + srcs + ["-o", tmp, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)
     return out

@@ -34,23 +34,8 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
-#include <complex.h>
 
-typedef struct {
-    int32_t n;                 /* sites */
-    int32_t n_elem;            /* group order */
-    const int32_t *perm;       /* [n_elem][n] */
-    const uint8_t *flip;       /* [n_elem] */
-    const double *chi_re;      /* [n_elem] */
-    const double *chi_im;
-    const uint8_t *chi_one;    /* [n_elem]: 1 iff chi(g) == 1 */
-    int32_t n_bonds;
-    const int32_t *bonds;      /* [n_bonds][2] */
-    const double *bond_J;
-    int32_t n_tri;
-    const int32_t *tris;       /* [n_tri][3] */
-    const double *tri_J;
-} orc_problem;
+#include "oracle.h"
 
 static inline int spin_at(uint64_t s, int n, int site) { return (int)((s >> (n - 1 - site)) & 1u); }
 static inline uint64_t site_bit(int n, int site) { return (uint64_t)1 << (n - 1 - site); }
@@ -185,7 +170,7 @@ int64_t orc_find(const uint64_t *reps, int64_t dim, uint64_t s)
 
 /* all non-branching pieces H_k acting on s: appends (tau, h) pairs, returns count.
  * The Ising part is returned as a single diagonal piece (tau = s). */
-static int apply_terms(const orc_problem *p, uint64_t s, uint64_t *tau, double complex *h)
+int orc_apply_terms(const orc_problem *p, uint64_t s, uint64_t *tau, double complex *h)
 {
     int n = p->n, m = 0;
     double diag = 0.0;
@@ -242,7 +227,7 @@ int64_t orc_coo(const orc_problem *p, const uint64_t *reps, const int32_t *stabs
         double complex *h = malloc(sizeof(double complex) * mt);
         #pragma omp for schedule(dynamic, 64)
         for (int64_t j = 0; j < dim; ++j) {
-            int m = apply_terms(p, reps[j], tau, h);
+            int m = orc_apply_terms(p, reps[j], tau, h);
             int64_t k = 0;
             for (int q = 0; q < m; ++q) {
                 if (h[q] == 0) continue;
@@ -257,7 +242,7 @@ int64_t orc_coo(const orc_problem *p, const uint64_t *reps, const int32_t *stabs
         #pragma omp for schedule(dynamic, 64)
         for (int64_t j = 0; j < dim; ++j) {
             if (cnt[dim] > cap) continue;
-            int m = apply_terms(p, reps[j], tau, h);
+            int m = orc_apply_terms(p, reps[j], tau, h);
             int64_t k = cnt[j];
             for (int q = 0; q < m; ++q) {
                 if (h[q] == 0) continue;
@@ -305,7 +290,7 @@ int64_t orc_rows(const orc_problem *p, const uint64_t *rows, int64_t n_rows, int
             uint64_t rs; int32_t gs, sts, tvs;
             orc_rep(p, s, &rs, &gs, &sts, &tvs);
             row_ok[r] = (rs == s && tvs) ? 1 : 0;
-            int m = apply_terms(p, s, tau, h);
+            int m = orc_apply_terms(p, s, tau, h);
             int64_t k = 0;
             int ne = 0;
             for (int q = 0; q < m; ++q) {
@@ -333,7 +318,7 @@ int64_t orc_rows(const orc_problem *p, const uint64_t *rows, int64_t n_rows, int
             uint64_t s = rows[r];
             uint64_t rs; int32_t gs, sts, tvs;
             orc_rep(p, s, &rs, &gs, &sts, &tvs);
-            int m = apply_terms(p, s, tau, h);
+            int m = orc_apply_terms(p, s, tau, h);
             int64_t k = cnt[r];
             for (int q = 0; q < m; ++q) {
                 if (h[q] == 0) continue;
