@@ -83,7 +83,7 @@ def lowest_by_spin(make_sectors, spins, n_iter=100, mode=0, seed=1):
     return table
 
 
-def good_ritz(alpha, beta, k, tol=1e-10):
+def good_ritz(alpha, beta, k, tol=1e-12):
     """Lowest k distinct eigenvalues of the Lanczos T-matrix with the
     spurious ones removed (Cullum and Willoughby's test, 1985).  Without
     reorthogonalization T acquires, besides repeated copies of converged
@@ -92,7 +92,17 @@ def good_ritz(alpha, beta, k, tol=1e-10):
     deleted, to rounding, because the start vector has no weight on it.  A
     cluster of T eigenvalues equal to 1e-8 (relative) counts once; a simple
     one closer than ``tol`` (relative to the largest |eigenvalue|) to an
-    eigenvalue of the reduced matrix is dropped."""
+    eigenvalue of the reduced matrix is dropped.
+
+    A genuine level lies about D u^2 from the nearest eigenvalue of the
+    reduced matrix, u being the start vector's weight on it and D of the
+    order of the spectral width: about 1e-7 for a random start vector in a
+    10^8-state sector, and now and then orders of magnitude less, while
+    the spurious values sit at rounding distance.  Hence ``tol`` is at
+    rounding scale, and the lowest value is always kept: T's eigenvalues
+    never fall below the sector's lowest level (beyond rounding), so the
+    lowest one is that level or its approximation from above, never a
+    spurious value."""
     a = np.ascontiguousarray(alpha, np.float64)
     b = np.ascontiguousarray(beta, np.float64)
     n = len(a)
@@ -105,7 +115,7 @@ def good_ritz(alpha, beta, k, tol=1e-10):
         j = i + 1
         while j < n and lam[j] - lam[i] <= 1e-8 * scale:
             j += 1
-        if j - i > 1 or len(mu) == 0 or np.min(np.abs(mu - lam[i])) > tol * scale:
+        if i == 0 or j - i > 1 or len(mu) == 0 or np.min(np.abs(mu - lam[i])) > tol * scale:
             out.append(float(lam[i]))
         i = j
     return out

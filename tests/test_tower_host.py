@@ -58,3 +58,31 @@ def test_spin_levels_cut_lowered_by_drift():
     assert rows == [(-3.0, "a")]
     rows0, cut0 = T.spin_levels(at_s, at_s1, safety=0.0)
     assert rows0 == [(-3.0, "a"), (-2.0005, "a")]       # without the margin it would pass
+
+
+def test_good_ritz_keeps_levels_with_small_start_weight():
+    """A genuine level on which the start vector has little weight u lies
+    about D u^2 from an eigenvalue of the reduced T-matrix (D ~ spectral
+    width), as close as 1e-10 for u^2 ~ 1e-11 - the weight of a random start
+    vector in a 10^8-state sector, now and then.  It must not be taken for a
+    spurious value: a diagonal H with an isolated lowest level and a second
+    level, each given such a weight."""
+    from paper_2210_03511_amd import tower as T
+    rng = np.random.default_rng(0)
+    dim = 200_000
+    ev = np.sort(rng.normal(0.0, 5.0, dim))
+    ev[0] = ev[2] - 0.6
+    ev[1] = ev[2] - 0.3
+    v0 = np.random.default_rng(1).standard_normal(dim)
+    v0[0] = 3e-6 * np.linalg.norm(v0)     # u^2 ~ 1e-11 on the lowest level
+    v0[1] = 5e-6 * np.linalg.norm(v0)     # and on the second
+    a, b = O.lanczos(lambda v: ev * v, v0, 100)
+    lam = T.symed.eigenvalues(a, b, len(a))
+    mu = T.symed.eigenvalues(a[1:], b[1:], len(a) - 1)
+    scale = max(1.0, float(np.max(np.abs(lam))))
+    # both levels converged and close to the reduced matrix's eigenvalues
+    for e in ev[:2]:
+        assert np.min(np.abs(lam - e)) < 1e-9
+        assert np.min(np.abs(mu - e)) < 1e-10 * scale
+    got = T.good_ritz(a, b, 3)
+    assert abs(got[0] - ev[0]) < 1e-9 and abs(got[1] - ev[1]) < 1e-9
