@@ -490,3 +490,72 @@ def test_no_admissible_decomposition_is_refused(S):
         S.Basis.build(L.chain(48, n_up=3, sublat=(2, 4)))
     assert e.value.status == S.ED_ENOTSTABLE
     assert "SymmetryAction" in str(e.value)
+
+
+# --- stored values of the fast CPU oracle at 36 and 40 sites -----------------
+
+def _fast_oracle_gold(name):
+    import json
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not written (tests/golden/make_golden_large.py)")
+    return json.load(open(path))
+
+
+@pytest.mark.parametrize("make,name", [(L.tri36_K, "triangular36_K.json"),
+                                       (L.square40, "square40_gamma_a_even.json")],
+                         ids=["triangular36_K", "square40"])
+def test_full_size_against_fast_oracle(S, make, name):
+    """The 36-site triangular K sector and the 40-site square sector against
+    whole-sector values of the fast CPU oracle: basis checksums; one H.x over
+    every row (sum, squared norm, <x, Hx>, and every stride-th row element
+    by element); the first Lanczos coefficients and the lowest Ritz value
+    from the seeded start vector - in every lookup mode."""
+    torch = _torch()
+    gold = _fast_oracle_gold(name)
+    inst = make()
+    cplx = inst.is_complex
+    _say("fast-oracle gold", inst.name, inst.sector)
+    b = S.Basis.build(inst)
+    assert b.dim == gold["dim"]
+    reps, stab = b.export()
+    assert int(np.sum(reps, dtype=np.uint64)) == gold["reps_sum_mod_2_64"]
+    assert int(np.bitwise_xor.reduce(reps)) == gold["reps_xor"]
+    assert int(stab.astype(np.int64).sum()) == gold["stab_sum"]
+    x = V.state_vector(reps, gold["hv_state_vector_seed"], cplx)
+    del reps, stab
+    xt = _dev(torch, x)
+    rows = np.arange(0, gold["dim"], gold["hv_stride"])
+    ref = np.array(gold["hv_rows"])
+    if cplx:
+        ref = ref[:, 0] + 1j * ref[:, 1]
+    hv_sum = complex(*gold["hv_sum"])
+    norm = gold["hv_norm2"] ** 0.5
+    b.train_index()
+    b.build_hash()
+    v0 = _dev(torch, V.start_vector(gold["dim"], gold["lanczos_seed"], cplx))
+    it_t = torch.from_numpy(rows).cuda()
+    for mode in (0, 1, 2):
+        yt = torch.zeros_like(xt)
+        b.apply_H(xt, yt, mode=mode)
+        torch.cuda.synchronize()
+        err = float(np.max(np.abs(yt[it_t].cpu().numpy() - ref)))
+        s = complex(yt.sum().item())
+        n2 = float(torch.vdot(yt, yt).real.item()) if cplx else float(torch.dot(yt, yt).item())
+        xhx = float(torch.vdot(xt, yt).real.item()) if cplx else float(torch.dot(xt, yt).item())
+        del yt
+        _say("  mode", mode, "rows", len(rows), "max err", err, "sum", s, "norm2", n2)
+        assert err < 1e-12
+        assert abs(s - hv_sum) <= 1e-10 * norm
+        assert abs(n2 - gold["hv_norm2"]) <= 1e-11 * gold["hv_norm2"]
+        assert abs(xhx - gold["hv_xHx"]) <= 1e-10 * norm * float(torch.linalg.vector_norm(xt).item())
+        k = gold["lanczos_steps"]
+        a, be, n, broken = b.lanczos(v0, k, mode=mode)
+        assert n == k and not broken
+        assert np.max(np.abs(a[:k] - np.array(gold["alpha"]))) <= 1e-10 * max(1.0, np.max(np.abs(gold["alpha"])))
+        assert np.max(np.abs(be[:k] - np.array(gold["beta"]))) <= 1e-10 * max(1.0, np.max(gold["beta"]))
+        e = S.eigenvalues(a, be, 1)[0]
+        _say("  mode", mode, "Ritz value after", k, "steps", repr(e), "oracle", gold["ritz0"])
+        assert abs(e - gold["ritz0"]) <= 1e-10 * abs(gold["ritz0"])
+    del xt, v0
+    b.free()
