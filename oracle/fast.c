@@ -33,7 +33,8 @@
  *     one of its sublattices X has Rep_X below the leading substate (some g
  *     then maps the configuration below itself);
  *   - H.v in the pull form of oracle.c (orc_rows), with the pieces of
- *     orc_apply_terms and the index found by binary search; OpenMP over
+ *     orc_apply_terms and the index found by binary search inside the
+ *     range that a table of limits on the leading bits gives; OpenMP over
  *     rows.
  */
 #include <complex.h>
@@ -277,6 +278,40 @@ int64_t orf_enumerate(const orf_tables *t, int n_up, uint64_t *reps, int32_t *st
 }
 
 /*
+ * Index of a representative through a table of limits on its leading bits
+ * (the thesis's "Limits" lookup of its distributed-memory section): the
+ * representatives with leading P bits equal to q occupy positions
+ * [lim[q], lim[q + 1]) of the ascending basis, and a binary search runs
+ * inside that range only.  -1 if absent.
+ */
+typedef struct {
+    int shift;             /* n - P */
+    int64_t *lim;          /* [2^P + 1] */
+} orf_limits;
+
+static orf_limits limits_build(const uint64_t *reps, int64_t dim, int n)
+{
+    orf_limits L;
+    const int P = n < 22 ? n : 22;
+    const uint64_t Q = (uint64_t)1 << P;
+    L.shift = n - P;
+    L.lim = malloc(sizeof(int64_t) * (Q + 1));
+    int64_t i = 0;
+    for (uint64_t q = 0; q <= Q; ++q) {
+        while (i < dim && (reps[i] >> L.shift) < q) ++i;
+        L.lim[q] = i;
+    }
+    return L;
+}
+
+static int64_t limits_find(const orf_limits *L, const uint64_t *reps, uint64_t s)
+{
+    const uint64_t q = s >> L->shift;
+    const int64_t j = orc_find(reps + L->lim[q], L->lim[q + 1] - L->lim[q], s);
+    return j < 0 ? -1 : L->lim[q] + j;
+}
+
+/*
  * y = H x over the whole basis, pull form (as orc_rows):
  *   y_i = sum_k chi(g) sqrt(|Stab tau~| / |Stab sigma_i|) conj(h_k) x(tau~_k)
  * over the pieces of orc_apply_terms whose target lies in the basis.
@@ -286,6 +321,7 @@ void orf_apply(const orc_problem *p, const orf_tables *t, const uint64_t *reps, 
                const double *x, double *y, int cplx)
 {
     const int mt = orc_max_terms(p);
+    orf_limits lim = limits_build(reps, dim, t->n);
     #pragma omp parallel
     {
         uint64_t *tau = malloc(sizeof(uint64_t) * mt);
@@ -299,7 +335,7 @@ void orf_apply(const orc_problem *p, const orf_tables *t, const uint64_t *reps, 
                 uint64_t r; int32_t g, st, tv;
                 orf_find_rep(t, tau[q], &r, &g, &st, &tv);
                 if (!tv) continue;
-                const int64_t j = orc_find(reps, dim, r);
+                const int64_t j = limits_find(&lim, reps, r);
                 if (j < 0) continue;
                 const double complex chi = p->chi_re[g] + I * p->chi_im[g];
                 const double complex c = chi * sqrt((double)st / (double)stabs[i]) * conj(h[q]);
@@ -312,4 +348,5 @@ void orf_apply(const orc_problem *p, const orf_tables *t, const uint64_t *reps, 
         free(tau);
         free(h);
     }
+    free(lim.lim);
 }
