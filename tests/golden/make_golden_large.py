@@ -13,8 +13,8 @@ Stored per sector:
     norm, <x, Hx>, and y on every row whose index is a multiple of the stride;
   - the first Lanczos coefficients from start_vector(dim, seed) and the
     lowest Ritz value after that many steps.
-Each H.x costs about 5 minutes at 36 sites and half an hour at 40 sites on
-8 cores, so the Lanczos runs are short.
+Each H.x costs minutes at 36 sites and about 20 minutes at 40 sites on 8
+cores, so the Lanczos runs are short.
 """
 import argparse
 import json
