@@ -10,8 +10,8 @@ It is pinned against things it does not compute itself:
   - the 32-site stored values written by tests/golden/make_golden.py from the
     brute-force oracle (dimension, checksums of the representatives and
     stabilizers, sum and norm of one H.x);
-  - representatives of random configurations at 32, 36 and 40 sites against
-    the brute-force orbit minimum;
+  - representatives of 10^6 random configurations at each of 32, 36 and 40
+    sites against the brute-force orbit minimum;
   - the character-formula dimension of the 36-site sector.
 """
 import json
@@ -113,21 +113,25 @@ def test_square32_stored_values():
 @pytest.mark.parametrize("make,n_sub", [(L.square32, 4), (L.tri36_K, 4), (L.square40, 4)],
                          ids=["square32", "triangular36_K", "square40"])
 def test_representatives_at_full_size(make, n_sub):
+    """10^6 uniformly random configurations of the Sz sector per lattice."""
     inst = make()
     F = O.Fast(inst, n_sub)
     rng = np.random.default_rng(11)
-    n = inst.n_sites
-    states = np.zeros(4000, np.uint64)
-    for i in range(len(states)):
-        up = rng.choice(n, inst.n_up, replace=False)
-        states[i] = np.sum(np.uint64(1) << (np.uint64(n - 1) - up.astype(np.uint64)))
+    n, m = inst.n_sites, 1_000_000
+    states = np.zeros(m, np.uint64)
+    for a in range(0, m, 250_000):
+        # the n_up sites with the smallest of n uniform keys: a uniform subset
+        up = np.argsort(rng.random((min(250_000, m - a), n)), axis=1)[:, :inst.n_up]
+        states[a:a + len(up)] = np.bitwise_or.reduce(np.uint64(1) << (np.uint64(n - 1) - up.astype(np.uint64)),
+                                                      axis=1)
+    assert np.all(np.bitwise_count(states) == inst.n_up)
     rep, g, st, tv = F.rep_many(states)
     rep0, g0, st0, tv0 = O.rep_many(inst, states)
     assert np.array_equal(rep, rep0)
     assert np.array_equal(st, st0)
     assert np.array_equal(tv, tv0.astype(bool))
     # the reported element maps each state onto its representative
-    for i in range(0, len(states), 97):
+    for i in range(0, len(states), 9973):
         assert O.act(inst, int(g[i]), int(states[i])) == int(rep[i])
 
 
