@@ -87,6 +87,7 @@ orf_tables *orf_build(const orc_problem *p, int n_sub)
     if ((double)n_sub * G * (double)S * 8.0 > 4.0e9) return NULL;
     /* image sublattice of every (g, X); -1: not stable */
     int *img = malloc(sizeof(int) * (size_t)G * n_sub);
+    if (!img) return NULL;
     for (int g = 0; g < G; ++g)
         for (int X = 0; X < n_sub; ++X) {
             const int32_t *pm = p->perm + (size_t)g * n;
@@ -96,10 +97,13 @@ orf_tables *orf_build(const orc_problem *p, int n_sub)
             img[g * n_sub + X] = Y;
         }
     orf_tables *t = calloc(1, sizeof(orf_tables));
+    if (!t) { free(img); return NULL; }
     t->n = n; t->n_sub = n_sub; t->b = b; t->G = G; t->S = S; t->chi_re = p->chi_re; t->chi_im = p->chi_im;
     t->act = malloc(sizeof(uint64_t) * (size_t)n_sub * G * S);
     t->rep = malloc(sizeof(uint64_t) * (size_t)n_sub * S);
     t->sym_off = malloc(sizeof(int64_t) * ((size_t)n_sub * S + 1));
+    int64_t *cnt = calloc((size_t)n_sub * S + 1, sizeof(int64_t));
+    if (!t->act || !t->rep || !t->sym_off || !cnt) { free(cnt); free(img); orf_free(t); return NULL; }
     /* SymmetryAction: the spin of site i goes to site perm[i], reversed when g flips */
     #pragma omp parallel for collapse(2) schedule(static)
     for (int X = 0; X < n_sub; ++X)
@@ -117,7 +121,6 @@ orf_tables *orf_build(const orc_problem *p, int n_sub)
             }
         }
     /* Rep and the sizes of the Sym lists */
-    int64_t *cnt = calloc((size_t)n_sub * S + 1, sizeof(int64_t));
     #pragma omp parallel for collapse(2) schedule(static)
     for (int X = 0; X < n_sub; ++X)
         for (uint64_t s = 0; s < S; ++s) {
@@ -134,6 +137,7 @@ orf_tables *orf_build(const orc_problem *p, int n_sub)
     for (uint64_t q = 0; q < (uint64_t)n_sub * S; ++q) cnt[q + 1] += cnt[q];
     memcpy(t->sym_off, cnt, sizeof(int64_t) * ((size_t)n_sub * S + 1));
     t->sym = malloc(sizeof(int32_t) * (size_t)(cnt[(size_t)n_sub * S] + 1));
+    if (!t->sym) { free(cnt); free(img); orf_free(t); return NULL; }
     #pragma omp parallel for collapse(2) schedule(static)
     for (int X = 0; X < n_sub; ++X)
         for (uint64_t s = 0; s < S; ++s) {
@@ -296,6 +300,7 @@ static orf_limits limits_build(const uint64_t *reps, int64_t dim, int n)
     const uint64_t Q = (uint64_t)1 << P;
     L.shift = n - P;
     L.lim = malloc(sizeof(int64_t) * (Q + 1));
+    if (!L.lim) return L;
     int64_t i = 0;
     for (uint64_t q = 0; q <= Q; ++q) {
         while (i < dim && (reps[i] >> L.shift) < q) ++i;
@@ -315,13 +320,15 @@ static int64_t limits_find(const orf_limits *L, const uint64_t *reps, uint64_t s
  * y = H x over the whole basis, pull form (as orc_rows):
  *   y_i = sum_k chi(g) sqrt(|Stab tau~| / |Stab sigma_i|) conj(h_k) x(tau~_k)
  * over the pieces of orc_apply_terms whose target lies in the basis.
- * x, y: interleaved complex (re, im) when cplx, else real.
+ * x, y: interleaved complex (re, im) when cplx, else real.  Returns 0, or
+ * -1 when the table of limits cannot be allocated (y untouched).
  */
-void orf_apply(const orc_problem *p, const orf_tables *t, const uint64_t *reps, const int32_t *stabs, int64_t dim,
+int orf_apply(const orc_problem *p, const orf_tables *t, const uint64_t *reps, const int32_t *stabs, int64_t dim,
                const double *x, double *y, int cplx)
 {
     const int mt = orc_max_terms(p);
     orf_limits lim = limits_build(reps, dim, t->n);
+    if (!lim.lim) return -1;
     #pragma omp parallel
     {
         uint64_t *tau = malloc(sizeof(uint64_t) * mt);
@@ -349,4 +356,5 @@ void orf_apply(const orc_problem *p, const orf_tables *t, const uint64_t *reps, 
         free(h);
     }
     free(lim.lim);
+    return 0;
 }

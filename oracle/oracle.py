@@ -3,7 +3,8 @@
 Only the tests, the smoke check and the CPU-baseline leg of the benchmark
 may import this module.  It shares no code with the HIP library: the C part
 (``oracle.c`` and ``fast.c``, built into ``liboracle.so``) does brute-force
-orbit scans, binary search and the host sublattice-coding method; this module adds the dense and Lanczos layers in numpy/scipy.
+orbit scans, binary search and the host sublattice-coding method; this
+module adds the dense and Lanczos layers in numpy/scipy.
 
 What each function follows (thesis sections / equations):
   * ``enumerate_basis``  - representatives = orbit minima ("representative
@@ -108,7 +109,7 @@ def lib():
         L.orf_rep_of.argtypes = [vp, ctypes.c_int, ctypes.c_uint64]
         L.orf_sym_of.restype = ctypes.c_int
         L.orf_sym_of.argtypes = [vp, ctypes.c_int, ctypes.c_uint64, vp, ctypes.c_int]
-        L.orf_apply.restype = None
+        L.orf_apply.restype = ctypes.c_int
         L.orf_apply.argtypes = [P, vp, vp, vp, ctypes.c_int64, vp, vp, ctypes.c_int]
         _LIB = L
     return _LIB
@@ -202,7 +203,8 @@ class Fast:
         cplx = bool(np.iscomplexobj(x))
         xv = np.ascontiguousarray(x, np.complex128 if cplx else np.float64)
         y = np.zeros_like(xv)
-        lib().orf_apply(self.p.ref, self.h, _ptr(reps), _ptr(stabs), len(reps), _ptr(xv), _ptr(y), int(cplx))
+        if lib().orf_apply(self.p.ref, self.h, _ptr(reps), _ptr(stabs), len(reps), _ptr(xv), _ptr(y), int(cplx)):
+            raise MemoryError("fast oracle: no memory for the table of limits")
         return y
 
 
