@@ -248,7 +248,10 @@ def test_all_46_sectors_batched_lanczos_against_stored_oracle_energies(S):
     relative: Gamma.A1.even from the start vector of seed 2002, and the
     smallest complex sector, (0, 1/4).1.even, from seed 4001 + 10; every
     other sector starts from seed 4001 + its number.  The lowest level over
-    all sectors lies in Gamma.A1.even."""
+    all sectors lies in Gamma.A1.even.  Every sector against the fast CPU
+    oracle's whole-sector values (tests/golden/make_golden_sectors32.py):
+    dimension, the first Lanczos coefficients and the Ritz value after
+    them, to 1e-10."""
     import json
     import os
     torch = _torch()
@@ -283,6 +286,19 @@ def test_all_46_sectors_batched_lanczos_against_stored_oracle_energies(S):
     assert np.max(np.abs(a[:10] - np.array(g_cplx["alpha_first10"]))) < 1e-10
     assert np.max(np.abs(b[:10] - np.array(g_cplx["beta_first10"]))) < 1e-10
     assert int(np.argmin(e0)) == 0
+    g_all = json.load(open(os.path.join(here, "square32_sectors.json")))
+    assert len(g_all["sectors"]) == len(insts)
+    steps = g_all["lanczos_steps"]
+    for (a, b, n, broken), inst, d, gs in zip(res, insts, dims, g_all["sectors"]):
+        assert gs["sector"] == inst.sector and gs["dim"] == d
+        assert gs["lanczos_seed"] == seeds[gs["index"]]
+        sc = max(1.0, float(np.max(np.abs(gs["alpha"]))))
+        assert np.max(np.abs(a[:steps] - np.array(gs["alpha"]))) <= 1e-10 * sc, inst.sector
+        assert np.max(np.abs(b[:steps] - np.array(gs["beta"]))) <= 1e-10 * max(sc, float(np.max(gs["beta"]))), \
+            inst.sector
+        r = float(S.eigenvalues(a[:steps], b[:steps], 1)[0])
+        assert abs(r - gs["ritz0"]) <= 1e-10 * abs(gs["ritz0"]), inst.sector
+    _say("  46 sectors: first", steps, "Lanczos coefficients and Ritz values equal the fast oracle's")
     batch.free()
     for b in bases:
         b.free()
