@@ -78,7 +78,8 @@ def test_unstable_sublattices_rejected():
                 O.Fast(inst, ns)
 
 
-@pytest.mark.parametrize("inst", L.small_instances() + [L.chain16()], ids=lambda i: f"{i.name}-{i.sector}")
+@pytest.mark.parametrize("inst", L.small_instances() + [L.chain16()] + L.kagome_instances(),
+                         ids=lambda i: f"{i.name}-{i.sector}")
 def test_basis_and_hv_equal_bruteforce(inst):
     reps, stabs = O.enumerate_basis(inst)
     H = O.coo_matrix(inst, reps, stabs)

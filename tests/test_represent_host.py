@@ -44,7 +44,7 @@ def _write(inst, path):
             f.write(np.ascontiguousarray(a, t).tobytes())
 
 
-CASES = L.small_instances() + [L.chain16(), L.chain(6, sublat=(2,)), L.chain(6, sublat=(3,))]
+CASES = L.small_instances() + [L.chain16(), L.chain(6, sublat=(2,)), L.chain(6, sublat=(3,))] + L.kagome_instances()
 
 
 @pytest.mark.parametrize("inst", CASES, ids=lambda i: f"{i.name}-{i.sector}")
@@ -81,6 +81,8 @@ def _large_cases():
         ("triangular36 E2 sector", L.two_dim_sectors("triangular", t36, c36, J2=0.0, n_up=18)[2]),
         ("square32 E sector", L.two_dim_sectors("square", L.SQ32_L, L.SQ32_CHAIN, J2=0.5, n_up=16)[0]),
         ("square40", L.square40()),
+        ("kagome27 C6v Sz=1/2", L.kagome27(J2=0.2, J3=0.1)),
+        ("kagome27 chiral C6", L.kagome27(Jchi=0.3)),
     ]
 
 

@@ -244,13 +244,20 @@ class Torus2D:
                 out.append((self.site(r), self.site(_add(r, d))))
         return out
 
+    # momenta are defined modulo the dual of the translation lattice: the
+    # integers for a Bravais torus
+    q_period = Fraction(1)
+
+    def reduce_q(self, q):
+        m = self.q_period
+        return tuple(x - m * ((x / m).numerator // (x / m).denominator) for x in q)
+
     def little_group(self, q):
-        """Point-group elements P with P^T q = q modulo integers."""
+        """Point-group elements P with P^T q = q modulo the dual lattice."""
         out = []
         for P in self.pg:
             qp = (P[0][0] * q[0] + P[1][0] * q[1], P[0][1] * q[0] + P[1][1] * q[1])
-            d = (qp[0] - q[0], qp[1] - q[1])
-            if d[0].denominator == 1 and d[1].denominator == 1:
+            if self.reduce_q(qp) == self.reduce_q(q):
                 out.append(P)
         return out
 
@@ -281,12 +288,77 @@ def _add(a, b):
     return (a[0] + b[0], a[1] + b[1])
 
 
+def _kagome_site(p):
+    """A point of the fine triangular lattice is a kagome site unless both
+    coordinates are even (those points are the hexagon centres)."""
+    return (p[0] % 2, p[1] % 2) != (0, 0)
+
+
+class KagomeTorus(Torus2D):
+    """The kagome lattice on a torus, in coordinates of the triangular lattice
+    of half its lattice constant (the "fine" lattice, a1 = (1, 0), a2 =
+    (1/2, sqrt3/2)): its sites are the fine points with a coordinate odd, three
+    per unit cell of the Bravais lattice 2 a1, 2 a2.  The removed points are
+    the hexagon centres, so C6v about the origin maps the lattice onto itself.
+    ``L1``, ``L2``: torus periods (even vectors); ``sublat_chain``: as for
+    ``Torus2D``, even vectors, the classes of kagome sites modulo each being
+    the sublattices (modulo (2, 0), (0, 2): the three kagome sublattices)."""
+
+    q_period = Fraction(1, 2)
+
+    def __init__(self, L1, L2, pg_gens, sublat_chain):
+        L1, L2 = tuple(L1), tuple(L2)
+        assert all(c % 2 == 0 for c in L1 + L2), "kagome torus periods must be even"
+        self.L1, self.L2 = L1, L2
+        self.cart = np.array(TRI_CART, dtype=float)
+        pts = set()
+        R = max(abs(c) for c in L1 + L2) + 1
+        for x in range(-2 * R, 2 * R + 1):
+            for y in range(-2 * R, 2 * R + 1):
+                pts.add(_reduce((x, y), L1, L2))
+        assert len(pts) == abs(_cross(L1, L2))
+        self.trans = sorted(p for p in pts if not _kagome_site(p))
+        pts = {p for p in pts if _kagome_site(p)}
+        self.N = len(pts)
+        self.pg = [P for P in _group_closure(pg_gens)
+                   if _in_lattice(_matvec(P, L1), L1, L2) and _in_lattice(_matvec(P, L2), L1, L2)]
+        self.sublat_chain = [tuple(map(tuple, c)) for c in sublat_chain]
+        coset_ids, opts = [], []
+        for B1, B2 in self.sublat_chain:
+            assert all(c % 2 == 0 for c in B1 + B2)
+            assert _in_lattice(L1, B1, B2) and _in_lattice(L2, B1, B2)
+            reps = sorted({_reduce(p, B1, B2) for p in pts})
+            coset_ids.append({p: reps.index(_reduce(p, B1, B2)) for p in pts})
+            opts.append(len(reps))
+        order = sorted(pts, key=lambda p: tuple(c[p] for c in coset_ids) + (p[1], p[0]))
+        self.coords = order
+        self.index = {p: i for i, p in enumerate(order)}
+        self.sublat_options = opts
+
+    def translations(self):
+        """The Bravais translations (even fine vectors) modulo the torus."""
+        return list(self.trans)
+
+    def momenta(self):
+        """All allowed q (chi(t) = exp(2 pi i q.t) for even t) as Fractions
+        in [0, 1/2)^2."""
+        det = _cross(self.L1, self.L2)
+        L = [[self.L1[0], self.L2[0]], [self.L1[1], self.L2[1]]]
+        g1 = (Fraction(L[1][1], det), Fraction(-L[0][1], det))
+        g2 = (Fraction(-L[1][0], det), Fraction(L[0][0], det))
+        qs = set()
+        for m1 in range(abs(det)):
+            for m2 in range(abs(det)):
+                qs.add(self.reduce_q((m1 * g1[0] + m2 * g2[0], m1 * g1[1] + m2 * g2[1])))
+        assert len(qs) == len(self.trans)
+        return sorted(qs)
+
+
 def _pg_orbit(lat, q):
     orb = set()
     for P in lat.pg:
         qp = (P[0][0] * q[0] + P[1][0] * q[1], P[0][1] * q[0] + P[1][1] * q[1])
-        qp = tuple(x - (x.numerator // x.denominator) for x in qp)
-        orb.add(qp)
+        orb.add(lat.reduce_q(qp))
     return orb
 
 
@@ -395,6 +467,69 @@ def triangular_j1j2chi(L1, L2, J1, J2, Jchi, q, irrep="A", flip=1, sublat_chain=
     n = lat.N
     return Instance(name=name, n_sites=n, bonds=np.array(bonds, np.int32), bond_J=np.array(bJ, float),
                     tris=np.array(tris, np.int32).reshape(-1, 3), tri_Jchi=np.full(len(tris), float(Jchi)),
+                    n_up=n // 2 if n_up is None else n_up, perms=perms, flips=flips, chi=chis,
+                    sublat_options=lat.sublat_options,
+                    sector=f"q={tuple(map(str, q))}.{irrep}.{_flipname(flip)}",
+                    meta=dict(lattice=lat, little=little, q=q, irrep=0 if irrep in ("A", "A1") else irrep,
+                              flip=flip))
+
+
+KAG_VEC1 = [(1, 0), (0, 1), (-1, 1)]      # nearest neighbours (fine units)
+KAG_VEC2 = [(1, 1), (-1, 2), (-2, 1)]      # second neighbours, distance sqrt3
+KAG_VEC3 = [(1, 0), (0, 1), (-1, 1)]       # hexagon diagonals: r -> r + 2 d through a centre
+
+
+def kagome_lattice(L1, L2, sublat_chain, mirrors=True, pg_gens=None):
+    gens = pg_gens if pg_gens is not None else [TRI_R60] + ([TRI_MY] if mirrors else [])
+    lat = KagomeTorus(L1, L2, gens, sublat_chain)
+    lat.kind = "kagome"
+    return lat
+
+
+def kagome_j1j2j3chi(L1, L2, J1, J2, J3, Jchi, q, irrep="A", flip=1, sublat_chain=None, mirrors=None,
+                     n_up=None, name="kagome", pg_gens=None):
+    """Kagome J1-J2-J3-Jchi model (thesis chapter on the kagome chiral spin
+    liquid): J1 on nearest-neighbour bonds, J2 on second neighbours, J3 on
+    the diagonals of the hexagons, Jchi S_i.(S_j x S_k) on every elementary
+    triangle, counter-clockwise.  Point group C6v about a hexagon centre (C6
+    when Jchi != 0)."""
+    if mirrors is None:
+        mirrors = (Jchi == 0)
+    lat = kagome_lattice(L1, L2, sublat_chain, mirrors=mirrors, pg_gens=pg_gens)
+    site = lat.index
+
+    def pairs(vecs, step=1):
+        out = []
+        for r in lat.coords:
+            for d in vecs:
+                t = _reduce((r[0] + step * d[0], r[1] + step * d[1]), lat.L1, lat.L2)
+                if t in site and (step == 1 or not _kagome_site(_add(r, d))):
+                    out.append((site[r], site[t]))
+        return out
+
+    b1 = pairs(KAG_VEC1)
+    b2 = pairs(KAG_VEC2) if J2 != 0 else []
+    b3 = pairs(KAG_VEC3, 2) if J3 != 0 else []
+    bonds = b1 + b2 + b3
+    bJ = [J1] * len(b1) + [J2] * len(b2) + [J3] * len(b3)
+    tris = []
+    if Jchi != 0:
+        # the fine triangles with no hexagon centre among their corners: up
+        # triangles (r, r + a1, r + a2) at r with both coordinates odd, down
+        # triangles (r + a1, r + a1 + a2, r + a2) at the centres
+        for r in lat.coords + lat.translations():
+            for tri in ((r, _add(r, (1, 0)), _add(r, (0, 1))),
+                        (_add(r, (1, 0)), _add(r, (1, 1)), _add(r, (0, 1)))):
+                red = [_reduce(v, lat.L1, lat.L2) for v in tri]
+                if all(v in site for v in red):
+                    tris.append(tuple(site[v] for v in red))
+    little = lat.little_group(q)
+    rho = _irrep_by_name(little, irrep)
+    perms, flips, chis = build_group(lat, q, rho, flip, little)
+    n = lat.N
+    return Instance(name=name, n_sites=n, bonds=np.array(bonds, np.int32).reshape(-1, 2),
+                    bond_J=np.array(bJ, float), tris=np.array(tris, np.int32).reshape(-1, 3),
+                    tri_Jchi=np.full(len(tris), float(Jchi)),
                     n_up=n // 2 if n_up is None else n_up, perms=perms, flips=flips, chi=chis,
                     sublat_options=lat.sublat_options,
                     sector=f"q={tuple(map(str, q))}.{irrep}.{_flipname(flip)}",
@@ -747,6 +882,33 @@ def small_instances():
     out.append(triangular_j1j2chi(TRI12_L[0], TRI12_L[1], 1.0, 0.0, 0.3, (F(1, 2), F(0)), 1, None,
                                   TRI12_CHAIN, name="triangular12"))
     return out
+
+
+KAG12_L = ((4, 0), (0, 4))                        # 2 x 2 unit cells
+KAG12_CHAIN = [((2, 0), (0, 2))]                   # the three kagome sublattices
+KAG27_L = ((6, 0), (0, 6))                        # 3 x 3 unit cells
+KAG27_CHAIN = [((2, 0), (0, 2)), ((2, 2), (-2, 4))]   # 3 sublattices, then 9 (sqrt3 x sqrt3 cells)
+
+
+def kagome_instances():
+    """Small kagome sectors (J1-J2-J3-Jchi): C6v and chiral C6, momenta
+    modulo the kagome reciprocal lattice, spin flip, Sz != 0."""
+    Mq = (F(1, 4), F(0))           # an M point: half a reciprocal vector of the kagome lattice
+    return [
+        kagome_j1j2j3chi(KAG12_L[0], KAG12_L[1], 1.0, 0.0, 0.0, 0.0, Q0, "A1", 1, KAG12_CHAIN, name="kagome12"),
+        kagome_j1j2j3chi(KAG12_L[0], KAG12_L[1], 1.0, 0.2, 0.1, 0.0, Q0, 1, -1, KAG12_CHAIN, name="kagome12"),
+        kagome_j1j2j3chi(KAG12_L[0], KAG12_L[1], 1.0, 0.2, 0.1, 0.0, Mq, 2, 1, KAG12_CHAIN, name="kagome12"),
+        kagome_j1j2j3chi(KAG12_L[0], KAG12_L[1], 1.0, 0.0, 0.0, 0.3, Q0, 1, 1, KAG12_CHAIN, name="kagome12"),
+        kagome_j1j2j3chi(KAG12_L[0], KAG12_L[1], 1.0, 0.1, 0.0, 0.3, Mq, "A", None, KAG12_CHAIN, n_up=5,
+                         name="kagome12"),
+    ]
+
+
+def kagome27(J2=0.0, J3=0.0, Jchi=0.0, q=Q0, irrep="A", n_up=13):
+    """27-site kagome (3 x 3 unit cells), Sz = 1/2 by default."""
+    inst = kagome_j1j2j3chi(KAG27_L[0], KAG27_L[1], 1.0, J2, J3, Jchi, q, irrep, None, KAG27_CHAIN, n_up=n_up,
+                            name="kagome27")
+    return inst
 
 
 def chain_distance_bonds(inst, r):
