@@ -489,9 +489,10 @@ def kagome_lattice(L1, L2, sublat_chain, mirrors=True, pg_gens=None):
 def kagome_j1j2j3chi(L1, L2, J1, J2, J3, Jchi, q, irrep="A", flip=1, sublat_chain=None, mirrors=None,
                      n_up=None, name="kagome", pg_gens=None):
     """Kagome J1-J2-J3-Jchi model (thesis chapter on the kagome chiral spin
-    liquid): J1 on nearest-neighbour bonds, J2 on second neighbours, J3 on
-    the diagonals of the hexagons, Jchi S_i.(S_j x S_k) on every elementary
-    triangle, counter-clockwise.  Point group C6v about a hexagon centre (C6
+    liquid, its Hamiltonian): J1 on nearest-neighbour bonds, J2 on second
+    neighbours, J3 on third neighbours across the hexagons (the hexagon
+    diagonals), Jchi S_i.(S_j x S_k) on every elementary triangle (up and
+    down), counter-clockwise.  Point group C6v about a hexagon centre (C6
     when Jchi != 0)."""
     if mirrors is None:
         mirrors = (Jchi == 0)
