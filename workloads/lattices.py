@@ -191,6 +191,30 @@ def one_dim_irreps(elems):
     return [f[1] for f in found]
 
 
+def _torus_points(L1, L2):
+    """Canonical representatives of all lattice points modulo L1, L2."""
+    pts = set()
+    R = max(abs(c) for c in tuple(L1) + tuple(L2)) + 1
+    for x in range(-2 * R, 2 * R + 1):
+        for y in range(-2 * R, 2 * R + 1):
+            pts.add(_reduce((x, y), L1, L2))
+    assert len(pts) == abs(_cross(L1, L2)), (len(pts), abs(_cross(L1, L2)))
+    return pts
+
+
+def _label_sites(pts, chain, L1, L2):
+    """Site order: by coset along the sublattice chain (coarse to fine), then
+    by coordinates.  Returns (ordered points, index, classes per level)."""
+    coset_ids, opts = [], []
+    for B1, B2 in chain:
+        assert _in_lattice(L1, B1, B2) and _in_lattice(L2, B1, B2)
+        reps = sorted({_reduce(p, B1, B2) for p in pts})
+        coset_ids.append({p: reps.index(_reduce(p, B1, B2)) for p in pts})
+        opts.append(len(reps))
+    order = sorted(pts, key=lambda p: tuple(c[p] for c in coset_ids) + (p[1], p[0]))
+    return order, {p: i for i, p in enumerate(order)}, opts
+
+
 class Torus2D:
     """A Bravais lattice on a torus, in integer lattice coordinates.
 
@@ -203,30 +227,19 @@ class Torus2D:
 
     def __init__(self, L1, L2, pg_gens, sublat_chain, cart=((1.0, 0.0), (0.0, 1.0))):
         self.L1, self.L2 = tuple(L1), tuple(L2)
-        self.N = abs(_cross(self.L1, self.L2))
         self.cart = np.array(cart, dtype=float)  # rows: a1, a2 cartesian
-        pts = set()
-        R = max(abs(c) for c in self.L1 + self.L2) + 1
-        for x in range(-2 * R, 2 * R + 1):
-            for y in range(-2 * R, 2 * R + 1):
-                pts.add(_reduce((x, y), self.L1, self.L2))
-        assert len(pts) == self.N, (len(pts), self.N)
-        pg = [P for P in _group_closure(pg_gens)
-              if _in_lattice(_matvec(P, self.L1), self.L1, self.L2)
-              and _in_lattice(_matvec(P, self.L2), self.L1, self.L2)]
-        self.pg = pg
+        pts = _torus_points(self.L1, self.L2)
+        self.N = len(pts)
+        self.pg = self._point_group(pg_gens)
         self.sublat_chain = [tuple(map(tuple, s)) for s in sublat_chain]
-        for B1, B2 in self.sublat_chain:
-            assert _in_lattice(self.L1, B1, B2) and _in_lattice(self.L2, B1, B2)
-        # label sites: sort by coset ids along the chain, then coordinates
-        coset_ids = []
-        for B1, B2 in self.sublat_chain:
-            reps = sorted({_reduce(p, B1, B2) for p in pts})
-            coset_ids.append({p: reps.index(_reduce(p, B1, B2)) for p in pts})
-        order = sorted(pts, key=lambda p: tuple(c[p] for c in coset_ids) + (p[1], p[0]))
-        self.coords = order
-        self.index = {p: i for i, p in enumerate(order)}
-        self.sublat_options = [abs(_cross(B1, B2)) for (B1, B2) in self.sublat_chain]
+        self.coords, self.index, self.sublat_options = _label_sites(pts, self.sublat_chain, self.L1, self.L2)
+
+    def _point_group(self, gens):
+        """The elements of the group generated by ``gens`` that map the torus
+        onto itself."""
+        return [P for P in _group_closure(gens)
+                if _in_lattice(_matvec(P, self.L1), self.L1, self.L2)
+                and _in_lattice(_matvec(P, self.L2), self.L1, self.L2)]
 
     def site(self, r):
         return self.index[_reduce(r, self.L1, self.L2)]
@@ -307,33 +320,17 @@ class KagomeTorus(Torus2D):
     q_period = Fraction(1, 2)
 
     def __init__(self, L1, L2, pg_gens, sublat_chain):
-        L1, L2 = tuple(L1), tuple(L2)
-        assert all(c % 2 == 0 for c in L1 + L2), "kagome torus periods must be even"
-        self.L1, self.L2 = L1, L2
+        self.L1, self.L2 = tuple(L1), tuple(L2)
+        assert all(c % 2 == 0 for c in self.L1 + self.L2), "kagome torus periods must be even"
         self.cart = np.array(TRI_CART, dtype=float)
-        pts = set()
-        R = max(abs(c) for c in L1 + L2) + 1
-        for x in range(-2 * R, 2 * R + 1):
-            for y in range(-2 * R, 2 * R + 1):
-                pts.add(_reduce((x, y), L1, L2))
-        assert len(pts) == abs(_cross(L1, L2))
+        pts = _torus_points(self.L1, self.L2)
         self.trans = sorted(p for p in pts if not _kagome_site(p))
         pts = {p for p in pts if _kagome_site(p)}
         self.N = len(pts)
-        self.pg = [P for P in _group_closure(pg_gens)
-                   if _in_lattice(_matvec(P, L1), L1, L2) and _in_lattice(_matvec(P, L2), L1, L2)]
+        self.pg = self._point_group(pg_gens)
         self.sublat_chain = [tuple(map(tuple, c)) for c in sublat_chain]
-        coset_ids, opts = [], []
-        for B1, B2 in self.sublat_chain:
-            assert all(c % 2 == 0 for c in B1 + B2)
-            assert _in_lattice(L1, B1, B2) and _in_lattice(L2, B1, B2)
-            reps = sorted({_reduce(p, B1, B2) for p in pts})
-            coset_ids.append({p: reps.index(_reduce(p, B1, B2)) for p in pts})
-            opts.append(len(reps))
-        order = sorted(pts, key=lambda p: tuple(c[p] for c in coset_ids) + (p[1], p[0]))
-        self.coords = order
-        self.index = {p: i for i, p in enumerate(order)}
-        self.sublat_options = opts
+        assert all(c % 2 == 0 for B in self.sublat_chain for v in B for c in v)
+        self.coords, self.index, self.sublat_options = _label_sites(pts, self.sublat_chain, self.L1, self.L2)
 
     def translations(self):
         """The Bravais translations (even fine vectors) modulo the torus."""
