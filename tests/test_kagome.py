@@ -133,3 +133,38 @@ def test_kagome27_chain_is_stable():
         O.Fast(inst, 3).close()
         F = O.Fast(inst, 9)
         assert len(F.basis()[0]) == O.character_formula_dim(inst) == dim
+
+
+def test_kagome_sectors_named_and_inside_the_spectrum():
+    """Every one-dimensional sector of the 12-site kagome J1-J2-J3 model at
+    Sz = 0 and 1: dimension = character formula, names in the thesis's form
+    (Gamma, M, K of the kagome zone), and every sector level is a level of
+    the unsymmetrized Sz sector."""
+    for n_up in (6, 7):
+        insts = L.kagome_sectors(L.KAG12_L, L.KAG12_CHAIN, J2=0.2, J3=0.1, n_up=n_up)
+        full_inst = L.kagome_j1j2j3chi(L.KAG12_L[0], L.KAG12_L[1], 1.0, 0.2, 0.1, 0.0, L.Q0, "A", None,
+                                       L.KAG12_CHAIN, pg_gens=[], n_up=n_up)
+        _, Hs = O.unsym_sector_matrix(full_inst)
+        full = np.linalg.eigvalsh(Hs.toarray())
+        names = [(L.sector_label(i), i.meta["flip"]) for i in insts]
+        assert len(set(names)) == len(names)
+        moms = {n.split(".")[0] for n, _ in names}
+        assert moms == {"Gamma", "M"}                 # the 2 x 2 cell torus holds Gamma and the three M
+        assert {"Gamma.A1", "Gamma.A2", "Gamma.B1", "Gamma.B2"} <= {n for n, _ in names}
+        for inst in insts:
+            reps, stabs = O.enumerate_basis(inst)
+            assert len(reps) == O.character_formula_dim(inst)
+            if len(reps):
+                ev = np.linalg.eigvalsh(O.coo_matrix(inst, reps, stabs).toarray())
+                assert all(np.min(np.abs(full - e)) < 1e-10 for e in ev), L.sector_label(inst)
+
+
+def test_kagome27_sector_momenta():
+    """The 3 x 3 cell torus: Gamma, K (K and K' one star) and one six-member
+    star; C6v irreps named as on the triangular lattice."""
+    insts = L.kagome_sectors(L.KAG27_L, L.KAG27_CHAIN, n_up=13)
+    names = {L.sector_label(i) for i in insts}
+    assert names == {"Gamma.A1", "Gamma.A2", "Gamma.B1", "Gamma.B2", "K.A1", "K.ir1", "(0,1/3).A1", "(0,1/3).ir1"}
+    lat = insts[0].meta["lattice"]
+    stars = {frozenset(L._pg_orbit(lat, q)) for q in lat.momenta()}
+    assert sorted(len(st) for st in stars) == [1, 2, 6]

@@ -700,6 +700,10 @@ def pg_character(inst, P):
 
 
 def _momentum_name(kind, q):
+    if kind == "kagome":
+        # kagome momenta are taken modulo half the fine reciprocal lattice:
+        # twice q names the point of the kagome Brillouin zone
+        return _momentum_name("triangular", tuple(2 * x for x in q))
     h = Fraction(1, 2)
     names = {(Fraction(0), Fraction(0)): "Gamma"}
     if kind == "square":
@@ -731,10 +735,10 @@ def sector_label(inst):
     mirrored = any(P[0][0] * P[1][1] - P[0][1] * P[1][0] < 0 for P in little)
     if ir == 0:
         return f"{mom}.A1" if mirrored else f"{mom}.A"
-    if lat.kind == "triangular" and mom == "Gamma" and TRI_MY in little:
+    if lat.kind in ("triangular", "kagome") and mom == "Gamma" and TRI_MY in little:
         c = (round(pg_character(inst, TRI_R60).real), round(pg_character(inst, TRI_MY).real))
         return "Gamma." + {(1, -1): "A2", (-1, 1): "B1", (-1, -1): "B2"}[c]
-    if lat.kind == "triangular" and mom == "Gamma" and TRI_R60 in little and not mirrored:
+    if lat.kind in ("triangular", "kagome") and mom == "Gamma" and TRI_R60 in little and not mirrored:
         m = int(round(np.angle(pg_character(inst, TRI_R60)) * 6 / (2 * np.pi))) % 6
         return "Gamma." + {3: "B", 1: "E1a", 5: "E1b", 2: "E2a", 4: "E2b"}[m]
     if mom == "M" and not mirrored and TRI_C2 in little and len(little) == 2:
@@ -900,6 +904,17 @@ def kagome_instances():
         kagome_j1j2j3chi(KAG12_L[0], KAG12_L[1], 1.0, 0.1, 0.0, 0.3, Mq, "A", None, KAG12_CHAIN, n_up=5,
                          name="kagome12"),
     ]
+
+
+def kagome_sectors(L, chain, J2=0.0, J3=0.0, n_up=None, name="kagome"):
+    """Every one-dimensional sector of the kagome J1-J2-J3 model (J1 = 1, no
+    chirality, point group C6v about a hexagon centre) on the torus L at the
+    given number of up spins; ``meta`` as for ``square_sectors``."""
+    lat = kagome_lattice(L[0], L[1], chain, mirrors=True)
+    n_up = lat.N // 2 if n_up is None else n_up
+    return _all_sectors(lat, lambda q, ir, fl: kagome_j1j2j3chi(L[0], L[1], 1.0, J2, J3, 0.0, q, irrep=ir, flip=fl,
+                                                                sublat_chain=chain, mirrors=True, n_up=n_up),
+                        n_up, name)
 
 
 def kagome27(J2=0.0, J3=0.0, Jchi=0.0, q=Q0, irrep="A", n_up=13):
