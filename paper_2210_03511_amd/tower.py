@@ -261,9 +261,9 @@ def _main(argv=None):
     from workloads import lattices as L
 
     ap = argparse.ArgumentParser(description="Tower-of-states sweep: the low levels of every one-dimensional "
-                                             "sector at Sz = S, square J1-J2 (16, 32 sites) or triangular J1-J2 "
-                                             "(12, 36 sites, C6v).")
-    ap.add_argument("--lattice", default="square", choices=["square", "triangular"])
+                                             "sector at Sz = S, square J1-J2 (16, 32 sites), triangular J1-J2 "
+                                             "(12, 36 sites, C6v) or kagome J1-J2 (12 sites, C6v).")
+    ap.add_argument("--lattice", default="square", choices=["square", "triangular", "kagome"])
     ap.add_argument("--sites", type=int, default=32, choices=[12, 16, 32, 36])
     ap.add_argument("--J2", type=float, default=0.0)
     ap.add_argument("--spins", type=int, nargs="+", default=[0, 1, 2, 3])
@@ -284,11 +284,15 @@ def _main(argv=None):
         _order_main(a, L)
         return
     makers = {("square", 32): L.square32_sectors, ("square", 16): L.square16_sectors,
-              ("triangular", 12): L.triangular12_sectors, ("triangular", 36): L.triangular36_sectors}
+              ("triangular", 12): L.triangular12_sectors, ("triangular", 36): L.triangular36_sectors,
+              ("kagome", 12): lambda J2=0.0, n_up=None: L.kagome_sectors(L.KAG12_L, L.KAG12_CHAIN, J2=J2,
+                                                                         n_up=n_up)}
     if (a.lattice, a.sites) not in makers:
         ap.error(f"no {a.sites}-site {a.lattice} cluster; available: "
                  + ", ".join(f"{lat} {n}" for lat, n in makers))
     make = makers[(a.lattice, a.sites)]
+    if a.with_e and a.lattice == "kagome":
+        ap.error("--with-e: no sectors of 2-D irreps for the kagome lattice")
     if a.with_e:
         geo = {("square", 32): (L.SQ32_L, L.SQ32_CHAIN), ("square", 16): (L.SQ16_L, L.SQ16_CHAIN),
                ("triangular", 12): (L.TRI12_L, L.TRI12_CHAIN),
