@@ -33,9 +33,9 @@
  *     one of its sublattices X has Rep_X below the leading substate (some g
  *     then maps the configuration below itself);
  *   - H.v in the pull form of oracle.c (orc_rows), with the pieces of
- *     orc_apply_terms and the index found by binary search inside the
- *     range that a table of limits on the leading bits gives; OpenMP over
- *     rows.
+ *     orc_apply_terms (those with equal targets merged), the index found by
+ *     binary search inside the range that a table of limits on the leading
+ *     bits gives; OpenMP over rows.
  */
 #include <complex.h>
 #include <math.h>
@@ -317,11 +317,72 @@ static int64_t limits_find(const orf_limits *L, const uint64_t *reps, uint64_t s
 }
 
 /*
+ * Pieces of one row with equal targets, their amplitudes summed (the
+ * non-branching terms that flip the same pair of spins, e.g. an exchange and
+ * the chirality terms on that bond, act as one term with the summed
+ * amplitude): a small open-addressing table keyed by the target, emptied per
+ * row by a generation count.
+ */
+typedef struct {
+    int mask;
+    uint64_t *key;
+    int32_t *slot;         /* position in the merged list */
+    uint32_t *gen;
+    uint32_t cur;
+} orf_merge;
+
+static int merge_init(orf_merge *M, int mt)
+{
+    int size = 16;
+    while (size < 2 * mt) size <<= 1;
+    M->mask = size - 1;
+    M->key = malloc(sizeof(uint64_t) * size);
+    M->slot = malloc(sizeof(int32_t) * size);
+    M->gen = calloc(size, sizeof(uint32_t));
+    M->cur = 0;
+    return M->key && M->slot && M->gen;
+}
+
+static void merge_free(orf_merge *M)
+{
+    free(M->key);
+    free(M->slot);
+    free(M->gen);
+}
+
+/* merges the m pieces (tau, h) in place; returns the number of distinct targets */
+static int merge_pieces(orf_merge *M, uint64_t *tau, double complex *h, int m)
+{
+    if (++M->cur == 0) {                 /* generation wrapped: clear */
+        memset(M->gen, 0, sizeof(uint32_t) * (size_t)(M->mask + 1));
+        M->cur = 1;
+    }
+    int u = 0;
+    for (int q = 0; q < m; ++q) {
+        uint64_t k = tau[q] * 0x9E3779B97F4A7C15ull;
+        int e = (int)(k >> 40) & M->mask;
+        while (M->gen[e] == M->cur && M->key[e] != tau[q]) e = (e + 1) & M->mask;
+        if (M->gen[e] == M->cur) {
+            h[M->slot[e]] += h[q];
+        } else {
+            M->gen[e] = M->cur;
+            M->key[e] = tau[q];
+            M->slot[e] = u;
+            tau[u] = tau[q];
+            h[u] = h[q];
+            ++u;
+        }
+    }
+    return u;
+}
+
+/*
  * y = H x over the whole basis, pull form (as orc_rows):
  *   y_i = sum_k chi(g) sqrt(|Stab tau~| / |Stab sigma_i|) conj(h_k) x(tau~_k)
- * over the pieces of orc_apply_terms whose target lies in the basis.
- * x, y: interleaved complex (re, im) when cplx, else real.  Returns 0, or
- * -1 when the table of limits cannot be allocated (y untouched).
+ * over the pieces of orc_apply_terms whose target lies in the basis, pieces
+ * with equal targets merged first.  x, y: interleaved complex (re, im) when
+ * cplx, else real.  Returns 0, or -1 when the table of limits or a merge
+ * table cannot be allocated (y untouched).
  */
 int orf_apply(const orc_problem *p, const orf_tables *t, const uint64_t *reps, const int32_t *stabs, int64_t dim,
                const double *x, double *y, int cplx)
@@ -329,32 +390,41 @@ int orf_apply(const orc_problem *p, const orf_tables *t, const uint64_t *reps, c
     const int mt = orc_max_terms(p);
     orf_limits lim = limits_build(reps, dim, t->n);
     if (!lim.lim) return -1;
+    int failed = 0;
     #pragma omp parallel
     {
         uint64_t *tau = malloc(sizeof(uint64_t) * mt);
         double complex *h = malloc(sizeof(double complex) * mt);
-        #pragma omp for schedule(dynamic, 256)
-        for (int64_t i = 0; i < dim; ++i) {
-            const int m = orc_apply_terms(p, reps[i], tau, h);
-            double complex acc = 0;
-            for (int q = 0; q < m; ++q) {
-                if (h[q] == 0) continue;
-                uint64_t r; int32_t g, st, tv;
-                orf_find_rep(t, tau[q], &r, &g, &st, &tv);
-                if (!tv) continue;
-                const int64_t j = limits_find(&lim, reps, r);
-                if (j < 0) continue;
-                const double complex chi = p->chi_re[g] + I * p->chi_im[g];
-                const double complex c = chi * sqrt((double)st / (double)stabs[i]) * conj(h[q]);
-                const double complex xj = cplx ? x[2 * j] + I * x[2 * j + 1] : x[j];
-                acc += c * xj;
+        orf_merge M;
+        const int ok = merge_init(&M, mt) && tau && h;
+        #pragma omp atomic
+        failed += !ok;
+        #pragma omp barrier
+        if (!failed) {
+            #pragma omp for schedule(dynamic, 256)
+            for (int64_t i = 0; i < dim; ++i) {
+                const int m = merge_pieces(&M, tau, h, orc_apply_terms(p, reps[i], tau, h));
+                double complex acc = 0;
+                for (int q = 0; q < m; ++q) {
+                    if (h[q] == 0) continue;
+                    uint64_t r; int32_t g, st, tv;
+                    orf_find_rep(t, tau[q], &r, &g, &st, &tv);
+                    if (!tv) continue;
+                    const int64_t j = limits_find(&lim, reps, r);
+                    if (j < 0) continue;
+                    const double complex chi = p->chi_re[g] + I * p->chi_im[g];
+                    const double complex c = chi * sqrt((double)st / (double)stabs[i]) * conj(h[q]);
+                    const double complex xj = cplx ? x[2 * j] + I * x[2 * j + 1] : x[j];
+                    acc += c * xj;
+                }
+                if (cplx) { y[2 * i] = creal(acc); y[2 * i + 1] = cimag(acc); }
+                else y[i] = creal(acc);
             }
-            if (cplx) { y[2 * i] = creal(acc); y[2 * i + 1] = cimag(acc); }
-            else y[i] = creal(acc);
         }
         free(tau);
         free(h);
+        merge_free(&M);
     }
     free(lim.lim);
-    return 0;
+    return failed ? -1 : 0;
 }
