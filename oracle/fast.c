@@ -219,7 +219,8 @@ void orf_find_rep_many(const orf_tables *t, const uint64_t *c, int64_t m, uint64
  *     prefix: some g in G_X maps the configuration below itself.
  * A configuration that survives is checked by orf_find_rep.  Pass 1 counts
  * per leading substate, pass 2 writes (when reps is not NULL and the
- * dimension fits cap).  Returns the dimension.
+ * dimension fits cap).  Returns the dimension, or -1 without memory for the
+ * counts.
  */
 typedef struct {
     const orf_tables *t;
@@ -258,6 +259,7 @@ int64_t orf_enumerate(const orf_tables *t, int n_up, uint64_t *reps, int32_t *st
 {
     const uint64_t S = t->S;
     int64_t *cnt = calloc(S + 1, sizeof(int64_t));
+    if (!cnt) return -1;
     #pragma omp parallel for schedule(dynamic, 1)
     for (uint64_t s0 = 0; s0 < S; ++s0) {
         const int pc = popc(s0);

@@ -189,6 +189,8 @@ class Fast:
     def basis(self):
         L = lib()
         dim = L.orf_enumerate(self.h, self.inst.n_up, None, None, 0)
+        if dim < 0:
+            raise MemoryError("fast oracle: no memory for the enumeration counts")
         reps = np.zeros(dim, np.uint64)
         stabs = np.zeros(dim, np.int32)
         if dim:
